@@ -1,0 +1,178 @@
+/*
+ * swdb — score-only Smith-Waterman / Gotoh protein database search on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper Section 2.2, equations for H, E and F): for a query Q
+ * (m residues, rows i) and each database subject D (n residues, columns j),
+ *
+ *   H[i][j] = max(0, H[i-1][j-1] + SM(Q[i], D[j]), E[i][j], F[i][j])
+ *   E[i][j] = max(H[i][j-1] - Go, E[i][j-1] - Ge)
+ *   F[i][j] = max(H[i-1][j] - Go, F[i-1][j] - Ge)
+ *
+ * with H = E = F = 0 on row 0 and column 0; the subject's score is the
+ * largest H of its matrix (the optimal local alignment score), returned as
+ * int32.  A gap of L residues therefore costs Go + (L-1)*Ge.  Scores are exact
+ * integers: every mode of this library returns bit-identical results.
+ *
+ * Conventions for every call:
+ *   - "device" pointers are HIP device memory of the current device (for
+ *     example torch tensors' data_ptr()); "host" pointers are ordinary memory;
+ *   - the caller owns every buffer it passes; the library owns only what a
+ *     database handle allocates (see sw_db_prepare);
+ *   - searches are asynchronous on `stream` (a hipStream_t, NULL = default
+ *     stream); results are valid once the stream has been synchronised;
+ *   - every call returns SW_OK (0) or a negative SW_E* code and validates its
+ *     arguments before any HIP call; sw_last_error() gives detail text.
+ *
+ * Residues are uint8 codes 0..31; the substitution matrix is 32x32 int32,
+ * row-major, indexed [query residue][subject residue], entries in
+ * [-128, 127].  Gap penalties are non-negative magnitudes (subtracted as in
+ * the E and F equations), each at most SW_MAX_GAP.
+ */
+#ifndef SWDB_H
+#define SWDB_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SW_ALPHA 32
+#define SW_MAX_GAP 32000
+#define SW_MAX_QLEN (1 << 24)
+
+#define SW_OK 0
+#define SW_EINVAL (-1)     /* bad argument (null, negative, out of range)        */
+#define SW_ENOMEM (-2)     /* workspace too small, or an allocation failed        */
+#define SW_EHIP (-3)       /* a HIP runtime call failed; see sw_last_error()      */
+#define SW_EUNSUP (-4)     /* the current device is not gfx950                    */
+#define SW_EBADRES (-5)    /* a database residue code is >= SW_ALPHA              */
+
+/* Arithmetic mode of a search.  All modes give identical scores. */
+#define SW_MODE_AUTO 0     /* packed 16-bit lanes + exact int32 rescore           */
+#define SW_MODE_I32 1      /* int32 lanes (the paper's 32-bit formulation)        */
+#define SW_MODE_I16 2      /* packed 2x16-bit saturating lanes; subjects whose
+                              16-bit score reaches 32767 are rescored in int32    */
+
+typedef struct sw_db_s* sw_db_t;
+
+/* Tuning knobs.  Zero-initialise and set what you need; 0 = library default. */
+typedef struct sw_options {
+    int32_t mode;          /* SW_MODE_*                                            */
+    int32_t waves;         /* wavefronts per workgroup (1..4)                      */
+    int32_t lane_cells;    /* target cells per lane per work item (load balance)  */
+    int32_t max_lanes;     /* largest lane group per subject (1..64, power of 2)   */
+    int32_t lds_limit;     /* largest query profile staged in LDS, bytes           */
+    int32_t grid_limit;    /* cap on persistent workgroups (0 = fill the device)   */
+    int32_t reserved[10];
+} sw_options;
+
+/* Plan summary (for measurement; all counts are per search call). */
+typedef struct sw_plan_stats {
+    int64_t cells;         /* sum over queries of m * (sum of subject lengths)     */
+    int64_t lane_cells;    /* cells the lanes sweep including padding              */
+    int64_t items;         /* wavefront work items                                 */
+    int64_t wg_items;      /* workgroup work items (queue length)                  */
+    int64_t grid;          /* persistent workgroups launched                       */
+    int64_t slot_bytes;    /* per-wavefront pass-boundary scratch                  */
+    int64_t workspace;     /* bytes sw_workspace_bytes() returns                   */
+    int32_t variant;       /* kernel variant (0: int32 8-bit profile, 1: int32
+                              16-bit profile, 2: packed 16-bit)                    */
+    int32_t rows;          /* query rows per lane                                  */
+} sw_plan_stats;
+
+/*
+ * One-shot search (paper Section 2.2 problem statement; the database search
+ * workload of Section 4.1).
+ *   query        device, uint8[qlen]
+ *   db_residues  device, uint8[sum of lengths], subject i at db_offsets[i]
+ *   db_offsets   device, int64[nseq]
+ *   db_lengths   device, int32[nseq], each >= 0
+ *   subst_matrix HOST, int32[32*32], [query residue][subject residue]
+ *   scores_out   device, int32[nseq], in the caller's subject order
+ * Prepares a temporary database, allocates its own workspace, searches in
+ * SW_MODE_AUTO and synchronises `stream` before returning (this call is
+ * blocking).  qlen = 0, nseq = 0 and empty subjects are legal (score 0).
+ */
+int sw_db_search(const uint8_t* query, int32_t qlen,
+                 const uint8_t* db_residues, const int64_t* db_offsets,
+                 const int32_t* db_lengths, int32_t nseq,
+                 const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
+                 int32_t* scores_out, hipStream_t stream);
+
+/*
+ * Resident database (paper Section 3.1: the database is split by length; here
+ * it is sorted by length, descending, and lane-interleaved 64 subjects to a
+ * chunk).  Arguments as for sw_db_search.  Blocking: copies the lengths to
+ * the host, sorts, then builds the device layout on `stream` and waits for
+ * it.  The handle owns that device memory (about sum of lengths + padding,
+ * plus 12 bytes per subject) until sw_db_release().  Returns SW_EBADRES if a
+ * residue code is >= 32, SW_EUNSUP off gfx950.  A handle may be used by
+ * several streams at once if each call has its own workspace.
+ */
+int sw_db_prepare(const uint8_t* db_residues, const int64_t* db_offsets,
+                  const int32_t* db_lengths, int32_t nseq, hipStream_t stream,
+                  sw_db_t* out);
+
+/* Frees the handle's device memory.  No search may still be in flight. */
+int sw_db_release(sw_db_t db);
+
+/* nseq, residues and device bytes held by the handle (any pointer may be NULL). */
+int sw_db_info(sw_db_t db, int64_t* nseq, int64_t* residues, int64_t* device_bytes);
+
+/*
+ * Workspace bytes a search of nq queries with HOST lengths q_lens[nq] needs
+ * under `opt` (NULL = defaults).  Returns 0 on invalid arguments.
+ */
+size_t sw_workspace_bytes(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt);
+
+/* Plan summary for the same arguments (host only; no HIP call). */
+int sw_plan_info(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt,
+                 sw_plan_stats* out);
+
+/*
+ * One query against a resident database.
+ *   query       device, uint8[qlen]
+ *   workspace   device, at least sw_workspace_bytes(db, 1, &qlen, opt) bytes,
+ *               256-byte aligned; must not be shared by concurrent calls
+ *   scores_out  device, int32[nseq], caller's subject order
+ * Asynchronous on `stream`; the host returns once the work is enqueued.
+ */
+int sw_db_search_ex(sw_db_t db, const uint8_t* query, int32_t qlen,
+                    const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
+                    const sw_options* opt, void* workspace, size_t ws_bytes,
+                    int32_t* scores_out, hipStream_t stream);
+
+/*
+ * nq queries against a resident database in one persistent launch (paper
+ * Section 4.1: 20 queries per search; length-binned work items served
+ * longest first).
+ *   queries     device, uint8, query k at q_offsets[k]
+ *   q_offsets   HOST, int64[nq]
+ *   q_lens      HOST, int32[nq], each in [0, SW_MAX_QLEN]
+ *   scores_out  device, int32[nq][nseq] (row k = query k, caller's order)
+ * Workspace as for sw_db_search_ex with all nq lengths.  Asynchronous.
+ */
+int sw_db_search_batch(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets,
+                       const int32_t* q_lens, int32_t nq,
+                       const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
+                       const sw_options* opt, void* workspace, size_t ws_bytes,
+                       int32_t* scores_out, hipStream_t stream);
+
+/*
+ * Number of subjects the last search that used `workspace` sent to the int32
+ * rescore (16-bit modes).  Synchronises `stream`.  Negative on error.
+ */
+int64_t sw_flagged_count(const void* workspace, hipStream_t stream);
+
+const char* sw_strerror(int code);
+const char* sw_last_error(void);   /* thread-local detail of the last failure */
+const char* sw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWDB_H */

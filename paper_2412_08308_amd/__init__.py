@@ -1,0 +1,282 @@
+"""Python binding of ``libswdb.so``: score-only Smith-Waterman / Gotoh protein
+database search on MI355X (gfx950).
+
+Every step of the search runs in the library's HIP kernels; this module only
+marshals arguments through ctypes.  PyTorch supplies device memory (tensors)
+and streams.  If the library is missing, every entry point raises
+``SwdbError`` -- there is no CPU fallback.
+
+Names mirror the C-ABI in ``include/swdb.h``:
+
+* ``search`` -> ``sw_db_search`` (one-shot, blocking);
+* ``Database`` -> ``sw_db_prepare`` / ``sw_db_release`` (resident database),
+  with ``search`` -> ``sw_db_search_ex`` and ``search_batch`` ->
+  ``sw_db_search_batch`` (asynchronous on the current stream), and
+  ``workspace_bytes`` / ``plan_info``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswdb.so")
+
+SW_OK = 0
+MODE_AUTO, MODE_I32, MODE_I16 = 0, 1, 2
+MODES = {"auto": MODE_AUTO, "i32": MODE_I32, "i16": MODE_I16}
+MAX_GAP = 32000
+
+
+class SwdbError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str = ""):
+        super().__init__(f"{where}: {detail or 'error'} (code {code})")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("lane_cells", ctypes.c_int32), ("max_lanes", ctypes.c_int32),
+                ("lds_limit", ctypes.c_int32), ("grid_limit", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 10)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("cells", ctypes.c_int64), ("lane_cells", ctypes.c_int64),
+                ("items", ctypes.c_int64), ("wg_items", ctypes.c_int64),
+                ("grid", ctypes.c_int64), ("slot_bytes", ctypes.c_int64),
+                ("workspace", ctypes.c_int64), ("variant", ctypes.c_int32),
+                ("rows", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libswdb.so`` (raises ``SwdbError`` when it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SwdbError(-100, "load", f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.sw_db_search.restype = ctypes.c_int
+    L.sw_db_search.argtypes = [vp, i32, vp, vp, vp, i32, vp, i32, i32, vp, vp]
+    L.sw_db_prepare.restype = ctypes.c_int
+    L.sw_db_prepare.argtypes = [vp, vp, vp, i32, vp, ctypes.POINTER(vp)]
+    L.sw_db_release.restype = ctypes.c_int
+    L.sw_db_release.argtypes = [vp]
+    L.sw_db_info.restype = ctypes.c_int
+    L.sw_db_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.sw_workspace_bytes.restype = sz
+    L.sw_workspace_bytes.argtypes = [vp, i32, vp, ctypes.POINTER(Options)]
+    L.sw_plan_info.restype = ctypes.c_int
+    L.sw_plan_info.argtypes = [vp, i32, vp, ctypes.POINTER(Options), ctypes.POINTER(PlanStats)]
+    L.sw_db_search_ex.restype = ctypes.c_int
+    L.sw_db_search_ex.argtypes = [vp, vp, i32, vp, i32, i32, ctypes.POINTER(Options), vp, sz, vp, vp]
+    L.sw_db_search_batch.restype = ctypes.c_int
+    L.sw_db_search_batch.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, ctypes.POINTER(Options),
+                                     vp, sz, vp, vp]
+    L.sw_flagged_count.restype = ctypes.c_int64
+    L.sw_flagged_count.argtypes = [vp, vp]
+    L.sw_strerror.restype = ctypes.c_char_p
+    L.sw_strerror.argtypes = [ctypes.c_int]
+    L.sw_last_error.restype = ctypes.c_char_p
+    L.sw_last_error.argtypes = []
+    L.sw_version.restype = ctypes.c_char_p
+    L.sw_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str):
+    if rc != SW_OK:
+        L = lib()
+        raise SwdbError(rc, where, f"{L.sw_strerror(rc).decode()}: {L.sw_last_error().decode()}")
+
+
+def version() -> str:
+    return lib().sw_version().decode()
+
+
+def options(mode="auto", waves=0, lane_cells=0, max_lanes=0, lds_limit=0, grid_limit=0) -> Options:
+    o = Options()
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    o.waves, o.lane_cells, o.max_lanes = int(waves), int(lane_cells), int(max_lanes)
+    o.lds_limit, o.grid_limit = int(lds_limit), int(grid_limit)
+    return o
+
+
+def _matrix(sm) -> np.ndarray:
+    """Host int32 32x32 copy (the ABI takes the matrix from host memory)."""
+    if hasattr(sm, "detach"):
+        sm = sm.detach().cpu().numpy()
+    m = np.ascontiguousarray(np.asarray(sm, dtype=np.int32))
+    if m.shape != (32, 32):
+        raise ValueError("substitution matrix must be 32x32")
+    return m
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
+def search(query, residues, offsets, lengths, matrix, gap_open: int, gap_extend: int,
+           out=None, stream=None):
+    """One-shot ``sw_db_search`` (blocking).  Returns int32 scores on the device."""
+    import torch
+    n = int(lengths.numel())
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=lengths.device)
+    sm = _matrix(matrix)
+    rc = lib().sw_db_search(_dev(query, torch.uint8, "query"), int(query.numel()),
+                            _dev(residues, torch.uint8, "residues"), _dev(offsets, torch.int64, "offsets"),
+                            _dev(lengths, torch.int32, "lengths"), n, sm.ctypes.data,
+                            int(gap_open), int(gap_extend), _dev(out, torch.int32, "out"), _stream(stream))
+    _check(rc, "sw_db_search")
+    return out
+
+
+class Database:
+    """A resident, length-sorted, lane-interleaved database (``sw_db_prepare``)."""
+
+    def __init__(self, residues, offsets, lengths, stream=None):
+        import torch
+        self.nseq = int(lengths.numel())
+        self.device = lengths.device
+        h = ctypes.c_void_p()
+        rc = lib().sw_db_prepare(_dev(residues, torch.uint8, "residues"),
+                                 _dev(offsets, torch.int64, "offsets"),
+                                 _dev(lengths, torch.int32, "lengths"), self.nseq,
+                                 _stream(stream), ctypes.byref(h))
+        _check(rc, "sw_db_prepare")
+        self._h = h
+        n, r, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().sw_db_info(h, ctypes.byref(n), ctypes.byref(r), ctypes.byref(b)), "sw_db_info")
+        self.total = int(r.value)
+        self.device_bytes = int(b.value)
+
+    @classmethod
+    def from_host(cls, db, device="cuda", stream=None):
+        """From a ``synth.Database``-like object with numpy arrays."""
+        import torch
+        res = torch.from_numpy(np.ascontiguousarray(db.residues)).to(device)
+        off = torch.from_numpy(np.ascontiguousarray(db.offsets, dtype=np.int64)).to(device)
+        ln = torch.from_numpy(np.ascontiguousarray(db.lengths, dtype=np.int32)).to(device)
+        return cls(res, off, ln, stream)
+
+    def _handle(self):
+        if self._h is None:
+            raise SwdbError(-1, "Database", "released")
+        return self._h
+
+    def release(self):
+        if getattr(self, "_h", None) is not None:
+            lib().sw_db_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, qlens: Sequence[int], opt: Optional[Options] = None) -> int:
+        ql = np.ascontiguousarray(np.asarray(qlens, dtype=np.int32))
+        n = lib().sw_workspace_bytes(self._handle(), len(ql), ql.ctypes.data if len(ql) else None,
+                                     ctypes.byref(opt) if opt is not None else None)
+        if n == 0 and len(ql):
+            raise SwdbError(-1, "sw_workspace_bytes", lib().sw_last_error().decode())
+        return int(n)
+
+    def plan_info(self, qlens: Sequence[int], opt: Optional[Options] = None) -> dict:
+        ql = np.ascontiguousarray(np.asarray(qlens, dtype=np.int32))
+        st = PlanStats()
+        _check(lib().sw_plan_info(self._handle(), len(ql), ql.ctypes.data if len(ql) else None,
+                                  ctypes.byref(opt) if opt is not None else None, ctypes.byref(st)),
+               "sw_plan_info")
+        return st.as_dict()
+
+    def alloc_workspace(self, qlens: Sequence[int], opt: Optional[Options] = None):
+        import torch
+        n = self.workspace_bytes(qlens, opt)
+        return torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
+
+    def search(self, query, matrix, gap_open: int, gap_extend: int, opt: Optional[Options] = None,
+               out=None, workspace=None, stream=None):
+        """``sw_db_search_ex``: one device query; asynchronous on ``stream``."""
+        import torch
+        m = int(query.numel())
+        if workspace is None:
+            workspace = self.alloc_workspace([m], opt)
+        if out is None:
+            out = torch.empty(self.nseq, dtype=torch.int32, device=self.device)
+        sm = _matrix(matrix)
+        rc = lib().sw_db_search_ex(self._handle(), _dev(query, torch.uint8, "query"), m, sm.ctypes.data,
+                                   int(gap_open), int(gap_extend),
+                                   ctypes.byref(opt) if opt is not None else None,
+                                   _dev(workspace, torch.uint8, "workspace"), int(workspace.numel()),
+                                   _dev(out, torch.int32, "out"), _stream(stream))
+        _check(rc, "sw_db_search_ex")
+        self._last_ws = workspace
+        return out
+
+    def search_batch(self, queries, matrix, gap_open: int, gap_extend: int,
+                     opt: Optional[Options] = None, out=None, workspace=None, stream=None):
+        """``sw_db_search_batch``.  ``queries``: a list of device uint8 tensors,
+        or a tuple (concatenated device tensor, host offsets, host lengths)."""
+        import torch
+        if isinstance(queries, tuple):
+            cat, offs, lens = queries
+            offs = np.ascontiguousarray(np.asarray(offs, dtype=np.int64))
+            lens = np.ascontiguousarray(np.asarray(lens, dtype=np.int32))
+        else:
+            lens = np.array([int(q.numel()) for q in queries], dtype=np.int32)
+            offs = np.zeros(len(lens), dtype=np.int64)
+            if len(lens) > 1:
+                offs[1:] = np.cumsum(lens[:-1])
+            cat = (torch.cat([q.reshape(-1) for q in queries]) if len(queries)
+                   else torch.empty(0, dtype=torch.uint8, device=self.device))
+        nq = len(lens)
+        if workspace is None:
+            workspace = self.alloc_workspace(lens, opt)
+        if out is None:
+            out = torch.empty((nq, self.nseq), dtype=torch.int32, device=self.device)
+        sm = _matrix(matrix)
+        rc = lib().sw_db_search_batch(self._handle(), _dev(cat, torch.uint8, "queries"),
+                                      offs.ctypes.data if nq else None, lens.ctypes.data if nq else None,
+                                      nq, sm.ctypes.data, int(gap_open), int(gap_extend),
+                                      ctypes.byref(opt) if opt is not None else None,
+                                      _dev(workspace, torch.uint8, "workspace"), int(workspace.numel()),
+                                      _dev(out, torch.int32, "out"), _stream(stream))
+        _check(rc, "sw_db_search_batch")
+        self._keep = (cat, workspace)
+        return out
+
+    def flagged_count(self, workspace, stream=None) -> int:
+        import torch
+        v = lib().sw_flagged_count(_dev(workspace, torch.uint8, "workspace"), _stream(stream))
+        if v < 0:
+            _check(int(v), "sw_flagged_count")
+        return int(v)

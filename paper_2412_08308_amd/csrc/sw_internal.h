@@ -1,0 +1,105 @@
+// Internal declarations shared by the gfx950 kernels and the host runtime.
+//
+// Terminology (query Q of m residues along rows i, subject D of n residues
+// along columns j, as in the paper's Section 2.2 recurrence):
+//   R      query rows a lane keeps in registers (a "row block")
+//   K      lanes that cooperate on one subject (a pipelined group)
+//   pass   one sweep over all columns of a subject covering K row blocks
+//   item   the work of one wavefront: 64/K subjects (int32 path) or 128/K
+//          subjects (packed 16-bit path), all of one query
+//   slot   per-wavefront scratch in the workspace that carries the bottom row
+//          (H - Go, F) of one pass to the first row of the next pass
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace swdb {
+
+constexpr int kAlpha = 32;           // residue codes 0..31 accepted at the ABI
+constexpr int kCodes = 33;           // + internal pad code
+constexpr uint8_t kPad = 32;         // pad code: subject tails and chunk fill
+constexpr int kWave = 64;
+
+// Work item (one wavefront).  meta = nsub | logK << 16.
+struct Item {
+    int32_t s0;      // first sorted subject index
+    int32_t ncols;   // columns to sweep: longest subject of the item, rounded up to 16
+    int32_t q;       // query index in the batch
+    int32_t meta;
+};
+
+// Per-query descriptor, built on the host, uploaded with the items.
+struct QueryDesc {
+    int64_t prof_off;   // byte offset of this query's profile in the profile area
+    int32_t m;          // query length
+    int32_t nbr;        // row blocks: ceil(m / R)
+    int32_t prof_bytes; // (nbr + 1) * 33 * code stride
+    int32_t lds;        // 1: profile staged in LDS; 0: read from global memory
+    int32_t wg_begin;   // first workgroup item of this query in the queue
+    int32_t wg_count;   // number of workgroup items of this query
+};
+
+struct Matrix8 {
+    int8_t v[kAlpha * kAlpha];   // [query residue][subject residue]
+};
+
+struct SearchArgs {
+    // prepared database
+    const uint8_t* res;          // lane-interleaved residues (16 per lane per block)
+    const int64_t* chunk_off;    // byte offset of each 64-subject chunk
+    const int32_t* perm;         // sorted index -> caller's index
+    const int32_t* slen;         // sorted index -> length
+    int32_t nseq;
+    // plan
+    const Item* items;           // n_wg * waves entries
+    const QueryDesc* qd;
+    int32_t nq;
+    int32_t n_wg;                // workgroup items in the queue
+    const uint8_t* prof;         // profile area (global)
+    // outputs and scratch
+    int32_t* scores;             // [nq][out_stride]
+    int64_t out_stride;
+    int32_t* counters;           // [0] queue head, [1] overflow-flag count
+    int2* bnd;                   // slots
+    int64_t slot_elems;          // int2 entries per slot
+    int2* flags;                 // (q, sorted subject) of 16-bit overflows
+    int32_t flag_cap;
+    int32_t go, ge;
+};
+
+struct ProfileArgs {
+    const uint8_t* queries;      // concatenated query residues (device)
+    const int64_t* q_off;        // device copy of offsets
+    const QueryDesc* qd;
+    uint8_t* prof;
+    int32_t* counters;
+    int32_t nq;
+    int32_t go;
+    Matrix8 sm;
+};
+
+// Kernel variants the runtime may launch.
+enum Variant : int {
+    kI32_R32_P8 = 0,   // int32 lanes, 32 rows, 8-bit profile
+    kI32_R32_P16 = 1,  // int32 lanes, 32 rows, 16-bit profile
+    kI16_R16 = 2,      // packed 16-bit lanes, 16 rows, 16-bit profile
+};
+
+struct LaunchInfo {
+    int rows;            // R
+    int prof_elem;       // bytes per profile entry
+    int subjects_per_lane;
+};
+LaunchInfo variant_info(Variant v);
+
+// Host-side launchers (defined with the kernels).
+hipError_t launch_profile(const ProfileArgs& a, int rows, int elem, int max_entries, hipStream_t st);
+hipError_t launch_search(Variant v, const SearchArgs& a, int grid, int waves, int lds_bytes, hipStream_t st);
+hipError_t launch_rescore(Variant v, const SearchArgs& a, int grid, int waves, hipStream_t st);
+hipError_t launch_interleave(const uint8_t* src, const int64_t* src_off, const int32_t* perm,
+                             const int32_t* slen, const int64_t* chunk_off, int32_t nseq,
+                             int64_t nthreads_total, const int64_t* block_prefix, int32_t nchunks,
+                             uint8_t* dst, int32_t* bad, hipStream_t st);
+int search_occupancy(Variant v, int waves, int lds_bytes);   // workgroups per CU
+
+}  // namespace swdb

@@ -1,0 +1,743 @@
+// Host runtime and C-ABI of the gfx950 Smith-Waterman / Gotoh database search.
+//
+// Responsibilities:
+//   * argument validation (before any HIP call);
+//   * database preparation: length sort (descending, stable), chunking of 64
+//     subjects, lane interleaving on the device (paper Section 3.1 splits the
+//     database by length; here every subject gets a lane group sized to it);
+//   * planning: per query, the sorted subjects are cut into wavefront items
+//     whose lane group K grows with subject length so that every item carries a
+//     bounded amount of work per lane; items are grouped four to a workgroup
+//     item and ordered longest-first (longest-processing-time scheduling);
+//     batches place the largest query first;
+//   * workspace layout, plan upload through pinned staging buffers, and the
+//     profile / search / rescore launches, all asynchronous on the caller's
+//     stream.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "swdb.h"
+#include "sw_internal.h"
+
+using namespace swdb;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            return fail(SW_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+constexpr int kDefaultWaves = 4;
+constexpr int64_t kDefaultLaneCells = 96 * 1024;
+constexpr int kDefaultLdsLimit = 64 * 1024;
+constexpr int kLdsPerCU = 160 * 1024;
+constexpr int kMaxWavesPerCU = 16;      // 4 per SIMD: kernels are built for <= 128 VGPRs
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int64_t align_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+struct Staging {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+
+struct PlanKey {
+    int rows, spl, waves, kmax, nbr;
+    int64_t target;
+    bool operator<(const PlanKey& o) const
+    {
+        return std::tie(rows, spl, waves, kmax, nbr, target) <
+               std::tie(o.rows, o.spl, o.waves, o.kmax, o.nbr, o.target);
+    }
+};
+
+// Items of one query (q field 0), grouped by workgroup item, longest first.
+struct QPlan {
+    std::vector<Item> items;      // n_wg * waves
+    int64_t n_wg = 0;
+    int64_t slot_elems = 0;       // int2 entries a multi-pass item needs
+    int64_t lane_cells = 0;       // sum over items of 64 * per-lane cells
+    int64_t cost = 0;             // sum of workgroup-item costs
+    int64_t nitems = 0;
+};
+
+struct Resolved {
+    Variant v;
+    int rows, elem, spl, waves, kmax, lds_limit, grid_limit;
+    int64_t target;
+    bool i16;
+};
+
+}  // namespace
+
+struct sw_db_s {
+    int device = 0;
+    int cu = 0;
+    int lds_max = 64 * 1024;      // dynamic LDS a workgroup may use on this device
+    int32_t nseq = 0;
+    int64_t total = 0;
+    int32_t nchunks = 0;
+    int32_t max_len = 0;
+    uint8_t* d_res = nullptr;
+    int64_t* d_chunk_off = nullptr;
+    int32_t* d_perm = nullptr;
+    int32_t* d_slen = nullptr;
+    int64_t res_bytes = 0;
+    int64_t dev_bytes = 0;
+    std::vector<int32_t> slen;    // sorted lengths
+    std::mutex mu;
+    std::vector<Staging> staging;
+    std::map<PlanKey, std::shared_ptr<QPlan>> plans;
+    std::deque<PlanKey> plan_order;
+};
+
+namespace {
+
+bool validate_options(const sw_options* opt, std::string& why)
+{
+    if (!opt)
+        return true;
+    if (opt->mode < SW_MODE_AUTO || opt->mode > SW_MODE_I16) { why = "options.mode"; return false; }
+    if (opt->waves < 0 || opt->waves > 4) { why = "options.waves must be 0..4"; return false; }
+    if (opt->lane_cells < 0) { why = "options.lane_cells"; return false; }
+    if (opt->max_lanes < 0 || opt->max_lanes > 64 || (opt->max_lanes & (opt->max_lanes - 1))) {
+        why = "options.max_lanes must be 0 or a power of two <= 64";
+        return false;
+    }
+    if (opt->lds_limit < 0 || opt->lds_limit > 128 * 1024) { why = "options.lds_limit"; return false; }
+    if (opt->grid_limit < 0) { why = "options.grid_limit"; return false; }
+    return true;
+}
+
+Resolved resolve(const sw_db_s* db, const sw_options* opt, int elem_i32)
+{
+    Resolved r{};
+    const int mode = opt ? opt->mode : SW_MODE_AUTO;
+    r.i16 = mode != SW_MODE_I32;
+    if (r.i16) {
+        r.v = kI16_R16;
+    } else {
+        r.v = elem_i32 == 1 ? kI32_R32_P8 : kI32_R32_P16;
+    }
+    const LaunchInfo li = variant_info(r.v);
+    r.rows = li.rows;
+    r.elem = li.prof_elem;
+    r.spl = li.subjects_per_lane;
+    r.waves = (opt && opt->waves) ? opt->waves : kDefaultWaves;
+    r.kmax = (opt && opt->max_lanes) ? opt->max_lanes : 64;
+    r.target = (opt && opt->lane_cells) ? opt->lane_cells : kDefaultLaneCells;
+    r.lds_limit = (opt && opt->lds_limit) ? opt->lds_limit : kDefaultLdsLimit;
+    r.lds_limit = std::min(r.lds_limit, db->lds_max - 1024);
+    r.grid_limit = opt ? opt->grid_limit : 0;
+    return r;
+}
+
+int64_t prof_bytes_for(int nbr, int rows, int elem)
+{
+    const int64_t cs = (int64_t)rows * elem + 16;
+    return (int64_t)(nbr + 1) * kCodes * cs;
+}
+
+// Per-lane cells of an item: the columns it sweeps (with pipeline fill for K > 1)
+// times the rows of all its passes.
+int64_t lane_work(int64_t n, int K, int nbr, int rows)
+{
+    const int64_t cols = K == 1 ? align_up(n, 16) : align_up(n + K - 1, 16);
+    const int64_t passes = nbr == 0 ? 0 : ceil_div(nbr, K);
+    return std::max<int64_t>(cols, 16) * passes * rows;
+}
+
+std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, const Resolved& r)
+{
+    auto p = std::make_shared<QPlan>();
+    const int64_t N = (int64_t)slen.size();
+    int kcap = 1;
+    while (kcap < nbr && kcap < r.kmax)
+        kcap <<= 1;
+    struct WItem { Item it; int64_t cost; };
+    std::vector<WItem> wis;
+    int64_t s = 0;
+    while (s < N) {
+        const int64_t n = slen[s];
+        int K = 1;
+        while (K < kcap && lane_work(n, K, nbr, r.rows) > r.target)
+            K <<= 1;
+        const int64_t per = (int64_t)(kWave / K) * r.spl;
+        const int64_t take = std::min<int64_t>(per, N - s);
+        Item it;
+        it.s0 = (int32_t)s;
+        it.ncols = (int32_t)align_up(n, 16);
+        it.q = 0;
+        int logK = 0;
+        while ((1 << logK) < K) ++logK;
+        it.meta = (int32_t)take | (logK << 16);
+        const int64_t lw = lane_work(n, K, nbr, r.rows);
+        wis.push_back({it, lw});
+        p->lane_cells += lw * kWave;
+        if (nbr > K)
+            p->slot_elems = std::max<int64_t>(p->slot_elems, (int64_t)it.ncols * (kWave / K));
+        s += take;
+    }
+    p->nitems = (int64_t)wis.size();
+    // group into workgroup items of `waves` consecutive wavefront items
+    struct WG { int64_t first, count, cost; };
+    std::vector<WG> wgs;
+    for (int64_t i = 0; i < (int64_t)wis.size(); i += r.waves) {
+        WG w{i, std::min<int64_t>(r.waves, (int64_t)wis.size() - i), 0};
+        for (int64_t k = 0; k < w.count; ++k)
+            w.cost = std::max(w.cost, wis[i + k].cost);
+        wgs.push_back(w);
+    }
+    std::stable_sort(wgs.begin(), wgs.end(), [](const WG& a, const WG& b) { return a.cost > b.cost; });
+    p->n_wg = (int64_t)wgs.size();
+    p->items.resize((size_t)p->n_wg * r.waves);
+    for (size_t w = 0; w < wgs.size(); ++w) {
+        for (int k = 0; k < r.waves; ++k) {
+            Item it{0, 0, 0, 0};
+            if (k < wgs[w].count)
+                it = wis[wgs[w].first + k].it;
+            p->items[w * r.waves + k] = it;
+        }
+        p->cost += wgs[w].cost;
+    }
+    p->slot_elems = align_up(p->slot_elems, 4);
+    return p;
+}
+
+std::shared_ptr<QPlan> get_plan(sw_db_s* db, int nbr, const Resolved& r)
+{
+    PlanKey key{r.rows, r.spl, r.waves, r.kmax, nbr, r.target};
+    std::lock_guard<std::mutex> lk(db->mu);
+    auto f = db->plans.find(key);
+    if (f != db->plans.end())
+        return f->second;
+    auto p = build_plan(db->slen, nbr, r);
+    db->plans[key] = p;
+    db->plan_order.push_back(key);
+    while (db->plan_order.size() > 512) {
+        db->plans.erase(db->plan_order.front());
+        db->plan_order.pop_front();
+    }
+    return p;
+}
+
+// Workspace layout of one search.
+struct Layout {
+    Resolved r;
+    int32_t nq = 0;
+    std::vector<QueryDesc> qd;
+    std::vector<std::shared_ptr<QPlan>> plans;
+    std::vector<int32_t> order;       // queue order of queries
+    int64_t n_wg = 0;
+    int64_t grid = 0, rgrid = 0;
+    int64_t slot_elems = 0, rslot_elems = 0;
+    int lds_bytes = 0;
+    int64_t cells = 0, lane_cells = 0, nitems = 0;
+    int max_entries = 0;
+    size_t off_counters = 0, off_qd = 0, off_qoff = 0, off_items = 0, off_prof = 0,
+           off_flags = 0, off_slots = 0, total = 0, blob = 0;
+    int64_t flag_cap = 0;
+};
+
+int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& r, Layout& L)
+{
+    L.r = r;
+    L.nq = nq;
+    L.qd.assign(nq, QueryDesc{});
+    L.plans.assign(nq, nullptr);
+    int64_t prof = 0;
+    int64_t slot_need = 0;
+    for (int32_t k = 0; k < nq; ++k) {
+        const int32_t m = q_lens[k];
+        const int nbr = (int)ceil_div(m, r.rows);
+        const int64_t pb = prof_bytes_for(nbr, r.rows, 2);   // sized for 16-bit entries
+        L.qd[k].prof_off = prof;
+        L.qd[k].m = m;
+        L.qd[k].nbr = nbr;
+        const int64_t pbe = prof_bytes_for(nbr, r.rows, r.elem);
+        L.qd[k].prof_bytes = (int32_t)pbe;
+        L.qd[k].lds = pbe <= r.lds_limit ? 1 : 0;
+        if (L.qd[k].lds)
+            L.lds_bytes = std::max<int>(L.lds_bytes, (int)pbe);
+        L.max_entries = std::max<int>(L.max_entries, (nbr + 1) * kCodes * r.rows);
+        prof += align_up(pb, 256);
+        L.plans[k] = get_plan(db, nbr, r);
+        slot_need = std::max(slot_need, L.plans[k]->slot_elems);
+        L.cells += (int64_t)m * db->total;
+        L.lane_cells += L.plans[k]->lane_cells;
+        L.nitems += L.plans[k]->nitems;
+    }
+    // queue: largest query first
+    L.order.resize(nq);
+    std::iota(L.order.begin(), L.order.end(), 0);
+    std::stable_sort(L.order.begin(), L.order.end(),
+                     [&](int a, int b) { return L.plans[a]->cost > L.plans[b]->cost; });
+    int64_t wg = 0;
+    for (int32_t k : L.order) {
+        L.qd[k].wg_begin = (int32_t)wg;
+        L.qd[k].wg_count = (int32_t)L.plans[k]->n_wg;
+        wg += L.plans[k]->n_wg;
+    }
+    L.n_wg = wg;
+    if (wg > INT32_MAX / 8)
+        return fail(SW_EINVAL, "batch too large for one launch");
+    // persistent grid: occupancy model (<= 16 waves per CU, LDS per CU).  Slots
+    // are sized for the register-limited maximum so that the workspace size does
+    // not depend on the profile entry width chosen from the matrix.
+    const int wg_cap = std::max(kMaxWavesPerCU / r.waves, 1);
+    int64_t slot_grid = std::min<int64_t>(wg, (int64_t)db->cu * wg_cap);
+    if (r.grid_limit > 0)
+        slot_grid = std::min<int64_t>(slot_grid, r.grid_limit);
+    int wg_per_cu = wg_cap;
+    if (L.lds_bytes > 0)
+        wg_per_cu = std::min(wg_per_cu, kLdsPerCU / (L.lds_bytes + 1024));
+    wg_per_cu = std::max(wg_per_cu, 1);
+    L.grid = std::min<int64_t>(slot_grid, (int64_t)db->cu * wg_per_cu);
+    L.slot_elems = align_up(std::max<int64_t>(slot_need, 4), 4);
+    if (r.i16) {
+        L.rgrid = std::max<int64_t>(1, (int64_t)db->cu * 2);
+        L.rslot_elems = align_up(std::max<int64_t>(align_up(db->max_len, 16), 4), 4);
+        L.flag_cap = (int64_t)nq * db->nseq;
+    }
+    // byte layout
+    size_t off = 0;
+    L.off_counters = off; off += 256;
+    L.off_qd = off; off += align_up(sizeof(QueryDesc) * nq, 16);
+    L.off_qoff = off; off += align_up(sizeof(int64_t) * nq, 16);
+    L.off_items = off;
+    int64_t nit = L.n_wg * r.waves;
+    off += align_up(sizeof(Item) * nit, 256);
+    L.blob = off - L.off_qd;
+    L.off_prof = off; off += align_up(prof, 256);
+    L.off_flags = off; off += align_up(sizeof(int2) * L.flag_cap, 256);
+    L.off_slots = off;
+    const int64_t main_slots = slot_grid * r.waves * L.slot_elems * (int64_t)sizeof(int2);
+    const int64_t res_slots = L.rgrid * r.waves * L.rslot_elems * (int64_t)sizeof(int2);
+    off += align_up(std::max(main_slots, res_slots), 256);
+    L.total = off;
+    return SW_OK;
+}
+
+int validate_query_set(sw_db_t db, int32_t nq, const int32_t* q_lens)
+{
+    if (!db) return fail(SW_EINVAL, "null database handle");
+    if (nq < 0) return fail(SW_EINVAL, "nq < 0");
+    if (nq > 0 && !q_lens) return fail(SW_EINVAL, "null q_lens");
+    for (int32_t k = 0; k < nq; ++k)
+        if (q_lens[k] < 0 || q_lens[k] > SW_MAX_QLEN)
+            return fail(SW_EINVAL, "query length out of range");
+    return SW_OK;
+}
+
+int matrix_elem(const int32_t* sm, int32_t go, std::string& why)
+{
+    int mn = 1 << 30, mx = -(1 << 30);
+    for (int i = 0; i < kAlpha * kAlpha; ++i) {
+        if (sm[i] < -128 || sm[i] > 127) {
+            why = "substitution matrix entry outside [-128, 127]";
+            return 0;
+        }
+        mn = std::min(mn, sm[i]);
+        mx = std::max(mx, sm[i]);
+    }
+    return (mx + go <= 127 && mn + go >= -128) ? 1 : 2;
+}
+
+void* acquire_staging(sw_db_s* db, size_t bytes, Staging** out)
+{
+    std::lock_guard<std::mutex> lk(db->mu);
+    for (auto& st : db->staging) {
+        if (st.pending && hipEventQuery(st.ev) == hipSuccess)
+            st.pending = false;
+        if (!st.pending && st.cap >= bytes) {
+            st.pending = true;
+            *out = &st;
+            return st.host;
+        }
+    }
+    Staging st;
+    st.cap = std::max<size_t>(bytes, 1 << 20);
+    if (hipHostMalloc(&st.host, st.cap, hipHostMallocDefault) != hipSuccess)
+        return nullptr;
+    if (hipEventCreateWithFlags(&st.ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(st.host);
+        return nullptr;
+    }
+    st.pending = true;
+    db->staging.push_back(st);
+    *out = &db->staging.back();
+    return st.host;
+}
+
+int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, const int32_t* q_lens,
+              int32_t nq, const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt,
+              void* ws, size_t ws_bytes, int32_t* scores, hipStream_t stream)
+{
+    int rc = validate_query_set(db, nq, q_lens);
+    if (rc) return rc;
+    if (nq > 0 && !q_offsets) return fail(SW_EINVAL, "null q_offsets");
+    int64_t sumq = 0;
+    for (int32_t k = 0; k < nq; ++k) {
+        if (q_offsets[k] < 0) return fail(SW_EINVAL, "negative query offset");
+        sumq += q_lens[k];
+    }
+    if (sumq > 0 && !queries) return fail(SW_EINVAL, "null queries");
+    if (!sm) return fail(SW_EINVAL, "null substitution matrix");
+    if (go < 0 || ge < 0 || go > SW_MAX_GAP || ge > SW_MAX_GAP)
+        return fail(SW_EINVAL, "gap penalties must be in [0, SW_MAX_GAP]");
+    std::string why;
+    if (!validate_options(opt, why)) return fail(SW_EINVAL, why);
+    const int elem = matrix_elem(sm, go, why);
+    if (!elem) return fail(SW_EINVAL, why);
+    if (nq == 0 || db->nseq == 0)
+        return SW_OK;
+    if (!scores) return fail(SW_EINVAL, "null scores_out");
+    if (!ws) return fail(SW_EINVAL, "null workspace");
+    if (((uintptr_t)ws & 255) != 0) return fail(SW_EINVAL, "workspace must be 256-byte aligned");
+
+    Layout L;
+    rc = make_layout(db, nq, q_lens, resolve(db, opt, elem), L);
+    if (rc) return rc;
+    if (ws_bytes < L.total)
+        return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    const Resolved& r = L.r;
+    uint8_t* w = static_cast<uint8_t*>(ws);
+
+    // plan blob: query descriptors, query offsets, items
+    Staging* st = nullptr;
+    uint8_t* h = static_cast<uint8_t*>(acquire_staging(db, L.blob, &st));
+    if (!h) return fail(SW_ENOMEM, "pinned staging allocation failed");
+    {
+        std::vector<QueryDesc> qd = L.qd;
+        for (int32_t k = 0; k < nq; ++k)
+            qd[k].prof_off = L.qd[k].prof_off;
+        std::memcpy(h, qd.data(), sizeof(QueryDesc) * nq);
+        std::memcpy(h + (L.off_qoff - L.off_qd), q_offsets, sizeof(int64_t) * nq);
+        Item* items = reinterpret_cast<Item*>(h + (L.off_items - L.off_qd));
+        int64_t pos = 0;
+        for (int32_t k : L.order) {
+            const QPlan& p = *L.plans[k];
+            for (const Item& it0 : p.items) {
+                Item it = it0;
+                it.q = k;
+                items[pos++] = it;
+            }
+        }
+    }
+    hipError_t e = hipMemcpyAsync(w + L.off_qd, h, L.blob, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(st->ev, stream);
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> lk(db->mu);
+        st->pending = false;
+        return fail(SW_EHIP, std::string("plan upload: ") + hipGetErrorString(e));
+    }
+
+    ProfileArgs pa{};
+    pa.queries = queries;
+    pa.q_off = reinterpret_cast<const int64_t*>(w + L.off_qoff);
+    pa.qd = reinterpret_cast<const QueryDesc*>(w + L.off_qd);
+    pa.prof = w + L.off_prof;
+    pa.counters = reinterpret_cast<int32_t*>(w + L.off_counters);
+    pa.nq = nq;
+    pa.go = go;
+    for (int i = 0; i < kAlpha * kAlpha; ++i)
+        pa.sm.v[i] = (int8_t)sm[i];
+    HIPCHK(launch_profile(pa, r.rows, r.elem, L.max_entries, stream));
+
+    SearchArgs a{};
+    a.res = db->d_res;
+    a.chunk_off = db->d_chunk_off;
+    a.perm = db->d_perm;
+    a.slen = db->d_slen;
+    a.nseq = db->nseq;
+    a.items = reinterpret_cast<const Item*>(w + L.off_items);
+    a.qd = pa.qd;
+    a.nq = nq;
+    a.n_wg = (int32_t)L.n_wg;
+    a.prof = pa.prof;
+    a.scores = scores;
+    a.out_stride = db->nseq;
+    a.counters = pa.counters;
+    a.bnd = reinterpret_cast<int2*>(w + L.off_slots);
+    a.slot_elems = L.slot_elems;
+    a.flags = reinterpret_cast<int2*>(w + L.off_flags);
+    a.flag_cap = (int32_t)std::min<int64_t>(L.flag_cap, INT32_MAX);
+    a.go = go;
+    a.ge = ge;
+    if (L.grid > 0)
+        HIPCHK(launch_search(r.v, a, (int)L.grid, r.waves, L.lds_bytes, stream));
+    if (r.i16 && L.grid > 0) {
+        SearchArgs b = a;
+        b.slot_elems = L.rslot_elems;
+        HIPCHK(launch_rescore(r.v, b, (int)L.rgrid, r.waves, stream));
+    }
+    return SW_OK;
+}
+
+void free_db(sw_db_s* db)
+{
+    if (!db) return;
+    (void)hipFree(db->d_res);
+    (void)hipFree(db->d_chunk_off);
+    (void)hipFree(db->d_perm);
+    (void)hipFree(db->d_slen);
+    for (auto& st : db->staging) {
+        if (st.ev) {
+            (void)hipEventSynchronize(st.ev);
+            (void)hipEventDestroy(st.ev);
+        }
+        if (st.host) (void)hipHostFree(st.host);
+    }
+    delete db;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sw_version(void) { return "swdb 0.1.0 (gfx950)"; }
+
+const char* sw_last_error(void) { return g_err.c_str(); }
+
+const char* sw_strerror(int code)
+{
+    switch (code) {
+    case SW_OK: return "ok";
+    case SW_EINVAL: return "invalid argument";
+    case SW_ENOMEM: return "out of memory or workspace too small";
+    case SW_EHIP: return "HIP runtime error";
+    case SW_EUNSUP: return "unsupported device (gfx950 required)";
+    case SW_EBADRES: return "database residue code >= 32";
+    }
+    return "unknown error";
+}
+
+int sw_db_prepare(const uint8_t* residues, const int64_t* offsets, const int32_t* lengths,
+                  int32_t nseq, hipStream_t stream, sw_db_t* out)
+{
+    if (!out) return fail(SW_EINVAL, "null output handle");
+    *out = nullptr;
+    if (nseq < 0) return fail(SW_EINVAL, "nseq < 0");
+    if (nseq > 0 && (!offsets || !lengths)) return fail(SW_EINVAL, "null offsets or lengths");
+    if (nseq > (INT32_MAX / 2)) return fail(SW_EINVAL, "nseq too large");
+
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SW_EUNSUP, std::string("device is ") + prop.gcnArchName);
+
+    std::vector<int32_t> len(nseq);
+    std::vector<int64_t> off(nseq);
+    if (nseq > 0) {
+        HIPCHK(hipMemcpyAsync(len.data(), lengths, sizeof(int32_t) * nseq, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipMemcpyAsync(off.data(), offsets, sizeof(int64_t) * nseq, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+    }
+    int64_t total = 0;
+    int32_t maxl = 0;
+    for (int32_t i = 0; i < nseq; ++i) {
+        if (len[i] < 0) return fail(SW_EINVAL, "negative subject length");
+        if (off[i] < 0) return fail(SW_EINVAL, "negative subject offset");
+        total += len[i];
+        maxl = std::max(maxl, len[i]);
+    }
+    if (total > 0 && !residues) return fail(SW_EINVAL, "null residues");
+
+    std::vector<int32_t> perm(nseq);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+    std::vector<int32_t> slen(nseq);
+    for (int32_t s = 0; s < nseq; ++s)
+        slen[s] = len[perm[s]];
+    const int32_t nchunks = (int32_t)ceil_div(nseq, 64);
+    std::vector<int64_t> bprefix(nchunks + 1, 0), coff(std::max(nchunks, 1), 0);
+    for (int32_t c = 0; c < nchunks; ++c) {
+        const int64_t cols = align_up(slen[(int64_t)c * 64], 16);
+        bprefix[c + 1] = bprefix[c] + cols / 16;
+        coff[c] = bprefix[c] * 1024;
+    }
+    const int64_t res_bytes = std::max<int64_t>(bprefix[nchunks] * 1024, 16);
+
+    auto* db = new sw_db_s();
+    db->device = dev;
+    db->cu = prop.multiProcessorCount;
+    db->lds_max = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+    db->nseq = nseq;
+    db->total = total;
+    db->nchunks = nchunks;
+    db->max_len = maxl;
+    db->res_bytes = res_bytes;
+    db->slen = slen;
+    int64_t* d_bprefix = nullptr;
+    int32_t* d_bad = nullptr;
+    auto cleanup = [&](int code, const std::string& msg) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(d_bprefix);
+        (void)hipFree(d_bad);
+        free_db(db);
+        return fail(code, msg);
+    };
+#define PCHK(x)                                                                                 \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess) return cleanup(SW_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+    PCHK(hipMalloc(&db->d_res, res_bytes));
+    PCHK(hipMalloc(&db->d_chunk_off, sizeof(int64_t) * std::max(nchunks, 1)));
+    PCHK(hipMalloc(&db->d_perm, sizeof(int32_t) * std::max(nseq, 1)));
+    PCHK(hipMalloc(&db->d_slen, sizeof(int32_t) * std::max(nseq, 1)));
+    PCHK(hipMalloc(&d_bprefix, sizeof(int64_t) * (nchunks + 1)));
+    PCHK(hipMalloc(&d_bad, sizeof(int32_t)));
+    db->dev_bytes = res_bytes + sizeof(int64_t) * std::max(nchunks, 1) + 8 * (int64_t)std::max(nseq, 1);
+    if (nseq > 0) {
+        PCHK(hipMemcpyAsync(db->d_chunk_off, coff.data(), sizeof(int64_t) * nchunks, hipMemcpyHostToDevice, stream));
+        PCHK(hipMemcpyAsync(db->d_perm, perm.data(), sizeof(int32_t) * nseq, hipMemcpyHostToDevice, stream));
+        PCHK(hipMemcpyAsync(db->d_slen, slen.data(), sizeof(int32_t) * nseq, hipMemcpyHostToDevice, stream));
+        PCHK(hipMemcpyAsync(d_bprefix, bprefix.data(), sizeof(int64_t) * (nchunks + 1), hipMemcpyHostToDevice, stream));
+        PCHK(hipMemsetAsync(d_bad, 0, sizeof(int32_t), stream));
+        PCHK(launch_interleave(residues, offsets, db->d_perm, db->d_slen, db->d_chunk_off, nseq,
+                               bprefix[nchunks] * 64, d_bprefix, nchunks, db->d_res, d_bad, stream));
+        int32_t bad = 0;
+        PCHK(hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        PCHK(hipStreamSynchronize(stream));
+        if (bad)
+            return cleanup(SW_EBADRES, "database residue code >= 32");
+    }
+    (void)hipFree(d_bprefix);
+    (void)hipFree(d_bad);
+#undef PCHK
+    *out = db;
+    return SW_OK;
+}
+
+int sw_db_release(sw_db_t db)
+{
+    if (!db) return fail(SW_EINVAL, "null database handle");
+    free_db(db);
+    return SW_OK;
+}
+
+int sw_db_info(sw_db_t db, int64_t* nseq, int64_t* residues, int64_t* device_bytes)
+{
+    if (!db) return fail(SW_EINVAL, "null database handle");
+    if (nseq) *nseq = db->nseq;
+    if (residues) *residues = db->total;
+    if (device_bytes) *device_bytes = db->dev_bytes;
+    return SW_OK;
+}
+
+size_t sw_workspace_bytes(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt)
+{
+    if (validate_query_set(db, nq, q_lens)) return 0;
+    std::string why;
+    if (!validate_options(opt, why)) { fail(SW_EINVAL, why); return 0; }
+    Layout L;
+    if (make_layout(db, nq, q_lens, resolve(db, opt, 2), L)) return 0;
+    return L.total;
+}
+
+int sw_plan_info(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt, sw_plan_stats* out)
+{
+    int rc = validate_query_set(db, nq, q_lens);
+    if (rc) return rc;
+    if (!out) return fail(SW_EINVAL, "null output");
+    std::string why;
+    if (!validate_options(opt, why)) return fail(SW_EINVAL, why);
+    Layout L;
+    rc = make_layout(db, nq, q_lens, resolve(db, opt, 2), L);
+    if (rc) return rc;
+    out->cells = L.cells;
+    out->lane_cells = L.lane_cells;
+    out->items = L.nitems;
+    out->wg_items = L.n_wg;
+    out->grid = L.grid;
+    out->slot_bytes = L.slot_elems * (int64_t)sizeof(int2);
+    out->workspace = (int64_t)L.total;
+    out->variant = (int32_t)L.r.v;
+    out->rows = L.r.rows;
+    return SW_OK;
+}
+
+int sw_db_search_ex(sw_db_t db, const uint8_t* query, int32_t qlen, const int32_t* sm,
+                    int32_t go, int32_t ge, const sw_options* opt, void* ws, size_t ws_bytes,
+                    int32_t* scores, hipStream_t stream)
+{
+    const int64_t off = 0;
+    return do_search(db, query, &off, &qlen, 1, sm, go, ge, opt, ws, ws_bytes, scores, stream);
+}
+
+int sw_db_search_batch(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets,
+                       const int32_t* q_lens, int32_t nq, const int32_t* sm, int32_t go, int32_t ge,
+                       const sw_options* opt, void* ws, size_t ws_bytes, int32_t* scores,
+                       hipStream_t stream)
+{
+    return do_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, stream);
+}
+
+int64_t sw_flagged_count(const void* ws, hipStream_t stream)
+{
+    if (!ws) return fail(SW_EINVAL, "null workspace");
+    int32_t c[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(c, ws, sizeof(c), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return c[1];
+}
+
+int sw_db_search(const uint8_t* query, int32_t qlen, const uint8_t* residues, const int64_t* offsets,
+                 const int32_t* lengths, int32_t nseq, const int32_t* sm, int32_t go, int32_t ge,
+                 int32_t* scores, hipStream_t stream)
+{
+    if (qlen < 0 || qlen > SW_MAX_QLEN) return fail(SW_EINVAL, "qlen out of range");
+    if (qlen > 0 && !query) return fail(SW_EINVAL, "null query");
+    if (!sm) return fail(SW_EINVAL, "null substitution matrix");
+    if (go < 0 || ge < 0 || go > SW_MAX_GAP || ge > SW_MAX_GAP)
+        return fail(SW_EINVAL, "gap penalties must be in [0, SW_MAX_GAP]");
+    if (nseq < 0) return fail(SW_EINVAL, "nseq < 0");
+    if (nseq > 0 && !scores) return fail(SW_EINVAL, "null scores_out");
+    std::string why;
+    if (!matrix_elem(sm, go, why)) return fail(SW_EINVAL, why);
+    if (nseq == 0) return SW_OK;
+    sw_db_t db = nullptr;
+    int rc = sw_db_prepare(residues, offsets, lengths, nseq, stream, &db);
+    if (rc) return rc;
+    const size_t need = sw_workspace_bytes(db, 1, &qlen, nullptr);
+    void* ws = nullptr;
+    if (need == 0 || hipMalloc(&ws, need) != hipSuccess) {
+        sw_db_release(db);
+        return fail(SW_ENOMEM, "workspace allocation failed");
+    }
+    rc = sw_db_search_ex(db, query, qlen, sm, go, ge, nullptr, ws, need, scores, stream);
+    const hipError_t e = hipStreamSynchronize(stream);
+    (void)hipFree(ws);
+    sw_db_release(db);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(SW_EHIP, std::string("search: ") + hipGetErrorString(e));
+    return SW_OK;
+}
+
+}  // extern "C"

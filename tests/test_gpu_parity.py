@@ -1,0 +1,185 @@
+"""Bit-exact parity of the HIP path against the CPU oracle (GPU required).
+
+Scores are integers, so the bar is equality.  Inputs are seeded and synthetic;
+shapes cover several work items, ragged tails of every tiling (16-column
+blocks, 64-subject chunks, R-row blocks, K-lane passes) and the degenerate
+cases of the recurrence.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpuhelp import (announce, gpu_batch, gpu_db, gpu_scores, have_gpu, mismatch_report,
+                     oracle_scores, overflow_matrix, overflow_sequence)
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="needs a GPU")]
+
+MODES = ["i32", "i16", "auto"]
+
+
+def _check(db, q, sm, go, ge, modes=MODES, ids=None, **kw):
+    exp = oracle_scores(db, q, sm, go, ge, ids=ids)
+    gdb = gpu_db(db)
+    try:
+        for mode in modes:
+            announce(f"mode={mode} m={len(q)} nseq={db.nseq} go={go} ge={ge} {kw}")
+            got = gpu_scores(gdb, q, sm, go, ge, mode=mode, **kw)
+            if ids is not None:
+                got = got[np.asarray(ids)]
+            assert np.array_equal(got, exp), f"{mode}: " + mismatch_report(got, exp, ids)
+    finally:
+        gdb.release()
+
+
+def test_config0_all_modes():
+    w = synth.config(0)
+    _check(w.db, w.queries[0], w.matrix, w.gap_open, w.gap_extend)
+
+
+def test_one_shot_entry_point():
+    import torch
+    import paper_2412_08308_amd as swdb
+    w = synth.config(0, scale=0.1)
+    exp = oracle_scores(w.db, w.queries[0], w.matrix, 10, 2)
+    announce("sw_db_search one-shot")
+    res = torch.from_numpy(w.db.residues).cuda()
+    off = torch.from_numpy(w.db.offsets).cuda()
+    ln = torch.from_numpy(w.db.lengths).cuda()
+    q = torch.from_numpy(w.queries[0]).cuda()
+    got = swdb.search(q, res, off, ln, w.matrix, 10, 2).cpu().numpy()
+    assert np.array_equal(got, exp), mismatch_report(got, exp)
+
+
+@pytest.mark.parametrize("m", [0, 1, 15, 16, 17, 31, 32, 33, 47, 64, 65, 100, 257])
+def test_query_lengths(m):
+    rng = np.random.default_rng(1000 + m)
+    lens = [0, 1, 2, 15, 16, 17, 31, 32, 33, 63, 64, 65, 127, 128, 129, 300, 511, 700]
+    lens = lens * 5 + rng.integers(0, 400, size=110).tolist()
+    q, db = synth.random_case(rng, m, lens)
+    _check(db, q, synth.blosum_style_matrix(), 10, 2)
+
+
+@pytest.mark.parametrize("nseq", [1, 2, 63, 64, 65, 127, 128, 129, 257])
+def test_chunk_edges(nseq):
+    rng = np.random.default_rng(2000 + nseq)
+    q, db = synth.random_case(rng, 90, rng.integers(1, 200, size=nseq).tolist())
+    _check(db, q, synth.blosum_style_matrix(), 10, 2)
+
+
+def test_asymmetric_random_matrix():
+    rng = np.random.default_rng(7)
+    sm = synth.random_matrix(rng, -5, 5)
+    q, db = synth.random_case(rng, 150, rng.integers(0, 300, size=400).tolist(), alpha=32)
+    _check(db, q, sm, 7, 3)
+
+
+@pytest.mark.parametrize("go,ge", [(3, 5), (4, 4), (10, 0), (0, 0), (0, 3), (32000, 32000), (200, 50)])
+def test_gap_penalty_regimes(go, ge):
+    rng = np.random.default_rng(go * 131 + ge)
+    q, db = synth.random_case(rng, 120, rng.integers(0, 260, size=300).tolist())
+    _check(db, q, synth.blosum_style_matrix(), go, ge)
+
+
+def test_extreme_matrix_values():
+    rng = np.random.default_rng(8)
+    sm = synth.random_matrix(rng, -128, 127)
+    q, db = synth.random_case(rng, 70, rng.integers(0, 150, size=200).tolist(), alpha=32)
+    _check(db, q, sm, 20, 3)
+
+
+def test_long_subjects_and_lane_groups():
+    # a few long subjects force multi-lane groups (K up to 64) and many passes
+    rng = np.random.default_rng(9)
+    lens = [35000, 12000, 5000, 4097, 2049, 1000] + rng.integers(10, 400, size=300).tolist()
+    q, db = synth.random_case(rng, 567, lens)
+    _check(db, q, synth.blosum_style_matrix(), 10, 2)
+
+
+@pytest.mark.parametrize("kw", [dict(max_lanes=1), dict(max_lanes=2), dict(max_lanes=8),
+                                dict(lane_cells=2000), dict(lane_cells=1 << 24),
+                                dict(waves=1), dict(waves=3), dict(lds_limit=1024),
+                                dict(grid_limit=1)])
+def test_plan_knobs_do_not_change_scores(kw):
+    rng = np.random.default_rng(10)
+    lens = [3000, 1500, 800] + rng.integers(10, 600, size=500).tolist()
+    q, db = synth.random_case(rng, 333, lens)
+    _check(db, q, synth.blosum_style_matrix(), 10, 2, **kw)
+
+
+def test_long_query_global_profile():
+    # profile larger than the LDS budget: read from global memory
+    rng = np.random.default_rng(11)
+    q, db = synth.random_case(rng, 3000, rng.integers(10, 500, size=200).tolist())
+    _check(db, q, synth.blosum_style_matrix(), 10, 2)
+
+
+def test_int16_overflow_boundary():
+    sm = overflow_matrix()
+    seqs, targets = [], [32766, 32767, 32768, 40000, 32000, 1000]
+    for t in targets:
+        seqs.append(overflow_sequence(t))
+    rng = np.random.default_rng(12)
+    # the query holds every constructed subject as a substring (a run of code 0
+    # followed by a run of code 1), so each subject scores its diagonal sum
+    q = np.concatenate([np.zeros(400, np.uint8), np.ones(300, np.uint8),
+                        rng.integers(2, 20, size=50).astype(np.uint8)])
+    subj = seqs + [rng.integers(0, 20, size=int(n)).astype(np.uint8)
+                   for n in rng.integers(10, 300, size=150)]
+    db = synth.Database.from_list(subj)
+    exp = oracle_scores(db, q, sm, 10, 2)
+    assert list(exp[:6]) == targets
+    _check(db, q, sm, 10, 2)
+    # the 16-bit pass flags exactly the subjects whose true score is >= 32767
+    import paper_2412_08308_amd as swdb
+    import torch
+    gdb = gpu_db(db)
+    try:
+        opt = swdb.options(mode="i16")
+        ws = gdb.alloc_workspace([len(q)], opt)
+        announce("int16 flag count")
+        gdb.search(torch.from_numpy(q).cuda(), sm, 10, 2, opt=opt, workspace=ws)
+        torch.cuda.synchronize()
+        assert gdb.flagged_count(ws) == int(np.sum(exp >= 32767))
+    finally:
+        gdb.release()
+
+
+def test_batch_rows_equal_single_queries():
+    rng = np.random.default_rng(13)
+    sm = synth.blosum_style_matrix()
+    _, db = synth.random_case(rng, 1, rng.integers(0, 700, size=700).tolist())
+    qs = [synth.residues(rng, int(m)) for m in [144, 0, 17, 600, 1, 2500, 333]]
+    gdb = gpu_db(db)
+    try:
+        for mode in MODES:
+            announce(f"batch mode={mode}")
+            got = gpu_batch(gdb, qs, sm, 10, 2, mode=mode)
+            for k, q in enumerate(qs):
+                exp = oracle_scores(db, q, sm, 10, 2)
+                assert np.array_equal(got[k], exp), f"{mode} query {k}: " + mismatch_report(got[k], exp)
+            # order of queries in the batch does not matter
+            perm = [6, 3, 0, 5, 1, 4, 2]
+            got2 = gpu_batch(gdb, [qs[i] for i in perm], sm, 10, 2, mode=mode)
+            assert np.array_equal(got2, got[perm])
+    finally:
+        gdb.release()
+
+
+def test_bad_residue_rejected():
+    import paper_2412_08308_amd as swdb
+    db = synth.Database.from_list([np.array([1, 2, 40, 3], dtype=np.uint8)])
+    announce("bad residue code")
+    with pytest.raises(swdb.SwdbError) as ei:
+        gpu_db(db)
+    assert ei.value.code == -5
+
+
+def test_config1_sampled():
+    """Full 200,000-subject database in the benchmark's launch configuration;
+    every subject of three length strata checked by the oracle one by one."""
+    w = synth.config(1)
+    order = np.argsort(-w.db.lengths, kind="stable")
+    rng = np.random.default_rng(14)
+    ids = np.unique(np.concatenate([order[:200], order[-100:],
+                                    rng.choice(w.db.nseq, size=700, replace=False)]))
+    _check(w.db, w.queries[0], w.matrix, w.gap_open, w.gap_extend, modes=["i32", "auto"], ids=ids)
