@@ -68,6 +68,12 @@ typedef struct sw_options {
     int32_t lds_limit;     /* largest query profile staged in LDS, bytes           */
     int32_t grid_limit;    /* cap on persistent workgroups (0 = fill the device)   */
     int32_t reserved[10];
+    /* Optional timing events (created by the caller, may be NULL): recorded on
+       the search stream immediately before the search kernel, immediately
+       after it, and after the int32 rescore (16-bit modes).                   */
+    hipEvent_t ev_search_begin;
+    hipEvent_t ev_search_end;
+    hipEvent_t ev_rescore_end;
 } sw_options;
 
 /* Plan summary (for measurement; all counts are per search call). */

@@ -41,7 +41,9 @@ class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("lane_cells", ctypes.c_int32), ("max_lanes", ctypes.c_int32),
                 ("lds_limit", ctypes.c_int32), ("grid_limit", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 10)]
+                ("reserved", ctypes.c_int32 * 10),
+                ("ev_search_begin", ctypes.c_void_p), ("ev_search_end", ctypes.c_void_p),
+                ("ev_rescore_end", ctypes.c_void_p)]
 
 
 class PlanStats(ctypes.Structure):

@@ -487,13 +487,19 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
     a.flag_cap = (int32_t)std::min<int64_t>(L.flag_cap, INT32_MAX);
     a.go = go;
     a.ge = ge;
+    hipEvent_t e0 = opt ? opt->ev_search_begin : nullptr;
+    hipEvent_t e1 = opt ? opt->ev_search_end : nullptr;
+    hipEvent_t e2 = opt ? opt->ev_rescore_end : nullptr;
+    if (e0) HIPCHK(hipEventRecord(e0, stream));
     if (L.grid > 0)
         HIPCHK(launch_search(r.v, a, (int)L.grid, r.waves, L.lds_bytes, stream));
+    if (e1) HIPCHK(hipEventRecord(e1, stream));
     if (r.i16 && L.grid > 0) {
         SearchArgs b = a;
         b.slot_elems = L.rslot_elems;
         HIPCHK(launch_rescore(r.v, b, (int)L.rgrid, r.waves, stream));
     }
+    if (e2) HIPCHK(hipEventRecord(e2, stream));
     return SW_OK;
 }
 
