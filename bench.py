@@ -68,13 +68,16 @@ def isa_counts():
         return json.load(fh)
 
 
+KNOBS = {}
+
+
 def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False):
     """Run warmup + steps searches; wall time per step and the search kernel's
     own time (HIP events recorded by the library around its launch)."""
     import torch
     import paper_2412_08308_amd as swdb
     lens = [int(q.numel()) for q in queries]
-    base = swdb.options(mode=mode)
+    base = swdb.options(mode=mode, **KNOBS)
     ws = gdb.alloc_workspace(lens, base)
     out = torch.empty((len(queries), gdb.nseq) if batch else (gdb.nseq,), dtype=torch.int32, device="cuda")
     if batch:
@@ -95,7 +98,7 @@ def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False)
     torch.cuda.synchronize()
     evs = []
     for _ in range(steps):
-        o = swdb.options(mode=mode)
+        o = swdb.options(mode=mode, **KNOBS)
         e = (ev.create(), ev.create(), ev.create())
         o.ev_search_begin, o.ev_search_end, o.ev_rescore_end = e[0].value, e[1].value, e[2].value
         evs.append((o, e))
@@ -162,7 +165,14 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-i32", action="store_true")
+    ap.add_argument("--lane-cells", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--lds-limit", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of MIB MiB (traffic calibration)")
     args = ap.parse_args(argv)
+    KNOBS.update(lane_cells=args.lane_cells, waves=args.waves, lds_limit=args.lds_limit)
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
               "(the search shards by database range across GPUs with one score gather, "
@@ -184,7 +194,13 @@ def main(argv=None):
     isa = isa_counts()
 
     main_run = timed_search(gdb, [q], w.matrix, w.gap_open, w.gap_extend, args.mode, args.steps, args.warmup, ev)
-    i32_run = timed_search(gdb, [q], w.matrix, w.gap_open, w.gap_extend, "i32", args.steps, args.warmup, ev)
+    i32_run = main_run if args.no_i32 else timed_search(gdb, [q], w.matrix, w.gap_open, w.gap_extend, "i32",
+                                                         args.steps, args.warmup, ev)
+    if args.copy_probe:
+        src = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     parity = None
     if not args.no_check:
@@ -198,12 +214,15 @@ def main(argv=None):
         parity = {"sampled_subjects": int(len(ids)),
                   "mismatches": int(np.sum(g1 != exp) + np.sum(g2 != exp))}
 
+    # the int32 kernels take 8-bit profile entries when every score + Go fits
+    p8 = int(w.matrix.max()) + w.gap_open <= 127 and int(w.matrix.min()) + w.gap_open >= -128
+    i32_isa = "i32_p8_lds_k1" if p8 else "i32_p16_lds_k1"
     variant = main_run["plan"]["variant"]
-    key = {0: "i32_p8_lds_k1", 1: "i32_p16_lds_k1", 2: "i16_lds_k1"}[variant]
+    key = "i16_lds_k1" if variant == 2 else i32_isa
     ops = isa[key]["valu_per_cell"]
     kernel_s = main_run["kernel_ms"] / 1e3
     achieved = cells * ops / kernel_s / 1e12
-    i32_key = {0: "i32_p8_lds_k1", 1: "i32_p16_lds_k1"}[i32_run["plan"]["variant"]]
+    i32_key = "i16_lds_k1" if i32_run["plan"]["variant"] == 2 else i32_isa
     gcups = cells / (main_run["wall_ms"] / 1e3) / 1e9
 
     batched = None
@@ -239,7 +258,7 @@ def main(argv=None):
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 3),
                      "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": None,
                      "kernel": "k_search<16,2,true> (packed 16-bit lanes)" if variant == 2
-                     else "k_search<32,1,false> (int32 lanes)",
+                     else ("k_search<32,1,false> (int32 lanes)" if p8 else "k_search<32,2,false> (int32 lanes)"),
                      "isa_valu_per_cell": ops, "search_kernel_ms": round(main_run["kernel_ms"], 3),
                      "isa_peak_gcups": round(PEAK_VALU_TOPS * 1e3 / ops, 1),
                      "paper_model_peak_gcups": round(PEAK_VALU_TOPS * 1e3 / PAPER_OPS_PER_CELL, 1),
@@ -255,6 +274,7 @@ def main(argv=None):
         "latency": None,
         "parity": parity,
         "plan": {k: main_run["plan"][k] for k in ("lane_cells", "items", "wg_items", "grid", "rows")},
+        "knobs": {k: v for k, v in KNOBS.items() if v},
         "cpu_baseline": cpu,
     }
     gdb.release()

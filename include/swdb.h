@@ -62,7 +62,7 @@ typedef struct sw_db_s* sw_db_t;
 /* Tuning knobs.  Zero-initialise and set what you need; 0 = library default. */
 typedef struct sw_options {
     int32_t mode;          /* SW_MODE_*                                            */
-    int32_t waves;         /* wavefronts per workgroup (1..4)                      */
+    int32_t waves;         /* wavefronts per workgroup (1..8)                      */
     int32_t lane_cells;    /* target cells per lane per work item (load balance)  */
     int32_t max_lanes;     /* largest lane group per subject (1..64, power of 2)   */
     int32_t lds_limit;     /* largest query profile staged in LDS, bytes           */
@@ -123,6 +123,16 @@ int sw_db_prepare(const uint8_t* db_residues, const int64_t* db_offsets,
                   const int32_t* db_lengths, int32_t nseq, hipStream_t stream,
                   sw_db_t* out);
 
+/*
+ * Host-only handle for planning (no device memory, no HIP call): subject
+ * lengths in HOST memory, and the device's compute-unit count and per-workgroup
+ * LDS bytes (0 = MI355X values: 256 and 160 KiB).  Valid for
+ * sw_workspace_bytes, sw_plan_info, sw_plan_items and sw_db_release; searches
+ * with it return SW_EINVAL.
+ */
+int sw_db_describe(const int32_t* lengths_host, int32_t nseq, int32_t cu_count, int32_t lds_bytes,
+                   sw_db_t* out);
+
 /* Frees the handle's device memory.  No search may still be in flight. */
 int sw_db_release(sw_db_t db);
 
@@ -138,6 +148,18 @@ size_t sw_workspace_bytes(sw_db_t db, int32_t nq, const int32_t* q_lens, const s
 /* Plan summary for the same arguments (host only; no HIP call). */
 int sw_plan_info(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt,
                  sw_plan_stats* out);
+
+/*
+ * The work queue a search would run, in queue order: for each wavefront item
+ * four int32 (first sorted subject, columns swept, query index, subjects |
+ * lanes-per-subject << 16), `waves` items per workgroup item.  Writes at most
+ * `cap` items to `out` (HOST) and returns the total count, or a negative code.
+ */
+int64_t sw_plan_items(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt,
+                      int32_t* out, int64_t cap);
+
+/* Sorted subject lengths (descending) of the handle, into HOST out[nseq]. */
+int sw_db_sorted_lengths(sw_db_t db, int32_t* out);
 
 /*
  * One query against a resident database.

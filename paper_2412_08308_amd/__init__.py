@@ -86,6 +86,12 @@ def lib():
     L.sw_db_search_batch.restype = ctypes.c_int
     L.sw_db_search_batch.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, ctypes.POINTER(Options),
                                      vp, sz, vp, vp]
+    L.sw_db_describe.restype = ctypes.c_int
+    L.sw_db_describe.argtypes = [vp, i32, i32, i32, ctypes.POINTER(vp)]
+    L.sw_plan_items.restype = ctypes.c_int64
+    L.sw_plan_items.argtypes = [vp, i32, vp, ctypes.POINTER(Options), vp, i64]
+    L.sw_db_sorted_lengths.restype = ctypes.c_int
+    L.sw_db_sorted_lengths.argtypes = [vp, vp]
     L.sw_flagged_count.restype = ctypes.c_int64
     L.sw_flagged_count.argtypes = [vp, vp]
     L.sw_strerror.restype = ctypes.c_char_p
@@ -162,6 +168,40 @@ def search(query, residues, offsets, lengths, matrix, gap_open: int, gap_extend:
 
 class Database:
     """A resident, length-sorted, lane-interleaved database (``sw_db_prepare``)."""
+
+    @classmethod
+    def describe(cls, lengths, cu_count: int = 0, lds_bytes: int = 0) -> "Database":
+        """Planning-only handle from host lengths (``sw_db_describe``): no GPU needed."""
+        self = cls.__new__(cls)
+        ln = np.ascontiguousarray(np.asarray(lengths, dtype=np.int32))
+        h = ctypes.c_void_p()
+        _check(lib().sw_db_describe(ln.ctypes.data if len(ln) else None, len(ln), int(cu_count),
+                                    int(lds_bytes), ctypes.byref(h)), "sw_db_describe")
+        self._h = h
+        self.nseq = len(ln)
+        self.device = None
+        self.total = int(ln.sum())
+        self.device_bytes = 0
+        return self
+
+    def plan_items(self, qlens: Sequence[int], opt: Optional[Options] = None) -> np.ndarray:
+        """``sw_plan_items``: the work queue as an int32 array [n, 4]."""
+        ql = np.ascontiguousarray(np.asarray(qlens, dtype=np.int32))
+        o = ctypes.byref(opt) if opt is not None else None
+        n = lib().sw_plan_items(self._handle(), len(ql), ql.ctypes.data if len(ql) else None, o, None, 0)
+        if n < 0:
+            _check(int(n), "sw_plan_items")
+        out = np.zeros((max(n, 1), 4), dtype=np.int32)
+        n2 = lib().sw_plan_items(self._handle(), len(ql), ql.ctypes.data if len(ql) else None, o,
+                                 out.ctypes.data, n)
+        if n2 < 0:
+            _check(int(n2), "sw_plan_items")
+        return out[:n]
+
+    def sorted_lengths(self) -> np.ndarray:
+        out = np.zeros(max(self.nseq, 1), dtype=np.int32)
+        _check(lib().sw_db_sorted_lengths(self._handle(), out.ctypes.data), "sw_db_sorted_lengths")
+        return out[:self.nseq]
 
     def __init__(self, residues, offsets, lengths, stream=None):
         import torch

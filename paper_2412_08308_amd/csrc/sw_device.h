@@ -133,12 +133,12 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
     constexpr int NV = R * ES / 16;
 
     const int nsub = it.meta & 0xffff;
-    const int logK = MULTI ? (it.meta >> 16) : 0;
-    const int K = 1 << logK;
-    const int nsubw = kWave >> logK;
-    const int g = lane & (K - 1);
-    const int sub = lane >> logK;
-    const bool valid = sub < nsub;
+    const int K = MULTI ? (it.meta >> 16) : 1;          // lanes per subject, 1..64
+    const int nsubw = MULTI ? kWave / K : kWave;        // lane groups in the wavefront
+    const int sub = MULTI ? lane / K : lane;
+    const int g = lane - sub * K;
+    const bool inb = sub < nsubw;                       // lane belongs to a group
+    const bool valid = sub < nsub;                      // nsub <= nsubw
     const int s = it.s0 + (valid ? sub : 0);
     const bool head = g == 0;
     const bool tail = g == K - 1;
@@ -147,7 +147,7 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
     const int own = (a.slen[s] + 15) & ~15;   // columns stored for this lane's subject
     const int ncols = it.ncols;
     const int nbr = qd.nbr;
-    const int P = (nbr + K - 1) >> logK;
+    const int P = (nbr + K - 1) / K;
     const int nsteps = MULTI ? ((ncols + K - 1 + 15) & ~15) : ncols;
     const int go = a.go, ge = a.ge;
     const uint8_t* __restrict__ gprof = a.prof + qd.prof_off;
@@ -172,7 +172,7 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
                 const uint32_t w = rv.x;                      // columns col0..col0+3
                 rv = make_uint4(rv.y, rv.z, rv.w, 0u);
                 int ringY[4], ringF[4];
-                if (rd && col0 < ncols) {
+                if (rd && col0 < ncols && inb) {
                     const int4* p4 = reinterpret_cast<const int4*>(slot + slot_index(col0, nsubw, sub));
                     const int4 v0 = p4[0], v1 = p4[1];
                     ringY[0] = v0.x; ringF[0] = v0.y; ringY[1] = v0.z; ringF[1] = v0.w;
@@ -224,7 +224,7 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
                     wF[u] = fbot;
                     if constexpr (MULTI) {
                         const int j = col0 + u - (K - 1);
-                        if (wr && tail && j >= 0 && j < ncols)
+                        if (wr && tail && inb && j >= 0 && j < ncols)
                             slot[slot_index(j, nsubw, sub)] = make_int2(ybot, fbot);
                     }
                 }
@@ -243,8 +243,9 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     if constexpr (MULTI) {
-        for (int off = 1; off < K; off <<= 1)
-            S = max(S, __shfl_xor(S, off));
+        const int hl = min(sub * K, kWave - 1);
+        for (int k = 1; k < K; ++k)
+            S = max(S, __shfl(S, min(hl + k, kWave - 1)));
     }
     if (head && valid)
         a.scores[(int64_t)it.q * a.out_stride + a.perm[s]] = S;
@@ -261,13 +262,13 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
     constexpr int NV = R * 2 / 16;
 
     const int nsub = it.meta & 0xffff;
-    const int logK = MULTI ? (it.meta >> 16) : 0;
-    const int K = 1 << logK;
-    const int nsubw = kWave >> logK;
-    const int g = lane & (K - 1);
-    const int sub = lane >> logK;
-    const bool validA = sub < nsub;
-    const bool validB = sub + nsubw < nsub;
+    const int K = MULTI ? (it.meta >> 16) : 1;
+    const int nsubw = MULTI ? kWave / K : kWave;
+    const int sub = MULTI ? lane / K : lane;
+    const int g = lane - sub * K;
+    const bool inb = sub < nsubw;
+    const bool validA = inb && sub < nsub;
+    const bool validB = inb && sub + nsubw < nsub;
     const int sA = it.s0 + (validA ? sub : 0);
     const int sB = it.s0 + (validB ? sub + nsubw : 0);
     const bool head = g == 0;
@@ -279,7 +280,7 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
     const int ownB = validB ? (a.slen[sB] + 15) & ~15 : 0;
     const int ncols = it.ncols;
     const int nbr = qd.nbr;
-    const int P = (nbr + K - 1) >> logK;
+    const int P = (nbr + K - 1) / K;
     const int nsteps = MULTI ? ((ncols + K - 1 + 15) & ~15) : ncols;
     const uint32_t go2 = (uint32_t)(a.go & 0xffff) * 0x10001u;
     const uint32_t ge2 = (uint32_t)(a.ge & 0xffff) * 0x10001u;
@@ -312,7 +313,7 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
                 rvA = make_uint4(rvA.y, rvA.z, rvA.w, 0u);
                 rvB = make_uint4(rvB.y, rvB.z, rvB.w, 0u);
                 uint32_t ringY[4], ringF[4];
-                if (rd && col0 < ncols) {
+                if (rd && col0 < ncols && inb) {
                     const uint4* p4 = reinterpret_cast<const uint4*>(slot + slot_index(col0, nsubw, sub));
                     const uint4 v0 = p4[0], v1 = p4[1];
                     ringY[0] = v0.x; ringF[0] = v0.y; ringY[1] = v0.z; ringF[1] = v0.w;
@@ -366,7 +367,7 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
                     wF[u] = fbot;
                     if constexpr (MULTI) {
                         const int j = col0 + u - (K - 1);
-                        if (wr && tail && j >= 0 && j < ncols)
+                        if (wr && tail && inb && j >= 0 && j < ncols)
                             slot[slot_index(j, nsubw, sub)] = make_int2((int)ybot, (int)fbot);
                     }
                 }
@@ -386,8 +387,11 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
     }
     uint32_t Su = asu(S);
     if constexpr (MULTI) {
-        for (int off = 1; off < K; off <<= 1)
-            Su = asu(__builtin_elementwise_max(as2(Su), as2((uint32_t)__shfl_xor((int)Su, off))));
+        const int hl = min(sub * K, kWave - 1);
+        uint32_t acc = Su;
+        for (int k = 1; k < K; ++k)
+            acc = asu(__builtin_elementwise_max(as2(acc), as2((uint32_t)__shfl((int)Su, min(hl + k, kWave - 1)))));
+        Su = acc;
     }
     if (head) {
         const int lo = (int)(int16_t)(Su & 0xffff);
@@ -429,7 +433,7 @@ __device__ __forceinline__ void stage_profile(const SearchArgs& a, const QueryDe
 // wavefront items of one workgroup item belong to one query, whose profile is
 // staged in LDS when the query changes.
 template <int R, int ES, bool I16>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_search(SearchArgs a)
 {
     __shared__ int s_wi;
@@ -497,7 +501,7 @@ k_rescore(SearchArgs a)
         it.s0 = e.y;
         it.q = e.x;
         it.ncols = (a.slen[e.y] + 15) & ~15;
-        it.meta = 1 | (6 << 16);
+        it.meta = 1 | (64 << 16);
         const QueryDesc qd = a.qd[it.q];
         item_i32<R, ES, false, true>(a, it, qd, slot, lane);
     }

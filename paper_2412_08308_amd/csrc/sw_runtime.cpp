@@ -51,6 +51,7 @@ constexpr int kDefaultWaves = 4;
 constexpr int64_t kDefaultLaneCells = 96 * 1024;
 constexpr int kDefaultLdsLimit = 64 * 1024;
 constexpr int kLdsPerCU = 160 * 1024;
+constexpr int kRescoreWaves = 4;      // workgroup size of the rescore kernel
 constexpr int kMaxWavesPerCU = 16;      // 4 per SIMD: kernels are built for <= 128 VGPRs
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -93,6 +94,7 @@ struct Resolved {
 }  // namespace
 
 struct sw_db_s {
+    bool host_only = false;       // planning handle: no device memory
     int device = 0;
     int cu = 0;
     int lds_max = 64 * 1024;      // dynamic LDS a workgroup may use on this device
@@ -120,7 +122,7 @@ bool validate_options(const sw_options* opt, std::string& why)
     if (!opt)
         return true;
     if (opt->mode < SW_MODE_AUTO || opt->mode > SW_MODE_I16) { why = "options.mode"; return false; }
-    if (opt->waves < 0 || opt->waves > 4) { why = "options.waves must be 0..4"; return false; }
+    if (opt->waves < 0 || opt->waves > 8) { why = "options.waves must be 0..8"; return false; }
     if (opt->lane_cells < 0) { why = "options.lane_cells"; return false; }
     if (opt->max_lanes < 0 || opt->max_lanes > 64 || (opt->max_lanes & (opt->max_lanes - 1))) {
         why = "options.max_lanes must be 0 or a power of two <= 64";
@@ -169,30 +171,62 @@ int64_t lane_work(int64_t n, int K, int nbr, int rows)
     return std::max<int64_t>(cols, 16) * passes * rows;
 }
 
+// Lane cells the wavefront sweeps per subject with lane groups of K: all 64
+// lanes (leftover lanes of 64 mod K idle) over the item's work, divided by the
+// subjects it carries.  Pipelined groups cost a few extra instructions per
+// column (DPP shifts, head selects), weighed in as 4%.
+double subject_cost(int64_t n, int K, int nbr, const Resolved& r)
+{
+    const double per = (double)(kWave / K) * r.spl;
+    return kWave * (double)lane_work(n, K, nbr, r.rows) / per * (K > 1 ? 1.04 : 1.0);
+}
+
+// Lane group size for a subject of length n: the cheapest (in swept cells per
+// subject) K whose per-lane work fits the target; if none fits, the K with the
+// least per-lane work.  K > nbr would only add idle row blocks.
+int choose_k(int64_t n, int nbr, const Resolved& r)
+{
+    const int kmax = std::max(1, std::min(r.kmax, nbr));
+    int best = -1, shortest = 1;
+    double best_cost = 0;
+    int64_t best_lw = lane_work(n, 1, nbr, r.rows);
+    for (int K = 1; K <= kmax; ++K) {
+        const int64_t lw = lane_work(n, K, nbr, r.rows);
+        const double c = subject_cost(n, K, nbr, r);
+        if (lw <= r.target && (best < 0 || c < best_cost)) {
+            best = K;
+            best_cost = c;
+        }
+        if (lw < best_lw) {
+            best_lw = lw;
+            shortest = K;
+        }
+    }
+    return best > 0 ? best : shortest;
+}
+
 std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, const Resolved& r)
 {
     auto p = std::make_shared<QPlan>();
     const int64_t N = (int64_t)slen.size();
-    int kcap = 1;
-    while (kcap < nbr && kcap < r.kmax)
-        kcap <<= 1;
     struct WItem { Item it; int64_t cost; };
     std::vector<WItem> wis;
     int64_t s = 0;
+    int64_t last_n = -1;
+    int K = 1;
     while (s < N) {
         const int64_t n = slen[s];
-        int K = 1;
-        while (K < kcap && lane_work(n, K, nbr, r.rows) > r.target)
-            K <<= 1;
+        if (n != last_n) {
+            K = choose_k(n, nbr, r);
+            last_n = n;
+        }
         const int64_t per = (int64_t)(kWave / K) * r.spl;
         const int64_t take = std::min<int64_t>(per, N - s);
         Item it;
         it.s0 = (int32_t)s;
         it.ncols = (int32_t)align_up(n, 16);
         it.q = 0;
-        int logK = 0;
-        while ((1 << logK) < K) ++logK;
-        it.meta = (int32_t)take | (logK << 16);
+        it.meta = (int32_t)take | (K << 16);
         const int64_t lw = lane_work(n, K, nbr, r.rows);
         wis.push_back({it, lw});
         p->lane_cells += lw * kWave;
@@ -334,7 +368,7 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
     L.off_flags = off; off += align_up(sizeof(int2) * L.flag_cap, 256);
     L.off_slots = off;
     const int64_t main_slots = slot_grid * r.waves * L.slot_elems * (int64_t)sizeof(int2);
-    const int64_t res_slots = L.rgrid * r.waves * L.rslot_elems * (int64_t)sizeof(int2);
+    const int64_t res_slots = L.rgrid * kRescoreWaves * L.rslot_elems * (int64_t)sizeof(int2);
     off += align_up(std::max(main_slots, res_slots), 256);
     L.total = off;
     return SW_OK;
@@ -411,6 +445,7 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
     if (!validate_options(opt, why)) return fail(SW_EINVAL, why);
     const int elem = matrix_elem(sm, go, why);
     if (!elem) return fail(SW_EINVAL, why);
+    if (db->host_only) return fail(SW_EINVAL, "planning-only handle cannot search");
     if (nq == 0 || db->nseq == 0)
         return SW_OK;
     if (!scores) return fail(SW_EINVAL, "null scores_out");
@@ -497,7 +532,7 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
     if (r.i16 && L.grid > 0) {
         SearchArgs b = a;
         b.slot_elems = L.rslot_elems;
-        HIPCHK(launch_rescore(r.v, b, (int)L.rgrid, r.waves, stream));
+        HIPCHK(launch_rescore(r.v, b, (int)L.rgrid, kRescoreWaves, stream));
     }
     if (e2) HIPCHK(hipEventRecord(e2, stream));
     return SW_OK;
@@ -638,6 +673,69 @@ int sw_db_prepare(const uint8_t* residues, const int64_t* offsets, const int32_t
     (void)hipFree(d_bad);
 #undef PCHK
     *out = db;
+    return SW_OK;
+}
+
+int sw_db_describe(const int32_t* lengths, int32_t nseq, int32_t cu_count, int32_t lds_bytes, sw_db_t* out)
+{
+    if (!out) return fail(SW_EINVAL, "null output handle");
+    *out = nullptr;
+    if (nseq < 0 || nseq > INT32_MAX / 2) return fail(SW_EINVAL, "nseq out of range");
+    if (nseq > 0 && !lengths) return fail(SW_EINVAL, "null lengths");
+    if (cu_count < 0 || lds_bytes < 0) return fail(SW_EINVAL, "negative device parameter");
+    std::vector<int32_t> len(lengths, lengths + nseq);
+    int64_t total = 0;
+    int32_t maxl = 0;
+    for (int32_t v : len) {
+        if (v < 0) return fail(SW_EINVAL, "negative subject length");
+        total += v;
+        maxl = std::max(maxl, v);
+    }
+    std::stable_sort(len.begin(), len.end(), [](int32_t a, int32_t b) { return a > b; });
+    auto* db = new sw_db_s();
+    db->host_only = true;
+    db->cu = cu_count ? cu_count : 256;
+    db->lds_max = lds_bytes ? std::min(lds_bytes, 160 * 1024) : 160 * 1024;
+    db->nseq = nseq;
+    db->total = total;
+    db->nchunks = (int32_t)ceil_div(nseq, 64);
+    db->max_len = maxl;
+    db->slen = std::move(len);
+    *out = db;
+    return SW_OK;
+}
+
+int64_t sw_plan_items(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt, int32_t* out,
+                      int64_t cap)
+{
+    int rc = validate_query_set(db, nq, q_lens);
+    if (rc) return rc;
+    std::string why;
+    if (!validate_options(opt, why)) return fail(SW_EINVAL, why);
+    if (cap > 0 && !out) return fail(SW_EINVAL, "null output");
+    Layout L;
+    rc = make_layout(db, nq, q_lens, resolve(db, opt, 2), L);
+    if (rc) return rc;
+    int64_t pos = 0;
+    for (int32_t k : L.order) {
+        for (const Item& it : L.plans[k]->items) {
+            if (pos < cap) {
+                out[4 * pos + 0] = it.s0;
+                out[4 * pos + 1] = it.ncols;
+                out[4 * pos + 2] = k;
+                out[4 * pos + 3] = it.meta;
+            }
+            ++pos;
+        }
+    }
+    return pos;
+}
+
+int sw_db_sorted_lengths(sw_db_t db, int32_t* out)
+{
+    if (!db) return fail(SW_EINVAL, "null database handle");
+    if (db->nseq > 0 && !out) return fail(SW_EINVAL, "null output");
+    std::copy(db->slen.begin(), db->slen.end(), out);
     return SW_OK;
 }
 

@@ -97,7 +97,7 @@ def test_long_subjects_and_lane_groups():
 
 @pytest.mark.parametrize("kw", [dict(max_lanes=1), dict(max_lanes=2), dict(max_lanes=8),
                                 dict(lane_cells=2000), dict(lane_cells=1 << 24),
-                                dict(waves=1), dict(waves=3), dict(lds_limit=1024),
+                                dict(waves=1), dict(waves=3), dict(waves=8), dict(lds_limit=1024),
                                 dict(grid_limit=1)])
 def test_plan_knobs_do_not_change_scores(kw):
     rng = np.random.default_rng(10)

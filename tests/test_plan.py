@@ -1,0 +1,104 @@
+"""Host logic of the planner (no GPU): work-queue invariants on planning-only
+handles built from subject lengths."""
+import numpy as np
+import pytest
+
+import paper_2412_08308_amd as swdb
+import synth
+
+WAVE = 64
+
+
+def _lengths(kind):
+    rng = np.random.default_rng(3)
+    if kind == "config0":
+        return synth.config(0).db.lengths
+    if kind == "config1":
+        return synth.lognormal_lengths(rng, 200_000, 300, 0.668, 10, 35_000)
+    if kind == "ragged":
+        base = [0, 0, 1, 15, 16, 17, 35000, 12000, 5000, 63, 64, 65, 127, 128, 129]
+        return np.array(base + rng.integers(0, 2000, size=700).tolist(), dtype=np.int32)
+    if kind == "tiny":
+        return np.array([5], dtype=np.int32)
+    raise ValueError(kind)
+
+
+def check_plan(db, qlens, opt, spl):
+    items = db.plan_items(qlens, opt)
+    waves = opt.waves or 4
+    slen = db.sorted_lengths()
+    assert len(items) % waves == 0
+    seen = np.zeros((len(qlens), db.nseq), dtype=np.int32)
+    for w in range(0, len(items), waves):
+        grp = items[w:w + waves]
+        qs = {int(it[2]) for it in grp if it[3] & 0xFFFF}
+        assert len(qs) <= 1, "a workgroup item mixes queries"
+    slot_need = 0
+    for s0, ncols, q, meta in items:
+        nsub, K = meta & 0xFFFF, meta >> 16
+        if nsub == 0:
+            continue
+        assert 1 <= K <= 64
+        assert nsub <= (WAVE // K) * spl
+        assert ncols % 16 == 0 and ncols == (int(slen[s0]) + 15) // 16 * 16
+        assert np.all(slen[s0:s0 + nsub] <= ncols)
+        seen[q, s0:s0 + nsub] += 1
+        nbr = -(-qlens[q] // (32 if spl == 1 else 16))
+        if nbr > K:
+            slot_need = max(slot_need, ncols * (WAVE // K) * 8)
+    assert np.all(seen == 1), "every subject exactly once per query"
+    info = db.plan_info(qlens, opt)
+    assert info["slot_bytes"] >= slot_need
+    assert info["lane_cells"] * (2 if spl == 2 else 1) >= info["cells"]
+    assert info["workspace"] == db.workspace_bytes(qlens, opt) > 0
+    return info
+
+
+@pytest.mark.parametrize("kind", ["config0", "ragged", "tiny"])
+@pytest.mark.parametrize("mode,spl", [("i32", 1), ("i16", 2), ("auto", 2)])
+def test_plan_invariants(kind, mode, spl):
+    db = swdb.Database.describe(_lengths(kind))
+    try:
+        for qlens in ([64], [0], [1], [567], [3000], [144, 0, 17, 600, 1, 2500, 333]):
+            for kw in ({}, dict(waves=1), dict(waves=8), dict(max_lanes=4), dict(lane_cells=4000)):
+                check_plan(db, qlens, swdb.options(mode=mode, **kw), spl)
+    finally:
+        db.release()
+
+
+def test_config1_plan_padding():
+    """Swept cells over real cells for the benchmark workload stay small: the
+    lane-group size is chosen per subject length so that row blocks divide
+    evenly over the group (567 rows = 18 blocks of 32 or 36 of 16)."""
+    db = swdb.Database.describe(_lengths("config1"))
+    try:
+        for mode, spl, bound in (("i32", 1, 1.08), ("i16", 2, 1.12)):
+            info = check_plan(db, [567], swdb.options(mode=mode), spl)
+            eff = info["lane_cells"] * spl / info["cells"]
+            assert eff < bound, (mode, eff)
+    finally:
+        db.release()
+
+
+def test_batch_plan_queue_order():
+    db = swdb.Database.describe(_lengths("ragged"))
+    try:
+        qlens = synth.c3_query_lengths()
+        items = db.plan_items(qlens, swdb.options())
+        qorder = []
+        for q in items[:, 2][items[:, 3] & 0xFFFF > 0]:
+            if not qorder or qorder[-1] != q:
+                qorder.append(int(q))
+        # each query's items are contiguous, largest query first
+        assert len(qorder) == len(set(qorder)) == len(qlens)
+        assert qorder[0] == int(np.argmax(qlens))
+    finally:
+        db.release()
+
+
+def test_describe_rejects_bad_input():
+    with pytest.raises(swdb.SwdbError):
+        swdb.Database.describe(np.array([3, -1], dtype=np.int32))
+    db = swdb.Database.describe(np.array([], dtype=np.int32))
+    assert db.workspace_bytes([10]) > 0
+    db.release()
