@@ -119,6 +119,54 @@ def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False)
                 rescore_ms=sum(r) / len(r), flagged=flagged, plan=plan, out=out)
 
 
+def serving(args, capacity_gcups, mode):
+    """Poisson request stream against config 4's 500,000-subject database through
+    the continuous-batching server; p50/p99 latency and sustained GCUPS."""
+    import numpy as np
+    import torch
+
+    import paper_2412_08308_amd as swdb
+    import synth
+    from paper_2412_08308_amd.serve import GpuBackend, Server
+
+    w5 = synth.config(4, scale=args.serve_scale)
+    gdb = swdb.Database.from_host(w5.db)
+    rng = np.random.default_rng(77)
+    n = args.serve_requests
+    qlens = synth.lognormal_lengths(rng, n, 350, 0.75, 50, 5000)
+    qs = [synth.residues(rng, int(m)) for m in qlens]
+    be = GpuBackend(gdb, w5.matrix, w5.gap_open, w5.gap_extend, mode=mode, n_streams=4, **KNOBS)
+    with Server(be, max_batch=16) as srv:                    # warm-up: plans, allocator, code
+        for f in [srv.submit(q) for q in qs[:8]]:
+            f.result()
+    torch.cuda.synchronize()
+    mean_m = float(np.mean(qlens))
+    runs = []
+    for rho in args.serve_rho:
+        lam = rho * capacity_gcups * 1e9 / (mean_m * w5.db.total)
+        arrivals = synth.poisson_arrivals(rng, lam, n)
+        srv = Server(be, max_batch=16).start()
+        futs = []
+        t0 = time.perf_counter()
+        for k, q in enumerate(qs):
+            dt = t0 + arrivals[k] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            futs.append(srv.submit(q))
+        for f in futs:
+            f.result()
+        srv.stop()
+        st = srv.stats()
+        runs.append({"rho": rho, "rate_per_s": round(lam, 2), "requests": n,
+                     "p50_ms": round(st["p50_s"] * 1e3, 2), "p99_ms": round(st["p99_s"] * 1e3, 2),
+                     "sustained_gcups": round(st["sustained_gcups"], 1),
+                     "mean_batch": round(st["mean_batch"], 2), "max_batch": st["max_batch"]})
+    gdb.release()
+    return {"workload": f"{w5.db.nseq} subjects ({w5.db.total} residues); {n} queries log-normal median 350 "
+                        "clamped 50-5000; Poisson arrivals at rho x single-query capacity",
+            "capacity_gcups": round(capacity_gcups, 1), "runs": runs}
+
+
 def cpu_baseline(w, seconds: float):
     """The oracle (plain C, int64, threads over subjects) on a random sample of
     the same database, sized for about ``seconds`` of host time."""
@@ -169,6 +217,10 @@ def main(argv=None):
     ap.add_argument("--lane-cells", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--lds-limit", type=int, default=0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-rho", type=float, nargs="+", default=[0.5, 0.8])
+    ap.add_argument("--serve-scale", type=float, default=1.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (traffic calibration)")
     args = ap.parse_args(argv)
@@ -237,6 +289,7 @@ def main(argv=None):
                    "ms_per_batch": round(b["wall_ms"], 2), "search_kernel_ms": round(b["kernel_ms"], 2),
                    "rescore_ms": round(b["rescore_ms"], 3), "flagged": b["flagged"], "cells": bcells}
 
+    latency = None if args.no_serve else serving(args, gcups, args.mode)
     cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_seconds)
 
     rec = {
@@ -271,7 +324,7 @@ def main(argv=None):
                                          / 1e12 / PEAK_VALU_TOPS, 4)},
         "i16": {"rescore_ms": round(main_run["rescore_ms"], 3), "flagged": main_run["flagged"]},
         "batched": batched,
-        "latency": None,
+        "latency": latency,
         "parity": parity,
         "plan": {k: main_run["plan"][k] for k in ("lane_cells", "items", "wg_items", "grid", "rows")},
         "knobs": {k: v for k, v in KNOBS.items() if v},

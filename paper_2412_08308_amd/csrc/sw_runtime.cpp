@@ -110,7 +110,7 @@ struct sw_db_s {
     int64_t dev_bytes = 0;
     std::vector<int32_t> slen;    // sorted lengths
     std::mutex mu;
-    std::vector<Staging> staging;
+    std::deque<Staging> staging;  // deque: elements stay put while others are added
     std::map<PlanKey, std::shared_ptr<QPlan>> plans;
     std::deque<PlanKey> plan_order;
 };

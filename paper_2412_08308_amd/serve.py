@@ -1,0 +1,297 @@
+"""Serving loop: continuous batching of database-search requests on one GPU.
+
+Requests (single queries) arrive at any time through ``Server.submit``.  A
+scheduler thread
+
+* admits requests in arrival order while the in-flight slot count and the
+  device-memory budget allow (each batch needs its workspace from
+  ``sw_workspace_bytes``, its score matrix and its query bytes);
+* groups everything admissible into one batched launch
+  (``sw_db_search_batch``) on a free stream of a small stream pool, so batches
+  that arrive while others run are searched concurrently on the device;
+* records a completion event per batch (after an asynchronous copy of the
+  scores to pinned host memory) and resolves each request's future when it
+  fires, with the latency (completion - arrival) attached.
+
+Scores are exact integers, so a request's result is identical whether it runs
+alone or inside any batch.  ``GpuBackend`` does the device work through the
+library; the scheduler itself only needs the small backend interface
+(``need_bytes``, ``launch``, ``poll``, ``results``, ``cells``).
+"""
+from __future__ import annotations
+
+import collections
+import itertools
+import threading
+import time
+from concurrent.futures import Future
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+
+class Request:
+    __slots__ = ("id", "query", "qlen", "arrival", "future", "started")
+
+    def __init__(self, rid, query, arrival):
+        self.id = rid
+        self.query = query
+        self.qlen = int(len(query)) if not hasattr(query, "numel") else int(query.numel())
+        self.arrival = arrival
+        self.future = Future()
+        self.future.latency = None
+        self.future.request_id = rid
+        self.started = False
+
+
+def percentiles(latencies: Sequence[float]):
+    """(p50, p99) by linear interpolation between order statistics."""
+    if len(latencies) == 0:
+        return None, None
+    x = np.sort(np.asarray(latencies, dtype=np.float64))
+    return float(np.percentile(x, 50)), float(np.percentile(x, 99))
+
+
+class GpuBackend:
+    """Batched searches on a pool of HIP streams through ``Database.search_batch``."""
+
+    def __init__(self, db, matrix, gap_open: int, gap_extend: int, mode="auto", n_streams: int = 4,
+                 **opt_kw):
+        import torch
+
+        from . import options
+        self.torch = torch
+        self.db = db
+        self.matrix = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
+        self.go, self.ge = int(gap_open), int(gap_extend)
+        self.opt = options(mode=mode, **opt_kw)
+        self.device = db.device
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        self.nseq = db.nseq
+
+    @property
+    def slots(self) -> int:
+        return len(self.streams)
+
+    def need_bytes(self, qlens: Sequence[int]) -> int:
+        ws = self.db.workspace_bytes(list(qlens), self.opt)
+        return ws + 4 * len(qlens) * self.nseq + int(sum(qlens))
+
+    def cells(self, qlens: Sequence[int]) -> int:
+        return int(sum(qlens)) * self.db.total
+
+    def launch(self, slot: int, queries: List[np.ndarray]):
+        torch = self.torch
+        s = self.streams[slot]
+        lens = [len(q) for q in queries]
+        offs = np.zeros(len(lens), dtype=np.int64)
+        if len(lens) > 1:
+            offs[1:] = np.cumsum(lens[:-1])
+        with torch.cuda.stream(s):
+            host = torch.from_numpy(np.concatenate(queries) if sum(lens) else np.zeros(1, np.uint8)).pin_memory()
+            cat = host.to(self.device, non_blocking=True)
+            ws = self.db.alloc_workspace(lens, self.opt)
+            out = torch.empty((len(lens), self.nseq), dtype=torch.int32, device=self.device)
+            self.db.search_batch((cat, offs, lens), self.matrix, self.go, self.ge, opt=self.opt, out=out,
+                                 workspace=ws, stream=s)
+            res = torch.empty((len(lens), self.nseq), dtype=torch.int32, pin_memory=True)
+            res.copy_(out, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return {"event": ev, "res": res, "keep": (host, cat, ws, out)}
+
+    def poll(self, handle) -> bool:
+        return handle["event"].query()
+
+    def results(self, handle) -> List[np.ndarray]:
+        handle["event"].synchronize()
+        r = handle["res"].numpy()
+        return [r[k].copy() for k in range(r.shape[0])]
+
+
+class Server:
+    """Continuous-batching request loop (see module docstring)."""
+
+    def __init__(self, backend, max_batch: int = 16, max_inflight: Optional[int] = None,
+                 mem_budget: Optional[int] = None, poll_interval: float = 1e-4, clock=time.perf_counter):
+        self.backend = backend
+        self.max_batch = int(max_batch)
+        self.max_inflight = int(max_inflight or getattr(backend, "slots", 4))
+        if mem_budget is None:
+            import torch
+            free, _ = torch.cuda.mem_get_info()
+            mem_budget = int(free * 0.5)
+        self.mem_budget = int(mem_budget)
+        self.poll_interval = poll_interval
+        self.clock = clock
+        self._ids = itertools.count()
+        self._pending = collections.deque()
+        self._inflight = []            # (slot, handle, requests, bytes)
+        self._free_slots = list(range(self.max_inflight))
+        self._in_use = 0
+        self._cv = threading.Condition()
+        self._running = False
+        self._thread = None
+        self.latencies = []
+        self.completed = 0
+        self.cells_done = 0
+        self.first_arrival = None
+        self.last_completion = None
+        self.max_in_use = 0
+        self.batch_sizes = []
+        self.errors = []
+
+    # ------------------------------------------------------------------ client side
+
+    def submit(self, query) -> Future:
+        """Queue one query (uint8 codes < 32, numpy); returns a Future of its scores."""
+        q = np.ascontiguousarray(np.asarray(query))
+        if q.dtype != np.uint8 or q.ndim != 1:
+            raise ValueError("query must be a 1-D uint8 array of residue codes")
+        if len(q) and int(q.max()) >= 32:
+            raise ValueError("query residue codes must be < 32")
+        now = self.clock()
+        req = Request(next(self._ids), q, now)
+        need = self.backend.need_bytes([req.qlen])
+        if need > self.mem_budget:
+            req.future.set_exception(MemoryError(f"request needs {need} bytes, budget {self.mem_budget}"))
+            return req.future
+        with self._cv:
+            if self.first_arrival is None:
+                self.first_arrival = now
+            self._pending.append(req)
+            self._cv.notify()
+        return req.future
+
+    def start(self):
+        if self._thread is None:
+            self._running = True
+            self._thread = threading.Thread(target=self._loop, name="swdb-serve", daemon=True)
+            self._thread.start()
+        return self
+
+    def stop(self, drain: bool = True, timeout: Optional[float] = None):
+        with self._cv:
+            if not drain:
+                while self._pending:
+                    r = self._pending.popleft()
+                    r.future.cancel()
+            self._running = False
+            self._cv.notify()
+        if self._thread is not None:
+            self._thread.join(timeout)
+            self._thread = None
+
+    def __enter__(self):
+        return self.start()
+
+    def __exit__(self, *exc):
+        self.stop(drain=True)
+
+    def stats(self) -> dict:
+        p50, p99 = percentiles(self.latencies)
+        span = (self.last_completion - self.first_arrival) if self.completed else None
+        return {"completed": self.completed, "p50_s": p50, "p99_s": p99,
+                "sustained_gcups": (self.cells_done / span / 1e9) if span else None,
+                "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else None,
+                "max_batch": max(self.batch_sizes) if self.batch_sizes else 0,
+                "max_bytes_in_use": self.max_in_use, "errors": len(self.errors)}
+
+    # ------------------------------------------------------------------ scheduler
+
+    def _complete(self):
+        done = []
+        for entry in self._inflight:
+            slot, h, reqs, nbytes = entry
+            if self.backend.poll(h):
+                done.append(entry)
+        for entry in done:
+            slot, h, reqs, nbytes = entry
+            self._inflight.remove(entry)
+            try:
+                rows = self.backend.results(h)
+                err = None
+            except Exception as e:           # a failed batch fails its own requests only
+                rows, err = None, e
+            t = self.clock()
+            for k, r in enumerate(reqs):
+                if err is not None:
+                    r.future.set_exception(err)
+                    self.errors.append(err)
+                    continue
+                r.future.latency = t - r.arrival
+                self.latencies.append(r.future.latency)
+                self.completed += 1
+                r.future.set_result(rows[k])
+            if err is None:
+                self.cells_done += self.backend.cells([r.qlen for r in reqs])
+                self.last_completion = t
+            with self._cv:
+                self._in_use -= nbytes
+                self._free_slots.append(slot)
+        return bool(done)
+
+    def _admit(self):
+        launched = False
+        while True:
+            with self._cv:
+                if not self._free_slots or not self._pending:
+                    return launched
+                batch, lens = [], []
+                while self._pending and len(batch) < self.max_batch:
+                    r = self._pending[0]
+                    if r.future.cancelled():
+                        self._pending.popleft()
+                        continue
+                    need = self.backend.need_bytes(lens + [r.qlen])
+                    if self._in_use + need > self.mem_budget:
+                        break
+                    self._pending.popleft()
+                    batch.append(r)
+                    lens.append(r.qlen)
+                if not batch:
+                    return launched
+                nbytes = self.backend.need_bytes(lens)
+                slot = self._free_slots.pop()
+                self._in_use += nbytes
+                self.max_in_use = max(self.max_in_use, self._in_use)
+            live = []
+            for r in batch:
+                if r.future.set_running_or_notify_cancel():     # False: cancelled meanwhile
+                    r.started = True
+                    live.append(r)
+            if len(live) != len(batch):
+                with self._cv:
+                    self._in_use -= nbytes
+                    if not live:
+                        self._free_slots.append(slot)
+                        continue
+                    nbytes = self.backend.need_bytes([r.qlen for r in live])
+                    self._in_use += nbytes
+                batch = live
+            try:
+                h = self.backend.launch(slot, [r.query for r in batch])
+            except Exception as e:
+                for r in batch:
+                    r.future.set_exception(e)
+                self.errors.append(e)
+                with self._cv:
+                    self._in_use -= nbytes
+                    self._free_slots.append(slot)
+                continue
+            self.batch_sizes.append(len(batch))
+            self._inflight.append((slot, h, batch, nbytes))
+            launched = True
+
+    def _loop(self):
+        while True:
+            progressed = self._complete()
+            progressed |= self._admit()
+            with self._cv:
+                if not self._running and not self._pending and not self._inflight:
+                    return
+                if not progressed:
+                    if self._inflight:
+                        self._cv.wait(self.poll_interval)
+                    else:
+                        self._cv.wait(0.05)

@@ -1,0 +1,71 @@
+"""Serving loop on the GPU: requests that overlap on the device in batches of
+any composition return exactly what each query returns alone."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpuhelp import announce, gpu_db, have_gpu
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="needs a GPU")]
+
+
+def _workload(n=3000, nq=40, seed=21):
+    rng = np.random.default_rng(seed)
+    lens = synth.lognormal_lengths(rng, n, 300, 0.668, 10, 35_000)
+    db = synth.make_db(rng, lens)
+    qlens = synth.lognormal_lengths(rng, nq, 350, 0.75, 50, 5000)
+    return db, [synth.residues(rng, int(m)) for m in qlens], rng
+
+
+@pytest.mark.parametrize("mode", ["auto", "i32"])
+def test_serve_results_equal_alone(mode):
+    import torch
+    from paper_2412_08308_amd.serve import GpuBackend, Server
+    db, qs, rng = _workload()
+    sm = synth.blosum_style_matrix()
+    gdb = gpu_db(db)
+    try:
+        alone = []
+        for q in qs:
+            announce(f"alone m={len(q)} mode={mode}")
+            alone.append(gdb.search(torch.from_numpy(q).cuda(), sm, 10, 2,
+                                    opt=__import__("paper_2412_08308_amd").options(mode=mode)).cpu().numpy())
+        torch.cuda.synchronize()
+        announce("serving mix")
+        be = GpuBackend(gdb, sm, 10, 2, mode=mode, n_streams=3)
+        with Server(be, max_batch=8) as srv:
+            futs = []
+            for q in qs:
+                futs.append(srv.submit(q))
+                time.sleep(float(rng.exponential(0.002)))
+            got = [f.result(timeout=120) for f in futs]
+        st = srv.stats()
+        assert st["completed"] == len(qs) and st["max_batch"] > 1
+        for k, (a, g) in enumerate(zip(alone, got)):
+            assert np.array_equal(a, g), f"request {k} differs in the mix"
+        for k in (0, 7):
+            assert np.array_equal(got[k], oracle.search_db(qs[k], db, sm, 10, 2))
+    finally:
+        gdb.release()
+
+
+def test_serve_memory_budget_forces_waiting():
+    from paper_2412_08308_amd.serve import GpuBackend, Server
+    db, qs, rng = _workload(n=2000, nq=12, seed=22)
+    sm = synth.blosum_style_matrix()
+    gdb = gpu_db(db)
+    try:
+        be = GpuBackend(gdb, sm, 10, 2, n_streams=4)
+        budget = be.need_bytes([max(len(q) for q in qs)] * 2)
+        announce(f"serving with budget {budget}")
+        with Server(be, max_batch=8, mem_budget=budget) as srv:
+            futs = [srv.submit(q) for q in qs]
+            got = [f.result(timeout=120) for f in futs]
+        assert srv.stats()["max_bytes_in_use"] <= budget
+        for q, g in zip(qs[:3], got[:3]):
+            assert np.array_equal(g, oracle.search_db(q, db, sm, 10, 2))
+    finally:
+        gdb.release()
