@@ -34,16 +34,27 @@ def test_serve_results_equal_alone(mode):
             alone.append(gdb.search(torch.from_numpy(q).cuda(), sm, 10, 2,
                                     opt=__import__("paper_2412_08308_amd").options(mode=mode)).cpu().numpy())
         torch.cuda.synchronize()
-        announce("serving mix")
         be = GpuBackend(gdb, sm, 10, 2, mode=mode, n_streams=3)
+        # burst queued before the scheduler starts: batches of up to 8 are certain
+        announce("serving burst")
+        srv = Server(be, max_batch=8)
+        futs = [srv.submit(q) for q in qs]
+        srv.start()
+        got = [f.result(timeout=120) for f in futs]
+        srv.stop()
+        st = srv.stats()
+        assert st["completed"] == len(qs) and st["max_batch"] == 8
+        for k, (a, g) in enumerate(zip(alone, got)):
+            assert np.array_equal(a, g), f"request {k} differs in a batch"
+        # timed arrivals: batches form and overlap as the device allows
+        announce("serving timed arrivals")
         with Server(be, max_batch=8) as srv:
             futs = []
             for q in qs:
                 futs.append(srv.submit(q))
                 time.sleep(float(rng.exponential(0.002)))
             got = [f.result(timeout=120) for f in futs]
-        st = srv.stats()
-        assert st["completed"] == len(qs) and st["max_batch"] > 1
+        assert srv.stats()["completed"] == len(qs)
         for k, (a, g) in enumerate(zip(alone, got)):
             assert np.array_equal(a, g), f"request {k} differs in the mix"
         for k in (0, 7):
