@@ -135,24 +135,32 @@ def lognormal_lengths(rng: np.random.Generator, n: int, median: float, sigma: fl
 
 def mutate(rng: np.random.Generator, src: np.ndarray, identity: float,
            indel_rate: float = 0.02, indel_mean: float = 3.0) -> np.ndarray:
-    """A near-homolog of ``src``: substitutions (from the background) so that
-    about ``identity`` of positions are kept, plus geometric-length indels."""
-    out = []
-    i = 0
+    """A near-homolog of ``src``: each position kept with probability
+    ``identity`` (else redrawn from the background), plus indel events at
+    ``indel_rate`` per position, half deletions and half insertions, with
+    geometric lengths of mean ``indel_mean``."""
+    src = np.asarray(src, dtype=np.uint8)
     n = len(src)
-    while i < n:
-        u = rng.random()
-        if u < indel_rate / 2:                      # deletion
-            i += int(rng.geometric(1.0 / indel_mean))
+    out = src.copy()
+    sub = rng.random(n) >= identity
+    out[sub] = residues(rng, int(sub.sum()))
+    ev = np.nonzero(rng.random(n) < indel_rate)[0]
+    if len(ev) == 0:
+        return out
+    pieces = []
+    pos = 0
+    for e in ev:
+        if e < pos:
             continue
-        if u < indel_rate:                          # insertion
-            out.append(residues(rng, int(rng.geometric(1.0 / indel_mean))))
-        if rng.random() < identity:
-            out.append(src[i:i + 1])
-        else:
-            out.append(residues(rng, 1))
-        i += 1
-    return np.concatenate(out).astype(np.uint8) if out else np.zeros(0, np.uint8)
+        pieces.append(out[pos:e])
+        L = int(rng.geometric(1.0 / indel_mean))
+        if rng.random() < 0.5:          # deletion of L source positions
+            pos = min(n, e + L)
+        else:                           # insertion of L random residues before e
+            pieces.append(residues(rng, L))
+            pos = e
+    pieces.append(out[pos:])
+    return np.concatenate(pieces).astype(np.uint8)
 
 
 @dataclass
