@@ -191,6 +191,27 @@ int sw_db_search_batch(sw_db_t db, const uint8_t* queries, const int64_t* q_offs
                        int32_t* scores_out, hipStream_t stream);
 
 /*
+ * Graph form of a batched search (the batched launch of paper Section 4.1's
+ * multi-query workload, replayed without per-launch host work): captures
+ * exactly what sw_db_search_batch would enqueue -- plan upload, profile,
+ * search and rescore kernels -- into a HIP graph.  The graph owns a pinned
+ * copy of the plan; it reads `queries` and writes `scores_out` and
+ * `workspace` (all device, fixed at capture) each time it is launched, so new
+ * query residues of the same lengths may be written into `queries` between
+ * launches.  The database handle and those buffers must outlive the graph.
+ * Launches are asynchronous on `stream`; concurrent launches of one graph
+ * race on its workspace.  Timing events in `opt` are ignored.
+ */
+typedef struct sw_graph_s* sw_graph_t;
+int sw_graph_create(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets,
+                    const int32_t* q_lens, int32_t nq,
+                    const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
+                    const sw_options* opt, void* workspace, size_t ws_bytes,
+                    int32_t* scores_out, sw_graph_t* out);
+int sw_graph_launch(sw_graph_t graph, hipStream_t stream);
+int sw_graph_destroy(sw_graph_t graph);
+
+/*
  * Number of subjects the last search that used `workspace` sent to the int32
  * rescore (16-bit modes).  Synchronises `stream`.  Negative on error.
  */

@@ -92,6 +92,13 @@ def lib():
     L.sw_plan_items.argtypes = [vp, i32, vp, ctypes.POINTER(Options), vp, i64]
     L.sw_db_sorted_lengths.restype = ctypes.c_int
     L.sw_db_sorted_lengths.argtypes = [vp, vp]
+    L.sw_graph_create.restype = ctypes.c_int
+    L.sw_graph_create.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, ctypes.POINTER(Options), vp, sz, vp,
+                                  ctypes.POINTER(vp)]
+    L.sw_graph_launch.restype = ctypes.c_int
+    L.sw_graph_launch.argtypes = [vp, vp]
+    L.sw_graph_destroy.restype = ctypes.c_int
+    L.sw_graph_destroy.argtypes = [vp]
     L.sw_flagged_count.restype = ctypes.c_int64
     L.sw_flagged_count.argtypes = [vp, vp]
     L.sw_strerror.restype = ctypes.c_char_p
@@ -148,6 +155,32 @@ def _dev(t, dtype, name):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
+class SearchGraph:
+    """A captured batched search (``sw_graph_*``).  ``queries`` is the device
+    buffer the graph reads: write new residues of the same lengths into it
+    (``queries.copy_(...)``) between launches."""
+
+    def __init__(self, handle, db, queries, workspace, out):
+        self._g = handle
+        self.db = db
+        self.queries, self.workspace, self.out = queries, workspace, out
+
+    def launch(self, stream=None):
+        _check(lib().sw_graph_launch(self._g, _stream(stream)), "sw_graph_launch")
+        return self.out
+
+    def destroy(self):
+        if getattr(self, "_g", None) is not None:
+            lib().sw_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def search(query, residues, offsets, lengths, matrix, gap_open: int, gap_extend: int,
@@ -289,17 +322,7 @@ class Database:
         """``sw_db_search_batch``.  ``queries``: a list of device uint8 tensors,
         or a tuple (concatenated device tensor, host offsets, host lengths)."""
         import torch
-        if isinstance(queries, tuple):
-            cat, offs, lens = queries
-            offs = np.ascontiguousarray(np.asarray(offs, dtype=np.int64))
-            lens = np.ascontiguousarray(np.asarray(lens, dtype=np.int32))
-        else:
-            lens = np.array([int(q.numel()) for q in queries], dtype=np.int32)
-            offs = np.zeros(len(lens), dtype=np.int64)
-            if len(lens) > 1:
-                offs[1:] = np.cumsum(lens[:-1])
-            cat = (torch.cat([q.reshape(-1) for q in queries]) if len(queries)
-                   else torch.empty(0, dtype=torch.uint8, device=self.device))
+        cat, offs, lens = self._batch_args(queries)
         nq = len(lens)
         if workspace is None:
             workspace = self.alloc_workspace(lens, opt)
@@ -315,6 +338,41 @@ class Database:
         _check(rc, "sw_db_search_batch")
         self._keep = (cat, workspace)
         return out
+
+    def capture(self, queries, matrix, gap_open: int, gap_extend: int, opt: Optional[Options] = None,
+                out=None, workspace=None) -> "SearchGraph":
+        """``sw_graph_create``: a replayable graph of one batched search."""
+        import torch
+        cat, offs, lens = self._batch_args(queries)
+        nq = len(lens)
+        if workspace is None:
+            workspace = self.alloc_workspace(lens, opt)
+        if out is None:
+            out = torch.empty((nq, self.nseq), dtype=torch.int32, device=self.device)
+        sm = _matrix(matrix)
+        g = ctypes.c_void_p()
+        rc = lib().sw_graph_create(self._handle(), _dev(cat, torch.uint8, "queries"),
+                                   offs.ctypes.data if nq else None, lens.ctypes.data if nq else None, nq,
+                                   sm.ctypes.data, int(gap_open), int(gap_extend),
+                                   ctypes.byref(opt) if opt is not None else None,
+                                   _dev(workspace, torch.uint8, "workspace"), int(workspace.numel()),
+                                   _dev(out, torch.int32, "out"), ctypes.byref(g))
+        _check(rc, "sw_graph_create")
+        return SearchGraph(g, self, cat, workspace, out)
+
+    def _batch_args(self, queries):
+        import torch
+        if isinstance(queries, tuple):
+            cat, offs, lens = queries
+            return (cat, np.ascontiguousarray(np.asarray(offs, dtype=np.int64)),
+                    np.ascontiguousarray(np.asarray(lens, dtype=np.int32)))
+        lens = np.array([int(q.numel()) for q in queries], dtype=np.int32)
+        offs = np.zeros(len(lens), dtype=np.int64)
+        if len(lens) > 1:
+            offs[1:] = np.cumsum(lens[:-1])
+        cat = (torch.cat([q.reshape(-1) for q in queries]) if len(queries)
+               else torch.empty(0, dtype=torch.uint8, device=self.device))
+        return cat, offs, lens
 
     def flagged_count(self, workspace, stream=None) -> int:
         import torch

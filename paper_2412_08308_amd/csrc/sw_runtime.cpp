@@ -425,10 +425,12 @@ void* acquire_staging(sw_db_s* db, size_t bytes, Staging** out)
     return st.host;
 }
 
-int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, const int32_t* q_lens,
-              int32_t nq, const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt,
-              void* ws, size_t ws_bytes, int32_t* scores, hipStream_t stream)
+// Validation and planning shared by every search entry point.
+int plan_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, const int32_t* q_lens,
+                int32_t nq, const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt,
+                void* ws, size_t ws_bytes, int32_t* scores, Layout& L, bool& nothing)
 {
+    nothing = false;
     int rc = validate_query_set(db, nq, q_lens);
     if (rc) return rc;
     if (nq > 0 && !q_offsets) return fail(SW_EINVAL, "null q_offsets");
@@ -446,49 +448,46 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
     const int elem = matrix_elem(sm, go, why);
     if (!elem) return fail(SW_EINVAL, why);
     if (db->host_only) return fail(SW_EINVAL, "planning-only handle cannot search");
-    if (nq == 0 || db->nseq == 0)
+    if (nq == 0 || db->nseq == 0) {
+        nothing = true;
         return SW_OK;
+    }
     if (!scores) return fail(SW_EINVAL, "null scores_out");
     if (!ws) return fail(SW_EINVAL, "null workspace");
     if (((uintptr_t)ws & 255) != 0) return fail(SW_EINVAL, "workspace must be 256-byte aligned");
-
-    Layout L;
     rc = make_layout(db, nq, q_lens, resolve(db, opt, elem), L);
     if (rc) return rc;
     if (ws_bytes < L.total)
         return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
-    const Resolved& r = L.r;
-    uint8_t* w = static_cast<uint8_t*>(ws);
+    return SW_OK;
+}
 
-    // plan blob: query descriptors, query offsets, items
-    Staging* st = nullptr;
-    uint8_t* h = static_cast<uint8_t*>(acquire_staging(db, L.blob, &st));
-    if (!h) return fail(SW_ENOMEM, "pinned staging allocation failed");
-    {
-        std::vector<QueryDesc> qd = L.qd;
-        for (int32_t k = 0; k < nq; ++k)
-            qd[k].prof_off = L.qd[k].prof_off;
-        std::memcpy(h, qd.data(), sizeof(QueryDesc) * nq);
-        std::memcpy(h + (L.off_qoff - L.off_qd), q_offsets, sizeof(int64_t) * nq);
-        Item* items = reinterpret_cast<Item*>(h + (L.off_items - L.off_qd));
-        int64_t pos = 0;
-        for (int32_t k : L.order) {
-            const QPlan& p = *L.plans[k];
-            for (const Item& it0 : p.items) {
-                Item it = it0;
-                it.q = k;
-                items[pos++] = it;
-            }
+// The plan blob (query descriptors, query offsets, work queue) in host memory.
+void fill_blob(const Layout& L, const int64_t* q_offsets, uint8_t* h)
+{
+    std::memcpy(h, L.qd.data(), sizeof(QueryDesc) * L.nq);
+    std::memcpy(h + (L.off_qoff - L.off_qd), q_offsets, sizeof(int64_t) * L.nq);
+    Item* items = reinterpret_cast<Item*>(h + (L.off_items - L.off_qd));
+    int64_t pos = 0;
+    for (int32_t k : L.order) {
+        for (const Item& it0 : L.plans[k]->items) {
+            Item it = it0;
+            it.q = k;
+            items[pos++] = it;
         }
     }
-    hipError_t e = hipMemcpyAsync(w + L.off_qd, h, L.blob, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipEventRecord(st->ev, stream);
-    if (e != hipSuccess) {
-        std::lock_guard<std::mutex> lk(db->mu);
-        st->pending = false;
-        return fail(SW_EHIP, std::string("plan upload: ") + hipGetErrorString(e));
-    }
+}
+
+// Everything a search puts on `stream`: plan upload from pinned host memory,
+// profile kernel (also clears the queue head and flag count), search kernel,
+// rescore kernel.  No memset: the sequence may be captured into a graph.
+int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8_t* queries,
+                   const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt, void* ws,
+                   int32_t* scores, hipStream_t stream)
+{
+    const Resolved& r = L.r;
+    uint8_t* w = static_cast<uint8_t*>(ws);
+    HIPCHK(hipMemcpyAsync(w + L.off_qd, blob, L.blob, hipMemcpyHostToDevice, stream));
 
     ProfileArgs pa{};
     pa.queries = queries;
@@ -496,7 +495,7 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
     pa.qd = reinterpret_cast<const QueryDesc*>(w + L.off_qd);
     pa.prof = w + L.off_prof;
     pa.counters = reinterpret_cast<int32_t*>(w + L.off_counters);
-    pa.nq = nq;
+    pa.nq = L.nq;
     pa.go = go;
     for (int i = 0; i < kAlpha * kAlpha; ++i)
         pa.sm.v[i] = (int8_t)sm[i];
@@ -510,7 +509,7 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
     a.nseq = db->nseq;
     a.items = reinterpret_cast<const Item*>(w + L.off_items);
     a.qd = pa.qd;
-    a.nq = nq;
+    a.nq = L.nq;
     a.n_wg = (int32_t)L.n_wg;
     a.prof = pa.prof;
     a.scores = scores;
@@ -536,6 +535,30 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
     }
     if (e2) HIPCHK(hipEventRecord(e2, stream));
     return SW_OK;
+}
+
+int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, const int32_t* q_lens,
+              int32_t nq, const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt,
+              void* ws, size_t ws_bytes, int32_t* scores, hipStream_t stream)
+{
+    Layout L;
+    bool nothing = false;
+    int rc = plan_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, L, nothing);
+    if (rc || nothing) return rc;
+    Staging* st = nullptr;
+    uint8_t* h = static_cast<uint8_t*>(acquire_staging(db, L.blob, &st));
+    if (!h) return fail(SW_ENOMEM, "pinned staging allocation failed");
+    fill_blob(L, q_offsets, h);
+    rc = enqueue_search(db, L, h, queries, sm, go, ge, opt, ws, scores, stream);
+    // the staging buffer is reusable once the stream has passed this point
+    const hipError_t e = hipEventRecord(st->ev, stream);
+    if (rc || e != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        std::lock_guard<std::mutex> lk(db->mu);
+        st->pending = false;
+        if (!rc) rc = fail(SW_EHIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
+    }
+    return rc;
 }
 
 void free_db(sw_db_s* db)
@@ -801,6 +824,84 @@ int sw_db_search_batch(sw_db_t db, const uint8_t* queries, const int64_t* q_offs
                        hipStream_t stream)
 {
     return do_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, stream);
+}
+
+}  // extern "C"
+
+struct sw_graph_s {
+    sw_db_t db = nullptr;
+    void* blob = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+void free_graph(sw_graph_s* g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    if (g->blob) (void)hipHostFree(g->blob);
+    delete g;
+}
+}  // namespace
+
+extern "C" {
+
+int sw_graph_create(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, const int32_t* q_lens,
+                    int32_t nq, const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt,
+                    void* ws, size_t ws_bytes, int32_t* scores, sw_graph_t* out)
+{
+    if (!out) return fail(SW_EINVAL, "null output graph");
+    *out = nullptr;
+    Layout L;
+    bool nothing = false;
+    int rc = plan_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, L, nothing);
+    if (rc) return rc;
+    sw_options o{};
+    if (opt) o = *opt;
+    o.ev_search_begin = o.ev_search_end = o.ev_rescore_end = nullptr;
+    auto* g = new sw_graph_s();
+    g->db = db;
+    auto bail = [&](int code, const std::string& msg) {
+        free_graph(g);
+        return fail(code, msg);
+    };
+    hipError_t e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(SW_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    if (!nothing) {
+        e = hipHostMalloc(&g->blob, std::max<size_t>(L.blob, 16), hipHostMallocDefault);
+        if (e != hipSuccess) return bail(SW_ENOMEM, "pinned plan allocation failed");
+        fill_blob(L, q_offsets, static_cast<uint8_t*>(g->blob));
+    }
+    e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bail(SW_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    if (!nothing)
+        rc = enqueue_search(db, L, static_cast<uint8_t*>(g->blob), queries, sm, go, ge, &o, ws, scores, g->cap);
+    const std::string err = g_err;
+    e = hipStreamEndCapture(g->cap, &g->graph);
+    if (rc) return bail(rc, "capture: " + err);
+    if (e != hipSuccess) return bail(SW_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return bail(SW_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    *out = g;
+    return SW_OK;
+}
+
+int sw_graph_launch(sw_graph_t g, hipStream_t stream)
+{
+    if (!g || !g->exec) return fail(SW_EINVAL, "null graph");
+    HIPCHK(hipGraphLaunch(g->exec, stream));
+    return SW_OK;
+}
+
+int sw_graph_destroy(sw_graph_t g)
+{
+    if (!g) return fail(SW_EINVAL, "null graph");
+    free_graph(g);
+    return SW_OK;
 }
 
 int64_t sw_flagged_count(const void* ws, hipStream_t stream)
