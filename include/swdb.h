@@ -56,6 +56,9 @@ extern "C" {
 #define SW_MODE_I32 1      /* int32 lanes (the paper's 32-bit formulation)        */
 #define SW_MODE_I16 2      /* packed 2x16-bit saturating lanes; subjects whose
                               16-bit score reaches 32767 are rescored in int32    */
+#define SW_MODE_TUNED 3    /* per query length, the schedule sw_autotune chose or
+                              sw_tune_set installed on the handle (AUTO if none);
+                              a batch runs one persistent launch per schedule      */
 
 typedef struct sw_db_s* sw_db_t;
 
@@ -75,6 +78,14 @@ typedef struct sw_options {
     hipEvent_t ev_search_end;
     hipEvent_t ev_rescore_end;
 } sw_options;
+
+/* One autotuner result: the schedule for queries of length <= qlen. */
+typedef struct sw_tune_entry {
+    int32_t qlen;
+    int32_t pad;
+    double gcups;          /* measured with the chosen schedule                     */
+    sw_options opt;        /* mode, waves, lane_cells (events unused)               */
+} sw_tune_entry;
 
 /* Plan summary (for measurement; all counts are per search call). */
 typedef struct sw_plan_stats {
@@ -210,6 +221,25 @@ int sw_graph_create(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets
                     int32_t* scores_out, sw_graph_t* out);
 int sw_graph_launch(sw_graph_t graph, hipStream_t stream);
 int sw_graph_destroy(sw_graph_t graph);
+
+/*
+ * Autotuner (schedule choice for the batched and single-query searches).  For
+ * each length qlens[b] (HOST, ascending), times candidate schedules -- arithmetic
+ * mode (packed 16-bit + rescore, or int32) x per-item work target x waves per
+ * workgroup -- on this database with a query of that length drawn from the
+ * database's own residue composition, and keeps the fastest.  Results go to
+ * out[nbins] (HOST) and are installed on the handle for SW_MODE_TUNED.
+ * Blocking (synchronises `stream`); allocates and frees its own device memory.
+ */
+int sw_autotune(sw_db_t db, const int32_t* qlens, int32_t nbins, const int32_t* subst_matrix,
+                int32_t gap_open, int32_t gap_extend, hipStream_t stream, sw_tune_entry* out);
+
+/* Install (n > 0) or clear (n == 0) the handle's tuned schedules, e.g. from a
+   cache of an earlier sw_autotune on the same database and device. */
+int sw_tune_set(sw_db_t db, const sw_tune_entry* entries, int32_t n);
+
+/* Copy up to cap installed entries to out (HOST); returns how many exist. */
+int32_t sw_tune_get(sw_db_t db, sw_tune_entry* out, int32_t cap);
 
 /*
  * Number of subjects the last search that used `workspace` sent to the int32

@@ -26,8 +26,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswdb.so")
 
 SW_OK = 0
-MODE_AUTO, MODE_I32, MODE_I16 = 0, 1, 2
-MODES = {"auto": MODE_AUTO, "i32": MODE_I32, "i16": MODE_I16}
+MODE_AUTO, MODE_I32, MODE_I16, MODE_TUNED = 0, 1, 2, 3
+MODES = {"auto": MODE_AUTO, "i32": MODE_I32, "i16": MODE_I16, "tuned": MODE_TUNED}
 MAX_GAP = 32000
 
 
@@ -44,6 +44,25 @@ class Options(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 10),
                 ("ev_search_begin", ctypes.c_void_p), ("ev_search_end", ctypes.c_void_p),
                 ("ev_rescore_end", ctypes.c_void_p)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("qlen", ctypes.c_int32), ("pad", ctypes.c_int32), ("gcups", ctypes.c_double),
+                ("opt", Options)]
+
+    def as_dict(self):
+        return {"qlen": self.qlen, "gcups": self.gcups, "mode": self.opt.mode, "waves": self.opt.waves,
+                "lane_cells": self.opt.lane_cells, "max_lanes": self.opt.max_lanes,
+                "lds_limit": self.opt.lds_limit, "grid_limit": self.opt.grid_limit}
+
+    @classmethod
+    def from_dict(cls, d):
+        e = cls()
+        e.qlen, e.gcups = int(d["qlen"]), float(d.get("gcups", 0.0))
+        e.opt = options(mode=int(d["mode"]), waves=d.get("waves", 0), lane_cells=d.get("lane_cells", 0),
+                        max_lanes=d.get("max_lanes", 0), lds_limit=d.get("lds_limit", 0),
+                        grid_limit=d.get("grid_limit", 0))
+        return e
 
 
 class PlanStats(ctypes.Structure):
@@ -92,6 +111,12 @@ def lib():
     L.sw_plan_items.argtypes = [vp, i32, vp, ctypes.POINTER(Options), vp, i64]
     L.sw_db_sorted_lengths.restype = ctypes.c_int
     L.sw_db_sorted_lengths.argtypes = [vp, vp]
+    L.sw_autotune.restype = ctypes.c_int
+    L.sw_autotune.argtypes = [vp, vp, i32, vp, i32, i32, vp, ctypes.POINTER(TuneEntry)]
+    L.sw_tune_set.restype = ctypes.c_int
+    L.sw_tune_set.argtypes = [vp, ctypes.POINTER(TuneEntry), i32]
+    L.sw_tune_get.restype = ctypes.c_int32
+    L.sw_tune_get.argtypes = [vp, ctypes.POINTER(TuneEntry), i32]
     L.sw_graph_create.restype = ctypes.c_int
     L.sw_graph_create.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, ctypes.POINTER(Options), vp, sz, vp,
                                   ctypes.POINTER(vp)]
@@ -373,6 +398,28 @@ class Database:
         cat = (torch.cat([q.reshape(-1) for q in queries]) if len(queries)
                else torch.empty(0, dtype=torch.uint8, device=self.device))
         return cat, offs, lens
+
+    def autotune(self, qlens: Sequence[int], matrix, gap_open: int, gap_extend: int, stream=None):
+        """``sw_autotune``: time candidate schedules per query length; installs
+        the winners for mode ``"tuned"`` and returns them as dicts."""
+        ql = np.ascontiguousarray(np.sort(np.asarray(qlens, dtype=np.int32)))
+        out = (TuneEntry * len(ql))()
+        sm = _matrix(matrix)
+        _check(lib().sw_autotune(self._handle(), ql.ctypes.data, len(ql), sm.ctypes.data, int(gap_open),
+                                 int(gap_extend), _stream(stream), out), "sw_autotune")
+        return [e.as_dict() for e in out]
+
+    def set_tuning(self, entries):
+        arr = (TuneEntry * len(entries))(*[TuneEntry.from_dict(d) for d in entries])
+        _check(lib().sw_tune_set(self._handle(), arr, len(entries)), "sw_tune_set")
+
+    def get_tuning(self):
+        n = lib().sw_tune_get(self._handle(), None, 0)
+        if n < 0:
+            _check(int(n), "sw_tune_get")
+        arr = (TuneEntry * max(n, 1))()
+        lib().sw_tune_get(self._handle(), arr, n)
+        return [arr[k].as_dict() for k in range(n)]
 
     def flagged_count(self, workspace, stream=None) -> int:
         import torch

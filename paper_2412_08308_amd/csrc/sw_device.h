@@ -248,7 +248,7 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
             S = max(S, __shfl(S, min(hl + k, kWave - 1)));
     }
     if (head && valid)
-        a.scores[(int64_t)it.q * a.out_stride + a.perm[s]] = S;
+        a.scores[(int64_t)qd.out_row * a.out_stride + a.perm[s]] = S;
 }
 
 // ------------------------------------------------------------------ packed 16-bit item
@@ -396,7 +396,7 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
     if (head) {
         const int lo = (int)(int16_t)(Su & 0xffff);
         const int hi = (int)(int16_t)(Su >> 16);
-        const int64_t ob = (int64_t)it.q * a.out_stride;
+        const int64_t ob = (int64_t)qd.out_row * a.out_stride;
         if (validA) {
             if (lo == 32767) {
                 const int k = atomicAdd(&a.counters[1], 1);

@@ -38,6 +38,8 @@ struct QueryDesc {
     int32_t lds;        // 1: profile staged in LDS; 0: read from global memory
     int32_t wg_begin;   // first workgroup item of this query in the queue
     int32_t wg_count;   // number of workgroup items of this query
+    int32_t out_row;    // row of the score matrix this query writes
+    int32_t pad;
 };
 
 struct Matrix8 {

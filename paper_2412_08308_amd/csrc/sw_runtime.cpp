@@ -113,6 +113,7 @@ struct sw_db_s {
     std::deque<Staging> staging;  // deque: elements stay put while others are added
     std::map<PlanKey, std::shared_ptr<QPlan>> plans;
     std::deque<PlanKey> plan_order;
+    std::vector<sw_tune_entry> tune;   // by ascending qlen (SW_MODE_TUNED)
 };
 
 namespace {
@@ -121,7 +122,7 @@ bool validate_options(const sw_options* opt, std::string& why)
 {
     if (!opt)
         return true;
-    if (opt->mode < SW_MODE_AUTO || opt->mode > SW_MODE_I16) { why = "options.mode"; return false; }
+    if (opt->mode < SW_MODE_AUTO || opt->mode > SW_MODE_TUNED) { why = "options.mode"; return false; }
     if (opt->waves < 0 || opt->waves > 8) { why = "options.waves must be 0..8"; return false; }
     if (opt->lane_cells < 0) { why = "options.lane_cells"; return false; }
     if (opt->max_lanes < 0 || opt->max_lanes > 64 || (opt->max_lanes & (opt->max_lanes - 1))) {
@@ -308,6 +309,7 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
         const int nbr = (int)ceil_div(m, r.rows);
         const int64_t pb = prof_bytes_for(nbr, r.rows, 2);   // sized for 16-bit entries
         L.qd[k].prof_off = prof;
+        L.qd[k].out_row = k;
         L.qd[k].m = m;
         L.qd[k].nbr = nbr;
         const int64_t pbe = prof_bytes_for(nbr, r.rows, r.elem);
@@ -425,10 +427,81 @@ void* acquire_staging(sw_db_s* db, size_t bytes, Staging** out)
     return st.host;
 }
 
+// One launch group of a search: queries that share a schedule.  Plain modes
+// give one group; SW_MODE_TUNED groups queries by the tuned schedule of their
+// length and launches the groups one after another on the stream.
+struct Part {
+    Layout L;
+    std::vector<int32_t> idx;        // caller's query indices (score rows)
+    std::vector<int32_t> lens;
+    std::vector<int64_t> offs;
+    size_t total() const { return L.total; }
+};
+
+sw_options tuned_for(const sw_db_s* db, int32_t m, int* which)
+{
+    sw_options o{};
+    *which = -1;
+    if (db->tune.empty())
+        return o;
+    int k = (int)db->tune.size() - 1;
+    for (int i = 0; i < (int)db->tune.size(); ++i)
+        if (db->tune[i].qlen >= m) { k = i; break; }
+    *which = k;
+    o = db->tune[k].opt;
+    o.ev_search_begin = o.ev_search_end = o.ev_rescore_end = nullptr;
+    return o;
+}
+
+int build_parts(sw_db_s* db, int32_t nq, const int32_t* q_lens, const int64_t* q_offsets,
+                const sw_options* opt, int elem, std::vector<Part>& parts)
+{
+    parts.clear();
+    const bool tuned = opt && opt->mode == SW_MODE_TUNED;
+    std::map<int, size_t> group_of;
+    std::vector<sw_options> gopt;
+    for (int32_t k = 0; k < nq; ++k) {
+        int which = -1;
+        sw_options o{};
+        if (tuned) {
+            std::lock_guard<std::mutex> lk(db->mu);
+            o = tuned_for(db, q_lens[k], &which);
+        } else if (opt) {
+            o = *opt;
+        }
+        auto f = group_of.find(which);
+        if (f == group_of.end()) {
+            f = group_of.emplace(which, parts.size()).first;
+            parts.emplace_back();
+            gopt.push_back(o);
+        }
+        Part& P = parts[f->second];
+        P.idx.push_back(k);
+        P.lens.push_back(q_lens[k]);
+        P.offs.push_back(q_offsets ? q_offsets[k] : 0);
+    }
+    for (size_t g = 0; g < parts.size(); ++g) {
+        Part& P = parts[g];
+        const int rc = make_layout(db, (int32_t)P.idx.size(), P.lens.data(), resolve(db, &gopt[g], elem), P.L);
+        if (rc) return rc;
+        for (size_t k = 0; k < P.idx.size(); ++k)
+            P.L.qd[k].out_row = P.idx[k];
+    }
+    return SW_OK;
+}
+
+size_t parts_bytes(const std::vector<Part>& parts)
+{
+    size_t b = 0;
+    for (const Part& P : parts)
+        b = std::max(b, P.total());
+    return b;
+}
+
 // Validation and planning shared by every search entry point.
 int plan_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, const int32_t* q_lens,
                 int32_t nq, const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt,
-                void* ws, size_t ws_bytes, int32_t* scores, Layout& L, bool& nothing)
+                void* ws, size_t ws_bytes, int32_t* scores, std::vector<Part>& parts, bool& nothing)
 {
     nothing = false;
     int rc = validate_query_set(db, nq, q_lens);
@@ -455,10 +528,15 @@ int plan_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, co
     if (!scores) return fail(SW_EINVAL, "null scores_out");
     if (!ws) return fail(SW_EINVAL, "null workspace");
     if (((uintptr_t)ws & 255) != 0) return fail(SW_EINVAL, "workspace must be 256-byte aligned");
-    rc = make_layout(db, nq, q_lens, resolve(db, opt, elem), L);
+    rc = build_parts(db, nq, q_lens, q_offsets, opt, elem, parts);
     if (rc) return rc;
-    if (ws_bytes < L.total)
-        return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    // the size requirement is the one sw_workspace_bytes reports (16-bit profile sizing)
+    std::vector<Part> sizing;
+    rc = build_parts(db, nq, q_lens, q_offsets, opt, 2, sizing);
+    if (rc) return rc;
+    const size_t need = parts_bytes(sizing);
+    if (ws_bytes < need)
+        return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
     return SW_OK;
 }
 
@@ -482,8 +560,8 @@ void fill_blob(const Layout& L, const int64_t* q_offsets, uint8_t* h)
 // profile kernel (also clears the queue head and flag count), search kernel,
 // rescore kernel.  No memset: the sequence may be captured into a graph.
 int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8_t* queries,
-                   const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt, void* ws,
-                   int32_t* scores, hipStream_t stream)
+                   const int32_t* sm, int32_t go, int32_t ge, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2,
+                   void* ws, int32_t* scores, hipStream_t stream)
 {
     const Resolved& r = L.r;
     uint8_t* w = static_cast<uint8_t*>(ws);
@@ -521,9 +599,6 @@ int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8
     a.flag_cap = (int32_t)std::min<int64_t>(L.flag_cap, INT32_MAX);
     a.go = go;
     a.ge = ge;
-    hipEvent_t e0 = opt ? opt->ev_search_begin : nullptr;
-    hipEvent_t e1 = opt ? opt->ev_search_end : nullptr;
-    hipEvent_t e2 = opt ? opt->ev_rescore_end : nullptr;
     if (e0) HIPCHK(hipEventRecord(e0, stream));
     if (L.grid > 0)
         HIPCHK(launch_search(r.v, a, (int)L.grid, r.waves, L.lds_bytes, stream));
@@ -537,25 +612,51 @@ int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8
     return SW_OK;
 }
 
+// Events of a multi-part search: begin before the first search kernel, end
+// after the last one, rescore-end after the last rescore.
+int enqueue_parts(sw_db_t db, const std::vector<Part>& parts, const std::vector<uint8_t*>& blobs,
+                  const uint8_t* queries, const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt,
+                  void* ws, int32_t* scores, hipStream_t stream)
+{
+    for (size_t g = 0; g < parts.size(); ++g) {
+        const bool first = g == 0, last = g + 1 == parts.size();
+        const int rc = enqueue_search(db, parts[g].L, blobs[g], queries, sm, go, ge,
+                                      first && opt ? opt->ev_search_begin : nullptr,
+                                      last && opt ? opt->ev_search_end : nullptr,
+                                      last && opt ? opt->ev_rescore_end : nullptr, ws, scores, stream);
+        if (rc) return rc;
+    }
+    return SW_OK;
+}
+
 int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, const int32_t* q_lens,
               int32_t nq, const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt,
               void* ws, size_t ws_bytes, int32_t* scores, hipStream_t stream)
 {
-    Layout L;
+    std::vector<Part> parts;
     bool nothing = false;
-    int rc = plan_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, L, nothing);
+    int rc = plan_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, parts, nothing);
     if (rc || nothing) return rc;
-    Staging* st = nullptr;
-    uint8_t* h = static_cast<uint8_t*>(acquire_staging(db, L.blob, &st));
-    if (!h) return fail(SW_ENOMEM, "pinned staging allocation failed");
-    fill_blob(L, q_offsets, h);
-    rc = enqueue_search(db, L, h, queries, sm, go, ge, opt, ws, scores, stream);
-    // the staging buffer is reusable once the stream has passed this point
-    const hipError_t e = hipEventRecord(st->ev, stream);
+    std::vector<Staging*> st(parts.size(), nullptr);
+    std::vector<uint8_t*> blobs(parts.size(), nullptr);
+    for (size_t g = 0; g < parts.size(); ++g) {
+        blobs[g] = static_cast<uint8_t*>(acquire_staging(db, parts[g].L.blob, &st[g]));
+        if (!blobs[g]) {
+            std::lock_guard<std::mutex> lk(db->mu);
+            for (size_t k = 0; k < g; ++k) st[k]->pending = false;
+            return fail(SW_ENOMEM, "pinned staging allocation failed");
+        }
+        fill_blob(parts[g].L, parts[g].offs.data(), blobs[g]);
+    }
+    rc = enqueue_parts(db, parts, blobs, queries, sm, go, ge, opt, ws, scores, stream);
+    // the staging buffers are reusable once the stream has passed this point
+    hipError_t e = hipSuccess;
+    for (size_t g = 0; g < parts.size() && e == hipSuccess; ++g)
+        e = hipEventRecord(st[g]->ev, stream);
     if (rc || e != hipSuccess) {
         (void)hipStreamSynchronize(stream);
         std::lock_guard<std::mutex> lk(db->mu);
-        st->pending = false;
+        for (Staging* x : st) x->pending = false;
         if (!rc) rc = fail(SW_EHIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
     }
     return rc;
@@ -736,19 +837,21 @@ int64_t sw_plan_items(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_op
     std::string why;
     if (!validate_options(opt, why)) return fail(SW_EINVAL, why);
     if (cap > 0 && !out) return fail(SW_EINVAL, "null output");
-    Layout L;
-    rc = make_layout(db, nq, q_lens, resolve(db, opt, 2), L);
+    std::vector<Part> parts;
+    rc = build_parts(db, nq, q_lens, nullptr, opt, 2, parts);
     if (rc) return rc;
     int64_t pos = 0;
-    for (int32_t k : L.order) {
-        for (const Item& it : L.plans[k]->items) {
-            if (pos < cap) {
-                out[4 * pos + 0] = it.s0;
-                out[4 * pos + 1] = it.ncols;
-                out[4 * pos + 2] = k;
-                out[4 * pos + 3] = it.meta;
+    for (const Part& P : parts) {
+        for (int32_t k : P.L.order) {
+            for (const Item& it : P.L.plans[k]->items) {
+                if (pos < cap) {
+                    out[4 * pos + 0] = it.s0;
+                    out[4 * pos + 1] = it.ncols;
+                    out[4 * pos + 2] = P.idx[k];
+                    out[4 * pos + 3] = it.meta;
+                }
+                ++pos;
             }
-            ++pos;
         }
     }
     return pos;
@@ -783,9 +886,9 @@ size_t sw_workspace_bytes(sw_db_t db, int32_t nq, const int32_t* q_lens, const s
     if (validate_query_set(db, nq, q_lens)) return 0;
     std::string why;
     if (!validate_options(opt, why)) { fail(SW_EINVAL, why); return 0; }
-    Layout L;
-    if (make_layout(db, nq, q_lens, resolve(db, opt, 2), L)) return 0;
-    return L.total;
+    std::vector<Part> parts;
+    if (build_parts(db, nq, q_lens, nullptr, opt, 2, parts)) return 0;
+    return std::max<size_t>(parts_bytes(parts), 256);
 }
 
 int sw_plan_info(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt, sw_plan_stats* out)
@@ -795,18 +898,24 @@ int sw_plan_info(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options
     if (!out) return fail(SW_EINVAL, "null output");
     std::string why;
     if (!validate_options(opt, why)) return fail(SW_EINVAL, why);
-    Layout L;
-    rc = make_layout(db, nq, q_lens, resolve(db, opt, 2), L);
+    std::vector<Part> parts;
+    rc = build_parts(db, nq, q_lens, nullptr, opt, 2, parts);
     if (rc) return rc;
-    out->cells = L.cells;
-    out->lane_cells = L.lane_cells;
-    out->items = L.nitems;
-    out->wg_items = L.n_wg;
-    out->grid = L.grid;
-    out->slot_bytes = L.slot_elems * (int64_t)sizeof(int2);
-    out->workspace = (int64_t)L.total;
-    out->variant = (int32_t)L.r.v;
-    out->rows = L.r.rows;
+    *out = sw_plan_stats{};
+    for (const Part& P : parts) {
+        const Layout& L = P.L;
+        out->cells += L.cells;
+        out->lane_cells += L.lane_cells;
+        out->items += L.nitems;
+        out->wg_items += L.n_wg;
+        out->grid = std::max<int64_t>(out->grid, L.grid);
+        out->slot_bytes = std::max<int64_t>(out->slot_bytes, L.slot_elems * (int64_t)sizeof(int2));
+    }
+    out->workspace = (int64_t)std::max<size_t>(parts_bytes(parts), 256);
+    if (!parts.empty()) {
+        out->variant = (int32_t)parts[0].L.r.v;
+        out->rows = parts[0].L.r.rows;
+    }
     return SW_OK;
 }
 
@@ -826,11 +935,152 @@ int sw_db_search_batch(sw_db_t db, const uint8_t* queries, const int64_t* q_offs
     return do_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, stream);
 }
 
+int sw_tune_set(sw_db_t db, const sw_tune_entry* entries, int32_t n)
+{
+    if (!db) return fail(SW_EINVAL, "null database handle");
+    if (n < 0 || (n > 0 && !entries)) return fail(SW_EINVAL, "bad tune table");
+    std::vector<sw_tune_entry> t(entries, entries + n);
+    for (auto& e : t) {
+        std::string why;
+        if (e.qlen < 0 || !validate_options(&e.opt, why) || e.opt.mode == SW_MODE_TUNED)
+            return fail(SW_EINVAL, "bad tune entry");
+        e.opt.ev_search_begin = e.opt.ev_search_end = e.opt.ev_rescore_end = nullptr;
+    }
+    std::stable_sort(t.begin(), t.end(), [](const sw_tune_entry& a, const sw_tune_entry& b) {
+        return a.qlen < b.qlen;
+    });
+    std::lock_guard<std::mutex> lk(db->mu);
+    db->tune = std::move(t);
+    return SW_OK;
+}
+
+int32_t sw_tune_get(sw_db_t db, sw_tune_entry* out, int32_t cap)
+{
+    if (!db) return fail(SW_EINVAL, "null database handle");
+    std::lock_guard<std::mutex> lk(db->mu);
+    const int32_t n = (int32_t)db->tune.size();
+    for (int32_t k = 0; k < n && k < cap && out; ++k)
+        out[k] = db->tune[k];
+    return n;
+}
+
+int sw_autotune(sw_db_t db, const int32_t* qlens, int32_t nbins, const int32_t* sm, int32_t go, int32_t ge,
+                hipStream_t stream, sw_tune_entry* out)
+{
+    if (!db) return fail(SW_EINVAL, "null database handle");
+    if (db->host_only) return fail(SW_EINVAL, "planning-only handle cannot search");
+    if (nbins <= 0 || !qlens || !out || !sm) return fail(SW_EINVAL, "bad autotune arguments");
+    std::string why;
+    if (!matrix_elem(sm, go, why)) return fail(SW_EINVAL, why);
+    if (go < 0 || ge < 0 || go > SW_MAX_GAP || ge > SW_MAX_GAP) return fail(SW_EINVAL, "gap penalties");
+    int32_t maxm = 0;
+    for (int32_t b = 0; b < nbins; ++b) {
+        if (qlens[b] < 1 || qlens[b] > SW_MAX_QLEN) return fail(SW_EINVAL, "tune length out of range");
+        maxm = std::max(maxm, qlens[b]);
+    }
+    if (db->nseq == 0) return fail(SW_EINVAL, "empty database");
+
+    // residue composition of the database: a sample of its stored codes
+    std::vector<uint8_t> sample((size_t)std::min<int64_t>(db->res_bytes, 1 << 20));
+    HIPCHK(hipMemcpyAsync(sample.data(), db->d_res, sample.size(), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    std::vector<uint8_t> codes;
+    for (uint8_t c : sample)
+        if (c < kAlpha) codes.push_back(c);
+    if (codes.empty()) codes.push_back(0);
+
+    struct Cand { int32_t mode, waves, lane_cells; };
+    const Cand cands[] = {
+        {SW_MODE_I16, 4, 49152}, {SW_MODE_I16, 4, 98304}, {SW_MODE_I16, 4, 196608}, {SW_MODE_I16, 8, 98304},
+        {SW_MODE_I32, 4, 49152}, {SW_MODE_I32, 4, 98304}, {SW_MODE_I32, 4, 196608}, {SW_MODE_I32, 8, 98304},
+    };
+    size_t ws_need = 0;
+    for (int32_t b = 0; b < nbins; ++b)
+        for (const Cand& c : cands) {
+            sw_options o{};
+            o.mode = c.mode;
+            o.waves = c.waves;
+            o.lane_cells = c.lane_cells;
+            ws_need = std::max(ws_need, sw_workspace_bytes(db, 1, &qlens[b], &o));
+        }
+    uint8_t* d_q = nullptr;
+    void* d_ws = nullptr;
+    int32_t* d_sc = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::vector<uint8_t> hq(maxm);
+    int rc = SW_OK;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(d_q);
+        (void)hipFree(d_ws);
+        (void)hipFree(d_sc);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+#define TCHK(x)                                                                               \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess) {                                                               \
+            cleanup();                                                                        \
+            return fail(SW_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));             \
+        }                                                                                     \
+    } while (0)
+    TCHK(hipMalloc(&d_q, std::max<int32_t>(maxm, 1)));
+    TCHK(hipMalloc(&d_ws, std::max<size_t>(ws_need, 256)));
+    TCHK(hipMalloc(&d_sc, sizeof(int32_t) * db->nseq));
+    TCHK(hipEventCreate(&ev[0]));
+    TCHK(hipEventCreate(&ev[1]));
+    uint64_t x = 0x9E3779B97F4A7C15ull;              // xorshift64* draws of sample positions
+    std::vector<sw_tune_entry> res(nbins);
+    for (int32_t b = 0; b < nbins && rc == SW_OK; ++b) {
+        const int32_t m = qlens[b];
+        for (int32_t i = 0; i < m; ++i) {
+            x ^= x >> 12; x ^= x << 25; x ^= x >> 27;
+            hq[i] = codes[(size_t)((x * 0x2545F4914F6CDD1Dull) >> 33) % codes.size()];
+        }
+        TCHK(hipMemcpyAsync(d_q, hq.data(), m, hipMemcpyHostToDevice, stream));
+        TCHK(hipStreamSynchronize(stream));          // hq is reused for the next bin
+        float best = -1;
+        sw_tune_entry be{};
+        for (const Cand& c : cands) {
+            sw_options o{};
+            o.mode = c.mode;
+            o.waves = c.waves;
+            o.lane_cells = c.lane_cells;
+            float tmin = -1;
+            for (int rep = 0; rep < 3 && rc == SW_OK; ++rep) {     // first run warms the plan cache
+                TCHK(hipEventRecord(ev[0], stream));
+                rc = sw_db_search_ex(db, d_q, m, sm, go, ge, &o, d_ws, ws_need, d_sc, stream);
+                TCHK(hipEventRecord(ev[1], stream));
+                TCHK(hipEventSynchronize(ev[1]));
+                float ms = 0;
+                TCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                if (rep > 0 && (tmin < 0 || ms < tmin)) tmin = ms;
+            }
+            if (rc) break;
+            if (best < 0 || tmin < best) {
+                best = tmin;
+                be.qlen = m;
+                be.opt = o;
+                be.gcups = (double)m * (double)db->total / (tmin * 1e-3) / 1e9;
+            }
+        }
+        res[b] = be;
+    }
+#undef TCHK
+    const std::string err = g_err;
+    cleanup();
+    if (rc) return fail(rc, "autotune search: " + err);
+    for (int32_t b = 0; b < nbins; ++b)
+        out[b] = res[b];
+    return sw_tune_set(db, res.data(), nbins);
+}
+
 }  // extern "C"
 
 struct sw_graph_s {
     sw_db_t db = nullptr;
-    void* blob = nullptr;
+    std::vector<void*> blobs;     // pinned plan copies, one per launch group
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -843,7 +1093,7 @@ void free_graph(sw_graph_s* g)
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->cap) (void)hipStreamDestroy(g->cap);
-    if (g->blob) (void)hipHostFree(g->blob);
+    for (void* b : g->blobs) (void)hipHostFree(b);
     delete g;
 }
 }  // namespace
@@ -856,13 +1106,10 @@ int sw_graph_create(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets
 {
     if (!out) return fail(SW_EINVAL, "null output graph");
     *out = nullptr;
-    Layout L;
+    std::vector<Part> parts;
     bool nothing = false;
-    int rc = plan_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, L, nothing);
+    int rc = plan_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, parts, nothing);
     if (rc) return rc;
-    sw_options o{};
-    if (opt) o = *opt;
-    o.ev_search_begin = o.ev_search_end = o.ev_rescore_end = nullptr;
     auto* g = new sw_graph_s();
     g->db = db;
     auto bail = [&](int code, const std::string& msg) {
@@ -871,15 +1118,19 @@ int sw_graph_create(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets
     };
     hipError_t e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return bail(SW_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
-    if (!nothing) {
-        e = hipHostMalloc(&g->blob, std::max<size_t>(L.blob, 16), hipHostMallocDefault);
+    std::vector<uint8_t*> blobs;
+    for (const Part& P : parts) {
+        void* b = nullptr;
+        e = hipHostMalloc(&b, std::max<size_t>(P.L.blob, 16), hipHostMallocDefault);
         if (e != hipSuccess) return bail(SW_ENOMEM, "pinned plan allocation failed");
-        fill_blob(L, q_offsets, static_cast<uint8_t*>(g->blob));
+        g->blobs.push_back(b);
+        fill_blob(P.L, P.offs.data(), static_cast<uint8_t*>(b));
+        blobs.push_back(static_cast<uint8_t*>(b));
     }
     e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bail(SW_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     if (!nothing)
-        rc = enqueue_search(db, L, static_cast<uint8_t*>(g->blob), queries, sm, go, ge, &o, ws, scores, g->cap);
+        rc = enqueue_parts(db, parts, blobs, queries, sm, go, ge, nullptr, ws, scores, g->cap);
     const std::string err = g_err;
     e = hipStreamEndCapture(g->cap, &g->graph);
     if (rc) return bail(rc, "capture: " + err);

@@ -102,3 +102,30 @@ def test_describe_rejects_bad_input():
     db = swdb.Database.describe(np.array([], dtype=np.int32))
     assert db.workspace_bytes([10]) > 0
     db.release()
+
+
+def test_tuned_mode_splits_batch_by_schedule():
+    db = swdb.Database.describe(_lengths("ragged"))
+    try:
+        db.set_tuning([{"qlen": 300, "mode": swdb.MODE_I32, "lane_cells": 49152},
+                       {"qlen": 100000, "mode": swdb.MODE_I16, "waves": 8}])
+        t = db.get_tuning()
+        assert [e["qlen"] for e in t] == [300, 100000] and t[0]["mode"] == swdb.MODE_I32
+        qlens = [144, 2500, 17, 600, 333]
+        tuned = swdb.options(mode="tuned")
+        items = db.plan_items(qlens, tuned)
+        # every query covered once; the short queries (int32, one subject per lane)
+        # and the long ones (two per lane) come from different launch groups
+        per_q = {q: 0 for q in range(len(qlens))}
+        for s0, ncols, q, meta in items:
+            per_q[int(q)] += meta & 0xFFFF
+        assert all(v == db.nseq for v in per_q.values())
+        ws = db.workspace_bytes(qlens, tuned)
+        assert ws == max(db.workspace_bytes([144, 17], swdb.options(mode="i32", lane_cells=49152)),
+                         db.workspace_bytes([2500, 600, 333], swdb.options(mode="i16", waves=8)))
+        db.set_tuning([])
+        assert db.get_tuning() == []
+        with pytest.raises(swdb.SwdbError):
+            db.set_tuning([{"qlen": 10, "mode": swdb.MODE_TUNED}])
+    finally:
+        db.release()
