@@ -418,6 +418,20 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
 
 // ------------------------------------------------------------------ persistent kernels
 
+// Defence against a work item inconsistent with the launch: every index the
+// item functions derive (subjects, slot entries) stays inside its buffer.
+template <bool I16>
+__device__ __forceinline__ bool item_fits(const SearchArgs& a, const Item& it, const QueryDesc& qd)
+{
+    const int nsub = it.meta & 0xffff;
+    const int K = it.meta >> 16;
+    if (nsub <= 0 || K < 1 || K > kWave || it.s0 < 0 || it.ncols < 0)
+        return false;
+    if (nsub > (kWave / K) * (I16 ? 2 : 1) || (int64_t)it.s0 + nsub > a.nseq)
+        return false;
+    return qd.nbr <= K || (int64_t)it.ncols * (kWave / K) <= a.slot_elems;
+}
+
 // Copy one query's profile into LDS (all threads of the workgroup).
 __device__ __forceinline__ void stage_profile(const SearchArgs& a, const QueryDesc& qd)
 {
@@ -451,14 +465,18 @@ k_search(SearchArgs a)
             break;
         const Item it = a.items[(int64_t)wi * W + wave];
         const int q = a.items[(int64_t)wi * W].q;
+        if (q < 0 || q >= a.nq) {                 // uniform: a malformed queue entry is skipped
+            __syncthreads();
+            continue;
+        }
         const QueryDesc qd = a.qd[q];
         if (qd.lds && q != cur_q) {
             stage_profile(a, qd);
             __syncthreads();
             cur_q = q;
         }
-        if ((it.meta & 0xffff) != 0) {
-            const bool multi = (it.meta >> 16) != 0;
+        if (item_fits<I16>(a, it, qd) && it.q == q) {
+            const bool multi = (it.meta >> 16) > 1;     // lanes per subject
             if constexpr (I16) {
                 if (qd.lds) {
                     if (multi) item_i16<R, true, true>(a, it, qd, slot, lane);
@@ -497,6 +515,9 @@ k_rescore(SearchArgs a)
     const int cnt = min(a.counters[1], a.flag_cap);
     for (int f = gw; f < cnt; f += nw) {
         const int2 e = a.flags[f];
+        if (e.x < 0 || e.x >= a.nq || e.y < 0 || e.y >= a.nseq ||
+            (int64_t)((a.slen[e.y] + 15) & ~15) > a.slot_elems)
+            continue;
         Item it;
         it.s0 = e.y;
         it.q = e.x;

@@ -57,11 +57,15 @@ constexpr int kMaxWavesPerCU = 16;      // 4 per SIMD: kernels are built for <= 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 int64_t align_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+// Pinned host buffer for one plan upload.  States: free; held (handed to a
+// call that has not yet recorded its completion event -- never reclaimable);
+// in flight (event recorded after the upload; reclaimable once it completes).
 struct Staging {
+    enum State { kFree, kHeld, kInFlight };
     void* host = nullptr;
     size_t cap = 0;
     hipEvent_t ev = nullptr;
-    bool pending = false;
+    State state = kFree;
 };
 
 struct PlanKey {
@@ -405,10 +409,10 @@ void* acquire_staging(sw_db_s* db, size_t bytes, Staging** out)
 {
     std::lock_guard<std::mutex> lk(db->mu);
     for (auto& st : db->staging) {
-        if (st.pending && hipEventQuery(st.ev) == hipSuccess)
-            st.pending = false;
-        if (!st.pending && st.cap >= bytes) {
-            st.pending = true;
+        if (st.state == Staging::kInFlight && hipEventQuery(st.ev) == hipSuccess)
+            st.state = Staging::kFree;
+        if (st.state == Staging::kFree && st.cap >= bytes) {
+            st.state = Staging::kHeld;
             *out = &st;
             return st.host;
         }
@@ -421,7 +425,7 @@ void* acquire_staging(sw_db_s* db, size_t bytes, Staging** out)
         (void)hipHostFree(st.host);
         return nullptr;
     }
-    st.pending = true;
+    st.state = Staging::kHeld;
     db->staging.push_back(st);
     *out = &db->staging.back();
     return st.host;
@@ -643,7 +647,7 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
         blobs[g] = static_cast<uint8_t*>(acquire_staging(db, parts[g].L.blob, &st[g]));
         if (!blobs[g]) {
             std::lock_guard<std::mutex> lk(db->mu);
-            for (size_t k = 0; k < g; ++k) st[k]->pending = false;
+            for (size_t k = 0; k < g; ++k) st[k]->state = Staging::kFree;
             return fail(SW_ENOMEM, "pinned staging allocation failed");
         }
         fill_blob(parts[g].L, parts[g].offs.data(), blobs[g]);
@@ -656,10 +660,13 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
     if (rc || e != hipSuccess) {
         (void)hipStreamSynchronize(stream);
         std::lock_guard<std::mutex> lk(db->mu);
-        for (Staging* x : st) x->pending = false;
+        for (Staging* x : st) x->state = Staging::kFree;
         if (!rc) rc = fail(SW_EHIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
+        return rc;
     }
-    return rc;
+    std::lock_guard<std::mutex> lk(db->mu);
+    for (Staging* x : st) x->state = Staging::kInFlight;
+    return SW_OK;
 }
 
 void free_db(sw_db_s* db)
