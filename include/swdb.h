@@ -163,7 +163,8 @@ int sw_plan_info(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options
 /*
  * The work queue a search would run, in queue order: for each wavefront item
  * four int32 (first sorted subject, columns swept, query index, subjects |
- * lanes-per-subject << 16), `waves` items per workgroup item.  Writes at most
+ * lanes-per-subject << 16 | critical-path flag << 24), `waves` items per
+ * workgroup item.  Writes at most
  * `cap` items to `out` (HOST) and returns the total count, or a negative code.
  */
 int64_t sw_plan_items(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt,

@@ -133,7 +133,7 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
     constexpr int NV = R * ES / 16;
 
     const int nsub = it.meta & 0xffff;
-    const int K = MULTI ? (it.meta >> 16) : 1;          // lanes per subject, 1..64
+    const int K = MULTI ? ((it.meta >> 16) & 0xff) : 1; // lanes per subject, 1..64
     const int nsubw = MULTI ? kWave / K : kWave;        // lane groups in the wavefront
     const int sub = MULTI ? lane / K : lane;
     const int g = lane - sub * K;
@@ -262,7 +262,7 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
     constexpr int NV = R * 2 / 16;
 
     const int nsub = it.meta & 0xffff;
-    const int K = MULTI ? (it.meta >> 16) : 1;
+    const int K = MULTI ? ((it.meta >> 16) & 0xff) : 1;
     const int nsubw = MULTI ? kWave / K : kWave;
     const int sub = MULTI ? lane / K : lane;
     const int g = lane - sub * K;
@@ -424,7 +424,7 @@ template <bool I16>
 __device__ __forceinline__ bool item_fits(const SearchArgs& a, const Item& it, const QueryDesc& qd)
 {
     const int nsub = it.meta & 0xffff;
-    const int K = it.meta >> 16;
+    const int K = (it.meta >> 16) & 0xff;
     if (nsub <= 0 || K < 1 || K > kWave || it.s0 < 0 || it.ncols < 0)
         return false;
     if (nsub > (kWave / K) * (I16 ? 2 : 1) || (int64_t)it.s0 + nsub > a.nseq)
@@ -442,10 +442,47 @@ __device__ __forceinline__ void stage_profile(const SearchArgs& a, const QueryDe
         dst[i] = src[i];
 }
 
-// Work queue: workgroup items are taken in order from counters[0] until the
-// queue is exhausted (every wavefront leaves through the same test).  The
-// wavefront items of one workgroup item belong to one query, whose profile is
-// staged in LDS when the query changes.
+// One work item with the variant its lane groups and profile location need.
+// Items on the critical path (far more per-lane work than the planner's
+// target: the longest subjects) raise their wavefront's issue priority so the
+// waves sharing the SIMD do not stretch them.
+template <int R, int ES, bool I16>
+__device__ __forceinline__ void run_item(const SearchArgs& a, const Item& it, const QueryDesc& qd,
+                                         int2* __restrict__ slot, int lane)
+{
+    const bool multi = ((it.meta >> 16) & 0xff) > 1;
+    const bool crit = (it.meta >> 24) & 1;
+    if (crit)
+        __builtin_amdgcn_s_setprio(2);
+    if constexpr (I16) {
+        if (qd.lds) {
+            if (multi) item_i16<R, true, true>(a, it, qd, slot, lane);
+            else item_i16<R, true, false>(a, it, qd, slot, lane);
+        } else {
+            if (multi) item_i16<R, false, true>(a, it, qd, slot, lane);
+            else item_i16<R, false, false>(a, it, qd, slot, lane);
+        }
+    } else {
+        if (qd.lds) {
+            if (multi) item_i32<R, ES, true, true>(a, it, qd, slot, lane);
+            else item_i32<R, ES, true, false>(a, it, qd, slot, lane);
+        } else {
+            if (multi) item_i32<R, ES, false, true>(a, it, qd, slot, lane);
+            else item_i32<R, ES, false, false>(a, it, qd, slot, lane);
+        }
+    }
+    if (crit)
+        __builtin_amdgcn_s_setprio(0);
+}
+
+// Work queue, taken in order from counters[0] until exhausted (every wavefront
+// leaves through the same test).
+//  * One query: its profile is staged in LDS once per workgroup, then every
+//    wavefront takes wavefront items on its own -- no barriers, so waves of a
+//    workgroup never wait for each other.
+//  * Several queries: workgroups take workgroup items (the `waves` wavefront
+//    items of one query); the profile is restaged when the query changes, with
+//    barriers around it.
 template <int R, int ES, bool I16>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_search(SearchArgs a)
@@ -455,6 +492,25 @@ k_search(SearchArgs a)
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     int2* __restrict__ slot = a.bnd + (int64_t)(blockIdx.x * W + wave) * a.slot_elems;
+    if (a.nq == 1) {
+        const QueryDesc qd = a.qd[0];
+        if (qd.lds)
+            stage_profile(a, qd);
+        __syncthreads();
+        const int64_t nitems = (int64_t)a.n_wg * W;
+        for (;;) {
+            int wi = 0;
+            if (lane == 0)
+                wi = atomicAdd(&a.counters[0], 1);
+            wi = __builtin_amdgcn_readfirstlane(wi);
+            if (wi >= nitems)
+                break;
+            const Item it = a.items[wi];
+            if (it.q == 0 && item_fits<I16>(a, it, qd))
+                run_item<R, ES, I16>(a, it, qd, slot, lane);
+        }
+        return;
+    }
     int cur_q = -1;
     for (;;) {
         if (threadIdx.x == 0)
@@ -475,26 +531,8 @@ k_search(SearchArgs a)
             __syncthreads();
             cur_q = q;
         }
-        if (item_fits<I16>(a, it, qd) && it.q == q) {
-            const bool multi = (it.meta >> 16) > 1;     // lanes per subject
-            if constexpr (I16) {
-                if (qd.lds) {
-                    if (multi) item_i16<R, true, true>(a, it, qd, slot, lane);
-                    else item_i16<R, true, false>(a, it, qd, slot, lane);
-                } else {
-                    if (multi) item_i16<R, false, true>(a, it, qd, slot, lane);
-                    else item_i16<R, false, false>(a, it, qd, slot, lane);
-                }
-            } else {
-                if (qd.lds) {
-                    if (multi) item_i32<R, ES, true, true>(a, it, qd, slot, lane);
-                    else item_i32<R, ES, true, false>(a, it, qd, slot, lane);
-                } else {
-                    if (multi) item_i32<R, ES, false, true>(a, it, qd, slot, lane);
-                    else item_i32<R, ES, false, false>(a, it, qd, slot, lane);
-                }
-            }
-        }
+        if (item_fits<I16>(a, it, qd) && it.q == q)
+            run_item<R, ES, I16>(a, it, qd, slot, lane);
         __syncthreads();    // LDS profile and s_wi are reused by the next item
     }
 }

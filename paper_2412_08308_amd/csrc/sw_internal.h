@@ -20,8 +20,9 @@ constexpr int kCodes = 33;           // + internal pad code
 constexpr uint8_t kPad = 32;         // pad code: subject tails and chunk fill
 constexpr int kWave = 64;
 
-// Work item (one wavefront).  meta = nsub | K << 16 (K = lanes per subject,
-// 1..64; floor(64 / K) lane groups per wavefront).
+// Work item (one wavefront).  meta = nsub | K << 16 | critical << 24 (K =
+// lanes per subject, 1..64, floor(64 / K) lane groups per wavefront; critical
+// marks items whose per-lane work is far above the planner's target).
 struct Item {
     int32_t s0;      // first sorted subject index
     int32_t ncols;   // columns to sweep: longest subject of the item, rounded up to 16

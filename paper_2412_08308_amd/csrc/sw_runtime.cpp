@@ -231,8 +231,9 @@ std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, con
         it.s0 = (int32_t)s;
         it.ncols = (int32_t)align_up(n, 16);
         it.q = 0;
-        it.meta = (int32_t)take | (K << 16);
         const int64_t lw = lane_work(n, K, nbr, r.rows);
+        // bit 24: critical-path item (per-lane work well above the target)
+        it.meta = (int32_t)take | (K << 16) | ((lw >= 2 * r.target) ? (1 << 24) : 0);
         wis.push_back({it, lw});
         p->lane_cells += lw * kWave;
         if (nbr > K)

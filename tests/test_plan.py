@@ -35,7 +35,7 @@ def check_plan(db, qlens, opt, spl):
         assert len(qs) <= 1, "a workgroup item mixes queries"
     slot_need = 0
     for s0, ncols, q, meta in items:
-        nsub, K = meta & 0xFFFF, meta >> 16
+        nsub, K = meta & 0xFFFF, (meta >> 16) & 0xFF
         if nsub == 0:
             continue
         assert 1 <= K <= 64
