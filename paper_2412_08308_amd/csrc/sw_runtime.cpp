@@ -47,8 +47,13 @@ int fail(int code, const std::string& msg)
             return fail(SW_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));         \
     } while (0)
 
-constexpr int kDefaultWaves = 4;
-constexpr int64_t kDefaultLaneCells = 96 * 1024;
+// Defaults measured on MI355X (config 1 and the 20-query batch): one query
+// runs barrier-free per-wavefront pulls, where 8-wavefront workgroups share one
+// LDS profile; batches use 4-wavefront workgroup items.
+constexpr int kDefaultWavesSingle = 8;
+constexpr int kDefaultWavesBatch = 4;
+constexpr int64_t kDefaultLaneCellsSingle = 48 * 1024;
+constexpr int64_t kDefaultLaneCellsBatch = 96 * 1024;
 constexpr int kDefaultLdsLimit = 64 * 1024;
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kRescoreWaves = 4;      // workgroup size of the rescore kernel
@@ -138,7 +143,7 @@ bool validate_options(const sw_options* opt, std::string& why)
     return true;
 }
 
-Resolved resolve(const sw_db_s* db, const sw_options* opt, int elem_i32)
+Resolved resolve(const sw_db_s* db, const sw_options* opt, int elem_i32, int32_t nq)
 {
     Resolved r{};
     const int mode = opt ? opt->mode : SW_MODE_AUTO;
@@ -152,9 +157,11 @@ Resolved resolve(const sw_db_s* db, const sw_options* opt, int elem_i32)
     r.rows = li.rows;
     r.elem = li.prof_elem;
     r.spl = li.subjects_per_lane;
-    r.waves = (opt && opt->waves) ? opt->waves : kDefaultWaves;
+    const bool single = nq == 1;
+    r.waves = (opt && opt->waves) ? opt->waves : (single ? kDefaultWavesSingle : kDefaultWavesBatch);
     r.kmax = (opt && opt->max_lanes) ? opt->max_lanes : 64;
-    r.target = (opt && opt->lane_cells) ? opt->lane_cells : kDefaultLaneCells;
+    r.target = (opt && opt->lane_cells) ? opt->lane_cells
+                                        : (single ? kDefaultLaneCellsSingle : kDefaultLaneCellsBatch);
     r.lds_limit = (opt && opt->lds_limit) ? opt->lds_limit : kDefaultLdsLimit;
     r.lds_limit = std::min(r.lds_limit, db->lds_max - 1024);
     r.grid_limit = opt ? opt->grid_limit : 0;
@@ -487,7 +494,8 @@ int build_parts(sw_db_s* db, int32_t nq, const int32_t* q_lens, const int64_t* q
     }
     for (size_t g = 0; g < parts.size(); ++g) {
         Part& P = parts[g];
-        const int rc = make_layout(db, (int32_t)P.idx.size(), P.lens.data(), resolve(db, &gopt[g], elem), P.L);
+        const int32_t n = (int32_t)P.idx.size();
+        const int rc = make_layout(db, n, P.lens.data(), resolve(db, &gopt[g], elem, n), P.L);
         if (rc) return rc;
         for (size_t k = 0; k < P.idx.size(); ++k)
             P.L.qd[k].out_row = P.idx[k];
@@ -998,10 +1006,11 @@ int sw_autotune(sw_db_t db, const int32_t* qlens, int32_t nbins, const int32_t* 
     if (codes.empty()) codes.push_back(0);
 
     struct Cand { int32_t mode, waves, lane_cells; };
-    const Cand cands[] = {
-        {SW_MODE_I16, 4, 49152}, {SW_MODE_I16, 4, 98304}, {SW_MODE_I16, 4, 196608}, {SW_MODE_I16, 8, 98304},
-        {SW_MODE_I32, 4, 49152}, {SW_MODE_I32, 4, 98304}, {SW_MODE_I32, 4, 196608}, {SW_MODE_I32, 8, 98304},
-    };
+    std::vector<Cand> cands;
+    for (int32_t mode : {SW_MODE_I16, SW_MODE_I32})
+        for (int32_t waves : {4, 8})
+            for (int32_t lc : {24576, 49152, 98304, 196608})
+                cands.push_back({mode, waves, lc});
     size_t ws_need = 0;
     for (int32_t b = 0; b < nbins; ++b)
         for (const Cand& c : cands) {
