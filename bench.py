@@ -69,6 +69,38 @@ def isa_counts():
 
 
 KNOBS = {}
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_search_q567_vs_200k.json")
+
+
+def kernel_fingerprint() -> str:
+    """Hash of the sources that decide what the search kernel reads and writes
+    (kernels, plan, layout); stored counter readings are used only while it
+    matches."""
+    import hashlib
+    h = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_2412_08308_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip", ".cpp")) and f != "sw_isa_probe.hip":
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(mode: str):
+    """HBM bytes per search-kernel launch from the committed FETCH_SIZE /
+    WRITE_SIZE readings, each scaled by the same counter's reading for a
+    device-to-device copy of known size; None if absent or stale."""
+    if not os.path.exists(TRAFFIC):
+        return None
+    with open(TRAFFIC) as fh:
+        t = json.load(fh)
+    e = t.get("modes", {}).get(mode)
+    if not e or t.get("fingerprint") != kernel_fingerprint() or KNOBS.get("lane_cells") or KNOBS.get("waves"):
+        return None
+    c = t["copy"]
+    fetch = e["fetch_kib"] * c["bytes"] / c["fetch_kib"]
+    write = e["write_kib"] * c["bytes"] / c["write_kib"]
+    return {"bytes": int(fetch + write), "fetch_bytes": int(fetch), "write_bytes": int(write)}
 
 
 def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False):
@@ -305,6 +337,7 @@ def main(argv=None):
     # the int32 kernels take 8-bit profile entries when every score + Go fits
     p8 = int(w.matrix.max()) + w.gap_open <= 127 and int(w.matrix.min()) + w.gap_open >= -128
     i32_isa = "i32_p8_lds_k1" if p8 else "i32_p16_lds_k1"
+    traffic = traffic_bytes(args.mode)
     variant = main_run["plan"]["variant"]
     key = "i16_lds_k1" if variant == 2 else i32_isa
     ops = isa[key]["valu_per_cell"]
@@ -349,7 +382,11 @@ def main(argv=None):
                                f"(sum {w.db.total} residues), BLOSUM62-style, gaps 10/2",
                    "mode": args.mode, "cells": cells},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 3),
-                     "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": None,
+                     "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
+                     "traffic": (None if traffic is None else traffic["bytes"]),
+                     "traffic_detail": traffic,
+                     "algorithmic_bytes": int(w.db.total + len(w.queries[0]) + 4 * w.db.nseq),
+                     "kernel_fingerprint": kernel_fingerprint(),
                      "kernel": "k_search<16,2,true> (packed 16-bit lanes)" if variant == 2
                      else ("k_search<32,1,false> (int32 lanes)" if p8 else "k_search<32,2,false> (int32 lanes)"),
                      "isa_valu_per_cell": ops, "search_kernel_ms": round(main_run["kernel_ms"], 3),
