@@ -387,7 +387,7 @@ def main(argv=None):
                      "traffic_detail": traffic,
                      "algorithmic_bytes": int(w.db.total + len(w.queries[0]) + 4 * w.db.nseq),
                      "kernel_fingerprint": kernel_fingerprint(),
-                     "kernel": "k_search<16,2,true> (packed 16-bit lanes)" if variant == 2
+                     "kernel": "k_search<24,2,true> (packed 16-bit lanes)" if variant == 2
                      else ("k_search<32,1,false> (int32 lanes)" if p8 else "k_search<32,2,false> (int32 lanes)"),
                      "isa_valu_per_cell": ops, "search_kernel_ms": round(main_run["kernel_ms"], 3),
                      "isa_peak_gcups": round(PEAK_VALU_TOPS * 1e3 / ops, 1),

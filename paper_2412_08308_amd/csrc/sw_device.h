@@ -113,11 +113,13 @@ typedef short v2s __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ v2s as2(uint32_t x) { return __builtin_bit_cast(v2s, x); }
 __device__ __forceinline__ uint32_t asu(v2s x) { return __builtin_bit_cast(uint32_t, x); }
 
-// Slot entry of column `col` for subject slot `sub`: 4 columns of (Y, F) pairs
-// are contiguous per subject slot, so a 4-column group is two 16-byte accesses.
-__device__ __forceinline__ int64_t slot_index(int col, int nsubw, int sub)
+// Slot layout: for each group of 4 columns, each lane group's 4 (Y, F) pairs
+// are contiguous, so a 4-column group is two 16-byte accesses.  Entry of
+// column `col` for lane group `sub`: (col / 4 * nsubw + sub) * 4 + col % 4;
+// slot_col is the part that does not depend on the lane group.
+__device__ __forceinline__ int64_t slot_col(int col, int nsubw)
 {
-    return ((int64_t)(col >> 2) * nsubw + sub) * 4 + (col & 3);
+    return (int64_t)(col >> 2) * nsubw * 4 + (col & 3);
 }
 
 // ------------------------------------------------------------------ int32 item
@@ -151,6 +153,9 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
     const int nsteps = MULTI ? ((ncols + K - 1 + 15) & ~15) : ncols;
     const int go = a.go, ge = a.ge;
     const uint8_t* __restrict__ gprof = a.prof + qd.prof_off;
+    // this lane's slot entries: column c is lslot[slot_col(c, nsubw)] (a
+    // wavefront-uniform offset)
+    int2* __restrict__ lslot = slot + (int64_t)(inb ? sub : 0) * 4;
 
     int S = 0;
     for (int pass = 0; pass < P; ++pass) {
@@ -173,7 +178,7 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
                 rv = make_uint4(rv.y, rv.z, rv.w, 0u);
                 int ringY[4], ringF[4];
                 if (rd && col0 < ncols && inb) {
-                    const int4* p4 = reinterpret_cast<const int4*>(slot + slot_index(col0, nsubw, sub));
+                    const int4* p4 = reinterpret_cast<const int4*>(lslot + slot_col(col0, nsubw));
                     const int4 v0 = p4[0], v1 = p4[1];
                     ringY[0] = v0.x; ringF[0] = v0.y; ringY[1] = v0.z; ringF[1] = v0.w;
                     ringY[2] = v1.x; ringF[2] = v1.y; ringY[3] = v1.z; ringF[3] = v1.w;
@@ -225,12 +230,12 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
                     if constexpr (MULTI) {
                         const int j = col0 + u - (K - 1);
                         if (wr && tail && inb && j >= 0 && j < ncols)
-                            slot[slot_index(j, nsubw, sub)] = make_int2(ybot, fbot);
+                            lslot[slot_col(j, nsubw)] = make_int2(ybot, fbot);
                     }
                 }
                 if constexpr (!MULTI) {
                     if (wr && col0 < ncols) {
-                        int4* p4 = reinterpret_cast<int4*>(slot + slot_index(col0, nsubw, sub));
+                        int4* p4 = reinterpret_cast<int4*>(lslot + slot_col(col0, nsubw));
                         p4[0] = make_int4(wY[0], wF[0], wY[1], wF[1]);
                         p4[1] = make_int4(wY[2], wF[2], wY[3], wF[3]);
                     }
@@ -288,6 +293,7 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
     const uint8_t* __restrict__ gprof = a.prof + qd.prof_off;
     const v2s zero = {0, 0};
     const v2s vge = as2(ge2), vgo = as2(go2);
+    int2* __restrict__ lslot = slot + (int64_t)(inb ? sub : 0) * 4;
 
     v2s S = zero;
     for (int pass = 0; pass < P; ++pass) {
@@ -314,7 +320,7 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
                 rvB = make_uint4(rvB.y, rvB.z, rvB.w, 0u);
                 uint32_t ringY[4], ringF[4];
                 if (rd && col0 < ncols && inb) {
-                    const uint4* p4 = reinterpret_cast<const uint4*>(slot + slot_index(col0, nsubw, sub));
+                    const uint4* p4 = reinterpret_cast<const uint4*>(lslot + slot_col(col0, nsubw));
                     const uint4 v0 = p4[0], v1 = p4[1];
                     ringY[0] = v0.x; ringF[0] = v0.y; ringY[1] = v0.z; ringF[1] = v0.w;
                     ringY[2] = v1.x; ringF[2] = v1.y; ringY[3] = v1.z; ringF[3] = v1.w;
@@ -368,12 +374,12 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
                     if constexpr (MULTI) {
                         const int j = col0 + u - (K - 1);
                         if (wr && tail && inb && j >= 0 && j < ncols)
-                            slot[slot_index(j, nsubw, sub)] = make_int2((int)ybot, (int)fbot);
+                            lslot[slot_col(j, nsubw)] = make_int2((int)ybot, (int)fbot);
                     }
                 }
                 if constexpr (!MULTI) {
                     if (wr && col0 < ncols) {
-                        uint4* p4 = reinterpret_cast<uint4*>(slot + slot_index(col0, nsubw, sub));
+                        uint4* p4 = reinterpret_cast<uint4*>(lslot + slot_col(col0, nsubw));
                         p4[0] = make_uint4(wY[0], wF[0], wY[1], wF[1]);
                         p4[1] = make_uint4(wY[2], wF[2], wY[3], wF[3]);
                     }
@@ -492,48 +498,51 @@ k_search(SearchArgs a)
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     int2* __restrict__ slot = a.bnd + (int64_t)(blockIdx.x * W + wave) * a.slot_elems;
-    if (a.nq == 1) {
-        const QueryDesc qd = a.qd[0];
-        if (qd.lds)
-            stage_profile(a, qd);
+    const bool solo = a.nq == 1;                    // uniform over the launch
+    const int64_t nitems = (int64_t)a.n_wg * W;
+    int cur_q = -1;
+    if (solo) {
+        if (a.qd[0].lds)
+            stage_profile(a, a.qd[0]);
         __syncthreads();
-        const int64_t nitems = (int64_t)a.n_wg * W;
-        for (;;) {
+        cur_q = 0;
+    }
+    for (;;) {
+        Item it;
+        int q;
+        if (solo) {                                 // this wavefront's next item
             int wi = 0;
             if (lane == 0)
                 wi = atomicAdd(&a.counters[0], 1);
             wi = __builtin_amdgcn_readfirstlane(wi);
             if (wi >= nitems)
                 break;
-            const Item it = a.items[wi];
-            if (it.q == 0 && item_fits<I16>(a, it, qd))
-                run_item<R, ES, I16>(a, it, qd, slot, lane);
-        }
-        return;
-    }
-    int cur_q = -1;
-    for (;;) {
-        if (threadIdx.x == 0)
-            s_wi = atomicAdd(&a.counters[0], 1);
-        __syncthreads();
-        const int wi = s_wi;
-        if (wi >= a.n_wg)
-            break;
-        const Item it = a.items[(int64_t)wi * W + wave];
-        const int q = a.items[(int64_t)wi * W].q;
-        if (q < 0 || q >= a.nq) {                 // uniform: a malformed queue entry is skipped
+            it = a.items[wi];
+            q = 0;
+        } else {                                    // this workgroup's next item
+            if (threadIdx.x == 0)
+                s_wi = atomicAdd(&a.counters[0], 1);
             __syncthreads();
-            continue;
+            const int wi = s_wi;
+            if (wi >= a.n_wg)
+                break;
+            it = a.items[(int64_t)wi * W + wave];
+            q = a.items[(int64_t)wi * W].q;
+            if (q < 0 || q >= a.nq) {               // uniform: a malformed queue entry is skipped
+                __syncthreads();
+                continue;
+            }
+            if (a.qd[q].lds && q != cur_q) {
+                stage_profile(a, a.qd[q]);
+                __syncthreads();
+                cur_q = q;
+            }
         }
         const QueryDesc qd = a.qd[q];
-        if (qd.lds && q != cur_q) {
-            stage_profile(a, qd);
-            __syncthreads();
-            cur_q = q;
-        }
-        if (item_fits<I16>(a, it, qd) && it.q == q)
+        if (it.q == q && item_fits<I16>(a, it, qd))
             run_item<R, ES, I16>(a, it, qd, slot, lane);
-        __syncthreads();    // LDS profile and s_wi are reused by the next item
+        if (!solo)
+            __syncthreads();                        // LDS profile and s_wi are reused next
     }
 }
 

@@ -19,6 +19,7 @@ constexpr int kAlpha = 32;           // residue codes 0..31 accepted at the ABI
 constexpr int kCodes = 33;           // + internal pad code
 constexpr uint8_t kPad = 32;         // pad code: subject tails and chunk fill
 constexpr int kWave = 64;
+constexpr int kI16Rows = 24;       // query rows per lane of the packed 16-bit variant
 
 // Work item (one wavefront).  meta = nsub | K << 16 | critical << 24 (K =
 // lanes per subject, 1..64, floor(64 / K) lane groups per wavefront; critical
@@ -86,7 +87,7 @@ struct ProfileArgs {
 enum Variant : int {
     kI32_R32_P8 = 0,   // int32 lanes, 32 rows, 8-bit profile
     kI32_R32_P16 = 1,  // int32 lanes, 32 rows, 16-bit profile
-    kI16_R16 = 2,      // packed 16-bit lanes, 16 rows, 16-bit profile
+    kI16 = 2,          // packed 16-bit lanes, kI16Rows rows, 16-bit profile
 };
 
 struct LaunchInfo {

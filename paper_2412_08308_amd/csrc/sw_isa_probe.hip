@@ -29,10 +29,10 @@ template __global__ void isa_i32<32, 1, false, false>(SearchArgs);
 template __global__ void isa_i32<32, 1, false, true>(SearchArgs);
 template __global__ void isa_i32<32, 2, true, false>(SearchArgs);
 template __global__ void isa_i32<32, 2, false, false>(SearchArgs);
-template __global__ void isa_i16<16, true, false>(SearchArgs);
-template __global__ void isa_i16<16, true, true>(SearchArgs);
-template __global__ void isa_i16<16, false, false>(SearchArgs);
-template __global__ void isa_i16<16, false, true>(SearchArgs);
-template __global__ void isa_i32<16, 2, false, true>(SearchArgs);
+template __global__ void isa_i16<24, true, false>(SearchArgs);
+template __global__ void isa_i16<24, true, true>(SearchArgs);
+template __global__ void isa_i16<24, false, false>(SearchArgs);
+template __global__ void isa_i16<24, false, true>(SearchArgs);
+template __global__ void isa_i32<24, 2, false, true>(SearchArgs);
 
 }  // namespace swdb

@@ -16,7 +16,7 @@ LaunchInfo variant_info(Variant v)
     switch (v) {
     case kI32_R32_P8: return {32, 1, 1};
     case kI32_R32_P16: return {32, 2, 1};
-    case kI16_R16: return {16, 2, 2};
+    case kI16: return {kI16Rows, 2, 2};
     }
     return {0, 0, 0};
 }
@@ -113,14 +113,14 @@ hipError_t launch_search(Variant v, const SearchArgs& a, int grid, int waves, in
     switch (v) {
     case kI32_R32_P8: return launch_search_i32p8(a, grid, waves, lds_bytes, st);
     case kI32_R32_P16: return launch_search_i32p16(a, grid, waves, lds_bytes, st);
-    case kI16_R16: return launch_search_i16(a, grid, waves, lds_bytes, st);
+    case kI16: return launch_search_i16(a, grid, waves, lds_bytes, st);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_rescore(Variant v, const SearchArgs& a, int grid, int waves, hipStream_t st)
 {
-    if (v == kI16_R16)
+    if (v == kI16)
         return launch_rescore_i16(a, grid, waves, st);
     return hipErrorInvalidValue;   // int32 variants never flag subjects
 }
@@ -130,7 +130,7 @@ int search_occupancy(Variant v, int waves, int lds_bytes)
     switch (v) {
     case kI32_R32_P8: return occupancy_i32p8(waves, lds_bytes);
     case kI32_R32_P16: return occupancy_i32p16(waves, lds_bytes);
-    case kI16_R16: return occupancy_i16(waves, lds_bytes);
+    case kI16: return occupancy_i16(waves, lds_bytes);
     }
     return 1;
 }

@@ -149,7 +149,7 @@ Resolved resolve(const sw_db_s* db, const sw_options* opt, int elem_i32, int32_t
     const int mode = opt ? opt->mode : SW_MODE_AUTO;
     r.i16 = mode != SW_MODE_I32;
     if (r.i16) {
-        r.v = kI16_R16;
+        r.v = kI16;
     } else {
         r.v = elem_i32 == 1 ? kI32_R32_P8 : kI32_R32_P16;
     }

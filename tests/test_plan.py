@@ -43,7 +43,7 @@ def check_plan(db, qlens, opt, spl):
         assert ncols % 16 == 0 and ncols == (int(slen[s0]) + 15) // 16 * 16
         assert np.all(slen[s0:s0 + nsub] <= ncols)
         seen[q, s0:s0 + nsub] += 1
-        nbr = -(-qlens[q] // (32 if spl == 1 else 16))
+        nbr = -(-qlens[q] // (32 if spl == 1 else 24))
         if nbr > K:
             slot_need = max(slot_need, ncols * (WAVE // K) * 8)
     assert np.all(seen == 1), "every subject exactly once per query"
