@@ -498,51 +498,48 @@ k_search(SearchArgs a)
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     int2* __restrict__ slot = a.bnd + (int64_t)(blockIdx.x * W + wave) * a.slot_elems;
-    const bool solo = a.nq == 1;                    // uniform over the launch
-    const int64_t nitems = (int64_t)a.n_wg * W;
-    int cur_q = -1;
-    if (solo) {
-        if (a.qd[0].lds)
-            stage_profile(a, a.qd[0]);
+    if (a.nq == 1) {
+        const QueryDesc qd = a.qd[0];
+        if (qd.lds)
+            stage_profile(a, qd);
         __syncthreads();
-        cur_q = 0;
-    }
-    for (;;) {
-        Item it;
-        int q;
-        if (solo) {                                 // this wavefront's next item
+        const int64_t nitems = (int64_t)a.n_wg * W;
+        for (;;) {
             int wi = 0;
             if (lane == 0)
                 wi = atomicAdd(&a.counters[0], 1);
             wi = __builtin_amdgcn_readfirstlane(wi);
             if (wi >= nitems)
                 break;
-            it = a.items[wi];
-            q = 0;
-        } else {                                    // this workgroup's next item
-            if (threadIdx.x == 0)
-                s_wi = atomicAdd(&a.counters[0], 1);
+            const Item it = a.items[wi];
+            if (it.q == 0 && item_fits<I16>(a, it, qd))
+                run_item<R, ES, I16>(a, it, qd, slot, lane);
+        }
+        return;
+    }
+    int cur_q = -1;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_wi = atomicAdd(&a.counters[0], 1);
+        __syncthreads();
+        const int wi = s_wi;
+        if (wi >= a.n_wg)
+            break;
+        const Item it = a.items[(int64_t)wi * W + wave];
+        const int q = a.items[(int64_t)wi * W].q;
+        if (q < 0 || q >= a.nq) {                 // uniform: a malformed queue entry is skipped
             __syncthreads();
-            const int wi = s_wi;
-            if (wi >= a.n_wg)
-                break;
-            it = a.items[(int64_t)wi * W + wave];
-            q = a.items[(int64_t)wi * W].q;
-            if (q < 0 || q >= a.nq) {               // uniform: a malformed queue entry is skipped
-                __syncthreads();
-                continue;
-            }
-            if (a.qd[q].lds && q != cur_q) {
-                stage_profile(a, a.qd[q]);
-                __syncthreads();
-                cur_q = q;
-            }
+            continue;
         }
         const QueryDesc qd = a.qd[q];
-        if (it.q == q && item_fits<I16>(a, it, qd))
+        if (qd.lds && q != cur_q) {
+            stage_profile(a, qd);
+            __syncthreads();
+            cur_q = q;
+        }
+        if (item_fits<I16>(a, it, qd) && it.q == q)
             run_item<R, ES, I16>(a, it, qd, slot, lane);
-        if (!solo)
-            __syncthreads();                        // LDS profile and s_wi are reused next
+        __syncthreads();    // LDS profile and s_wi are reused by the next item
     }
 }
 

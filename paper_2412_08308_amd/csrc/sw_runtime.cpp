@@ -48,9 +48,9 @@ int fail(int code, const std::string& msg)
     } while (0)
 
 // Defaults measured on MI355X (config 1 and the 20-query batch): one query
-// runs barrier-free per-wavefront pulls, where 8-wavefront workgroups share one
-// LDS profile; batches use 4-wavefront workgroup items.
-constexpr int kDefaultWavesSingle = 8;
+// runs barrier-free per-wavefront pulls with 48K-cell items; batches use
+// workgroup items of 96K cells.  Four wavefronts per workgroup in both.
+constexpr int kDefaultWavesSingle = 4;
 constexpr int kDefaultWavesBatch = 4;
 constexpr int64_t kDefaultLaneCellsSingle = 48 * 1024;
 constexpr int64_t kDefaultLaneCellsBatch = 96 * 1024;
