@@ -408,7 +408,7 @@ def main(argv=None):
         "batched": batched,
         "latency": latency,
         "parity": parity,
-        "plan": {k: main_run["plan"][k] for k in ("lane_cells", "items", "wg_items", "grid", "rows")},
+        "plan": {k: main_run["plan"][k] for k in ("lane_cells", "items", "launches", "grid", "rows")},
         "knobs": {k: v for k, v in KNOBS.items() if v},
         "cpu_baseline": cpu,
     }

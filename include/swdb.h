@@ -92,7 +92,7 @@ typedef struct sw_plan_stats {
     int64_t cells;         /* sum over queries of m * (sum of subject lengths)     */
     int64_t lane_cells;    /* cells the lanes sweep including padding              */
     int64_t items;         /* wavefront work items                                 */
-    int64_t wg_items;      /* workgroup work items (queue length)                  */
+    int64_t launches;      /* search launches (launch groups of SW_MODE_TUNED)     */
     int64_t grid;          /* persistent workgroups launched                       */
     int64_t slot_bytes;    /* per-wavefront pass-boundary scratch                  */
     int64_t workspace;     /* bytes sw_workspace_bytes() returns                   */
@@ -161,11 +161,12 @@ int sw_plan_info(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options
                  sw_plan_stats* out);
 
 /*
- * The work queue a search would run, in queue order: for each wavefront item
- * four int32 (first sorted subject, columns swept, query index, subjects |
- * lanes-per-subject << 16 | critical-path flag << 24), `waves` items per
- * workgroup item.  Writes at most
- * `cap` items to `out` (HOST) and returns the total count, or a negative code.
+ * The work queues a search would run: for each wavefront item four int32
+ * (first sorted subject, columns swept, query index in the call, subjects |
+ * lanes-per-subject << 16 | critical-path flag << 24).  Each query's items are
+ * contiguous, largest per-lane work first; queries follow in queue order
+ * (largest query first) within each launch group.  Writes at most `cap` items
+ * to `out` (HOST) and returns the total count, or a negative code.
  */
 int64_t sw_plan_items(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt,
                       int32_t* out, int64_t cap);

@@ -67,7 +67,7 @@ class TuneEntry(ctypes.Structure):
 
 class PlanStats(ctypes.Structure):
     _fields_ = [("cells", ctypes.c_int64), ("lane_cells", ctypes.c_int64),
-                ("items", ctypes.c_int64), ("wg_items", ctypes.c_int64),
+                ("items", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("grid", ctypes.c_int64), ("slot_bytes", ctypes.c_int64),
                 ("workspace", ctypes.c_int64), ("variant", ctypes.c_int32),
                 ("rows", ctypes.c_int32)]

@@ -481,65 +481,44 @@ __device__ __forceinline__ void run_item(const SearchArgs& a, const Item& it, co
         __builtin_amdgcn_s_setprio(0);
 }
 
-// Work queue, taken in order from counters[0] until exhausted (every wavefront
-// leaves through the same test).
-//  * One query: its profile is staged in LDS once per workgroup, then every
-//    wavefront takes wavefront items on its own -- no barriers, so waves of a
-//    workgroup never wait for each other.
-//  * Several queries: workgroups take workgroup items (the `waves` wavefront
-//    items of one query); the profile is restaged when the query changes, with
-//    barriers around it.
+// Persistent search over per-query work queues.  Every workgroup walks the
+// queries in queue order (largest first); within a query each wavefront takes
+// items on its own with one atomic on that query's head -- no barriers, so the
+// waves of a workgroup never wait for each other inside a query.  A query whose
+// profile fits in LDS is staged there between two barriers: the first waits
+// until every wave of the workgroup has left the previous query's queue, the
+// second until the copy is complete (skipped when the queue is already empty:
+// a wave that saw it empty knows every later take fails too).  The barrier
+// sequence depends only on the descriptors, so every wave meets the same
+// barriers.
 template <int R, int ES, bool I16>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_search(SearchArgs a)
 {
-    __shared__ int s_wi;
     const int W = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     int2* __restrict__ slot = a.bnd + (int64_t)(blockIdx.x * W + wave) * a.slot_elems;
-    if (a.nq == 1) {
-        const QueryDesc qd = a.qd[0];
-        if (qd.lds)
-            stage_profile(a, qd);
-        __syncthreads();
-        const int64_t nitems = (int64_t)a.n_wg * W;
+    for (int p = 0; p < a.nq; ++p) {
+        const QueryDesc qd = a.qd[p];
+        if (qd.lds) {
+            __syncthreads();
+            if (__hip_atomic_load(&a.heads[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < qd.item_count)
+                stage_profile(a, qd);
+            __syncthreads();
+        }
         for (;;) {
             int wi = 0;
             if (lane == 0)
-                wi = atomicAdd(&a.counters[0], 1);
+                wi = atomicAdd(&a.heads[p], 1);
             wi = __builtin_amdgcn_readfirstlane(wi);
-            if (wi >= nitems)
+            const int64_t ix = (int64_t)qd.item_begin + wi;
+            if (wi >= qd.item_count || ix >= a.n_items)
                 break;
-            const Item it = a.items[wi];
-            if (it.q == 0 && item_fits<I16>(a, it, qd))
+            const Item it = a.items[ix];
+            if (it.q == p && item_fits<I16>(a, it, qd))
                 run_item<R, ES, I16>(a, it, qd, slot, lane);
         }
-        return;
-    }
-    int cur_q = -1;
-    for (;;) {
-        if (threadIdx.x == 0)
-            s_wi = atomicAdd(&a.counters[0], 1);
-        __syncthreads();
-        const int wi = s_wi;
-        if (wi >= a.n_wg)
-            break;
-        const Item it = a.items[(int64_t)wi * W + wave];
-        const int q = a.items[(int64_t)wi * W].q;
-        if (q < 0 || q >= a.nq) {                 // uniform: a malformed queue entry is skipped
-            __syncthreads();
-            continue;
-        }
-        const QueryDesc qd = a.qd[q];
-        if (qd.lds && q != cur_q) {
-            stage_profile(a, qd);
-            __syncthreads();
-            cur_q = q;
-        }
-        if (item_fits<I16>(a, it, qd) && it.q == q)
-            run_item<R, ES, I16>(a, it, qd, slot, lane);
-        __syncthreads();    // LDS profile and s_wi are reused by the next item
     }
 }
 

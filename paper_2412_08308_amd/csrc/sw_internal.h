@@ -38,8 +38,8 @@ struct QueryDesc {
     int32_t nbr;        // row blocks: ceil(m / R)
     int32_t prof_bytes; // (nbr + 1) * 33 * code stride
     int32_t lds;        // 1: profile staged in LDS; 0: read from global memory
-    int32_t wg_begin;   // first workgroup item of this query in the queue
-    int32_t wg_count;   // number of workgroup items of this query
+    int32_t item_begin; // first work item of this query in the item array
+    int32_t item_count; // number of work items of this query
     int32_t out_row;    // row of the score matrix this query writes
     int32_t pad;
 };
@@ -56,15 +56,16 @@ struct SearchArgs {
     const int32_t* slen;         // sorted index -> length
     int32_t nseq;
     // plan
-    const Item* items;           // n_wg * waves entries
-    const QueryDesc* qd;
+    const Item* items;           // every query's items, queries in queue order
+    const QueryDesc* qd;         // queue order (largest query first)
     int32_t nq;
-    int32_t n_wg;                // workgroup items in the queue
+    int32_t* heads;              // [nq] per-query queue heads
+    int64_t n_items;             // entries of items
     const uint8_t* prof;         // profile area (global)
     // outputs and scratch
     int32_t* scores;             // [nq][out_stride]
     int64_t out_stride;
-    int32_t* counters;           // [0] queue head, [1] overflow-flag count
+    int32_t* counters;           // [1] overflow-flag count
     int2* bnd;                   // slots
     int64_t slot_elems;          // int2 entries per slot
     int2* flags;                 // (q, sorted subject) of 16-bit overflows
@@ -78,6 +79,7 @@ struct ProfileArgs {
     const QueryDesc* qd;
     uint8_t* prof;
     int32_t* counters;
+    int32_t* heads;
     int32_t nq;
     int32_t go;
     Matrix8 sm;

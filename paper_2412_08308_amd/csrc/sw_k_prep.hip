@@ -25,13 +25,15 @@ LaunchInfo variant_info(Variant v)
 // row and subject residue code): entry (row block rb, code c, row r) =
 // SM[Q[rb*R + r]][c] + Go for rows inside the query and codes < 32, the pad
 // value (most negative entry) elsewhere; row block nbr is entirely padding.
-// Block (0, 0) also clears the queue head and the flag count.
+// Block (0, 0) also clears the flag count, block (0, q) query q's queue head.
 template <typename PE>
 __global__ void __launch_bounds__(256) k_profile(ProfileArgs a, int R)
 {
     const int q = blockIdx.y;
     if (blockIdx.x == 0 && q == 0 && threadIdx.x < 4)
         a.counters[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        a.heads[q] = 0;
     const QueryDesc qd = a.qd[q];
     const int entries = (qd.nbr + 1) * kCodes * R;
     const int cse = R + 16 / (int)sizeof(PE);      // code stride in entries

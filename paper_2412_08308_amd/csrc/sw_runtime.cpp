@@ -83,13 +83,12 @@ struct PlanKey {
     }
 };
 
-// Items of one query (q field 0), grouped by workgroup item, longest first.
+// Work items of one query (q field 0), largest per-lane work first.
 struct QPlan {
-    std::vector<Item> items;      // n_wg * waves
-    int64_t n_wg = 0;
+    std::vector<Item> items;
     int64_t slot_elems = 0;       // int2 entries a multi-pass item needs
     int64_t lane_cells = 0;       // sum over items of 64 * per-lane cells
-    int64_t cost = 0;             // sum of workgroup-item costs
+    int64_t cost = 0;             // sum of per-lane work over items
     int64_t nitems = 0;
 };
 
@@ -247,27 +246,13 @@ std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, con
             p->slot_elems = std::max<int64_t>(p->slot_elems, (int64_t)it.ncols * (kWave / K));
         s += take;
     }
+    // longest-processing-time order: largest per-lane work first
+    std::stable_sort(wis.begin(), wis.end(), [](const WItem& a, const WItem& b) { return a.cost > b.cost; });
     p->nitems = (int64_t)wis.size();
-    // group into workgroup items of `waves` consecutive wavefront items
-    struct WG { int64_t first, count, cost; };
-    std::vector<WG> wgs;
-    for (int64_t i = 0; i < (int64_t)wis.size(); i += r.waves) {
-        WG w{i, std::min<int64_t>(r.waves, (int64_t)wis.size() - i), 0};
-        for (int64_t k = 0; k < w.count; ++k)
-            w.cost = std::max(w.cost, wis[i + k].cost);
-        wgs.push_back(w);
-    }
-    std::stable_sort(wgs.begin(), wgs.end(), [](const WG& a, const WG& b) { return a.cost > b.cost; });
-    p->n_wg = (int64_t)wgs.size();
-    p->items.resize((size_t)p->n_wg * r.waves);
-    for (size_t w = 0; w < wgs.size(); ++w) {
-        for (int k = 0; k < r.waves; ++k) {
-            Item it{0, 0, 0, 0};
-            if (k < wgs[w].count)
-                it = wis[wgs[w].first + k].it;
-            p->items[w * r.waves + k] = it;
-        }
-        p->cost += wgs[w].cost;
+    p->items.resize(wis.size());
+    for (size_t i = 0; i < wis.size(); ++i) {
+        p->items[i] = wis[i].it;
+        p->cost += wis[i].cost;
     }
     p->slot_elems = align_up(p->slot_elems, 4);
     return p;
@@ -275,7 +260,7 @@ std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, con
 
 std::shared_ptr<QPlan> get_plan(sw_db_s* db, int nbr, const Resolved& r)
 {
-    PlanKey key{r.rows, r.spl, r.waves, r.kmax, nbr, r.target};
+    PlanKey key{r.rows, r.spl, 0, r.kmax, nbr, r.target};   // items do not depend on waves
     std::lock_guard<std::mutex> lk(db->mu);
     auto f = db->plans.find(key);
     if (f != db->plans.end())
@@ -294,16 +279,15 @@ std::shared_ptr<QPlan> get_plan(sw_db_s* db, int nbr, const Resolved& r)
 struct Layout {
     Resolved r;
     int32_t nq = 0;
-    std::vector<QueryDesc> qd;
-    std::vector<std::shared_ptr<QPlan>> plans;
-    std::vector<int32_t> order;       // queue order of queries
-    int64_t n_wg = 0;
+    std::vector<QueryDesc> qd;        // queue order; out_row = query's position in the call
+    std::vector<std::shared_ptr<QPlan>> plans;   // by position in the call
+    std::vector<int32_t> order;       // queue position -> position in the call
     int64_t grid = 0, rgrid = 0;
     int64_t slot_elems = 0, rslot_elems = 0;
     int lds_bytes = 0;
     int64_t cells = 0, lane_cells = 0, nitems = 0;
     int max_entries = 0;
-    size_t off_counters = 0, off_qd = 0, off_qoff = 0, off_items = 0, off_prof = 0,
+    size_t off_counters = 0, off_heads = 0, off_qd = 0, off_qoff = 0, off_items = 0, off_prof = 0,
            off_flags = 0, off_slots = 0, total = 0, blob = 0;
     int64_t flag_cap = 0;
 };
@@ -337,20 +321,23 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
         L.lane_cells += L.plans[k]->lane_cells;
         L.nitems += L.plans[k]->nitems;
     }
-    // queue: largest query first
+    // queue: largest query first; descriptors stored in queue order
     L.order.resize(nq);
     std::iota(L.order.begin(), L.order.end(), 0);
     std::stable_sort(L.order.begin(), L.order.end(),
                      [&](int a, int b) { return L.plans[a]->cost > L.plans[b]->cost; });
-    int64_t wg = 0;
-    for (int32_t k : L.order) {
-        L.qd[k].wg_begin = (int32_t)wg;
-        L.qd[k].wg_count = (int32_t)L.plans[k]->n_wg;
-        wg += L.plans[k]->n_wg;
+    std::vector<QueryDesc> by_call = L.qd;
+    int64_t nit = 0;
+    for (int32_t p = 0; p < nq; ++p) {
+        const int32_t k = L.order[p];
+        L.qd[p] = by_call[k];
+        L.qd[p].item_begin = (int32_t)nit;
+        L.qd[p].item_count = (int32_t)L.plans[k]->nitems;
+        nit += L.plans[k]->nitems;
+        if (nit > INT32_MAX / 2)
+            return fail(SW_EINVAL, "batch too large for one launch");
     }
-    L.n_wg = wg;
-    if (wg > INT32_MAX / 8)
-        return fail(SW_EINVAL, "batch too large for one launch");
+    const int64_t wg = ceil_div(nit, r.waves);
     // persistent grid: occupancy model (<= 16 waves per CU, LDS per CU).  Slots
     // are sized for the register-limited maximum so that the workspace size does
     // not depend on the profile entry width chosen from the matrix.
@@ -372,10 +359,10 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
     // byte layout
     size_t off = 0;
     L.off_counters = off; off += 256;
+    L.off_heads = off; off += align_up(sizeof(int32_t) * nq, 256);
     L.off_qd = off; off += align_up(sizeof(QueryDesc) * nq, 16);
     L.off_qoff = off; off += align_up(sizeof(int64_t) * nq, 16);
     L.off_items = off;
-    int64_t nit = L.n_wg * r.waves;
     off += align_up(sizeof(Item) * nit, 256);
     L.blob = off - L.off_qd;
     L.off_prof = off; off += align_up(prof, 256);
@@ -497,8 +484,8 @@ int build_parts(sw_db_s* db, int32_t nq, const int32_t* q_lens, const int64_t* q
         const int32_t n = (int32_t)P.idx.size();
         const int rc = make_layout(db, n, P.lens.data(), resolve(db, &gopt[g], elem, n), P.L);
         if (rc) return rc;
-        for (size_t k = 0; k < P.idx.size(); ++k)
-            P.L.qd[k].out_row = P.idx[k];
+        for (QueryDesc& d : P.L.qd)
+            d.out_row = P.idx[d.out_row];
     }
     return SW_OK;
 }
@@ -557,13 +544,15 @@ int plan_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, co
 void fill_blob(const Layout& L, const int64_t* q_offsets, uint8_t* h)
 {
     std::memcpy(h, L.qd.data(), sizeof(QueryDesc) * L.nq);
-    std::memcpy(h + (L.off_qoff - L.off_qd), q_offsets, sizeof(int64_t) * L.nq);
+    int64_t* qoff = reinterpret_cast<int64_t*>(h + (L.off_qoff - L.off_qd));
     Item* items = reinterpret_cast<Item*>(h + (L.off_items - L.off_qd));
     int64_t pos = 0;
-    for (int32_t k : L.order) {
+    for (int32_t p = 0; p < L.nq; ++p) {
+        const int32_t k = L.order[p];
+        qoff[p] = q_offsets[k];
         for (const Item& it0 : L.plans[k]->items) {
             Item it = it0;
-            it.q = k;
+            it.q = p;
             items[pos++] = it;
         }
     }
@@ -586,6 +575,7 @@ int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8
     pa.qd = reinterpret_cast<const QueryDesc*>(w + L.off_qd);
     pa.prof = w + L.off_prof;
     pa.counters = reinterpret_cast<int32_t*>(w + L.off_counters);
+    pa.heads = reinterpret_cast<int32_t*>(w + L.off_heads);
     pa.nq = L.nq;
     pa.go = go;
     for (int i = 0; i < kAlpha * kAlpha; ++i)
@@ -601,7 +591,8 @@ int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8
     a.items = reinterpret_cast<const Item*>(w + L.off_items);
     a.qd = pa.qd;
     a.nq = L.nq;
-    a.n_wg = (int32_t)L.n_wg;
+    a.heads = pa.heads;
+    a.n_items = L.nitems;
     a.prof = pa.prof;
     a.scores = scores;
     a.out_stride = db->nseq;
@@ -923,7 +914,7 @@ int sw_plan_info(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options
         out->cells += L.cells;
         out->lane_cells += L.lane_cells;
         out->items += L.nitems;
-        out->wg_items += L.n_wg;
+        out->launches += 1;
         out->grid = std::max<int64_t>(out->grid, L.grid);
         out->slot_bytes = std::max<int64_t>(out->slot_bytes, L.slot_elems * (int64_t)sizeof(int2));
     }

@@ -25,25 +25,31 @@ def _lengths(kind):
 
 def check_plan(db, qlens, opt, spl):
     items = db.plan_items(qlens, opt)
-    waves = opt.waves or 4
     slen = db.sorted_lengths()
-    assert len(items) % waves == 0
     seen = np.zeros((len(qlens), db.nseq), dtype=np.int32)
-    for w in range(0, len(items), waves):
-        grp = items[w:w + waves]
-        qs = {int(it[2]) for it in grp if it[3] & 0xFFFF}
-        assert len(qs) <= 1, "a workgroup item mixes queries"
+    # each query's items are contiguous, largest per-lane work first
+    runs = [int(items[0, 2])] if len(items) else []
+    for k in range(1, len(items)):
+        if items[k, 2] != items[k - 1, 2]:
+            runs.append(int(items[k, 2]))
+    assert len(runs) == len(set(runs)) == len(qlens)
     slot_need = 0
+    rows = 32 if spl == 1 else 24
+    last = None
     for s0, ncols, q, meta in items:
         nsub, K = meta & 0xFFFF, (meta >> 16) & 0xFF
-        if nsub == 0:
-            continue
+        assert nsub > 0, "no empty items"
         assert 1 <= K <= 64
+        nbr = -(-qlens[q] // rows)
+        cols = ncols if K == 1 else (int(slen[s0]) + K - 1 + 15) // 16 * 16
+        lw = max(cols, 16) * -(-nbr // K) * rows       # per-lane cells of the item
+        if last is not None and last[0] == q:
+            assert lw <= last[1], "items of a query not in decreasing per-lane work"
+        last = (q, lw)
         assert nsub <= (WAVE // K) * spl
         assert ncols % 16 == 0 and ncols == (int(slen[s0]) + 15) // 16 * 16
         assert np.all(slen[s0:s0 + nsub] <= ncols)
         seen[q, s0:s0 + nsub] += 1
-        nbr = -(-qlens[q] // (32 if spl == 1 else 24))
         if nbr > K:
             slot_need = max(slot_need, ncols * (WAVE // K) * 8)
     assert np.all(seen == 1), "every subject exactly once per query"
@@ -87,7 +93,7 @@ def test_batch_plan_queue_order():
         qlens = synth.c3_query_lengths()
         items = db.plan_items(qlens, swdb.options())
         qorder = []
-        for q in items[:, 2][items[:, 3] & 0xFFFF > 0]:
+        for q in items[:, 2]:
             if not qorder or qorder[-1] != q:
                 qorder.append(int(q))
         # each query's items are contiguous, largest query first
