@@ -152,7 +152,7 @@ def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False)
 
 
 def serving(args, capacity_gcups, mode):
-    """Poisson request stream against config 4's 500,000-subject database through
+    """Poisson request stream against the 500,000-subject serving database through
     the continuous-batching server; p50/p99 latency and sustained GCUPS."""
     import numpy as np
     import torch
@@ -161,7 +161,7 @@ def serving(args, capacity_gcups, mode):
     import synth
     from paper_2412_08308_amd.serve import GpuBackend, Server
 
-    w5 = synth.config(4, scale=args.serve_scale)
+    w5 = synth.workload("serve_500k", scale=args.serve_scale)
     gdb = swdb.Database.from_host(w5.db)
     rng = np.random.default_rng(77)
     n = args.serve_requests
@@ -200,13 +200,13 @@ def serving(args, capacity_gcups, mode):
 
 
 def planted(args, ev):
-    """Overflow workload: 8,000-residue query vs config 1's database with long
+    """Overflow workload: 8,000-residue query vs the 200,000-subject database with long
     subjects and near-homologs planted; 16-bit lanes + int32 rescore vs int32."""
     import torch
 
     import paper_2412_08308_amd as swdb
     import synth
-    w4 = synth.config(3, scale=args.scale)
+    w4 = synth.workload("q8000_planted_vs_200k", scale=args.scale)
     gdb = swdb.Database.from_host(w4.db)
     q = torch.from_numpy(w4.queries[0]).cuda()
     cells = len(w4.queries[0]) * w4.db.total
@@ -295,7 +295,7 @@ def main(argv=None):
     import synth
 
     torch.cuda.set_device(0)
-    w = synth.config(1, scale=args.scale)
+    w = synth.workload("q567_vs_200k", scale=args.scale)
     gdb = swdb.Database.from_host(w.db)
     q = torch.from_numpy(w.queries[0]).cuda()
     cells = len(w.queries[0]) * w.db.total
@@ -348,7 +348,7 @@ def main(argv=None):
 
     batched = None
     if not args.no_batch:
-        w3 = synth.config(2, scale=args.scale)
+        w3 = synth.workload("20q_vs_200k", scale=args.scale)
         qs = [torch.from_numpy(x).cuda() for x in w3.queries]
         bcells = sum(len(x) for x in w3.queries) * w.db.total
         batched = {"workload": "20 queries 144-5478 vs the same 200,000 subjects, one persistent launch "

@@ -47,13 +47,10 @@ int fail(int code, const std::string& msg)
             return fail(SW_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));         \
     } while (0)
 
-// Defaults measured on MI355X (config 1 and the 20-query batch): one query
-// runs barrier-free per-wavefront pulls with 48K-cell items; batches use
-// workgroup items of 96K cells.  Four wavefronts per workgroup in both.
-constexpr int kDefaultWavesSingle = 4;
-constexpr int kDefaultWavesBatch = 4;
-constexpr int64_t kDefaultLaneCellsSingle = 48 * 1024;
-constexpr int64_t kDefaultLaneCellsBatch = 96 * 1024;
+// Bounds of the default per-item lane-cell target (resolve() derives the
+// target from the work of the launch).
+constexpr int64_t kMinLaneCells = 24 * 1024;
+constexpr int64_t kMaxLaneCells = 192 * 1024;
 constexpr int kDefaultLdsLimit = 64 * 1024;
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kRescoreWaves = 4;      // workgroup size of the rescore kernel
@@ -142,7 +139,17 @@ bool validate_options(const sw_options* opt, std::string& why)
     return true;
 }
 
-Resolved resolve(const sw_db_s* db, const sw_options* opt, int elem_i32, int32_t nq)
+int64_t prof_bytes_for(int nbr, int rows, int elem);
+
+// Launch options of one launch group.  Defaults (measured on MI355X):
+//  * lane-cell target per item: about 4.5 items per wavefront slot of a
+//    nominally full device (12 waves per CU), clamped to [24K, 192K] -- short
+//    searches want small items for a short tail, large batches want large ones
+//    for less padding and fewer passes;
+//  * 4 wavefronts per workgroup, or 8 when queries with an LDS profile share
+//    the launch with queries whose profile stays in global memory, so that the
+//    LDS footprint still leaves 16 waves per CU to hide the global reads.
+Resolved resolve(const sw_db_s* db, const sw_options* opt, int elem_i32, int32_t nq, const int32_t* q_lens)
 {
     Resolved r{};
     const int mode = opt ? opt->mode : SW_MODE_AUTO;
@@ -156,14 +163,25 @@ Resolved resolve(const sw_db_s* db, const sw_options* opt, int elem_i32, int32_t
     r.rows = li.rows;
     r.elem = li.prof_elem;
     r.spl = li.subjects_per_lane;
-    const bool single = nq == 1;
-    r.waves = (opt && opt->waves) ? opt->waves : (single ? kDefaultWavesSingle : kDefaultWavesBatch);
     r.kmax = (opt && opt->max_lanes) ? opt->max_lanes : 64;
-    r.target = (opt && opt->lane_cells) ? opt->lane_cells
-                                        : (single ? kDefaultLaneCellsSingle : kDefaultLaneCellsBatch);
     r.lds_limit = (opt && opt->lds_limit) ? opt->lds_limit : kDefaultLdsLimit;
     r.lds_limit = std::min(r.lds_limit, db->lds_max - 1024);
     r.grid_limit = opt ? opt->grid_limit : 0;
+    double cells = 0;
+    bool in_lds = false, in_global = false;
+    for (int32_t k = 0; k < nq; ++k) {
+        cells += (double)q_lens[k] * (double)db->total;
+        const int nbr = (int)ceil_div(q_lens[k], r.rows);
+        (prof_bytes_for(nbr, r.rows, r.elem) <= r.lds_limit ? in_lds : in_global) = true;
+    }
+    if (opt && opt->lane_cells) {
+        r.target = opt->lane_cells;
+    } else {
+        const double slots = (double)kWave * std::max(db->cu, 1) * 12;
+        r.target = std::min<int64_t>(std::max<int64_t>((int64_t)(cells / slots / 4.5), kMinLaneCells),
+                                     kMaxLaneCells);
+    }
+    r.waves = (opt && opt->waves) ? opt->waves : ((in_lds && in_global) ? 8 : 4);
     return r;
 }
 
@@ -482,7 +500,7 @@ int build_parts(sw_db_s* db, int32_t nq, const int32_t* q_lens, const int64_t* q
     for (size_t g = 0; g < parts.size(); ++g) {
         Part& P = parts[g];
         const int32_t n = (int32_t)P.idx.size();
-        const int rc = make_layout(db, n, P.lens.data(), resolve(db, &gopt[g], elem, n), P.L);
+        const int rc = make_layout(db, n, P.lens.data(), resolve(db, &gopt[g], elem, n, P.lens.data()), P.L);
         if (rc) return rc;
         for (QueryDesc& d : P.L.qd)
             d.out_row = P.idx[d.out_row];

@@ -19,8 +19,8 @@ table is available here, so every input is synthetic:
 * database lengths follow a clamped log-normal law (median 300).
 
 All draws use numpy ``Generator(PCG64)`` streams spawned from one
-``SeedSequence`` per configuration, so every array is a pure function of
-(configuration, seed, scale).
+``SeedSequence`` per workload, so every array is a pure function of
+(workload, seed, scale).
 """
 from __future__ import annotations
 
@@ -226,21 +226,35 @@ def c3_query_lengths(nq: int = 20, lo: int = 144, hi: int = 5478) -> List[int]:
     return [int(round(lo * (hi / lo) ** (k / (nq - 1)))) for k in range(nq)]
 
 
-def config(k: int, seed: int = 0, scale: float = 1.0) -> Workload:
+# Workload names -> internal stream index (the index only seeds the streams).
+_WORKLOADS = {"q64_vs_2k": 0, "q567_vs_200k": 1, "20q_vs_200k": 2, "q8000_planted_vs_200k": 3,
+              "serve_500k": 4}
+
+
+def workload(name: str, seed: int = 0, scale: float = 1.0) -> Workload:
     """The five synthetic workloads.
 
-    0: query 64 vs 2,000 subjects, lengths uniform 32..512.
-    1: query 567 vs 200,000 subjects, log-normal lengths (median 300, sigma
-       0.668, clamped 10..35,000; about 75M residues).
-    2: 20 queries, lengths geometric over 144..5,478, against database 1.
-    3: database 1 with 0.5% subjects resampled log-uniform 10,000..35,000 and
-       1% replaced by near-homologs (30-90% identity, with indels) of a long
-       query (8,000 residues), so that 16-bit lanes overflow.
-    4: 500,000 subjects with database 1's length law (about 190M residues);
-       queries log-normal (median 350, sigma 0.75, clamped 50..5,000).
+    q64_vs_2k:     query 64 vs 2,000 subjects, lengths uniform 32..512 (parity).
+    q567_vs_200k:  query 567 vs 200,000 subjects, log-normal lengths (median
+                   300, sigma 0.668, clamped 10..35,000; about 75M residues).
+    20q_vs_200k:   20 queries, lengths geometric over 144..5,478, against the
+                   200,000-subject database.
+    q8000_planted_vs_200k: that database with 0.5% subjects resampled
+                   log-uniform 10,000..35,000 and 1% replaced by near-homologs
+                   (30-90% identity, with indels) of a long query (8,000
+                   residues), so that 16-bit lanes overflow.
+    serve_500k:    500,000 subjects with the same length law (about 190M
+                   residues); queries log-normal (median 350, sigma 0.75,
+                   clamped 50..5,000).
 
     ``scale`` shrinks subject counts (for quick tests); lengths keep their law.
     """
+    if name not in _WORKLOADS:
+        raise ValueError(f"no workload {name!r}; known: {sorted(_WORKLOADS)}")
+    return _build(_WORKLOADS[name], seed, scale)
+
+
+def _build(k: int, seed: int, scale: float) -> Workload:
     sm = blosum_style_matrix()
     if k == 0:
         r_len, r_res, r_q = _streams(seed, 3)
@@ -268,7 +282,7 @@ def config(k: int, seed: int = 0, scale: float = 1.0) -> Workload:
         db = make_db(r_res, lens)
         qlens = lognormal_lengths(r_q, 64, 350, 0.75, 50, 5000)
         return Workload("serve_500k", [residues(r_q, int(m)) for m in qlens], db, sm)
-    raise ValueError(f"no configuration {k}")
+    raise ValueError(f"no workload index {k}")
 
 
 def _plant(db: Database, sm: np.ndarray, rng: np.random.Generator, seed: int,
@@ -304,8 +318,8 @@ def _plant(db: Database, sm: np.ndarray, rng: np.random.Generator, seed: int,
 
 
 def planted(seed: int = 0, scale: float = 1.0, qlen: int = 8000) -> Workload:
-    """Configuration 3 with an explicit query length (the 567-residue query of
-    configuration 1 is the zero-overflow control)."""
+    """The planted overflow workload with an explicit query length (the
+    567-residue query is the zero-overflow control)."""
     r_len, r_res, r_q, r_q2, r_plant = _streams(seed + 1, 5)
     n = max(1, int(round(200_000 * scale)))
     lens = lognormal_lengths(r_len, n, 300, 0.668, 10, 35_000)

@@ -31,15 +31,15 @@ def _check(db, q, sm, go, ge, modes=MODES, ids=None, **kw):
         gdb.release()
 
 
-def test_config0_all_modes():
-    w = synth.config(0)
+def test_q64_vs_2k_all_modes():
+    w = synth.workload("q64_vs_2k")
     _check(w.db, w.queries[0], w.matrix, w.gap_open, w.gap_extend)
 
 
 def test_one_shot_entry_point():
     import torch
     import paper_2412_08308_amd as swdb
-    w = synth.config(0, scale=0.1)
+    w = synth.workload("q64_vs_2k", scale=0.1)
     exp = oracle_scores(w.db, w.queries[0], w.matrix, 10, 2)
     announce("sw_db_search one-shot")
     res = torch.from_numpy(w.db.residues).cuda()
@@ -174,10 +174,10 @@ def test_bad_residue_rejected():
     assert ei.value.code == -5
 
 
-def test_config1_sampled():
+def test_q567_vs_200k_sampled():
     """Full 200,000-subject database in the benchmark's launch configuration;
     every subject of three length strata checked by the oracle one by one."""
-    w = synth.config(1)
+    w = synth.workload("q567_vs_200k")
     order = np.argsort(-w.db.lengths, kind="stable")
     rng = np.random.default_rng(14)
     ids = np.unique(np.concatenate([order[:200], order[-100:],

@@ -37,7 +37,7 @@ def test_planted_reduced_scale_every_subject():
 
 
 def test_planted_full_scale_sampled():
-    w = synth.config(3)
+    w = synth.workload("q8000_planted_vs_200k")
     q = w.queries[0]
     rng = np.random.default_rng(31)
     hom, lng = w.extra["hom_ids"], w.extra["long_ids"]

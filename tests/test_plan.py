@@ -11,9 +11,9 @@ WAVE = 64
 
 def _lengths(kind):
     rng = np.random.default_rng(3)
-    if kind == "config0":
-        return synth.config(0).db.lengths
-    if kind == "config1":
+    if kind == "q64_vs_2k":
+        return synth.workload("q64_vs_2k").db.lengths
+    if kind == "q567_vs_200k":
         return synth.lognormal_lengths(rng, 200_000, 300, 0.668, 10, 35_000)
     if kind == "ragged":
         base = [0, 0, 1, 15, 16, 17, 35000, 12000, 5000, 63, 64, 65, 127, 128, 129]
@@ -60,7 +60,7 @@ def check_plan(db, qlens, opt, spl):
     return info
 
 
-@pytest.mark.parametrize("kind", ["config0", "ragged", "tiny"])
+@pytest.mark.parametrize("kind", ["q64_vs_2k", "ragged", "tiny"])
 @pytest.mark.parametrize("mode,spl", [("i32", 1), ("i16", 2), ("auto", 2)])
 def test_plan_invariants(kind, mode, spl):
     db = swdb.Database.describe(_lengths(kind))
@@ -72,12 +72,12 @@ def test_plan_invariants(kind, mode, spl):
         db.release()
 
 
-def test_config1_plan_padding():
+def test_q567_vs_200k_plan_padding():
     """Swept cells over real cells for the benchmark workload stay small (power-of-two
     groups alone gave 1.29 for int32 lanes): the
     lane-group size is chosen per subject length so that row blocks divide
     evenly over the group (567 rows = 18 blocks of 32 or 36 of 16)."""
-    db = swdb.Database.describe(_lengths("config1"))
+    db = swdb.Database.describe(_lengths("q567_vs_200k"))
     try:
         for mode, spl, bound in (("i32", 1, 1.13), ("i16", 2, 1.12)):
             info = check_plan(db, [567], swdb.options(mode=mode), spl)

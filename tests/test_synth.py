@@ -5,16 +5,16 @@ import synth
 
 
 def test_deterministic():
-    a = synth.config(0)
-    b = synth.config(0)
+    a = synth.workload("q64_vs_2k")
+    b = synth.workload("q64_vs_2k")
     assert np.array_equal(a.db.residues, b.db.residues)
     assert np.array_equal(a.queries[0], b.queries[0])
-    c = synth.config(0, seed=1)
+    c = synth.workload("q64_vs_2k", seed=1)
     assert not np.array_equal(a.db.residues, c.db.residues)
 
 
-def test_config0_shape():
-    w = synth.config(0)
+def test_q64_vs_2k_shape():
+    w = synth.workload("q64_vs_2k")
     assert len(w.queries) == 1 and len(w.queries[0]) == 64
     assert w.db.nseq == 2000
     assert w.db.lengths.min() >= 32 and w.db.lengths.max() <= 512
@@ -23,7 +23,7 @@ def test_config0_shape():
 
 
 def test_lognormal_law():
-    w = synth.config(1, scale=0.1)
+    w = synth.workload("q567_vs_200k", scale=0.1)
     L = w.db.lengths
     assert L.min() >= 10 and L.max() <= 35000
     assert abs(np.median(L) - 300) < 10
