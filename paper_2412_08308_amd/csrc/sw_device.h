@@ -150,7 +150,7 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
     const int ncols = it.ncols;
     const int nbr = qd.nbr;
     const int P = (nbr + K - 1) / K;
-    const int nsteps = MULTI ? ((ncols + K - 1 + 15) & ~15) : ncols;
+    const int nsteps = MULTI ? ((ncols + K - 1 + 3) & ~3) : ncols;   // multiple of 4
     const int go = a.go, ge = a.ge;
     const uint8_t* __restrict__ gprof = a.prof + qd.prof_off;
     // this lane's slot entries: column c is lslot[slot_col(c, nsubw)] (a
@@ -171,8 +171,9 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
         uint4 rv = (head && 0 < own) ? resp[0] : pad16();
         for (int blk = 0; blk < nsteps; blk += 16) {
             const uint4 rvn = (head && blk + 16 < own) ? resp[(blk + 16) * 4] : pad16();
+            const int n4 = min(4, (nsteps - blk) >> 2);   // 4-column groups in this block
 #pragma unroll 1
-            for (int k4 = 0; k4 < 4; ++k4) {
+            for (int k4 = 0; k4 < n4; ++k4) {
                 const int col0 = blk + 4 * k4;
                 const uint32_t w = rv.x;                      // columns col0..col0+3
                 rv = make_uint4(rv.y, rv.z, rv.w, 0u);
@@ -286,7 +287,7 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
     const int ncols = it.ncols;
     const int nbr = qd.nbr;
     const int P = (nbr + K - 1) / K;
-    const int nsteps = MULTI ? ((ncols + K - 1 + 15) & ~15) : ncols;
+    const int nsteps = MULTI ? ((ncols + K - 1 + 3) & ~3) : ncols;   // multiple of 4
     const uint32_t go2 = (uint32_t)(a.go & 0xffff) * 0x10001u;
     const uint32_t ge2 = (uint32_t)(a.ge & 0xffff) * 0x10001u;
     const uint32_t ngo2 = (uint32_t)((-a.go) & 0xffff) * 0x10001u;
@@ -312,8 +313,9 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
         for (int blk = 0; blk < nsteps; blk += 16) {
             const uint4 rvnA = (head && blk + 16 < ownA) ? respA[(blk + 16) * 4] : pad16();
             const uint4 rvnB = (head && blk + 16 < ownB) ? respB[(blk + 16) * 4] : pad16();
+            const int n4 = min(4, (nsteps - blk) >> 2);   // 4-column groups in this block
 #pragma unroll 1
-            for (int k4 = 0; k4 < 4; ++k4) {
+            for (int k4 = 0; k4 < n4; ++k4) {
                 const int col0 = blk + 4 * k4;
                 const uint32_t wA = rvA.x, wB = rvB.x;        // columns col0..col0+3
                 rvA = make_uint4(rvA.y, rvA.z, rvA.w, 0u);

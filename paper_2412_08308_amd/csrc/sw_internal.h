@@ -26,7 +26,7 @@ constexpr int kI16Rows = 24;       // query rows per lane of the packed 16-bit v
 // marks items whose per-lane work is far above the planner's target).
 struct Item {
     int32_t s0;      // first sorted subject index
-    int32_t ncols;   // columns to sweep: longest subject of the item, rounded up to 16
+    int32_t ncols;   // columns to sweep: longest subject of the item, rounded up to 4
     int32_t q;       // query index in the batch
     int32_t meta;
 };

@@ -195,9 +195,9 @@ int64_t prof_bytes_for(int nbr, int rows, int elem)
 // times the rows of all its passes.
 int64_t lane_work(int64_t n, int K, int nbr, int rows)
 {
-    const int64_t cols = K == 1 ? align_up(n, 16) : align_up(n + K - 1, 16);
+    const int64_t cols = K == 1 ? align_up(n, 4) : align_up(n + K - 1, 4);
     const int64_t passes = nbr == 0 ? 0 : ceil_div(nbr, K);
-    return std::max<int64_t>(cols, 16) * passes * rows;
+    return std::max<int64_t>(cols, 4) * passes * rows;
 }
 
 // Lane cells the wavefront sweeps per subject with lane groups of K: all 64
@@ -253,7 +253,7 @@ std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, con
         const int64_t take = std::min<int64_t>(per, N - s);
         Item it;
         it.s0 = (int32_t)s;
-        it.ncols = (int32_t)align_up(n, 16);
+        it.ncols = (int32_t)align_up(n, 4);
         it.q = 0;
         const int64_t lw = lane_work(n, K, nbr, r.rows);
         // bit 24: critical-path item (per-lane work well above the target)

@@ -41,13 +41,13 @@ def check_plan(db, qlens, opt, spl):
         assert nsub > 0, "no empty items"
         assert 1 <= K <= 64
         nbr = -(-qlens[q] // rows)
-        cols = ncols if K == 1 else (int(slen[s0]) + K - 1 + 15) // 16 * 16
-        lw = max(cols, 16) * -(-nbr // K) * rows       # per-lane cells of the item
+        cols = ncols if K == 1 else (int(slen[s0]) + K - 1 + 3) // 4 * 4
+        lw = max(cols, 4) * -(-nbr // K) * rows        # per-lane cells of the item
         if last is not None and last[0] == q:
             assert lw <= last[1], "items of a query not in decreasing per-lane work"
         last = (q, lw)
         assert nsub <= (WAVE // K) * spl
-        assert ncols % 16 == 0 and ncols == (int(slen[s0]) + 15) // 16 * 16
+        assert ncols % 4 == 0 and ncols == (int(slen[s0]) + 3) // 4 * 4
         assert np.all(slen[s0:s0 + nsub] <= ncols)
         seen[q, s0:s0 + nsub] += 1
         if nbr > K:
