@@ -9,9 +9,11 @@ exact int32 rescore of 16-bit overflows.  GCUPS = query length x database
 residues / step time (the paper's Section 3.2 definition).
 
 Printed (one JSON line): the headline GCUPS of the default exact mode, the
-int32-lane kernel on the same input, a batched 20-query launch, the
-integer-VALU roofline of the search kernel (timed live with HIP events on its
-stream), and the CPU oracle timed on a bounded sample on this host.
+int32-lane kernel on the same input, a batched 20-query launch, the 16-bit
+overflow workload, a Poisson serving run, single long DNA pairs at the
+paper's pairwise sizes, the integer-VALU roofline of the search kernel (timed
+live with HIP events on its stream), and the CPU oracle timed on a bounded
+sample on this host.
 
 Only one GPU is used; ``--gpus N`` with N > 1 exits with a message.
 """
@@ -70,6 +72,16 @@ def isa_counts():
 
 KNOBS = {}
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_search_q567_vs_200k.json")
+
+# kernel variant (sw_plan_stats.variant) -> (hot-loop instruction count key of
+# isa_count.py, kernel); the count is that of single-lane groups (K = 1), the
+# fewest instructions per cell the variant issues
+VARIANTS = {
+    0: ("i32_p8_lds_k1", "k_search<32,1,false> (int32 lanes, 8-bit profile)"),
+    1: ("i32_p16_lds_k1", "k_search<32,2,false> (int32 lanes, 16-bit profile)"),
+    2: ("i16_lds_k1", "k_search<24,2,true> (packed 16-bit lanes, 16-bit profile)"),
+    3: ("i16_p8_lds_k1", "k_search<24,1,true> (packed 16-bit lanes, 8-bit profile)"),
+}
 
 
 def kernel_fingerprint() -> str:
@@ -147,6 +159,7 @@ def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False)
             ev.destroy(x)
     flagged = gdb.flagged_count(ws) if mode != "i32" else 0
     plan = gdb.plan_info(lens, base)
+    plan["variant"] = swdb.select_variant(sm, go, base)   # plan_info reports the 16-bit sizing variant
     return dict(wall_ms=wall * 1e3, kernel_ms=sum(k) / len(k), kernel_min_ms=min(k),
                 rescore_ms=sum(r) / len(r), flagged=flagged, plan=plan, out=out)
 
@@ -221,6 +234,55 @@ def planted(args, ev):
             "i32_search_ms": round(b["kernel_ms"], 2), "cells": cells}
 
 
+def pairwise(args, ev):
+    """Single long DNA pairs at the sizes of the paper's pairwise workload
+    (synthetic homologous sequences, +1/-3, gaps 5/2): the whole device on one
+    matrix through anti-diagonal tile launches.  The largest pairs (9T and 35T
+    cells) run once each."""
+    import numpy as np
+    import torch
+
+    import paper_2412_08308_amd as swdb
+    import synth
+    sm = synth.dna_matrix(synth.DNA_MATCH, synth.DNA_MISMATCH)
+    go, ge = synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND
+    runs = []
+    for k in args.pair_sizes:
+        m, n = synth.DNA_PAIR_SIZES[k]
+        a, b = synth.dna_pair(m, n, seed=k)
+        qa, qb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        ws = torch.empty(swdb.pair_workspace_bytes(m, n), dtype=torch.uint8, device="cuda")
+        out = torch.empty(1, dtype=torch.int32, device="cuda")
+        big = m * n > 2e12
+        steps, warm = (1, 0) if big else (args.pair_steps, 1)
+        for _ in range(warm):
+            swdb.pair_score(qa, qb, sm, go, ge, workspace=ws, out=out)
+        torch.cuda.synchronize()
+        walls, kers = [], []
+        for _ in range(steps):
+            o = swdb.options()
+            e0, e1 = ev.create(), ev.create()
+            o.ev_search_begin, o.ev_search_end = e0.value, e1.value
+            t0 = time.perf_counter()
+            swdb.pair_score(qa, qb, sm, go, ge, opt=o, workspace=ws, out=out)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+            kers.append(ev.ms(e0, e1))
+            ev.destroy(e0)
+            ev.destroy(e1)
+        wall = sum(walls) / len(walls)
+        plan = swdb.pair_plan(m, n, cu_count=torch.cuda.get_device_properties(0).multi_processor_count)
+        runs.append({"m": m, "n": n, "cells": m * n, "gcups": round(m * n / wall / 1e9, 1),
+                     "ms": round(wall * 1e3, 2), "tiles_ms": round(sum(kers) / len(kers), 2),
+                     "score": int(out.cpu().item()), "steps": steps,
+                     "plan": {k2: plan[k2] for k2 in ("lanes", "cols", "bands", "chunks", "launches")},
+                     "model_ms": round(plan["est_ms"], 1)})
+        print(f"[bench] pair {m}x{n}: {runs[-1]['gcups']} GCUPS", file=sys.stderr, flush=True)
+        del qa, qb, ws
+    return {"workload": "one DNA pair per size (paper's pairwise sizes, synthetic 80%-identity homologs, "
+                        "+1/-3, gaps 5/2), int32 lanes, anti-diagonal tile launches", "runs": runs}
+
+
 def cpu_baseline(w, seconds: float):
     """The oracle (plain C, int64, threads over subjects) on a random sample of
     the same database, sized for about ``seconds`` of host time."""
@@ -275,6 +337,10 @@ def main(argv=None):
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-planted", action="store_true")
     ap.add_argument("--planted-steps", type=int, default=3)
+    ap.add_argument("--no-pair", action="store_true")
+    ap.add_argument("--pair-sizes", type=int, nargs="+", default=[0, 1, 2, 3, 4],
+                    help="indices into the paper's DNA pair sizes (162Kx172K .. 7Mx5M)")
+    ap.add_argument("--pair-steps", type=int, default=2)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rho", type=float, nargs="+", default=[0.5, 0.8])
     ap.add_argument("--serve-scale", type=float, default=1.0)
@@ -334,16 +400,13 @@ def main(argv=None):
         parity = {"sampled_subjects": int(len(ids)),
                   "mismatches": int(np.sum(g1 != exp) + np.sum(g2 != exp))}
 
-    # the int32 kernels take 8-bit profile entries when every score + Go fits
-    p8 = int(w.matrix.max()) + w.gap_open <= 127 and int(w.matrix.min()) + w.gap_open >= -128
-    i32_isa = "i32_p8_lds_k1" if p8 else "i32_p16_lds_k1"
     traffic = traffic_bytes(args.mode)
     variant = main_run["plan"]["variant"]
-    key = "i16_lds_k1" if variant == 2 else i32_isa
+    key, kname = VARIANTS[variant]
     ops = isa[key]["valu_per_cell"]
     kernel_s = main_run["kernel_ms"] / 1e3
     achieved = cells * ops / kernel_s / 1e12
-    i32_key = "i16_lds_k1" if i32_run["plan"]["variant"] == 2 else i32_isa
+    i32_key = VARIANTS[i32_run["plan"]["variant"]][0]
     gcups = cells / (main_run["wall_ms"] / 1e3) / 1e9
 
     batched = None
@@ -362,6 +425,7 @@ def main(argv=None):
         batched["gcups"] = max(v["gcups"] for k, v in batched.items() if isinstance(v, dict))
 
     overflow = None if args.no_planted else planted(args, ev)
+    pair = None if args.no_pair else pairwise(args, ev)
     latency = None if args.no_serve else serving(args, gcups, args.mode)
     cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_seconds)
 
@@ -387,8 +451,7 @@ def main(argv=None):
                      "traffic_detail": traffic,
                      "algorithmic_bytes": int(w.db.total + len(w.queries[0]) + 4 * w.db.nseq),
                      "kernel_fingerprint": kernel_fingerprint(),
-                     "kernel": "k_search<24,2,true> (packed 16-bit lanes)" if variant == 2
-                     else ("k_search<32,1,false> (int32 lanes)" if p8 else "k_search<32,2,false> (int32 lanes)"),
+                     "kernel": kname,
                      "isa_valu_per_cell": ops, "search_kernel_ms": round(main_run["kernel_ms"], 3),
                      "isa_peak_gcups": round(PEAK_VALU_TOPS * 1e3 / ops, 1),
                      "paper_model_peak_gcups": round(PEAK_VALU_TOPS * 1e3 / PAPER_OPS_PER_CELL, 1),
@@ -406,6 +469,7 @@ def main(argv=None):
             "schedules": [{k: e[k] for k in ("qlen", "mode", "waves", "lane_cells", "gcups")} for e in tuning]},
         "overflow": overflow,
         "batched": batched,
+        "pairwise": pair,
         "latency": latency,
         "parity": parity,
         "plan": {k: main_run["plan"][k] for k in ("lane_cells", "items", "launches", "grid", "rows")},

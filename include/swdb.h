@@ -67,10 +67,15 @@ typedef struct sw_options {
     int32_t mode;          /* SW_MODE_*                                            */
     int32_t waves;         /* wavefronts per workgroup (1..8)                      */
     int32_t lane_cells;    /* target cells per lane per work item (load balance)  */
-    int32_t max_lanes;     /* largest lane group per subject (1..64, power of 2)   */
+    int32_t max_lanes;     /* largest lane group per subject (1..64)               */
     int32_t lds_limit;     /* largest query profile staged in LDS, bytes           */
     int32_t grid_limit;    /* cap on persistent workgroups (0 = fill the device)   */
-    int32_t reserved[10];
+    int32_t wide_profile;  /* 1: 16-bit profile entries even where 8 bits hold
+                              every s + Go (measurement and testing)             */
+    int32_t pair_cols;     /* sw_pair_score: subject columns per tile (multiple
+                              of 16, <= 2^20; 0 = planner); max_lanes sets the
+                              lanes per band there (a power of two)              */
+    int32_t reserved[8];
     /* Optional timing events (created by the caller, may be NULL): recorded on
        the search stream immediately before the search kernel, immediately
        after it, and after the int32 rescore (16-bit modes).                   */
@@ -96,8 +101,10 @@ typedef struct sw_plan_stats {
     int64_t grid;          /* persistent workgroups launched                       */
     int64_t slot_bytes;    /* per-wavefront pass-boundary scratch                  */
     int64_t workspace;     /* bytes sw_workspace_bytes() returns                   */
-    int32_t variant;       /* kernel variant (0: int32 8-bit profile, 1: int32
-                              16-bit profile, 2: packed 16-bit)                    */
+    int32_t variant;       /* kernel variant (0: int32 lanes, 8-bit profile; 1:
+                              int32 lanes, 16-bit profile; 2: packed 16-bit lanes,
+                              16-bit profile; 3: packed 16-bit lanes, 8-bit
+                              profile)                                           */
     int32_t rows;          /* query rows per lane                                  */
 } sw_plan_stats;
 
@@ -155,6 +162,16 @@ int sw_db_info(sw_db_t db, int64_t* nseq, int64_t* residues, int64_t* device_byt
  * under `opt` (NULL = defaults).  Returns 0 on invalid arguments.
  */
 size_t sw_workspace_bytes(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt);
+
+/*
+ * Kernel variant (the numbering of sw_plan_stats.variant) a search runs with
+ * the HOST 32x32 matrix `sm`, gap-open penalty `go` and options `opt` (NULL =
+ * defaults; SW_MODE_TUNED answers for SW_MODE_AUTO): 8-bit profile entries
+ * wherever every s + Go fits (int32 lanes: [-128, 127]; packed lanes: [0, 127]),
+ * else 16-bit.  sw_plan_info, which does not see the matrix, reports the
+ * 16-bit variant its workspace sizing assumes.  Negative code on invalid input.
+ */
+int sw_select_variant(const int32_t* sm, int32_t go, const sw_options* opt);
 
 /* Plan summary for the same arguments (host only; no HIP call). */
 int sw_plan_info(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt,
@@ -252,6 +269,54 @@ int64_t sw_flagged_count(const void* workspace, hipStream_t stream);
 const char* sw_strerror(int code);
 const char* sw_last_error(void);   /* thread-local detail of the last failure */
 const char* sw_version(void);
+
+/* ------------------------------------------------------------------ one long pair
+ *
+ * Intra-task alignment (paper Section 2.2, Fig. 1; the pairwise DNA workload
+ * of Section 4.1): the score of ONE pair, query `query[m]` along the rows and
+ * subject `subject[n]` along the columns, with the whole device working on the
+ * single matrix.  The matrix is tiled into bands of K*32 query rows by chunks
+ * of `cols` subject columns; the tiles of each anti-diagonal run in one launch
+ * (int32 lanes, K lanes pipelined per band) and pass their boundary rows and
+ * columns to the next launch through the workspace.  Same recurrence, borders
+ * and result as sw_db_search; int32 score.
+ */
+typedef struct sw_pair_stats {
+    int32_t lanes;         /* K: lanes per band (band = 32*K query rows)          */
+    int32_t cols;          /* subject columns per tile                            */
+    int64_t bands;         /* ceil(m / (32*K))                                    */
+    int64_t chunks;        /* ceil(n / cols)                                      */
+    int64_t launches;      /* anti-diagonals: bands + chunks - 1                  */
+    double est_ms;         /* the planner's time model                            */
+    int64_t workspace;     /* sw_pair_workspace_bytes                             */
+} sw_pair_stats;
+
+/* Workspace bytes sw_pair_score needs for lengths m, n (0 on invalid input);
+   independent of the matrix and the device. */
+size_t sw_pair_workspace_bytes(int64_t m, int64_t n, const sw_options* opt);
+
+/* The schedule sw_pair_score would run on a device with `cu_count` compute
+   units (0 = 256); host only.  opt->max_lanes (a power of two) fixes K,
+   opt->pair_cols fixes the chunk width. */
+int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, sw_pair_stats* out);
+
+/*
+ * Score of one pair.
+ *   query, subject  device, uint8[m], uint8[n]; codes are read modulo 32
+ *                   (m, n in [0, SW_MAX_QLEN])
+ *   subst_matrix    HOST, int32[32*32], row = query residue, entries in [-128, 127]
+ *   gap_open/extend as in sw_db_search
+ *   opt             NULL or options (max_lanes, pair_cols, ev_search_begin/end)
+ *   workspace       device, >= sw_pair_workspace_bytes(m, n, opt), 256-byte aligned
+ *   score_out       device, int32[1]
+ * Asynchronous on `stream`; enqueues one preparation kernel, the profile
+ * kernel and bands + chunks - 1 tile launches.  Returns SW_EINVAL, SW_ENOMEM
+ * (workspace too small) or SW_EHIP.
+ */
+int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n,
+                  const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
+                  const sw_options* opt, void* workspace, size_t ws_bytes, int32_t* score_out,
+                  hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("lane_cells", ctypes.c_int32), ("max_lanes", ctypes.c_int32),
                 ("lds_limit", ctypes.c_int32), ("grid_limit", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 10),
+                ("wide_profile", ctypes.c_int32), ("pair_cols", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8),
                 ("ev_search_begin", ctypes.c_void_p), ("ev_search_end", ctypes.c_void_p),
                 ("ev_rescore_end", ctypes.c_void_p)]
 
@@ -76,6 +77,15 @@ class PlanStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class PairStats(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("cols", ctypes.c_int32), ("bands", ctypes.c_int64),
+                ("chunks", ctypes.c_int64), ("launches", ctypes.c_int64), ("est_ms", ctypes.c_double),
+                ("workspace", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -100,6 +110,14 @@ def lib():
     L.sw_workspace_bytes.argtypes = [vp, i32, vp, ctypes.POINTER(Options)]
     L.sw_plan_info.restype = ctypes.c_int
     L.sw_plan_info.argtypes = [vp, i32, vp, ctypes.POINTER(Options), ctypes.POINTER(PlanStats)]
+    L.sw_pair_workspace_bytes.restype = sz
+    L.sw_pair_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Options)]
+    L.sw_pair_plan.restype = ctypes.c_int
+    L.sw_pair_plan.argtypes = [i64, i64, ctypes.POINTER(Options), i32, ctypes.POINTER(PairStats)]
+    L.sw_pair_score.restype = ctypes.c_int
+    L.sw_pair_score.argtypes = [vp, i64, vp, i64, vp, i32, i32, ctypes.POINTER(Options), vp, sz, vp, vp]
+    L.sw_select_variant.restype = i32
+    L.sw_select_variant.argtypes = [vp, i32, ctypes.POINTER(Options)]
     L.sw_db_search_ex.restype = ctypes.c_int
     L.sw_db_search_ex.argtypes = [vp, vp, i32, vp, i32, i32, ctypes.POINTER(Options), vp, sz, vp, vp]
     L.sw_db_search_batch.restype = ctypes.c_int
@@ -146,12 +164,23 @@ def version() -> str:
     return lib().sw_version().decode()
 
 
-def options(mode="auto", waves=0, lane_cells=0, max_lanes=0, lds_limit=0, grid_limit=0) -> Options:
+def options(mode="auto", waves=0, lane_cells=0, max_lanes=0, lds_limit=0, grid_limit=0,
+            wide_profile=0, pair_cols=0) -> Options:
     o = Options()
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.waves, o.lane_cells, o.max_lanes = int(waves), int(lane_cells), int(max_lanes)
     o.lds_limit, o.grid_limit = int(lds_limit), int(grid_limit)
+    o.wide_profile, o.pair_cols = int(wide_profile), int(pair_cols)
     return o
+
+
+def select_variant(sm, gap_open: int, opt: Optional[Options] = None) -> int:
+    """``sw_select_variant``: the kernel variant a search with this matrix,
+    gap-open penalty and options runs (numbering of ``plan_info()["variant"]``)."""
+    m = _matrix(sm)
+    v = lib().sw_select_variant(m.ctypes.data, int(gap_open), ctypes.byref(opt) if opt is not None else None)
+    _check(min(v, 0), "sw_select_variant")
+    return int(v)
 
 
 def _matrix(sm) -> np.ndarray:
@@ -221,6 +250,42 @@ def search(query, residues, offsets, lengths, matrix, gap_open: int, gap_extend:
                             _dev(lengths, torch.int32, "lengths"), n, sm.ctypes.data,
                             int(gap_open), int(gap_extend), _dev(out, torch.int32, "out"), _stream(stream))
     _check(rc, "sw_db_search")
+    return out
+
+
+def pair_plan(m: int, n: int, opt: Optional[Options] = None, cu_count: int = 0) -> dict:
+    """``sw_pair_plan``: the tile schedule of one long pair (host only)."""
+    st = PairStats()
+    _check(lib().sw_pair_plan(int(m), int(n), ctypes.byref(opt) if opt is not None else None, int(cu_count),
+                              ctypes.byref(st)), "sw_pair_plan")
+    return st.as_dict()
+
+
+def pair_workspace_bytes(m: int, n: int, opt: Optional[Options] = None) -> int:
+    v = lib().sw_pair_workspace_bytes(int(m), int(n), ctypes.byref(opt) if opt is not None else None)
+    if v == 0:
+        raise SwdbError(-1, "sw_pair_workspace_bytes", lib().sw_last_error().decode())
+    return int(v)
+
+
+def pair_score(query, subject, matrix, gap_open: int, gap_extend: int, opt: Optional[Options] = None,
+               workspace=None, out=None, stream=None):
+    """``sw_pair_score``: score of one long pair on the device (asynchronous on
+    ``stream``).  Returns a device int32 tensor of one element."""
+    import torch
+    m, n = int(query.numel()), int(subject.numel())
+    dev = query.device if m else subject.device
+    if workspace is None:
+        workspace = torch.empty(pair_workspace_bytes(m, n, opt), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = torch.empty(1, dtype=torch.int32, device=dev)
+    sm = _matrix(matrix)
+    o = ctypes.byref(opt) if opt is not None else None
+    rc = lib().sw_pair_score(_dev(query, torch.uint8, "query") if m else None, m,
+                             _dev(subject, torch.uint8, "subject") if n else None, n, sm.ctypes.data,
+                             int(gap_open), int(gap_extend), o, _dev(workspace, torch.uint8, "workspace"),
+                             int(workspace.numel()), _dev(out, torch.int32, "out"), _stream(stream))
+    _check(rc, "sw_pair_score")
     return out
 
 

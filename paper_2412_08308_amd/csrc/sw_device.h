@@ -66,12 +66,28 @@ __device__ __forceinline__ uint4 ld16(const uint8_t* __restrict__ g, uint32_t of
         return *reinterpret_cast<const uint4*>(g + off);
 }
 
-template <int NV, bool LDSP>
-__device__ __forceinline__ void ldprof(uint4 (&v)[NV], const uint8_t* __restrict__ g, uint32_t off)
+template <bool LDSP>
+__device__ __forceinline__ uint2 ld8(const uint8_t* __restrict__ g, uint32_t off)
 {
+    if constexpr (LDSP)
+        return *reinterpret_cast<const uint2*>(sw_lds + off);
+    else
+        return *reinterpret_cast<const uint2*>(g + off);
+}
+
+// The NB profile bytes of one residue code in one row block (NB a multiple of
+// 8), as 16-byte vectors; a trailing half vector is zero-filled.
+template <int NB, bool LDSP>
+__device__ __forceinline__ void ldprof(uint4 (&v)[(NB + 15) / 16], const uint8_t* __restrict__ g, uint32_t off)
+{
+    static_assert(NB % 8 == 0, "profile row blocks are whole 8-byte units");
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
+    for (int i = 0; i < NB / 16; ++i)
         v[i] = ld16<LDSP>(g, off + 16 * i);
+    if constexpr (NB % 16 == 8) {
+        const uint2 t = ld8<LDSP>(g, off + NB - 8);
+        v[NB / 16] = make_uint4(t.x, t.y, 0u, 0u);
+    }
 }
 
 // profile entry r of a loaded row block (sign-extended)
@@ -130,9 +146,10 @@ template <int R, int ES, bool LDSP, bool MULTI>
 __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, const QueryDesc& qd,
                                          int2* __restrict__ slot, int lane)
 {
-    constexpr uint32_t CS = R * ES + 16;      // code stride (bytes)
-    constexpr uint32_t BS = kCodes * CS;      // row-block stride (bytes)
-    constexpr int NV = R * ES / 16;
+    constexpr uint32_t CS = code_stride(R, ES);   // code stride (bytes)
+    constexpr uint32_t BS = kCodes * CS;          // row-block stride (bytes)
+    constexpr int NB = R * ES;                    // profile bytes per code
+    constexpr int NV = (NB + 15) / 16;
 
     const int nsub = it.meta & 0xffff;
     const int K = MULTI ? ((it.meta >> 16) & 0xff) : 1; // lanes per subject, 1..64
@@ -200,7 +217,7 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
                         ft = head ? ft : fd;
                     }
                     uint4 pv[NV];
-                    ldprof<NV, LDSP>(pv, gprof, pbase + (uint32_t)code * CS);
+                    ldprof<NB, LDSP>(pv, gprof, pbase + (uint32_t)code * CS);
 
                     int dg = ydiag;
                     ydiag = yt;
@@ -259,13 +276,16 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
 
 // ------------------------------------------------------------------ packed 16-bit item
 
-template <int R, bool LDSP, bool MULTI>
+// ES = profile entry bytes: 2 (signed 16-bit) or 1 (8-bit entries in
+// [0, 127], zero-extended while the two subjects' entries are paired).
+template <int R, int ES, bool LDSP, bool MULTI>
 __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, const QueryDesc& qd,
                                          int2* __restrict__ slot, int lane)
 {
-    constexpr uint32_t CS = R * 2 + 16;
+    constexpr uint32_t CS = code_stride(R, ES);
     constexpr uint32_t BS = kCodes * CS;
-    constexpr int NV = R * 2 / 16;
+    constexpr int NB = R * ES;
+    constexpr int NV = (NB + 15) / 16;
 
     const int nsub = it.meta & 0xffff;
     const int K = MULTI ? ((it.meta >> 16) & 0xff) : 1;
@@ -343,18 +363,27 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
                         ft = head ? ft : fd;
                     }
                     uint4 pa[NV], pb[NV];
-                    ldprof<NV, LDSP>(pa, gprof, pbase + (uint32_t)(code & 0xff) * CS);
-                    ldprof<NV, LDSP>(pb, gprof, pbase + (uint32_t)(code >> 8) * CS);
+                    ldprof<NB, LDSP>(pa, gprof, pbase + (uint32_t)(code & 0xff) * CS);
+                    ldprof<NB, LDSP>(pb, gprof, pbase + (uint32_t)(code >> 8) * CS);
 
                     v2s dg = as2(ydiag);
                     ydiag = yt;
                     v2s hup = as2(yt), F = as2(ft);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const uint32_t xa = comp(pa[r >> 3], (r >> 1) & 3);
-                        const uint32_t xb = comp(pb[r >> 3], (r >> 1) & 3);
-                        // (subject A entry, subject B entry) of row r
-                        const uint32_t pr = __builtin_amdgcn_perm(xb, xa, (r & 1) ? 0x07060302u : 0x05040100u);
+                        // (subject A entry, subject B entry) of row r; selector
+                        // bytes 0-3 pick from xa, 4-7 from xb, 0x0c gives 0x00
+                        uint32_t pr;
+                        if constexpr (ES == 2) {
+                            const uint32_t xa = comp(pa[r >> 3], (r >> 1) & 3);
+                            const uint32_t xb = comp(pb[r >> 3], (r >> 1) & 3);
+                            pr = __builtin_amdgcn_perm(xb, xa, (r & 1) ? 0x07060302u : 0x05040100u);
+                        } else {
+                            const uint32_t xa = comp(pa[r >> 4], (r >> 2) & 3);
+                            const uint32_t xb = comp(pb[r >> 4], (r >> 2) & 3);
+                            pr = __builtin_amdgcn_perm(xb, xa, 0x0c000c00u | (uint32_t)(r & 3) |
+                                                                   ((uint32_t)(4 + (r & 3)) << 16));
+                        }
                         const v2s t = __builtin_elementwise_add_sat(dg, as2(pr));
                         const v2s e = __builtin_elementwise_max(__builtin_elementwise_sub_sat(as2(E[r]), vge), as2(Y[r]));
                         F = __builtin_elementwise_max(__builtin_elementwise_sub_sat(F, vge), hup);
@@ -464,11 +493,11 @@ __device__ __forceinline__ void run_item(const SearchArgs& a, const Item& it, co
         __builtin_amdgcn_s_setprio(2);
     if constexpr (I16) {
         if (qd.lds) {
-            if (multi) item_i16<R, true, true>(a, it, qd, slot, lane);
-            else item_i16<R, true, false>(a, it, qd, slot, lane);
+            if (multi) item_i16<R, ES, true, true>(a, it, qd, slot, lane);
+            else item_i16<R, ES, true, false>(a, it, qd, slot, lane);
         } else {
-            if (multi) item_i16<R, false, true>(a, it, qd, slot, lane);
-            else item_i16<R, false, false>(a, it, qd, slot, lane);
+            if (multi) item_i16<R, ES, false, true>(a, it, qd, slot, lane);
+            else item_i16<R, ES, false, false>(a, it, qd, slot, lane);
         }
     } else {
         if (qd.lds) {

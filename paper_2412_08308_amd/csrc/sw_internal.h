@@ -21,6 +21,11 @@ constexpr uint8_t kPad = 32;         // pad code: subject tails and chunk fill
 constexpr int kWave = 64;
 constexpr int kI16Rows = 24;       // query rows per lane of the packed 16-bit variant
 
+// Bytes between the profile entries of consecutive residue codes inside a row
+// block: R entries of ES bytes, rounded up to a multiple of 16 with at least 8
+// spare bytes (16-byte aligned loads, codes spread over the LDS banks).
+__host__ __device__ constexpr int code_stride(int R, int ES) { return (R * ES + 8 + 15) / 16 * 16; }
+
 // Work item (one wavefront).  meta = nsub | K << 16 | critical << 24 (K =
 // lanes per subject, 1..64, floor(64 / K) lane groups per wavefront; critical
 // marks items whose per-lane work is far above the planner's target).
@@ -36,7 +41,7 @@ struct QueryDesc {
     int64_t prof_off;   // byte offset of this query's profile in the profile area
     int32_t m;          // query length
     int32_t nbr;        // row blocks: ceil(m / R)
-    int32_t prof_bytes; // (nbr + 1) * 33 * code stride
+    int32_t prof_bytes; // (nbr + 1) * 33 * code_stride(R, entry bytes)
     int32_t lds;        // 1: profile staged in LDS; 0: read from global memory
     int32_t item_begin; // first work item of this query in the item array
     int32_t item_count; // number of work items of this query
@@ -82,7 +87,32 @@ struct ProfileArgs {
     int32_t* heads;
     int32_t nq;
     int32_t go;
+    int32_t pad;                 // entry of pad codes and pad rows
     Matrix8 sm;
+};
+
+// One anti-diagonal of tiles of a single long pair (query rows x subject
+// columns).  Band b holds rows [b*K*R, (b+1)*K*R), lane g of its group rows
+// [(b*K + g)*R, +R); chunk c holds columns [c*wc, (c+1)*wc).  Tiles (b, c)
+// with b + c = d run in one launch; boundaries pass between launches through
+// three buffers updated in place (each is read by a tile before that tile
+// overwrites it, and no two tiles of a launch share an entry):
+//   rowbuf[col]  (H - Go, F) of the bottom row of the band above, per column
+//   colbuf[row]  (H - Go, E) of the last column of the chunk to the left, per row
+//   corner[b*3 + c%3]  H - Go of the bottom-right cell of tile (b-1, c-1)
+struct PairArgs {
+    const uint8_t* subj;         // subject codes padded with the pad code to nc*wc (16-byte aligned)
+    const uint8_t* prof;         // query profile (nbr + 1 row blocks)
+    int2* rowbuf;                // [nc * wc]
+    int2* colbuf;                // [nb * K * R]
+    int32_t* corner;             // [(nb + 1) * 3]
+    int32_t* score;              // [1] running maximum (atomicMax)
+    int32_t nbr;                 // query row blocks: ceil(m / R)
+    int32_t nb, nc;              // bands, column chunks
+    int32_t K, wc;               // lanes per band, columns per chunk (multiple of 16)
+    int32_t go, ge;
+    int32_t d;                   // anti-diagonal: b + c
+    int32_t b_lo, ntiles;        // first band on the diagonal, tiles on it
 };
 
 // Kernel variants the runtime may launch.
@@ -90,6 +120,8 @@ enum Variant : int {
     kI32_R32_P8 = 0,   // int32 lanes, 32 rows, 8-bit profile
     kI32_R32_P16 = 1,  // int32 lanes, 32 rows, 16-bit profile
     kI16 = 2,          // packed 16-bit lanes, kI16Rows rows, 16-bit profile
+    kI16_P8 = 3,       // packed 16-bit lanes, kI16Rows rows, 8-bit profile with
+                       // every entry s + Go in [0, 127] (zero-extended)
 };
 
 struct LaunchInfo {
@@ -108,5 +140,11 @@ hipError_t launch_interleave(const uint8_t* src, const int64_t* src_off, const i
                              int64_t nthreads_total, const int64_t* block_prefix, int32_t nchunks,
                              uint8_t* dst, int32_t* bad, hipStream_t st);
 int search_occupancy(Variant v, int waves, int lds_bytes);   // workgroups per CU
+// Single long pair: the padded subject (codes modulo 32), the cleared score and
+// the query's profile descriptor; then one launch per anti-diagonal.
+constexpr int kPairRows = 32;        // query rows per lane (int32 lanes)
+hipError_t launch_pair_prep(const uint8_t* subj, int64_t n, int64_t n_pad, uint8_t* dst, int32_t* score,
+                            const QueryDesc& qd, QueryDesc* qd_out, int64_t* qoff_out, hipStream_t st);
+hipError_t launch_pair_diag(const PairArgs& a, int elem, hipStream_t st);
 
 }  // namespace swdb

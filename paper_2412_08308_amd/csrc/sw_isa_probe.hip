@@ -15,12 +15,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) i
     item_i32<R, ES, L, M>(a, it, qd, a.bnd + (int64_t)blockIdx.x * a.slot_elems, threadIdx.x & 63);
 }
 
-template <int R, bool L, bool M>
+template <int R, int ES, bool L, bool M>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) isa_i16(SearchArgs a)
 {
     const Item it = a.items[blockIdx.x];
     const QueryDesc qd = a.qd[0];
-    item_i16<R, L, M>(a, it, qd, a.bnd + (int64_t)blockIdx.x * a.slot_elems, threadIdx.x & 63);
+    item_i16<R, ES, L, M>(a, it, qd, a.bnd + (int64_t)blockIdx.x * a.slot_elems, threadIdx.x & 63);
 }
 
 template __global__ void isa_i32<32, 1, true, false>(SearchArgs);
@@ -29,10 +29,15 @@ template __global__ void isa_i32<32, 1, false, false>(SearchArgs);
 template __global__ void isa_i32<32, 1, false, true>(SearchArgs);
 template __global__ void isa_i32<32, 2, true, false>(SearchArgs);
 template __global__ void isa_i32<32, 2, false, false>(SearchArgs);
-template __global__ void isa_i16<24, true, false>(SearchArgs);
-template __global__ void isa_i16<24, true, true>(SearchArgs);
-template __global__ void isa_i16<24, false, false>(SearchArgs);
-template __global__ void isa_i16<24, false, true>(SearchArgs);
+template __global__ void isa_i16<24, 2, true, false>(SearchArgs);
+template __global__ void isa_i16<24, 2, true, true>(SearchArgs);
+template __global__ void isa_i16<24, 2, false, false>(SearchArgs);
+template __global__ void isa_i16<24, 2, false, true>(SearchArgs);
+template __global__ void isa_i16<24, 1, true, false>(SearchArgs);
+template __global__ void isa_i16<24, 1, true, true>(SearchArgs);
+template __global__ void isa_i16<24, 1, false, false>(SearchArgs);
+template __global__ void isa_i16<24, 1, false, true>(SearchArgs);
 template __global__ void isa_i32<24, 2, false, true>(SearchArgs);
+template __global__ void isa_i32<24, 1, false, true>(SearchArgs);
 
 }  // namespace swdb

@@ -6,10 +6,13 @@ namespace swdb {
 hipError_t launch_search_i32p8(const SearchArgs& a, int grid, int waves, int lds, hipStream_t st);
 hipError_t launch_search_i32p16(const SearchArgs& a, int grid, int waves, int lds, hipStream_t st);
 hipError_t launch_search_i16(const SearchArgs& a, int grid, int waves, int lds, hipStream_t st);
+hipError_t launch_search_i16p8(const SearchArgs& a, int grid, int waves, int lds, hipStream_t st);
 hipError_t launch_rescore_i16(const SearchArgs& a, int grid, int waves, hipStream_t st);
+hipError_t launch_rescore_i16p8(const SearchArgs& a, int grid, int waves, hipStream_t st);
 int occupancy_i32p8(int waves, int lds);
 int occupancy_i32p16(int waves, int lds);
 int occupancy_i16(int waves, int lds);
+int occupancy_i16p8(int waves, int lds);
 
 LaunchInfo variant_info(Variant v)
 {
@@ -17,6 +20,7 @@ LaunchInfo variant_info(Variant v)
     case kI32_R32_P8: return {32, 1, 1};
     case kI32_R32_P16: return {32, 2, 1};
     case kI16: return {kI16Rows, 2, 2};
+    case kI16_P8: return {kI16Rows, 1, 2};
     }
     return {0, 0, 0};
 }
@@ -24,7 +28,10 @@ LaunchInfo variant_info(Variant v)
 // Query profiles (the substitution term of the H equation, looked up per query
 // row and subject residue code): entry (row block rb, code c, row r) =
 // SM[Q[rb*R + r]][c] + Go for rows inside the query and codes < 32, the pad
-// value (most negative entry) elsewhere; row block nbr is entirely padding.
+// value elsewhere (the most negative entry, or 0 for the zero-extended 8-bit
+// profile of the packed lanes: a pad cell then adds -Go to its diagonal, so it
+// never exceeds the real cells it derives from); row block nbr is entirely
+// padding.
 // Block (0, 0) also clears the flag count, block (0, q) query q's queue head.
 template <typename PE>
 __global__ void __launch_bounds__(256) k_profile(ProfileArgs a, int R)
@@ -36,10 +43,10 @@ __global__ void __launch_bounds__(256) k_profile(ProfileArgs a, int R)
         a.heads[q] = 0;
     const QueryDesc qd = a.qd[q];
     const int entries = (qd.nbr + 1) * kCodes * R;
-    const int cse = R + 16 / (int)sizeof(PE);      // code stride in entries
+    const int cse = code_stride(R, (int)sizeof(PE)) / (int)sizeof(PE);   // code stride in entries
     PE* __restrict__ out = reinterpret_cast<PE*>(a.prof + qd.prof_off);
     const uint8_t* __restrict__ qs = a.queries + a.q_off[q];
-    const PE padv = sizeof(PE) == 1 ? (PE)-128 : (PE)-32768;
+    const PE padv = (PE)a.pad;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < entries; e += gridDim.x * blockDim.x) {
         const int r = e % R;
         const int c = (e / R) % kCodes;
@@ -116,6 +123,7 @@ hipError_t launch_search(Variant v, const SearchArgs& a, int grid, int waves, in
     case kI32_R32_P8: return launch_search_i32p8(a, grid, waves, lds_bytes, st);
     case kI32_R32_P16: return launch_search_i32p16(a, grid, waves, lds_bytes, st);
     case kI16: return launch_search_i16(a, grid, waves, lds_bytes, st);
+    case kI16_P8: return launch_search_i16p8(a, grid, waves, lds_bytes, st);
     }
     return hipErrorInvalidValue;
 }
@@ -124,6 +132,8 @@ hipError_t launch_rescore(Variant v, const SearchArgs& a, int grid, int waves, h
 {
     if (v == kI16)
         return launch_rescore_i16(a, grid, waves, st);
+    if (v == kI16_P8)
+        return launch_rescore_i16p8(a, grid, waves, st);
     return hipErrorInvalidValue;   // int32 variants never flag subjects
 }
 
@@ -133,6 +143,7 @@ int search_occupancy(Variant v, int waves, int lds_bytes)
     case kI32_R32_P8: return occupancy_i32p8(waves, lds_bytes);
     case kI32_R32_P16: return occupancy_i32p16(waves, lds_bytes);
     case kI16: return occupancy_i16(waves, lds_bytes);
+    case kI16_P8: return occupancy_i16p8(waves, lds_bytes);
     }
     return 1;
 }

@@ -1,0 +1,203 @@
+// Intra-task alignment of one long pair: every lane of the device works on
+// cells of a single matrix (paper Section 2.2 / Fig. 1, intra-task scheme; the
+// paper's pairwise workload aligns DNA sequences of 162K to 7M residues,
+// Section 4.1).
+//
+// The matrix is cut into tiles of K*R query rows (a band: K pipelined lanes of
+// R rows each, as in the database search) by wc subject columns (a chunk).
+// Tile (b, c) depends on (b-1, c), (b, c-1) and (b-1, c-1) only, so all tiles
+// of one anti-diagonal b + c = d are independent; the host launches the
+// diagonals in order on one stream.  No wave ever waits for another workgroup.
+// Boundaries travel between launches through in-place buffers (PairArgs).
+//
+// Each lane group runs one tile.  Lanes start from their rows of the chunk's
+// left boundary and keep H - Go and E in registers across the chunk; lane g
+// works on column step - g only while that is a column of the chunk (the
+// pipeline fill steps leave its state alone), the group head reads the band's
+// top boundary from rowbuf, the tail writes the band's bottom row back into it,
+// and after the sweep every lane writes its rows of the chunk's last column
+// into colbuf.
+#include "sw_device.h"
+
+namespace swdb {
+
+template <int R, int ES>
+__device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
+{
+    constexpr uint32_t CS = code_stride(R, ES);
+    constexpr uint32_t BS = kCodes * CS;
+    constexpr int NB = R * ES;
+    constexpr int NV = (NB + 15) / 16;
+
+    const int K = a.K;
+    const int nsubw = kWave / K;
+    const int sub = lane / K;
+    const int g = lane - sub * K;
+    const bool inb = sub < nsubw;
+    const int tile = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * nsubw) + (inb ? sub : 0);
+    const bool valid = inb && tile < a.ntiles;
+    const int b = a.b_lo + (valid ? tile : 0);
+    const int c = a.d - b;
+    const bool head = g == 0;
+    const bool tail = g == K - 1;
+    const int wc = a.wc;
+    const int64_t c0 = (int64_t)c * wc;
+    const int rb = b * K + g;
+    const int64_t row0 = (int64_t)rb * R;
+    const uint32_t pbase = (uint32_t)min(rb, a.nbr) * BS;
+    const int go = a.go, ge = a.ge;
+    const bool has_top = valid && b > 0;
+    const bool has_left = valid && c > 0;
+    const bool put_bottom = valid && tail && b < a.nb - 1;
+    const bool put_right = valid && c < a.nc - 1;
+    int2* __restrict__ top = a.rowbuf + c0;
+    int2* __restrict__ side = a.colbuf + row0;
+    const uint4* __restrict__ resp = reinterpret_cast<const uint4*>(a.subj + c0);
+
+    int Y[R], E[R];
+    if (has_left) {
+#pragma unroll
+        for (int r = 0; r < R; r += 2) {
+            const int4 v = *reinterpret_cast<const int4*>(side + r);
+            Y[r] = v.x; E[r] = v.y; Y[r + 1] = v.z; E[r + 1] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) { Y[r] = -go; E[r] = 0; }
+    }
+    // H - Go of the cell above-left of this lane's first row: the previous
+    // lane's last row in the chunk to the left, or the corner for the head
+    int ydiag = -go;
+    if (has_left)
+        ydiag = head ? (b > 0 ? a.corner[b * 3 + c % 3] : -go) : side[-1].x;
+    int ybot = -go, fbot = 0, code_prev = kPad;
+    int S = 0;
+
+    const int nsteps = (wc + K - 1 + 3) & ~3;
+    uint4 rv = head ? resp[0] : pad16();
+    for (int blk = 0; blk < nsteps; blk += 16) {
+        const uint4 rvn = head ? resp[(blk + 16) >> 4] : pad16();
+        const int n4 = min(4, (nsteps - blk) >> 2);
+#pragma unroll 1
+        for (int k4 = 0; k4 < n4; ++k4) {
+            const int col0 = blk + 4 * k4;
+            const uint32_t w = rv.x;
+            rv = make_uint4(rv.y, rv.z, rv.w, 0u);
+            int ringY[4], ringF[4];
+            if (has_top && head && col0 < wc) {
+                const int4* p4 = reinterpret_cast<const int4*>(top + col0);
+                const int4 v0 = p4[0], v1 = p4[1];
+                ringY[0] = v0.x; ringF[0] = v0.y; ringY[1] = v0.z; ringF[1] = v0.w;
+                ringY[2] = v1.x; ringF[2] = v1.y; ringY[3] = v1.z; ringF[3] = v1.w;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { ringY[k] = -go; ringF[k] = 0; }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                // the shifts run with every lane active (a shift reads other
+                // lanes' registers); the column body only for this lane's own
+                // columns 0..wc-1, so its state stays that of its last column
+                const int cd = shr1(code_prev);
+                const int yd = shr1(ybot), fd = shr1(fbot);
+                const int j = col0 + u - g;               // this lane's column
+                if ((unsigned)j < (unsigned)wc) {
+                    const int code = head ? (int)((w >> (8 * u)) & 0xffu) : cd;
+                    const int yt = head ? ringY[u] : yd;
+                    const int ft = head ? ringF[u] : fd;
+                    uint4 pv[NV];
+                    ldprof<NB, false>(pv, a.prof, pbase + (uint32_t)code * CS);
+
+                    int dg = ydiag;
+                    ydiag = yt;
+                    int hup = yt, F = ft;
+                    int hprev = 0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int t = dg + pent<ES>(pv, r);
+                        const int e = imax3(E[r] - ge, Y[r], 0);
+                        F = max(F - ge, hup);
+                        const int h = imax3(t, e, F);
+                        if (r & 1) {
+                            S = imax3(S, hprev, h);
+                            pin(S);
+                        } else {
+                            hprev = h;
+                        }
+                        dg = Y[r];
+                        hup = h - go;
+                        Y[r] = hup;
+                        E[r] = e;
+                    }
+                    ybot = hup;
+                    fbot = F;
+                    code_prev = code;
+                    if (put_bottom)
+                        top[j] = make_int2(ybot, fbot);
+                }
+            }
+        }
+        rv = rvn;
+    }
+    // right boundary: every lane's rows at the chunk's last column; the tail's
+    // bottom cell there is the corner of the tile down-right
+    if (put_right) {
+#pragma unroll
+        for (int r = 0; r < R; r += 2)
+            *reinterpret_cast<int4*>(side + r) = make_int4(Y[r], E[r], Y[r + 1], E[r + 1]);
+        if (put_bottom)
+            a.corner[(b + 1) * 3 + (c + 1) % 3] = ybot;
+    }
+    // tile maximum into the pair's score
+    S = valid ? S : 0;
+    for (int k = 32; k >= 1; k >>= 1)
+        S = max(S, __shfl_xor(S, k));
+    if (lane == 0 && S > 0)
+        atomicMax(a.score, S);
+}
+
+template <int R, int ES>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_pair_diag(PairArgs a)
+{
+    pair_tile<R, ES>(a, threadIdx.x & 63);
+}
+
+// Padded subject copy (codes taken modulo 32, pad code past the end) and the
+// score cleared; thread 0 also stores the query's profile descriptor and
+// offset, which the profile kernel reads from device memory.
+__global__ void __launch_bounds__(256) k_pair_prep(const uint8_t* __restrict__ src, int64_t n, int64_t n_pad,
+                                                   uint8_t* __restrict__ dst, int32_t* score, QueryDesc qd,
+                                                   QueryDesc* qd_out, int64_t* qoff_out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        *score = 0;
+        *qd_out = qd;
+        *qoff_out = 0;
+    }
+    for (int64_t j = t; j < n_pad; j += (int64_t)gridDim.x * blockDim.x)
+        dst[j] = j < n ? (uint8_t)(src[j] & (kAlpha - 1)) : kPad;
+}
+
+hipError_t launch_pair_prep(const uint8_t* subj, int64_t n, int64_t n_pad, uint8_t* dst, int32_t* score,
+                            const QueryDesc& qd, QueryDesc* qd_out, int64_t* qoff_out, hipStream_t st)
+{
+    const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n_pad + 255) / 256, 1), 4096);
+    hipLaunchKernelGGL(k_pair_prep, dim3((unsigned)blocks), dim3(256), 0, st, subj, n, n_pad, dst, score, qd,
+                       qd_out, qoff_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_diag(const PairArgs& a, int elem, hipStream_t st)
+{
+    const int groups_per_wave = kWave / a.K;
+    const int waves = (a.ntiles + groups_per_wave - 1) / groups_per_wave;
+    const int blocks = (waves + 3) / 4;
+    if (elem == 1)
+        hipLaunchKernelGGL((k_pair_diag<kPairRows, 1>), dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_pair_diag<kPairRows, 2>), dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace swdb

@@ -130,16 +130,21 @@ bool validate_options(const sw_options* opt, std::string& why)
     if (opt->mode < SW_MODE_AUTO || opt->mode > SW_MODE_TUNED) { why = "options.mode"; return false; }
     if (opt->waves < 0 || opt->waves > 8) { why = "options.waves must be 0..8"; return false; }
     if (opt->lane_cells < 0) { why = "options.lane_cells"; return false; }
-    if (opt->max_lanes < 0 || opt->max_lanes > 64 || (opt->max_lanes & (opt->max_lanes - 1))) {
-        why = "options.max_lanes must be 0 or a power of two <= 64";
-        return false;
-    }
+    if (opt->max_lanes < 0 || opt->max_lanes > 64) { why = "options.max_lanes must be 0..64"; return false; }
+    if (opt->wide_profile < 0 || opt->wide_profile > 1) { why = "options.wide_profile must be 0 or 1"; return false; }
     if (opt->lds_limit < 0 || opt->lds_limit > 128 * 1024) { why = "options.lds_limit"; return false; }
     if (opt->grid_limit < 0) { why = "options.grid_limit"; return false; }
+    if (opt->pair_cols < 0) { why = "options.pair_cols"; return false; }
     return true;
 }
 
 int64_t prof_bytes_for(int nbr, int rows, int elem);
+
+// Narrowest profile entries the matrix and gap-open penalty allow (profile
+// entries are s + Go): kFitU8 -- every entry in [0, 127] (8-bit profiles for
+// both lane widths); kFitS8 -- in [-128, 127] (8-bit for int32 lanes);
+// kFit16 -- 16-bit only.
+enum ProfileFit : int { kFitInvalid = 0, kFitS8 = 1, kFit16 = 2, kFitU8 = 3 };
 
 // Launch options of one launch group.  Defaults (measured on MI355X):
 //  * lane-cell target per item: about 4.5 items per wavefront slot of a
@@ -149,15 +154,18 @@ int64_t prof_bytes_for(int nbr, int rows, int elem);
 //  * 4 wavefronts per workgroup, or 8 when queries with an LDS profile share
 //    the launch with queries whose profile stays in global memory, so that the
 //    LDS footprint still leaves 16 waves per CU to hide the global reads.
-Resolved resolve(const sw_db_s* db, const sw_options* opt, int elem_i32, int32_t nq, const int32_t* q_lens)
+//  * the narrowest profile entries the matrix allows (`fit`, a ProfileFit),
+//    unless the options ask for 16-bit entries.
+Resolved resolve(const sw_db_s* db, const sw_options* opt, int fit, int32_t nq, const int32_t* q_lens)
 {
     Resolved r{};
     const int mode = opt ? opt->mode : SW_MODE_AUTO;
+    const bool wide = opt && opt->wide_profile;
     r.i16 = mode != SW_MODE_I32;
     if (r.i16) {
-        r.v = kI16;
+        r.v = (fit == kFitU8 && !wide) ? kI16_P8 : kI16;
     } else {
-        r.v = elem_i32 == 1 ? kI32_R32_P8 : kI32_R32_P16;
+        r.v = ((fit == kFitS8 || fit == kFitU8) && !wide) ? kI32_R32_P8 : kI32_R32_P16;
     }
     const LaunchInfo li = variant_info(r.v);
     r.rows = li.rows;
@@ -187,7 +195,7 @@ Resolved resolve(const sw_db_s* db, const sw_options* opt, int elem_i32, int32_t
 
 int64_t prof_bytes_for(int nbr, int rows, int elem)
 {
-    const int64_t cs = (int64_t)rows * elem + 16;
+    const int64_t cs = code_stride(rows, elem);
     return (int64_t)(nbr + 1) * kCodes * cs;
 }
 
@@ -355,19 +363,23 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
         if (nit > INT32_MAX / 2)
             return fail(SW_EINVAL, "batch too large for one launch");
     }
-    const int64_t wg = ceil_div(nit, r.waves);
-    // persistent grid: occupancy model (<= 16 waves per CU, LDS per CU).  Slots
-    // are sized for the register-limited maximum so that the workspace size does
-    // not depend on the profile entry width chosen from the matrix.
-    const int wg_cap = std::max(kMaxWavesPerCU / r.waves, 1);
-    int64_t slot_grid = std::min<int64_t>(wg, (int64_t)db->cu * wg_cap);
+    // Slots: one per resident wavefront, at most the register-limited 16 per
+    // CU (8 per workgroup at most).  Their count depends neither on the
+    // workgroup width nor on the profile entry width chosen from the matrix,
+    // so the workspace size (computed for 16-bit entries) covers every choice.
+    int64_t nslots = std::min<int64_t>(align_up(std::max<int64_t>(nit, 1), 8), (int64_t)db->cu * kMaxWavesPerCU);
     if (r.grid_limit > 0)
-        slot_grid = std::min<int64_t>(slot_grid, r.grid_limit);
+        nslots = std::min<int64_t>(nslots, (int64_t)r.grid_limit * 8);
+    nslots = align_up(nslots, 8);
+    // persistent grid: occupancy model (<= 16 waves per CU, LDS per CU)
+    const int wg_cap = std::max(kMaxWavesPerCU / r.waves, 1);
     int wg_per_cu = wg_cap;
     if (L.lds_bytes > 0)
         wg_per_cu = std::min(wg_per_cu, kLdsPerCU / (L.lds_bytes + 1024));
     wg_per_cu = std::max(wg_per_cu, 1);
-    L.grid = std::min<int64_t>(slot_grid, (int64_t)db->cu * wg_per_cu);
+    L.grid = std::min<int64_t>({ceil_div(nit, r.waves), nslots / r.waves, (int64_t)db->cu * wg_per_cu});
+    if (r.grid_limit > 0)
+        L.grid = std::min<int64_t>(L.grid, r.grid_limit);
     L.slot_elems = align_up(std::max<int64_t>(slot_need, 4), 4);
     if (r.i16) {
         L.rgrid = std::max<int64_t>(1, (int64_t)db->cu * 2);
@@ -386,7 +398,7 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
     L.off_prof = off; off += align_up(prof, 256);
     L.off_flags = off; off += align_up(sizeof(int2) * L.flag_cap, 256);
     L.off_slots = off;
-    const int64_t main_slots = slot_grid * r.waves * L.slot_elems * (int64_t)sizeof(int2);
+    const int64_t main_slots = nslots * L.slot_elems * (int64_t)sizeof(int2);
     const int64_t res_slots = L.rgrid * kRescoreWaves * L.rslot_elems * (int64_t)sizeof(int2);
     off += align_up(std::max(main_slots, res_slots), 256);
     L.total = off;
@@ -404,18 +416,22 @@ int validate_query_set(sw_db_t db, int32_t nq, const int32_t* q_lens)
     return SW_OK;
 }
 
+// The ProfileFit of a matrix and gap-open penalty; kFitInvalid with `why`
+// set if the matrix is invalid.
 int matrix_elem(const int32_t* sm, int32_t go, std::string& why)
 {
     int mn = 1 << 30, mx = -(1 << 30);
     for (int i = 0; i < kAlpha * kAlpha; ++i) {
         if (sm[i] < -128 || sm[i] > 127) {
             why = "substitution matrix entry outside [-128, 127]";
-            return 0;
+            return kFitInvalid;
         }
         mn = std::min(mn, sm[i]);
         mx = std::max(mx, sm[i]);
     }
-    return (mx + go <= 127 && mn + go >= -128) ? 1 : 2;
+    if (mx + go > 127 || mn + go < -128)
+        return kFit16;
+    return mn + go >= 0 ? kFitU8 : kFitS8;
 }
 
 void* acquire_staging(sw_db_s* db, size_t bytes, Staging** out)
@@ -555,6 +571,8 @@ int plan_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, co
     const size_t need = parts_bytes(sizing);
     if (ws_bytes < need)
         return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    if (parts_bytes(parts) > need)     // the layouts are built so that this never holds
+        return fail(SW_EINVAL, "internal error: search layout exceeds the workspace size");
     return SW_OK;
 }
 
@@ -596,6 +614,7 @@ int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8
     pa.heads = reinterpret_cast<int32_t*>(w + L.off_heads);
     pa.nq = L.nq;
     pa.go = go;
+    pa.pad = r.v == kI16_P8 ? 0 : (r.elem == 1 ? -128 : -32768);
     for (int i = 0; i < kAlpha * kAlpha; ++i)
         pa.sm.v[i] = (int8_t)sm[i];
     HIPCHK(launch_profile(pa, r.rows, r.elem, L.max_entries, stream));
@@ -916,6 +935,24 @@ size_t sw_workspace_bytes(sw_db_t db, int32_t nq, const int32_t* q_lens, const s
     return std::max<size_t>(parts_bytes(parts), 256);
 }
 
+int sw_select_variant(const int32_t* sm, int32_t go, const sw_options* opt)
+{
+    if (!sm) return fail(SW_EINVAL, "null substitution matrix");
+    if (go < 0 || go > SW_MAX_GAP) return fail(SW_EINVAL, "gap-open penalty must be in [0, SW_MAX_GAP]");
+    std::string why;
+    if (!validate_options(opt, why)) return fail(SW_EINVAL, why);
+    const int fit = matrix_elem(sm, go, why);
+    if (!fit) return fail(SW_EINVAL, why);
+    sw_db_s probe;
+    probe.host_only = true;
+    probe.lds_max = 160 * 1024;
+    sw_options o = opt ? *opt : sw_options{};
+    if (o.mode == SW_MODE_TUNED)
+        o.mode = SW_MODE_AUTO;
+    const int32_t one = 1;
+    return (int)resolve(&probe, &o, fit, 1, &one).v;
+}
+
 int sw_plan_info(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_options* opt, sw_plan_stats* out)
 {
     int rc = validate_query_set(db, nq, q_lens);
@@ -1219,6 +1256,237 @@ int sw_db_search(const uint8_t* query, int32_t qlen, const uint8_t* residues, co
     sw_db_release(db);
     if (rc) return rc;
     if (e != hipSuccess) return fail(SW_EHIP, std::string("search: ") + hipGetErrorString(e));
+    return SW_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ single long pair
+
+namespace {
+
+// Schedule of one pair: K lanes per band (K*R query rows), wc columns per
+// chunk.  Time model per anti-diagonal launch: its waves spread over the
+// device's SIMDs, each wave's instructions issued back to back (one wave64
+// VALU instruction per 4 cycles per SIMD), plus a fixed launch cost; the
+// candidate with the least total wins.
+struct PairPlanC {
+    int K = 0, wc = 0;
+    int64_t nb = 0, nc = 0, nbr = 0;
+    double est_s = 0;
+};
+
+constexpr int64_t kPairMaxCols = 1 << 20;
+constexpr double kPairInstrPerCell = 8.4;     // hot-loop VALU instructions per lane-cell (int32 lanes)
+constexpr double kPairLaunchS = 4e-6;
+
+// sum over t = 1..T of ceil(t / q)
+double sum_ceil(int64_t T, int64_t q)
+{
+    if (T <= 0) return 0;
+    const int64_t a = T / q, r = T % q;
+    return (double)q * a * (a + 1) / 2 + (double)(a + 1) * r;
+}
+
+double pair_time(int64_t m, int64_t n, int K, int wc, int cu)
+{
+    const int64_t nb = ceil_div(std::max<int64_t>(m, 1), (int64_t)K * kPairRows);
+    const int64_t nc = ceil_div(std::max<int64_t>(n, 1), wc);
+    // tiles per launch round: groups per wave x waves the SIMDs take at once
+    const int64_t q = (int64_t)(kWave / K) * 4 * std::max(cu, 1);
+    const double wave_s = kPairRows * (double)align_up(wc + K - 1, 4) * kPairInstrPerCell * 4.0 / 2.4e9;
+    // anti-diagonal d holds min(d + 1, lo, nb + nc - 1 - d) tiles: two ramps of
+    // 1..lo-1 tiles and max(nb, nc) - lo + 1 diagonals of lo tiles
+    const int64_t lo = std::min(nb, nc), hi = std::max(nb, nc);
+    const double rounds = 2 * sum_ceil(lo - 1, q) + (double)(hi - lo + 1) * (double)ceil_div(lo, q);
+    return rounds * wave_s + (double)(nb + nc - 1) * kPairLaunchS;
+}
+
+PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt)
+{
+    PairPlanC best;
+    best.est_s = 1e300;
+    const int fixK = opt ? opt->max_lanes : 0;
+    const int fixW = opt ? opt->pair_cols : 0;
+    for (int K : {1, 2, 4, 8, 16, 32, 64}) {
+        if (fixK && K != fixK) continue;
+        for (int wc : {64, 128, 256, 512, 1024, 2048, 4096, 8192}) {
+            if (fixW && wc != fixW) continue;
+            const double t = pair_time(m, n, K, wc, cu);
+            if (t < best.est_s) {
+                best.est_s = t;
+                best.K = K;
+                best.wc = wc;
+            }
+        }
+    }
+    if (fixK && !best.K) best.K = fixK;
+    if (fixW && !best.wc) best.wc = fixW;
+    if (fixK && fixW) best.est_s = pair_time(m, n, fixK, fixW, cu);
+    best.nb = ceil_div(std::max<int64_t>(m, 1), (int64_t)best.K * kPairRows);
+    best.nc = ceil_div(std::max<int64_t>(n, 1), best.wc);
+    best.nbr = ceil_div(m, kPairRows);
+    return best;
+}
+
+// Workspace of a pair, sized for every schedule (so the size does not depend
+// on the device or the matrix): padded subject, 16-bit profile, rowbuf,
+// colbuf, corners, profile descriptor and counters.
+struct PairLayout {
+    size_t subj = 0, prof = 0, rowbuf = 0, colbuf = 0, corner = 0, qd = 0, qoff = 0, counters = 0, total = 0;
+    int64_t n_pad = 0;
+};
+
+PairLayout pair_layout(int64_t m, int64_t n, const PairPlanC* p)
+{
+    PairLayout L;
+    const int64_t max_wc = kPairMaxCols;
+    const int64_t nbr = ceil_div(m, kPairRows);
+    const int64_t cols = p ? p->nc * p->wc : align_up(n, 16) + 8192;
+    L.n_pad = p ? cols + 128 : 0;
+    size_t off = 0;
+    L.counters = off; off += 256;
+    L.qd = off; off += 256;
+    L.qoff = off; off += 256;
+    L.corner = off; off += align_up((ceil_div(m, kPairRows) + 2) * 3 * 4, 256);
+    L.subj = off; off += align_up(p ? L.n_pad : align_up(n, 16) + 8192 + 128, 256);
+    L.prof = off; off += align_up(prof_bytes_for((int)nbr, kPairRows, 2), 256);
+    L.rowbuf = off; off += align_up((p ? cols : align_up(n, 16) + 8192) * (int64_t)sizeof(int2), 256);
+    L.colbuf = off; off += align_up((align_up(m, kPairRows) + (int64_t)kWave * kPairRows) * (int64_t)sizeof(int2), 256);
+    L.total = off;
+    (void)max_wc;
+    return L;
+}
+
+int validate_pair(int64_t m, int64_t n, const sw_options* opt, std::string& why)
+{
+    if (m < 0 || n < 0 || m > SW_MAX_QLEN || n > SW_MAX_QLEN) { why = "pair lengths must be in [0, SW_MAX_QLEN]"; return 0; }
+    if (!validate_options(opt, why)) return 0;
+    if (opt && opt->max_lanes && (opt->max_lanes & (opt->max_lanes - 1))) {
+        why = "options.max_lanes must be a power of two for pairs";
+        return 0;
+    }
+    if (opt && opt->pair_cols && (opt->pair_cols % 16 || opt->pair_cols > kPairMaxCols)) {
+        why = "options.pair_cols must be a multiple of 16, at most 2^20";
+        return 0;
+    }
+    return 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sw_pair_workspace_bytes(int64_t m, int64_t n, const sw_options* opt)
+{
+    std::string why;
+    if (!validate_pair(m, n, opt, why)) { fail(SW_EINVAL, why); return 0; }
+    // the padded subject and rowbuf of the chosen schedule never exceed the
+    // generic bound: nc * wc < n + wc <= n + 8192 for planner choices, and an
+    // explicit pair_cols adds its own width
+    size_t t = pair_layout(m, n, nullptr).total;
+    if (opt && opt->pair_cols > 8192)
+        t += (size_t)align_up((int64_t)opt->pair_cols * 9, 256);
+    return t;
+}
+
+int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, sw_pair_stats* out)
+{
+    std::string why;
+    if (!validate_pair(m, n, opt, why)) return fail(SW_EINVAL, why);
+    if (!out) return fail(SW_EINVAL, "null output");
+    const PairPlanC p = pair_plan(m, n, cu_count > 0 ? cu_count : 256, opt);
+    *out = sw_pair_stats{};
+    out->lanes = p.K;
+    out->cols = p.wc;
+    out->bands = p.nb;
+    out->chunks = p.nc;
+    out->launches = (m > 0 && n > 0) ? p.nb + p.nc - 1 : 0;
+    out->est_ms = p.est_s * 1e3;
+    out->workspace = (int64_t)sw_pair_workspace_bytes(m, n, opt);
+    return SW_OK;
+}
+
+int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n, const int32_t* sm,
+                  int32_t go, int32_t ge, const sw_options* opt, void* ws, size_t ws_bytes, int32_t* score_out,
+                  hipStream_t stream)
+{
+    std::string why;
+    if (!validate_pair(m, n, opt, why)) return fail(SW_EINVAL, why);
+    if (m > 0 && !query) return fail(SW_EINVAL, "null query");
+    if (n > 0 && !subject) return fail(SW_EINVAL, "null subject");
+    if (!sm) return fail(SW_EINVAL, "null substitution matrix");
+    if (!score_out) return fail(SW_EINVAL, "null score_out");
+    if (go < 0 || ge < 0 || go > SW_MAX_GAP || ge > SW_MAX_GAP)
+        return fail(SW_EINVAL, "gap penalties must be in [0, SW_MAX_GAP]");
+    const int fit = matrix_elem(sm, go, why);
+    if (!fit) return fail(SW_EINVAL, why);
+    if (!ws) return fail(SW_EINVAL, "null workspace");
+    if (((uintptr_t)ws & 255) != 0) return fail(SW_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = sw_pair_workspace_bytes(m, n, opt);
+    if (ws_bytes < need)
+        return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    int dev = 0, cu = 256;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const PairPlanC p = pair_plan(m, n, cu, opt);
+    const PairLayout L = pair_layout(m, n, &p);
+    if (L.total > need) return fail(SW_EINVAL, "internal error: pair layout exceeds the workspace size");
+    uint8_t* w = static_cast<uint8_t*>(ws);
+    const int elem = (fit == kFitS8 || fit == kFitU8) ? 1 : 2;
+
+    QueryDesc qd{};
+    qd.prof_off = 0;
+    qd.m = (int32_t)m;
+    qd.nbr = (int32_t)p.nbr;
+    qd.prof_bytes = (int32_t)std::min<int64_t>(prof_bytes_for((int)p.nbr, kPairRows, elem), INT32_MAX);
+    auto* qd_dev = reinterpret_cast<QueryDesc*>(w + L.qd);
+    auto* qoff_dev = reinterpret_cast<int64_t*>(w + L.qoff);
+    HIPCHK(launch_pair_prep(subject, n, (m > 0 && n > 0) ? L.n_pad : 0, w + L.subj, score_out, qd, qd_dev,
+                            qoff_dev, stream));
+    if (m == 0 || n == 0)
+        return SW_OK;      // score 0, written by the preparation kernel
+
+    ProfileArgs pa{};
+    pa.queries = query;
+    pa.q_off = qoff_dev;
+    pa.qd = qd_dev;
+    pa.prof = w + L.prof;
+    pa.counters = reinterpret_cast<int32_t*>(w + L.counters);
+    pa.heads = pa.counters + 8;
+    pa.nq = 1;
+    pa.go = go;
+    pa.pad = elem == 1 ? -128 : -32768;
+    for (int i = 0; i < kAlpha * kAlpha; ++i)
+        pa.sm.v[i] = (int8_t)sm[i];
+    HIPCHK(launch_profile(pa, kPairRows, elem, (int)std::min<int64_t>((p.nbr + 1) * kCodes * kPairRows, INT32_MAX),
+                          stream));
+
+    PairArgs a{};
+    a.subj = w + L.subj;
+    a.prof = w + L.prof;
+    a.rowbuf = reinterpret_cast<int2*>(w + L.rowbuf);
+    a.colbuf = reinterpret_cast<int2*>(w + L.colbuf);
+    a.corner = reinterpret_cast<int32_t*>(w + L.corner);
+    a.score = score_out;
+    a.nbr = (int32_t)p.nbr;
+    a.nb = (int32_t)p.nb;
+    a.nc = (int32_t)p.nc;
+    a.K = p.K;
+    a.wc = p.wc;
+    a.go = go;
+    a.ge = ge;
+    const bool ev = opt && opt->ev_search_begin;
+    if (ev) HIPCHK(hipEventRecord(opt->ev_search_begin, stream));
+    for (int64_t d = 0; d < p.nb + p.nc - 1; ++d) {
+        const int64_t b_lo = std::max<int64_t>(0, d - (p.nc - 1));
+        const int64_t b_hi = std::min<int64_t>(d, p.nb - 1);
+        a.d = (int32_t)d;
+        a.b_lo = (int32_t)b_lo;
+        a.ntiles = (int32_t)(b_hi - b_lo + 1);
+        HIPCHK(launch_pair_diag(a, elem, stream));
+    }
+    if (opt && opt->ev_search_end) HIPCHK(hipEventRecord(opt->ev_search_end, stream));
     return SW_OK;
 }
 

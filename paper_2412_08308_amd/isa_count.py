@@ -29,11 +29,16 @@ VARIANTS = {
     "i32_p8_glb_kn": ("isa_i32ILi32ELi1ELb0ELb1E", 32, 1),
     "i32_p16_lds_k1": ("isa_i32ILi32ELi2ELb1ELb0E", 32, 1),
     "i32_p16_glb_k1": ("isa_i32ILi32ELi2ELb0ELb0E", 32, 1),
-    "i16_lds_k1": ("isa_i16ILi24ELb1ELb0E", 24, 2),
-    "i16_lds_kn": ("isa_i16ILi24ELb1ELb1E", 24, 2),
-    "i16_glb_k1": ("isa_i16ILi24ELb0ELb0E", 24, 2),
-    "i16_glb_kn": ("isa_i16ILi24ELb0ELb1E", 24, 2),
+    "i16_lds_k1": ("isa_i16ILi24ELi2ELb1ELb0E", 24, 2),
+    "i16_lds_kn": ("isa_i16ILi24ELi2ELb1ELb1E", 24, 2),
+    "i16_glb_k1": ("isa_i16ILi24ELi2ELb0ELb0E", 24, 2),
+    "i16_glb_kn": ("isa_i16ILi24ELi2ELb0ELb1E", 24, 2),
+    "i16_p8_lds_k1": ("isa_i16ILi24ELi1ELb1ELb0E", 24, 2),
+    "i16_p8_lds_kn": ("isa_i16ILi24ELi1ELb1ELb1E", 24, 2),
+    "i16_p8_glb_k1": ("isa_i16ILi24ELi1ELb0ELb0E", 24, 2),
+    "i16_p8_glb_kn": ("isa_i16ILi24ELi1ELb0ELb1E", 24, 2),
     "rescore_i32_r24": ("isa_i32ILi24ELi2ELb0ELb1E", 24, 1),
+    "rescore_i32_r24_p8": ("isa_i32ILi24ELi1ELb0ELb1E", 24, 1),
 }
 
 

@@ -26,7 +26,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -134,16 +134,16 @@ def lognormal_lengths(rng: np.random.Generator, n: int, median: float, sigma: fl
 
 
 def mutate(rng: np.random.Generator, src: np.ndarray, identity: float,
-           indel_rate: float = 0.02, indel_mean: float = 3.0) -> np.ndarray:
+           indel_rate: float = 0.02, indel_mean: float = 3.0, freqs: np.ndarray = BACKGROUND) -> np.ndarray:
     """A near-homolog of ``src``: each position kept with probability
-    ``identity`` (else redrawn from the background), plus indel events at
+    ``identity`` (else redrawn from ``freqs``), plus indel events at
     ``indel_rate`` per position, half deletions and half insertions, with
     geometric lengths of mean ``indel_mean``."""
     src = np.asarray(src, dtype=np.uint8)
     n = len(src)
     out = src.copy()
     sub = rng.random(n) >= identity
-    out[sub] = residues(rng, int(sub.sum()))
+    out[sub] = residues(rng, int(sub.sum()), freqs)
     ev = np.nonzero(rng.random(n) < indel_rate)[0]
     if len(ev) == 0:
         return out
@@ -157,7 +157,7 @@ def mutate(rng: np.random.Generator, src: np.ndarray, identity: float,
         if rng.random() < 0.5:          # deletion of L source positions
             pos = min(n, e + L)
         else:                           # insertion of L random residues before e
-            pieces.append(residues(rng, L))
+            pieces.append(residues(rng, L, freqs))
             pos = e
     pieces.append(out[pos:])
     return np.concatenate(pieces).astype(np.uint8)
@@ -325,6 +325,32 @@ def planted(seed: int = 0, scale: float = 1.0, qlen: int = 8000) -> Workload:
     lens = lognormal_lengths(r_len, n, 300, 0.668, 10, 35_000)
     db = make_db(r_res, lens)
     return _plant(db, blosum_style_matrix(), r_plant, seed, qlen)
+
+
+# --------------------------------------------------------------------------- DNA pairs
+
+DNA_FREQS = np.full(4, 0.25)              # codes 0..3 = A, C, G, T
+DNA_MATCH, DNA_MISMATCH = 1, -3           # pairwise DNA scoring of the paper (Section 4.1)
+DNA_GAP_OPEN, DNA_GAP_EXTEND = 5, 2
+# (query, subject) lengths of the paper's five DNA alignments (its DNA table)
+DNA_PAIR_SIZES = [(162_000, 172_000), (543_000, 536_000), (1_000_000, 1_000_000),
+                  (3_000_000, 3_000_000), (7_000_000, 5_000_000)]
+
+
+def dna_pair(m: int, n: int, seed: int = 0, identity: float = 0.8,
+             indel_rate: float = 0.005) -> Tuple[np.ndarray, np.ndarray]:
+    """Synthetic stand-in for one of the paper's DNA pairs: a random query of
+    ``m`` bases and a subject of ``n`` bases made from a mutated copy of the
+    query (``identity``, indels at ``indel_rate``), cut or extended with random
+    bases to length ``n``, so that the best local alignment spans most of both."""
+    rq, rs = _streams(seed + 7, 2)
+    a = residues(rq, m, DNA_FREQS)
+    b = mutate(rs, a[:min(m, n)], identity, indel_rate=indel_rate, freqs=DNA_FREQS)
+    if len(b) >= n:
+        b = b[:n]
+    else:
+        b = np.concatenate([b, residues(rs, n - len(b), DNA_FREQS)])
+    return a, b.astype(np.uint8)
 
 
 def poisson_arrivals(rng: np.random.Generator, rate: float, n: int) -> np.ndarray:

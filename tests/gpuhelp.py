@@ -29,10 +29,18 @@ def gpu_db(db):
     return swdb.Database.from_host(db)
 
 
+def _opt(mode, kw):
+    """Options for a mode name; a trailing "w" asks for 16-bit profile entries
+    (the wide-profile kernel variants) where 8 bits would hold them."""
+    import paper_2412_08308_amd as swdb
+    if mode.endswith("w"):
+        mode, kw = mode[:-1], dict(kw, wide_profile=1)
+    return swdb.options(mode=mode, **kw)
+
+
 def gpu_scores(gdb, q, sm, go, ge, mode="auto", **kw):
     import torch
-    import paper_2412_08308_amd as swdb
-    opt = swdb.options(mode=mode, **kw)
+    opt = _opt(mode, kw)
     qt = torch.from_numpy(np.ascontiguousarray(q, dtype=np.uint8)).cuda()
     out = gdb.search(qt, sm, go, ge, opt=opt)
     torch.cuda.synchronize()
@@ -41,8 +49,7 @@ def gpu_scores(gdb, q, sm, go, ge, mode="auto", **kw):
 
 def gpu_batch(gdb, qs, sm, go, ge, mode="auto", **kw):
     import torch
-    import paper_2412_08308_amd as swdb
-    opt = swdb.options(mode=mode, **kw)
+    opt = _opt(mode, kw)
     qts = [torch.from_numpy(np.ascontiguousarray(q, dtype=np.uint8)).cuda() for q in qs]
     out = gdb.search_batch(qts, sm, go, ge, opt=opt)
     torch.cuda.synchronize()
@@ -51,6 +58,10 @@ def gpu_batch(gdb, qs, sm, go, ge, mode="auto", **kw):
 
 def oracle_scores(db, q, sm, go, ge, ids=None):
     return oracle.search_db(q, db, sm, go, ge, ids=ids)
+
+
+def oracle_pair(a, b, sm, go, ge):
+    return int(oracle.score(a, b, sm, go, ge))
 
 
 def mismatch_report(got, exp, ids=None, limit=8):
@@ -64,20 +75,20 @@ def mismatch_report(got, exp, ids=None, limit=8):
     return f"{len(bad)} mismatches; " + "; ".join(rows)
 
 
-def overflow_matrix():
-    """Matrix for constructed 16-bit overflow cases: code 0 scores 127 with
-    itself, code 1 scores 1 with itself, everything else -128; self-alignment
-    of a sequence over codes {0, 1} then scores its diagonal sum exactly."""
-    sm = np.full((32, 32), -128, dtype=np.int32)
-    sm[0, 0] = 127
-    sm[1, 1] = 1
-    for c in range(2, 32):
+def overflow_matrix(top: int = 127, low: int = -128):
+    """Matrix for constructed 16-bit overflow cases: code 0 scores `top` with
+    itself, every other code 1 with itself, everything else `low`; a sequence
+    over codes {0, 1} placed in the query as a substring then scores its
+    diagonal sum exactly (no residue can contribute more than its match)."""
+    sm = np.full((32, 32), low, dtype=np.int32)
+    sm[0, 0] = top
+    for c in range(1, 32):
         sm[c, c] = 1
     return sm
 
 
-def overflow_sequence(target: int) -> np.ndarray:
-    """Codes over {0, 1} whose diagonal sum under overflow_matrix() is target."""
-    n0 = target // 127
-    n1 = target - 127 * n0
+def overflow_sequence(target: int, top: int = 127) -> np.ndarray:
+    """Codes over {0, 1} whose diagonal sum under overflow_matrix(top) is target."""
+    n0 = target // top
+    n1 = target - top * n0
     return np.array([0] * n0 + [1] * n1, dtype=np.uint8)

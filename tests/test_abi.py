@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import paper_2412_08308_amd as swdb
+import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "swdb.h")
@@ -93,3 +94,19 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(swdb, "_lib", None)
     with pytest.raises(swdb.SwdbError):
         swdb.lib()
+
+
+def test_select_variant():
+    """8-bit profile entries wherever every s + Go fits the lane type's range."""
+    sm = synth.blosum_style_matrix()          # entries -4..11
+    assert swdb.select_variant(sm, 10) == 3                                  # packed, [0, 127]
+    assert swdb.select_variant(sm, 0) == 2                                   # -4 + 0 < 0
+    assert swdb.select_variant(sm, 10, swdb.options(wide_profile=1)) == 2
+    assert swdb.select_variant(sm, 10, swdb.options(mode="i32")) == 0
+    assert swdb.select_variant(sm, 0, swdb.options(mode="i32")) == 0        # [-128, 127]
+    assert swdb.select_variant(sm, 120, swdb.options(mode="i32")) == 1      # 131 > 127
+    assert swdb.select_variant(sm, 10, swdb.options(mode="tuned")) == 3
+    with pytest.raises(swdb.SwdbError):
+        swdb.select_variant(sm, -1)
+    with pytest.raises(swdb.SwdbError):
+        swdb.select_variant(sm, 10, swdb.options(wide_profile=2))

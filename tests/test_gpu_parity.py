@@ -14,7 +14,9 @@ from gpuhelp import (announce, gpu_batch, gpu_db, gpu_scores, have_gpu, mismatch
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="needs a GPU")]
 
-MODES = ["i32", "i16", "auto"]
+# "w": the same lanes with 16-bit profile entries (the default takes 8-bit
+# entries whenever every s + Go fits)
+MODES = ["i32", "i32w", "i16", "i16w", "auto"]
 
 
 def _check(db, q, sm, go, ge, modes=MODES, ids=None, **kw):
@@ -113,11 +115,16 @@ def test_long_query_global_profile():
     _check(db, q, synth.blosum_style_matrix(), 10, 2)
 
 
-def test_int16_overflow_boundary():
-    sm = overflow_matrix()
+@pytest.mark.parametrize("top,low", [(127, -128), (117, -10)])
+def test_int16_overflow_boundary(top, low):
+    # (127, -128): 16-bit profile entries; (117, -10) with Go = 10: every
+    # s + Go in [0, 127], so the packed lanes take 8-bit entries
+    import paper_2412_08308_amd as swdb
+    sm = overflow_matrix(top, low)
+    assert swdb.select_variant(sm, 10) == (3 if low == -10 else 2)
     seqs, targets = [], [32766, 32767, 32768, 40000, 32000, 1000]
     for t in targets:
-        seqs.append(overflow_sequence(t))
+        seqs.append(overflow_sequence(t, top))
     rng = np.random.default_rng(12)
     # the query holds every constructed subject as a substring (a run of code 0
     # followed by a run of code 1), so each subject scores its diagonal sum
@@ -130,7 +137,6 @@ def test_int16_overflow_boundary():
     assert list(exp[:6]) == targets
     _check(db, q, sm, 10, 2)
     # the 16-bit pass flags exactly the subjects whose true score is >= 32767
-    import paper_2412_08308_amd as swdb
     import torch
     gdb = gpu_db(db)
     try:
