@@ -187,25 +187,30 @@ def serving(args, capacity_gcups, mode):
     torch.cuda.synchronize()
     mean_m = float(np.mean(qlens))
     runs = []
-    for rho in args.serve_rho:
-        lam = rho * capacity_gcups * 1e9 / (mean_m * w5.db.total)
-        arrivals = synth.poisson_arrivals(rng, lam, n)
-        srv = Server(be, max_batch=16).start()
-        futs = []
-        t0 = time.perf_counter()
-        for k, q in enumerate(qs):
-            dt = t0 + arrivals[k] - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
-            futs.append(srv.submit(q))
-        for f in futs:
-            f.result()
-        srv.stop()
-        st = srv.stats()
-        runs.append({"rho": rho, "rate_per_s": round(lam, 2), "requests": n,
-                     "p50_ms": round(st["p50_s"] * 1e3, 2), "p99_ms": round(st["p99_s"] * 1e3, 2),
-                     "sustained_gcups": round(st["sustained_gcups"], 1),
-                     "mean_batch": round(st["mean_batch"], 2), "max_batch": st["max_batch"]})
+    rate = capacity_gcups * 1e9
+    for policy in args.serve_policies:
+        arng = np.random.default_rng(78)          # the same arrival times for every policy
+        for rho in args.serve_rho:
+            lam = rho * capacity_gcups * 1e9 / (mean_m * w5.db.total)
+            arrivals = synth.poisson_arrivals(arng, lam, n)
+            srv = Server(be, max_batch=16, policy=policy, rate_guess=rate).start()
+            futs = []
+            t0 = time.perf_counter()
+            for k, q in enumerate(qs):
+                dt = t0 + arrivals[k] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                futs.append(srv.submit(q))
+            for f in futs:
+                f.result()
+            srv.stop()
+            st = srv.stats()
+            print(f"[bench] serving {policy} rho={rho}: p50 {st['p50_s'] * 1e3:.1f} ms p99 {st['p99_s'] * 1e3:.1f} ms",
+                  file=sys.stderr, flush=True)
+            runs.append({"policy": policy, "rho": rho, "rate_per_s": round(lam, 2), "requests": n,
+                         "p50_ms": round(st["p50_s"] * 1e3, 2), "p99_ms": round(st["p99_s"] * 1e3, 2),
+                         "sustained_gcups": round(st["sustained_gcups"], 1),
+                         "mean_batch": round(st["mean_batch"], 2), "max_batch": st["max_batch"]})
     gdb.release()
     return {"workload": f"{w5.db.nseq} subjects ({w5.db.total} residues); {n} queries log-normal median 350 "
                         "clamped 50-5000; Poisson arrivals at rho x single-query capacity",
@@ -344,6 +349,7 @@ def main(argv=None):
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rho", type=float, nargs="+", default=[0.5, 0.8])
     ap.add_argument("--serve-scale", type=float, default=1.0)
+    ap.add_argument("--serve-policies", nargs="+", default=["edf", "fifo"], choices=["edf", "fifo"])
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (traffic calibration)")
     args = ap.parse_args(argv)

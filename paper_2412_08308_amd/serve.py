@@ -3,9 +3,13 @@
 Requests (single queries) arrive at any time through ``Server.submit``.  A
 scheduler thread
 
-* admits requests in arrival order while the in-flight slot count and the
-  device-memory budget allow (each batch needs its workspace from
-  ``sw_workspace_bytes``, its score matrix and its query bytes);
+* admits requests while the in-flight slot count and the device-memory
+  budget allow (each batch needs its workspace from ``sw_workspace_bytes``,
+  its score matrix and its query bytes), in order of deadline (``policy=
+  "edf"``: arrival time plus the request's estimated service time, its cells
+  over the device rate observed on completed batches, so a short request
+  overtakes long ones that arrived about as early, while no deadline moves)
+  or of arrival (``policy="fifo"``);
 * groups everything admissible into one batched launch
   (``sw_db_search_batch``) on a free stream of a small stream pool, so batches
   that arrive while others run are searched concurrently on the device;
@@ -31,13 +35,14 @@ import numpy as np
 
 
 class Request:
-    __slots__ = ("id", "query", "qlen", "arrival", "future", "started")
+    __slots__ = ("id", "query", "qlen", "arrival", "future", "started", "deadline")
 
     def __init__(self, rid, query, arrival):
         self.id = rid
         self.query = query
         self.qlen = int(len(query)) if not hasattr(query, "numel") else int(query.numel())
         self.arrival = arrival
+        self.deadline = arrival
         self.future = Future()
         self.future.latency = None
         self.future.request_id = rid
@@ -113,7 +118,12 @@ class Server:
     """Continuous-batching request loop (see module docstring)."""
 
     def __init__(self, backend, max_batch: int = 16, max_inflight: Optional[int] = None,
-                 mem_budget: Optional[int] = None, poll_interval: float = 1e-4, clock=time.perf_counter):
+                 mem_budget: Optional[int] = None, poll_interval: float = 1e-4, clock=time.perf_counter,
+                 policy: str = "edf", rate_guess: float = 1e12):
+        if policy not in ("edf", "fifo"):
+            raise ValueError("policy must be 'edf' or 'fifo'")
+        self.policy = policy
+        self.rate = float(rate_guess)       # cells per second, updated from completed batches
         self.backend = backend
         self.max_batch = int(max_batch)
         self.max_inflight = int(max_inflight or getattr(backend, "slots", 4))
@@ -126,7 +136,7 @@ class Server:
         self.clock = clock
         self._ids = itertools.count()
         self._pending = collections.deque()
-        self._inflight = []            # (slot, handle, requests, bytes)
+        self._inflight = []            # (slot, handle, requests, bytes, launch time)
         self._free_slots = list(range(self.max_inflight))
         self._in_use = 0
         self._cv = threading.Condition()
@@ -152,6 +162,7 @@ class Server:
             raise ValueError("query residue codes must be < 32")
         now = self.clock()
         req = Request(next(self._ids), q, now)
+        req.deadline = now + self.backend.cells([req.qlen]) / self.rate
         need = self.backend.need_bytes([req.qlen])
         if need > self.mem_budget:
             req.future.set_exception(MemoryError(f"request needs {need} bytes, budget {self.mem_budget}"))
@@ -202,11 +213,11 @@ class Server:
     def _complete(self):
         done = []
         for entry in self._inflight:
-            slot, h, reqs, nbytes = entry
+            slot, h, reqs, nbytes, t_launch = entry
             if self.backend.poll(h):
                 done.append(entry)
         for entry in done:
-            slot, h, reqs, nbytes = entry
+            slot, h, reqs, nbytes, t_launch = entry
             self._inflight.remove(entry)
             try:
                 rows = self.backend.results(h)
@@ -224,8 +235,12 @@ class Server:
                 self.completed += 1
                 r.future.set_result(rows[k])
             if err is None:
-                self.cells_done += self.backend.cells([r.qlen for r in reqs])
+                cells = self.backend.cells([r.qlen for r in reqs])
+                self.cells_done += cells
                 self.last_completion = t
+                if t > t_launch and cells > 0 and len(self._inflight) == 0:
+                    # rate of a batch that ran alone at the end: an estimate of the device rate
+                    self.rate = 0.7 * self.rate + 0.3 * cells / (t - t_launch)
             with self._cv:
                 self._in_use -= nbytes
                 self._free_slots.append(slot)
@@ -238,6 +253,8 @@ class Server:
                 if not self._free_slots or not self._pending:
                     return launched
                 batch, lens = [], []
+                if self.policy == "edf" and len(self._pending) > 1:
+                    self._pending = collections.deque(sorted(self._pending, key=lambda r: (r.deadline, r.id)))
                 while self._pending and len(batch) < self.max_batch:
                     r = self._pending[0]
                     if r.future.cancelled():
@@ -280,7 +297,7 @@ class Server:
                     self._free_slots.append(slot)
                 continue
             self.batch_sizes.append(len(batch))
-            self._inflight.append((slot, h, batch, nbytes))
+            self._inflight.append((slot, h, batch, nbytes, self.clock()))
             launched = True
 
     def _loop(self):

@@ -136,6 +136,34 @@ def test_cancel_pending():
     assert srv.stats()["completed"] == 1
 
 
+@pytest.mark.parametrize("policy", ["edf", "fifo"])
+def test_admission_order(policy):
+    """While one request runs, a long and then a short one arrive: deadline
+    order (arrival + estimated service time) runs the short one first, arrival
+    order the long one."""
+    db, sm = _db(), synth.blosum_style_matrix()
+    be = FakeBackend(db, sm, delay=0.05)
+    rate = be.cells([1]) / 1e-3        # 1 ms of service per query residue
+    srv = Server(be, max_batch=1, max_inflight=1, mem_budget=10**9, policy=policy, rate_guess=rate).start()
+    first = srv.submit(np.ones(20, np.uint8))
+    time.sleep(0.01)
+    long_ = srv.submit(np.ones(60, np.uint8))      # deadline about +60 ms
+    time.sleep(0.002)
+    short = srv.submit(np.ones(5, np.uint8))       # deadline about +7 ms
+    for f in (first, long_, short):
+        f.result(timeout=10)
+    srv.stop()
+    order = [lens[0] for _, lens in be.launches]
+    assert order[0] == 20
+    assert order[1:] == ([5, 60] if policy == "edf" else [60, 5])
+
+
+def test_policy_checked():
+    db, sm = _db(), synth.blosum_style_matrix()
+    with pytest.raises(ValueError):
+        Server(FakeBackend(db, sm), mem_budget=10**9, policy="lifo")
+
+
 def test_percentiles_known_values():
     p50, p99 = percentiles(list(range(1, 101)))
     assert p50 == pytest.approx(50.5) and p99 == pytest.approx(99.01)
