@@ -55,6 +55,7 @@ constexpr int kDefaultLdsLimit = 64 * 1024;
 constexpr int kLdsPerCU = 160 * 1024;
 constexpr int kRescoreWaves = 4;      // workgroup size of the rescore kernel
 constexpr int kMaxWavesPerCU = 16;      // 4 per SIMD: kernels are built for <= 128 VGPRs
+constexpr int kLdsWavesPerCU = 12;      // resident waves per CU when every profile is in LDS
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 int64_t align_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -371,8 +372,14 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
     if (r.grid_limit > 0)
         nslots = std::min<int64_t>(nslots, (int64_t)r.grid_limit * 8);
     nslots = align_up(nslots, 8);
-    // persistent grid: occupancy model (<= 16 waves per CU, LDS per CU)
-    const int wg_cap = std::max(kMaxWavesPerCU / r.waves, 1);
+    // persistent grid: occupancy model (LDS per CU; at most 16 waves per CU, 12
+    // when every profile is in LDS -- measured faster there: the longest items
+    // on the critical path share their SIMD with fewer waves)
+    bool all_lds = true;
+    for (int32_t p = 0; p < nq; ++p)
+        all_lds = all_lds && L.qd[p].lds;
+    const int wave_cap = all_lds ? kLdsWavesPerCU : kMaxWavesPerCU;
+    const int wg_cap = std::max(wave_cap / r.waves, 1);
     int wg_per_cu = wg_cap;
     if (L.lds_bytes > 0)
         wg_per_cu = std::min(wg_per_cu, kLdsPerCU / (L.lds_bytes + 1024));
