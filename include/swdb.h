@@ -75,7 +75,9 @@ typedef struct sw_options {
     int32_t pair_cols;     /* sw_pair_score: subject columns per tile (multiple
                               of 16, <= 2^20; 0 = planner); max_lanes sets the
                               lanes per band there (a power of two)              */
-    int32_t reserved[8];
+    int32_t pair_rows;     /* sw_pair_score: query rows per lane, 8 or 16
+                              (0 = planner)                                      */
+    int32_t reserved[7];
     /* Optional timing events (created by the caller, may be NULL): recorded on
        the search stream immediately before the search kernel, immediately
        after it, and after the int32 rescore (16-bit modes).                   */
@@ -275,16 +277,18 @@ const char* sw_version(void);
  * Intra-task alignment (paper Section 2.2, Fig. 1; the pairwise DNA workload
  * of Section 4.1): the score of ONE pair, query `query[m]` along the rows and
  * subject `subject[n]` along the columns, with the whole device working on the
- * single matrix.  The matrix is tiled into bands of K*32 query rows by chunks
- * of `cols` subject columns; the tiles of each anti-diagonal run in one launch
- * (int32 lanes, K lanes pipelined per band) and pass their boundary rows and
- * columns to the next launch through the workspace.  Same recurrence, borders
- * and result as sw_db_search; int32 score.
+ * single matrix.  The matrix is tiled into bands of K*R query rows (R = 8 or 16 rows
+ * per lane, K lanes pipelined per band, int32 lanes) by chunks of `cols`
+ * subject columns; the tiles of each anti-diagonal run in one launch and pass
+ * their boundary rows and columns to the next launch through the workspace.
+ * Same recurrence, borders and result as sw_db_search; int32 score.
  */
 typedef struct sw_pair_stats {
-    int32_t lanes;         /* K: lanes per band (band = 32*K query rows)          */
+    int32_t rows;          /* R: query rows per lane (8 or 16)                    */
+    int32_t lanes;         /* K: lanes per band (band = R*K query rows)           */
     int32_t cols;          /* subject columns per tile                            */
-    int64_t bands;         /* ceil(m / (32*K))                                    */
+    int32_t pad;
+    int64_t bands;         /* ceil(m / (R*K))                                     */
     int64_t chunks;        /* ceil(n / cols)                                      */
     int64_t launches;      /* anti-diagonals: bands + chunks - 1                  */
     double est_ms;         /* the planner's time model                            */
@@ -296,8 +300,8 @@ typedef struct sw_pair_stats {
 size_t sw_pair_workspace_bytes(int64_t m, int64_t n, const sw_options* opt);
 
 /* The schedule sw_pair_score would run on a device with `cu_count` compute
-   units (0 = 256); host only.  opt->max_lanes (a power of two) fixes K,
-   opt->pair_cols fixes the chunk width. */
+   units (0 = 256); host only.  opt->pair_rows fixes R, opt->max_lanes (a
+   power of two) K, opt->pair_cols the chunk width. */
 int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, sw_pair_stats* out);
 
 /*
@@ -306,7 +310,8 @@ int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, 
  *                   (m, n in [0, SW_MAX_QLEN])
  *   subst_matrix    HOST, int32[32*32], row = query residue, entries in [-128, 127]
  *   gap_open/extend as in sw_db_search
- *   opt             NULL or options (max_lanes, pair_cols, ev_search_begin/end)
+ *   opt             NULL or options (pair_rows, max_lanes, pair_cols,
+ *                   ev_search_begin/end around the tile launches)
  *   workspace       device, >= sw_pair_workspace_bytes(m, n, opt), 256-byte aligned
  *   score_out       device, int32[1]
  * Asynchronous on `stream`; enqueues one preparation kernel, the profile

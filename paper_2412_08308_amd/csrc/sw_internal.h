@@ -142,9 +142,12 @@ hipError_t launch_interleave(const uint8_t* src, const int64_t* src_off, const i
 int search_occupancy(Variant v, int waves, int lds_bytes);   // workgroups per CU
 // Single long pair: the padded subject (codes modulo 32), the cleared score and
 // the query's profile descriptor; then one launch per anti-diagonal.
-constexpr int kPairRows = 32;        // query rows per lane (int32 lanes)
+// Query rows per lane of the pair kernel (int32 lanes): fewer rows give more
+// lanes on each anti-diagonal (short pairs), more rows fewer instructions per
+// cell (long pairs).
+constexpr int kPairRowChoices[2] = {8, 16};
 hipError_t launch_pair_prep(const uint8_t* subj, int64_t n, int64_t n_pad, uint8_t* dst, int32_t* score,
                             const QueryDesc& qd, QueryDesc* qd_out, int64_t* qoff_out, hipStream_t st);
-hipError_t launch_pair_diag(const PairArgs& a, int elem, hipStream_t st);
+hipError_t launch_pair_diag(const PairArgs& a, int rows, int elem, hipStream_t st);
 
 }  // namespace swdb

@@ -70,18 +70,26 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
     int ydiag = -go;
     if (has_left)
         ydiag = head ? (b > 0 ? a.corner[b * 3 + c % 3] : -go) : side[-1].x;
-    int ybot = -go, fbot = 0, code_prev = kPad;
+    int ybot = -go, fbot = 0;
     int S = 0;
 
+    // Lane g works on column step - g.  Its code for the next step is the code
+    // lane g - 1 holds now (the head reads it from the residue stream), so the
+    // profile entries of the next column are loaded one step ahead, outside the
+    // per-lane column predicate, and their latency overlaps this column's cells.
     const int nsteps = (wc + K - 1 + 3) & ~3;
     uint4 rv = head ? resp[0] : pad16();
+    int code = head ? (int)(rv.x & 0xffu) : kPad;
+    uint4 pv[NV];
+    ldprof<NB, false>(pv, a.prof, pbase + (uint32_t)code * CS);
     for (int blk = 0; blk < nsteps; blk += 16) {
         const uint4 rvn = head ? resp[(blk + 16) >> 4] : pad16();
         const int n4 = min(4, (nsteps - blk) >> 2);
 #pragma unroll 1
         for (int k4 = 0; k4 < n4; ++k4) {
             const int col0 = blk + 4 * k4;
-            const uint32_t w = rv.x;
+            const uint32_t w = rv.x;                      // residues col0 .. col0 + 3
+            const uint32_t wn = k4 == 3 ? rvn.x : rv.y;   // col0 + 4 .. col0 + 7
             rv = make_uint4(rv.y, rv.z, rv.w, 0u);
             int ringY[4], ringF[4];
             if (has_top && head && col0 < wc) {
@@ -95,19 +103,24 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                // the shifts run with every lane active (a shift reads other
-                // lanes' registers); the column body only for this lane's own
-                // columns 0..wc-1, so its state stays that of its last column
-                const int cd = shr1(code_prev);
-                const int yd = shr1(ybot), fd = shr1(fbot);
+                // shifts and loads run with every lane active (a shift reads
+                // other lanes' registers); the column body only for this lane's
+                // own columns 0..wc-1, so its state stays that of its last column
+                // (pinned: a shift folded into the head/non-head select would be
+                // executed by the non-head lanes alone and read stale values)
+                int cd = shr1(code), yd = shr1(ybot), fd = shr1(fbot);
+                pin(cd);
+                pin(yd);
+                pin(fd);
+                const uint32_t wsrc = u < 3 ? w : wn;
+                const int shift = u < 3 ? 8 * (u + 1) : 0;
+                const int cnext = head ? (int)((wsrc >> shift) & 0xffu) : cd;
+                uint4 pvn[NV];
+                ldprof<NB, false>(pvn, a.prof, pbase + (uint32_t)cnext * CS);
                 const int j = col0 + u - g;               // this lane's column
                 if ((unsigned)j < (unsigned)wc) {
-                    const int code = head ? (int)((w >> (8 * u)) & 0xffu) : cd;
                     const int yt = head ? ringY[u] : yd;
                     const int ft = head ? ringF[u] : fd;
-                    uint4 pv[NV];
-                    ldprof<NB, false>(pv, a.prof, pbase + (uint32_t)code * CS);
-
                     int dg = ydiag;
                     ydiag = yt;
                     int hup = yt, F = ft;
@@ -131,10 +144,13 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
                     }
                     ybot = hup;
                     fbot = F;
-                    code_prev = code;
                     if (put_bottom)
                         top[j] = make_int2(ybot, fbot);
                 }
+                code = cnext;
+#pragma unroll
+                for (int i = 0; i < NV; ++i)
+                    pv[i] = pvn[i];
             }
         }
         rv = rvn;
@@ -188,15 +204,25 @@ hipError_t launch_pair_prep(const uint8_t* subj, int64_t n, int64_t n_pad, uint8
     return hipGetLastError();
 }
 
-hipError_t launch_pair_diag(const PairArgs& a, int elem, hipStream_t st)
+template <int R>
+void launch_pair_rows(const PairArgs& a, int elem, int blocks, hipStream_t st)
+{
+    if (elem == 1)
+        hipLaunchKernelGGL((k_pair_diag<R, 1>), dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_pair_diag<R, 2>), dim3(blocks), dim3(256), 0, st, a);
+}
+
+hipError_t launch_pair_diag(const PairArgs& a, int rows, int elem, hipStream_t st)
 {
     const int groups_per_wave = kWave / a.K;
     const int waves = (a.ntiles + groups_per_wave - 1) / groups_per_wave;
     const int blocks = (waves + 3) / 4;
-    if (elem == 1)
-        hipLaunchKernelGGL((k_pair_diag<kPairRows, 1>), dim3(blocks), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_pair_diag<kPairRows, 2>), dim3(blocks), dim3(256), 0, st, a);
+    switch (rows) {
+    case 8: launch_pair_rows<8>(a, elem, blocks, st); break;
+    case 16: launch_pair_rows<16>(a, elem, blocks, st); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

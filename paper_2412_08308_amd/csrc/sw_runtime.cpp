@@ -136,6 +136,7 @@ bool validate_options(const sw_options* opt, std::string& why)
     if (opt->lds_limit < 0 || opt->lds_limit > 128 * 1024) { why = "options.lds_limit"; return false; }
     if (opt->grid_limit < 0) { why = "options.grid_limit"; return false; }
     if (opt->pair_cols < 0) { why = "options.pair_cols"; return false; }
+    if (opt->pair_rows < 0) { why = "options.pair_rows"; return false; }
     return true;
 }
 
@@ -1272,67 +1273,91 @@ int sw_db_search(const uint8_t* query, int32_t qlen, const uint8_t* residues, co
 
 namespace {
 
-// Schedule of one pair: K lanes per band (K*R query rows), wc columns per
-// chunk.  Time model per anti-diagonal launch: its waves spread over the
-// device's SIMDs, each wave's instructions issued back to back (one wave64
-// VALU instruction per 4 cycles per SIMD), plus a fixed launch cost; the
-// candidate with the least total wins.
+// Schedule of one pair: R query rows per lane, K lanes per band (K*R query
+// rows), wc columns per chunk.  Time model: anti-diagonal launches in order;
+// a launch's waves spread over the device's SIMDs, each wave's instructions
+// issued back to back (one wave64 VALU instruction per 4 cycles per SIMD),
+// times a factor fitted to MI355X measurements of this kernel: about 1.25
+// with 1.5 to 3 waves per SIMD, more with fewer (latency shows) or more (the
+// waves' profile and boundary lines no longer fit the caches); plus a fixed
+// cost per launch.  The candidate with the least total wins.
 struct PairPlanC {
-    int K = 0, wc = 0;
+    int R = 0, K = 0, wc = 0;
     int64_t nb = 0, nc = 0, nbr = 0;
     double est_s = 0;
 };
 
 constexpr int64_t kPairMaxCols = 1 << 20;
-constexpr double kPairInstrPerCell = 8.4;     // hot-loop VALU instructions per lane-cell (int32 lanes)
 constexpr double kPairLaunchS = 4e-6;
 
-// sum over t = 1..T of ceil(t / q)
-double sum_ceil(int64_t T, int64_t q)
+// hot-loop VALU instructions per cell of the pair kernel by rows per lane
+// (counted in the gfx950 assembly of this code)
+double pair_instr_per_cell(int R)
 {
-    if (T <= 0) return 0;
-    const int64_t a = T / q, r = T % q;
-    return (double)q * a * (a + 1) / 2 + (double)(a + 1) * r;
+    return R == 8 ? 10.8 : 9.66;
 }
 
-double pair_time(int64_t m, int64_t n, int K, int wc, int cu)
+double pair_slowdown(double waves_per_simd)
 {
-    const int64_t nb = ceil_div(std::max<int64_t>(m, 1), (int64_t)K * kPairRows);
+    const double w = waves_per_simd;
+    if (w <= 1.0) return 1.45;
+    if (w <= 1.5) return 1.45 - 0.4 * (w - 1.0);
+    if (w <= 3.0) return 1.25;
+    return 1.25 + 0.28 * (w - 3.0);
+}
+
+double pair_time(int64_t m, int64_t n, int R, int K, int wc, int cu)
+{
+    const int64_t nb = ceil_div(std::max<int64_t>(m, 1), (int64_t)K * R);
     const int64_t nc = ceil_div(std::max<int64_t>(n, 1), wc);
-    // tiles per launch round: groups per wave x waves the SIMDs take at once
-    const int64_t q = (int64_t)(kWave / K) * 4 * std::max(cu, 1);
-    const double wave_s = kPairRows * (double)align_up(wc + K - 1, 4) * kPairInstrPerCell * 4.0 / 2.4e9;
+    const double per_wave = (double)(kWave / K);
+    const double simds = 4.0 * std::max(cu, 1);
+    const double wave_s = R * (double)align_up(wc + K - 1, 4) * pair_instr_per_cell(R) * 4.0 / 2.4e9;
     // anti-diagonal d holds min(d + 1, lo, nb + nc - 1 - d) tiles: two ramps of
     // 1..lo-1 tiles and max(nb, nc) - lo + 1 diagonals of lo tiles
     const int64_t lo = std::min(nb, nc), hi = std::max(nb, nc);
-    const double rounds = 2 * sum_ceil(lo - 1, q) + (double)(hi - lo + 1) * (double)ceil_div(lo, q);
-    return rounds * wave_s + (double)(nb + nc - 1) * kPairLaunchS;
+    auto launch = [&](int64_t tiles) {
+        const double w = std::ceil(tiles / per_wave) / simds;
+        return std::ceil(w) * wave_s * pair_slowdown(w);
+    };
+    double t = (double)(hi - lo + 1) * launch(lo);
+    for (int64_t tiles = 1; tiles < lo; ++tiles)
+        t += 2 * launch(tiles);
+    return t + (double)(nb + nc - 1) * kPairLaunchS;
 }
 
 PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt)
 {
     PairPlanC best;
     best.est_s = 1e300;
+    const int fixR = opt ? opt->pair_rows : 0;
     const int fixK = opt ? opt->max_lanes : 0;
     const int fixW = opt ? opt->pair_cols : 0;
-    for (int K : {1, 2, 4, 8, 16, 32, 64}) {
-        if (fixK && K != fixK) continue;
-        for (int wc : {64, 128, 256, 512, 1024, 2048, 4096, 8192}) {
-            if (fixW && wc != fixW) continue;
-            const double t = pair_time(m, n, K, wc, cu);
-            if (t < best.est_s) {
-                best.est_s = t;
-                best.K = K;
-                best.wc = wc;
+    for (int R : kPairRowChoices) {
+        if (fixR && R != fixR) continue;
+        for (int K : {1, 2, 4, 8, 16, 32, 64}) {
+            if (fixK && K != fixK) continue;
+            for (int wc : {64, 128, 256, 512, 1024, 2048, 4096, 8192}) {
+                if (fixW && wc != fixW) continue;
+                const double t = pair_time(m, n, R, K, wc, cu);
+                if (t < best.est_s) {
+                    best.est_s = t;
+                    best.R = R;
+                    best.K = K;
+                    best.wc = wc;
+                }
             }
         }
     }
-    if (fixK && !best.K) best.K = fixK;
-    if (fixW && !best.wc) best.wc = fixW;
-    if (fixK && fixW) best.est_s = pair_time(m, n, fixK, fixW, cu);
-    best.nb = ceil_div(std::max<int64_t>(m, 1), (int64_t)best.K * kPairRows);
+    if (fixW && !best.wc) {        // an explicit width outside the candidate list
+        best.wc = fixW;
+        best.R = fixR ? fixR : 16;
+        best.K = fixK ? fixK : 64;
+        best.est_s = pair_time(m, n, best.R, best.K, best.wc, cu);
+    }
+    best.nb = ceil_div(std::max<int64_t>(m, 1), (int64_t)best.K * best.R);
     best.nc = ceil_div(std::max<int64_t>(n, 1), best.wc);
-    best.nbr = ceil_div(m, kPairRows);
+    best.nbr = ceil_div(m, best.R);
     return best;
 }
 
@@ -1347,21 +1372,26 @@ struct PairLayout {
 PairLayout pair_layout(int64_t m, int64_t n, const PairPlanC* p)
 {
     PairLayout L;
-    const int64_t max_wc = kPairMaxCols;
-    const int64_t nbr = ceil_div(m, kPairRows);
+    // without a plan: the bound over every schedule (rows per lane 8..32)
     const int64_t cols = p ? p->nc * p->wc : align_up(n, 16) + 8192;
-    L.n_pad = p ? cols + 128 : 0;
+    int64_t prof = 0, rows_pad = 0, blocks = 0;
+    for (int R : kPairRowChoices) {
+        if (p && R != p->R) continue;
+        prof = std::max(prof, prof_bytes_for((int)ceil_div(m, R), R, 2));
+        rows_pad = std::max<int64_t>(rows_pad, align_up(m, R) + (int64_t)kWave * R);
+        blocks = std::max(blocks, ceil_div(m, R));
+    }
+    L.n_pad = cols + 128;
     size_t off = 0;
     L.counters = off; off += 256;
     L.qd = off; off += 256;
     L.qoff = off; off += 256;
-    L.corner = off; off += align_up((ceil_div(m, kPairRows) + 2) * 3 * 4, 256);
-    L.subj = off; off += align_up(p ? L.n_pad : align_up(n, 16) + 8192 + 128, 256);
-    L.prof = off; off += align_up(prof_bytes_for((int)nbr, kPairRows, 2), 256);
-    L.rowbuf = off; off += align_up((p ? cols : align_up(n, 16) + 8192) * (int64_t)sizeof(int2), 256);
-    L.colbuf = off; off += align_up((align_up(m, kPairRows) + (int64_t)kWave * kPairRows) * (int64_t)sizeof(int2), 256);
+    L.corner = off; off += align_up((blocks + 2) * 3 * 4, 256);
+    L.subj = off; off += align_up(L.n_pad, 256);
+    L.prof = off; off += align_up(prof, 256);
+    L.rowbuf = off; off += align_up(cols * (int64_t)sizeof(int2), 256);
+    L.colbuf = off; off += align_up(rows_pad * (int64_t)sizeof(int2), 256);
     L.total = off;
-    (void)max_wc;
     return L;
 }
 
@@ -1375,6 +1405,10 @@ int validate_pair(int64_t m, int64_t n, const sw_options* opt, std::string& why)
     }
     if (opt && opt->pair_cols && (opt->pair_cols % 16 || opt->pair_cols > kPairMaxCols)) {
         why = "options.pair_cols must be a multiple of 16, at most 2^20";
+        return 0;
+    }
+    if (opt && opt->pair_rows && opt->pair_rows != 8 && opt->pair_rows != 16) {
+        why = "options.pair_rows must be 0, 8 or 16";
         return 0;
     }
     return 1;
@@ -1404,6 +1438,7 @@ int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, 
     if (!out) return fail(SW_EINVAL, "null output");
     const PairPlanC p = pair_plan(m, n, cu_count > 0 ? cu_count : 256, opt);
     *out = sw_pair_stats{};
+    out->rows = p.R;
     out->lanes = p.K;
     out->cols = p.wc;
     out->bands = p.nb;
@@ -1446,7 +1481,7 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     qd.prof_off = 0;
     qd.m = (int32_t)m;
     qd.nbr = (int32_t)p.nbr;
-    qd.prof_bytes = (int32_t)std::min<int64_t>(prof_bytes_for((int)p.nbr, kPairRows, elem), INT32_MAX);
+    qd.prof_bytes = (int32_t)std::min<int64_t>(prof_bytes_for((int)p.nbr, p.R, elem), INT32_MAX);
     auto* qd_dev = reinterpret_cast<QueryDesc*>(w + L.qd);
     auto* qoff_dev = reinterpret_cast<int64_t*>(w + L.qoff);
     HIPCHK(launch_pair_prep(subject, n, (m > 0 && n > 0) ? L.n_pad : 0, w + L.subj, score_out, qd, qd_dev,
@@ -1466,8 +1501,7 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     pa.pad = elem == 1 ? -128 : -32768;
     for (int i = 0; i < kAlpha * kAlpha; ++i)
         pa.sm.v[i] = (int8_t)sm[i];
-    HIPCHK(launch_profile(pa, kPairRows, elem, (int)std::min<int64_t>((p.nbr + 1) * kCodes * kPairRows, INT32_MAX),
-                          stream));
+    HIPCHK(launch_profile(pa, p.R, elem, (int)std::min<int64_t>((p.nbr + 1) * kCodes * p.R, INT32_MAX), stream));
 
     PairArgs a{};
     a.subj = w + L.subj;
@@ -1491,7 +1525,7 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
         a.d = (int32_t)d;
         a.b_lo = (int32_t)b_lo;
         a.ntiles = (int32_t)(b_hi - b_lo + 1);
-        HIPCHK(launch_pair_diag(a, elem, stream));
+        HIPCHK(launch_pair_diag(a, p.R, elem, stream));
     }
     if (opt && opt->ev_search_end) HIPCHK(hipEventRecord(opt->ev_search_end, stream));
     return SW_OK;

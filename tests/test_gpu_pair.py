@@ -35,14 +35,15 @@ def test_dna_pairs(m, n):
     assert _gpu_pair(a, b, sm, go, ge) == exp
 
 
+@pytest.mark.parametrize("R", [8, 16])
 @pytest.mark.parametrize("K", [1, 2, 8, 64])
 @pytest.mark.parametrize("wc", [16, 64, 512])
-def test_tilings(K, wc):
+def test_tilings(R, K, wc):
     a, b = synth.dna_pair(3000, 3500, seed=5, identity=0.7, indel_rate=0.02)
     sm, go, ge = DNA
     exp = oracle_pair(a, b, sm, go, ge)
-    announce(f"pair tiling K={K} cols={wc}")
-    assert _gpu_pair(a, b, sm, go, ge, max_lanes=K, pair_cols=wc) == exp
+    announce(f"pair tiling R={R} K={K} cols={wc}")
+    assert _gpu_pair(a, b, sm, go, ge, pair_rows=R, max_lanes=K, pair_cols=wc) == exp
 
 
 @pytest.mark.parametrize("go,ge", [(10, 2), (0, 3), (3, 5), (120, 1)])
@@ -54,7 +55,8 @@ def test_protein_pairs_profile_widths(go, ge):
     b = synth.mutate(rng, a, 0.6)
     exp = oracle_pair(a, b, sm, go, ge)
     announce(f"protein pair go={go} ge={ge}")
-    assert _gpu_pair(a, b, sm, go, ge, max_lanes=16, pair_cols=256) == exp
+    for R in (8, 16):
+        assert _gpu_pair(a, b, sm, go, ge, pair_rows=R, max_lanes=16, pair_cols=256) == exp
     assert _gpu_pair(a, b, sm, go, ge) == exp
 
 
@@ -89,5 +91,5 @@ def test_large_tilings_agree():
     announce("pair 162k x 172k")
     ref = _gpu_pair(a, b, sm, go, ge)
     assert ref > 0.2 * 162_000          # a long homologous alignment (about 0.3 per base)
-    for K, wc in ((16, 256), (64, 4096)):
-        assert _gpu_pair(a, b, sm, go, ge, max_lanes=K, pair_cols=wc) == ref
+    for R, K, wc in ((16, 16, 256), (16, 64, 4096), (8, 64, 512), (16, 32, 1024)):
+        assert _gpu_pair(a, b, sm, go, ge, pair_rows=R, max_lanes=K, pair_cols=wc) == ref
