@@ -251,6 +251,8 @@ def pairwise(args, ev):
     import synth
     sm = synth.dna_matrix(synth.DNA_MATCH, synth.DNA_MISMATCH)
     go, ge = synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND
+    p8 = int(sm.max()) + go <= 127 and int(sm.min()) + go >= -128   # 8-bit profile entries
+    isa = isa_counts()
     runs = []
     for k in args.pair_sizes:
         m, n = synth.DNA_PAIR_SIZES[k]
@@ -277,11 +279,14 @@ def pairwise(args, ev):
             ev.destroy(e1)
         wall = sum(walls) / len(walls)
         plan = swdb.pair_plan(m, n, cu_count=torch.cuda.get_device_properties(0).multi_processor_count)
+        tiles_s = sum(kers) / len(kers) / 1e3
+        ops = isa[f"pair_r{plan['rows']}_p{8 if p8 else 16}"]["valu_per_cell"]
         runs.append({"m": m, "n": n, "cells": m * n, "gcups": round(m * n / wall / 1e9, 1),
-                     "ms": round(wall * 1e3, 2), "tiles_ms": round(sum(kers) / len(kers), 2),
+                     "ms": round(wall * 1e3, 2), "tiles_ms": round(tiles_s * 1e3, 2),
                      "score": int(out.cpu().item()), "steps": steps,
-                     "plan": {k2: plan[k2] for k2 in ("lanes", "cols", "bands", "chunks", "launches")},
-                     "model_ms": round(plan["est_ms"], 1)})
+                     "plan": {k2: plan[k2] for k2 in ("rows", "lanes", "cols", "bands", "chunks", "launches")},
+                     "model_ms": round(plan["est_ms"], 1), "isa_valu_per_cell": ops,
+                     "roofline_frac": round(m * n * ops / tiles_s / 1e12 / PEAK_VALU_TOPS, 4)})
         print(f"[bench] pair {m}x{n}: {runs[-1]['gcups']} GCUPS", file=sys.stderr, flush=True)
         del qa, qb, ws
     return {"workload": "one DNA pair per size (paper's pairwise sizes, synthetic 80%-identity homologs, "

@@ -1,10 +1,10 @@
 """VALU instructions per DP cell in the hot loops of the search kernels.
 
 Compiles ``csrc/sw_isa_probe.hip`` (each hot-loop variant alone in a kernel,
-same flags as the library) to AMD assembly of this build, finds each kernel's
-innermost loop -- one trip sweeps four subject columns of R query rows, i.e.
-4*R cells per lane (8*R for the packed 16-bit variant, two subjects per lane) --
-and counts its instructions by class.  The VALU count per cell is the ISA
+same flags as the library) and ``csrc/sw_pair.hip`` to AMD assembly of this
+build, finds each kernel's innermost loop -- one trip sweeps four subject
+columns of R query rows, i.e. 4*R cells per lane (8*R for the packed 16-bit
+variant, two subjects per lane) -- and counts its instructions by class.  The VALU count per cell is the ISA
 operation count of the integer-VALU roofline.
 """
 from __future__ import annotations
@@ -39,29 +39,42 @@ VARIANTS = {
     "i16_p8_glb_kn": ("isa_i16ILi24ELi1ELb0ELb1E", 24, 2),
     "rescore_i32_r24": ("isa_i32ILi24ELi2ELb0ELb1E", 24, 1),
     "rescore_i32_r24_p8": ("isa_i32ILi24ELi1ELb0ELb1E", 24, 1),
+    # single long pair (csrc/sw_pair.hip): R rows per lane, 8- / 16-bit profile
+    "pair_r8_p8": ("k_pair_diagILi8ELi1E", 8, 1),
+    "pair_r8_p16": ("k_pair_diagILi8ELi2E", 8, 1),
+    "pair_r16_p8": ("k_pair_diagILi16ELi1E", 16, 1),
+    "pair_r16_p16": ("k_pair_diagILi16ELi2E", 16, 1),
 }
+SOURCES = ["sw_isa_probe.hip", "sw_pair.hip"]
 
 
 def _innermost_loop(lines):
-    """Lines of the deepest loop (by the compiler's loop-depth comments)."""
+    """Lines of the blocks of the deepest loop: its header block and every
+    block the compiler annotates as inside it, wherever they are placed."""
+    blocks = []            # (label, annotation, start, end)
+    starts = [i for i, ln in enumerate(lines) if re.match(r"^\.LBB\w+:", ln)]
+    for n, i in enumerate(starts):
+        end = starts[n + 1] if n + 1 < len(starts) else len(lines)
+        ann = [lines[i]]                     # the label line and the comment lines after it
+        k = i + 1
+        while k < end and lines[k].strip().startswith(";"):
+            ann.append(lines[k])
+            k += 1
+        blocks.append((lines[i].split(":")[0], " ".join(ann), i, end))
     best = None
-    for i, ln in enumerate(lines):
-        m = re.search(r"Loop Header: Depth=(\d+)", ln)
-        if not m:
-            continue
-        depth = int(m.group(1))
-        j = i
-        while j > 0 and not lines[j].startswith(".LBB"):
-            j -= 1
-        label = lines[j].split(":")[0]
-        ends = [k for k, l in enumerate(lines) if re.search(r"s_c?branch\w*\s+" + re.escape(label) + r"\s*$", l)]
-        if not ends:
-            continue
-        if best is None or depth > best[0]:
-            best = (depth, j, max(ends))
+    for label, ann, i, end in blocks:
+        m = re.search(r"Loop Header: Depth=(\d+)", ann)
+        if m and (best is None or int(m.group(1)) > best[1]):
+            best = (label, int(m.group(1)))
     if best is None:
         return []
-    return lines[best[1]:best[2] + 1]
+    hdr, depth = best
+    tag = "Header=" + hdr[2:] + " Depth=" + str(depth)        # ".LBB1_2" -> "BB1_2"
+    out = []
+    for label, ann, i, end in blocks:
+        if label == hdr or tag in ann:
+            out.extend(lines[i:end])
+    return out
 
 
 def count(asm_text: str) -> dict:
@@ -89,14 +102,15 @@ def count(asm_text: str) -> dict:
 
 
 def run(out: str = OUT) -> dict:
+    res = {}
     with tempfile.TemporaryDirectory(prefix="swdb_isa_") as td:
-        asm = os.path.join(td, "probe.s")
-        cmd = [HIPCC] + FLAGS + ["-x", "hip", "--cuda-device-only", "-S",
-                                 os.path.join(CSRC, "sw_isa_probe.hip"), "-o", asm]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError("isa probe compile failed:\n" + r.stdout + r.stderr)
-        res = count(open(asm).read())
+        for src in SOURCES:
+            asm = os.path.join(td, src + ".s")
+            cmd = [HIPCC] + FLAGS + ["-x", "hip", "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", asm]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"{src} assembly failed:\n" + r.stdout + r.stderr)
+            res.update(count(open(asm).read()))
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1, sort_keys=True)
     return res
