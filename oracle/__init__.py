@@ -6,8 +6,10 @@ this package, and this package imports nothing from the GPU library.
 
 ``score`` / ``search`` call the plain C implementation in ``sw_oracle.c``
 (literal recurrence of the paper's Section 2.2 equations for H, E and F, int64
-arithmetic, borders initialised to 0, result = largest H).  ``score_py`` is the
-same recurrence in pure Python for tiny cases.
+arithmetic, borders initialised to 0, result = largest H).  ``align`` adds the
+traceback (full matrices, stated tie-breaks), pinned in
+``tests/test_oracle_align.py``.  ``score_py`` is the same recurrence in pure
+Python for tiny cases.
 
 Parity is pinned against the mathematics in ``tests/test_oracle_pins.py``:
 brute-force enumeration of local alignments, hand-worked examples in
@@ -45,6 +47,10 @@ def load(path: Optional[str] = None):
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                ctypes.c_void_p, ctypes.c_int]
+    lib.swo_align.restype = ctypes.c_int64
+    lib.swo_align.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                              ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                              ctypes.c_char_p, ctypes.c_int64]
     _libs[path] = lib
     if path == LIB:
         _lib = lib
@@ -103,6 +109,40 @@ def search(q, residues, offsets, lengths, sm, go: int, ge: int,
 def search_db(q, db, sm, go: int, ge: int, ids=None, threads=None, lib=None) -> np.ndarray:
     """``search`` over a ``synth.Database``-like object."""
     return search(q, db.residues, db.offsets, db.lengths, sm, go, ge, ids, threads, lib)
+
+
+def align(q, d, sm, go: int, ge: int, lib=None) -> dict:
+    """Optimal local alignment with its traceback (``swo_align``): score,
+    1-based inclusive begin/end positions in the query and the subject, and
+    the operations ('M', 'I' = query residue against a gap, 'D' = subject
+    residue against a gap) from begin to end.  Tie-breaks: end = first cell
+    with H = S in column-major order; diagonal before E before F; a gap opens
+    rather than extends when both give its value."""
+    lib = lib or load()
+    q, d, sm = _u8(q), _u8(d), _sm(sm)
+    out = np.zeros(5, dtype=np.int64)
+    cap = len(q) + len(d) + 1
+    buf = ctypes.create_string_buffer(cap)
+    n = lib.swo_align(q.ctypes.data, len(q), d.ctypes.data, len(d), sm.ctypes.data, int(go), int(ge),
+                      out.ctypes.data, buf, cap)
+    if n == -1:
+        raise MemoryError("oracle alignment: out of memory")
+    if n < 0:
+        raise RuntimeError("oracle alignment: traceback left the matrix")
+    return {"score": int(out[0]), "q_begin": int(out[1]), "s_begin": int(out[2]), "q_end": int(out[3]),
+            "s_end": int(out[4]), "ops": buf.raw[:n].decode()}
+
+
+def cigar(ops: str) -> str:
+    """Run-length form of an operation string ("MMMID" -> "3M1I1D")."""
+    out, k = [], 0
+    while k < len(ops):
+        r = k
+        while r < len(ops) and ops[r] == ops[k]:
+            r += 1
+        out.append(f"{r - k}{ops[k]}")
+        k = r
+    return "".join(out)
 
 
 def score_py(q, d, sm, go: int, ge: int) -> int:

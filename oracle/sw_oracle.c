@@ -21,8 +21,11 @@
  * and current) are kept, E runs along the current row.  Nothing is blocked,
  * fused or reordered beyond that.
  *
+ * swo_align (below) adds the alignment itself for one pair.
+ *
  * ORACLE_MUTANT (compile-time, default 0) plants one deliberate mistake so the
- * test suite can show that its pins catch it; products never set it.
+ * test suite can show that its pins catch it (1-7 in the score, 8-11 in the
+ * traceback); products never set it.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -163,4 +166,132 @@ int swo_search(const uint8_t *Q, int64_t m, const uint8_t *res, const int64_t *o
         pthread_join(th[t], NULL);
     free(th);
     return jb.failed ? -1 : 0;
+}
+
+/*
+ * One pair with its alignment (the traceback the paper mentions as the
+ * optional step after the score, Section 2.2).  Full int64 matrices H, E, F of
+ * (m+1) x (n+1) entries, filled with the same recurrence as swo_score.
+ *
+ * Reading of the unspecified choices (the paper gives none):
+ *   end cell   the first cell with H = S in column-major order: smallest
+ *              subject position j, then smallest query position i;
+ *   traceback  from the end cell in state H: the diagonal term if it gives
+ *              H, else E, else F; a gap state opens (from H) rather than
+ *              extends when both give its value; the alignment begins at the
+ *              diagonal step whose predecessor cell holds H = 0 (or lies on
+ *              the border).
+ * Output: S, 1-based inclusive begin/end positions, and the operations from
+ * begin to end: 'M' (query residue aligned to subject residue), 'I' (query
+ * residue against a gap, the F direction), 'D' (subject residue against a gap,
+ * the E direction).  S = 0 gives an empty alignment (positions 0).
+ * Returns the number of operations, -1 when memory runs out, -2 when `cap` is
+ * too small.
+ */
+int64_t swo_align(const uint8_t *Q, int64_t m, const uint8_t *D, int64_t n, const int32_t *SM,
+                  int64_t Go, int64_t Ge, int64_t *out5, char *ops, int64_t cap)
+{
+    out5[0] = out5[1] = out5[2] = out5[3] = out5[4] = 0;
+    if (m <= 0 || n <= 0)
+        return 0;
+    const int64_t W = n + 1;
+    const size_t cells = (size_t)(m + 1) * (size_t)W;
+    int64_t *H = calloc(cells, sizeof(int64_t));
+    int64_t *E = calloc(cells, sizeof(int64_t));
+    int64_t *F = calloc(cells, sizeof(int64_t));
+    if (!H || !E || !F) {
+        free(H); free(E); free(F);
+        return -1;
+    }
+#define AT(X, i, j) X[(size_t)(i) * (size_t)W + (size_t)(j)]
+    for (int64_t i = 1; i <= m; ++i) {
+        for (int64_t j = 1; j <= n; ++j) {
+            const int64_t sm = SM[(int)Q[i - 1] * 32 + (int)D[j - 1]];
+            AT(E, i, j) = max2(AT(H, i, j - 1) - Go, AT(E, i, j - 1) - Ge);
+            AT(F, i, j) = max2(AT(H, i - 1, j) - Go, AT(F, i - 1, j) - Ge);
+            AT(H, i, j) = max2(max2(0, AT(H, i - 1, j - 1) + sm), max2(AT(E, i, j), AT(F, i, j)));
+        }
+    }
+    int64_t S = 0, bi = 0, bj = 0;
+#if ORACLE_MUTANT == 8
+    for (int64_t i = 1; i <= m; ++i)            /* row-major first maximum */
+        for (int64_t j = 1; j <= n; ++j)
+#else
+    for (int64_t j = 1; j <= n; ++j)            /* column-major: first maximum */
+        for (int64_t i = 1; i <= m; ++i)
+#endif
+            if (AT(H, i, j) > S) {
+                S = AT(H, i, j);
+                bi = i;
+                bj = j;
+            }
+    int64_t nops = 0;
+    if (S > 0) {
+        int64_t i = bi, j = bj;
+        int state = 0;                           /* 0: H, 1: E, 2: F */
+        for (;;) {
+            if (nops >= cap || i < 1 || j < 1) {  /* never reached by the rules above */
+                free(H); free(E); free(F);
+                return -2;
+            }
+            if (state == 0) {
+                const int64_t sm = SM[(int)Q[i - 1] * 32 + (int)D[j - 1]];
+                const int64_t h = AT(H, i, j);
+#if ORACLE_MUTANT == 9
+                if (h == AT(E, i, j)) {          /* gap before diagonal */
+                    state = 1;
+                } else if (h == AT(H, i - 1, j - 1) + sm) {
+#else
+                if (h == AT(H, i - 1, j - 1) + sm) {
+#endif
+                    ops[nops++] = 'M';
+#if ORACLE_MUTANT == 11
+                    if (i == 1 || j == 1)        /* runs on through H = 0 */
+#else
+                    if (i == 1 || j == 1 || AT(H, i - 1, j - 1) == 0)
+#endif
+                        break;                   /* begins here */
+                    --i;
+                    --j;
+#if ORACLE_MUTANT == 9
+                } else {
+                    state = 2;
+                }
+#else
+                } else if (h == AT(E, i, j)) {
+                    state = 1;
+                } else {
+                    state = 2;
+                }
+#endif
+            } else if (state == 1) {             /* E: subject residue j against a gap */
+                ops[nops++] = 'D';
+#if ORACLE_MUTANT == 10
+                if (AT(E, i, j) != AT(E, i, j - 1) - Ge)    /* extend before open */
+#else
+                if (AT(E, i, j) == AT(H, i, j - 1) - Go)
+#endif
+                    state = 0;
+                --j;
+            } else {                             /* F: query residue i against a gap */
+                ops[nops++] = 'I';
+                if (AT(F, i, j) == AT(H, i - 1, j) - Go)
+                    state = 0;
+                --i;
+            }
+        }
+        out5[1] = i;                             /* begin (query, subject) */
+        out5[2] = j;
+        for (int64_t a = 0, b = nops - 1; a < b; ++a, --b) {
+            const char t = ops[a];
+            ops[a] = ops[b];
+            ops[b] = t;
+        }
+    }
+#undef AT
+    out5[0] = S;
+    out5[3] = bi;                                /* end (query, subject) */
+    out5[4] = bj;
+    free(H); free(E); free(F);
+    return nops;
 }

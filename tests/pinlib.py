@@ -144,3 +144,64 @@ def hand_examples() -> List[Dict]:
             rows.append(dict(name=name, q=expand(qs), d=expand(ds), match=int(ma),
                              mismatch=int(mi), go=int(go), ge=int(ge), expected=int(exp)))
     return rows
+
+
+def optimal_alignments(q, d, sm, go: int, ge: int):
+    """Every local alignment reaching the best score, by explicit enumeration
+    (tiny inputs only).  Returns (best, [(q_begin, s_begin, q_end, s_end,
+    ops)]) with 1-based inclusive positions and ops over 'M' (a residue pair),
+    'D' (a subject residue against a gap) and 'I' (a query residue against a
+    gap); gap runs cost ``go`` for the first residue and ``ge`` for each
+    further one (a run may be re-opened at ``go`` when go < ge).  Only
+    alignments that begin and end with 'M' are listed: trimming a trailing or
+    leading gap never lowers a score."""
+    m, n = len(q), len(d)
+    sm = np.asarray(sm)
+    found = []
+
+    def dfs(a, c, i, j, prev, s, ops):
+        if ops and ops[-1] == "M":
+            found.append((s, a + 1, c + 1, i, j, "".join(ops)))
+        if i < m and j < n:
+            ops.append("M")
+            dfs(a, c, i + 1, j + 1, "M", s + int(sm[q[i]][d[j]]), ops)
+            ops.pop()
+        if not ops:
+            return
+        for op, di, dj in (("D", 0, 1), ("I", 1, 0)):
+            if i + di > m or j + dj > n:
+                continue
+            costs = [ge] if prev == op else []
+            if prev != op or go < ge:
+                costs.append(go)
+            for cst in set(costs):
+                ops.append(op)
+                dfs(a, c, i + di, j + dj, op, s - cst, ops)
+                ops.pop()
+
+    for a in range(m):
+        for c in range(n):
+            dfs(a, c, a, c, "", 0, [])
+    best = max([f[0] for f in found] + [0])
+    return best, sorted({f[1:] for f in found if f[0] == best and best > 0})
+
+
+def ops_score(q, d, sm, go: int, ge: int, q_begin: int, s_begin: int, ops: str):
+    """Score of an alignment given by its begin positions (1-based) and ops,
+    and the (query, subject) positions it ends at; gap runs cost go + (L-1) ge."""
+    sm = np.asarray(sm)
+    i, j = q_begin - 1, s_begin - 1
+    s, prev = 0, ""
+    for op in ops:
+        if op == "M":
+            s += int(sm[q[i]][d[j]])
+            i += 1
+            j += 1
+        else:
+            s -= min(ge, go) if op == prev else go
+            if op == "D":
+                j += 1
+            else:
+                i += 1
+        prev = op
+    return s, i, j
