@@ -323,6 +323,50 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
                   const sw_options* opt, void* workspace, size_t ws_bytes, int32_t* score_out,
                   hipStream_t stream);
 
+/* ------------------------------------------------------------------ alignment of one pair
+ *
+ * The optional traceback after the score (paper Section 2.2: the alignment is
+ * recovered from the matrix "if required"): the optimal local alignment of
+ * one pair, not only its score.  Two passes of the pair tiles (8 query rows
+ * per lane, 64 lanes per band): the score, then the same cells again writing a
+ * 4-bit direction code per cell and finding the end cell; one lane then walks
+ * the codes back.  Tie-breaks (the paper gives none): the end is the first
+ * cell holding the score in column-major order (smallest subject position,
+ * then smallest query position); walking back, the diagonal is taken before E
+ * before F, a gap is opened (from H) rather than extended when both give its
+ * value, and the alignment begins at the first residue pair whose
+ * predecessor holds H = 0 or lies on the border.
+ */
+typedef struct sw_alignment {
+    int32_t score;
+    int32_t q_begin, s_begin;  /* 1-based, inclusive (0 when score = 0)        */
+    int32_t q_end, s_end;
+    int32_t n_ops;             /* operations written (-1: inconsistent codes)  */
+} sw_alignment;
+
+/* Workspace bytes sw_align_pair needs (0 on invalid input, or when m * n
+   exceeds 2^32 cells: the direction codes take half a byte per cell). */
+size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt);
+
+/*
+ * Optimal local alignment of query[m] (rows) against subject[n] (columns).
+ *   query, subject  device, uint8 codes (read modulo 32)
+ *   subst_matrix    HOST, int32[32*32]; gap_open/extend as in sw_db_search
+ *   opt             NULL or options (pair_cols; ev_search_begin/end around
+ *                   the tile passes)
+ *   workspace       device, >= sw_align_workspace_bytes(m, n, opt), 256-byte aligned
+ *   out             device, one sw_alignment
+ *   ops             device, char[m + n]: 'M' (query residue paired with a
+ *                   subject residue), 'I' (query residue against a gap), 'D'
+ *                   (subject residue against a gap), begin to end; out->n_ops
+ *                   of them are written
+ * Asynchronous on `stream`.  Returns SW_EINVAL, SW_ENOMEM or SW_EHIP.
+ */
+int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n,
+                  const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
+                  const sw_options* opt, void* workspace, size_t ws_bytes, sw_alignment* out,
+                  char* ops, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,6 +87,11 @@ class PairStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Alignment(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_int32), ("q_begin", ctypes.c_int32), ("s_begin", ctypes.c_int32),
+                ("q_end", ctypes.c_int32), ("s_end", ctypes.c_int32), ("n_ops", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -117,6 +122,10 @@ def lib():
     L.sw_pair_plan.argtypes = [i64, i64, ctypes.POINTER(Options), i32, ctypes.POINTER(PairStats)]
     L.sw_pair_score.restype = ctypes.c_int
     L.sw_pair_score.argtypes = [vp, i64, vp, i64, vp, i32, i32, ctypes.POINTER(Options), vp, sz, vp, vp]
+    L.sw_align_workspace_bytes.restype = sz
+    L.sw_align_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Options)]
+    L.sw_align_pair.restype = ctypes.c_int
+    L.sw_align_pair.argtypes = [vp, i64, vp, i64, vp, i32, i32, ctypes.POINTER(Options), vp, sz, vp, vp, vp]
     L.sw_select_variant.restype = i32
     L.sw_select_variant.argtypes = [vp, i32, ctypes.POINTER(Options)]
     L.sw_db_search_ex.restype = ctypes.c_int
@@ -288,6 +297,41 @@ def pair_score(query, subject, matrix, gap_open: int, gap_extend: int, opt: Opti
                              int(workspace.numel()), _dev(out, torch.int32, "out"), _stream(stream))
     _check(rc, "sw_pair_score")
     return out
+
+
+def align_workspace_bytes(m: int, n: int, opt: Optional[Options] = None) -> int:
+    v = lib().sw_align_workspace_bytes(int(m), int(n), ctypes.byref(opt) if opt is not None else None)
+    if v == 0:
+        raise SwdbError(-1, "sw_align_workspace_bytes", lib().sw_last_error().decode())
+    return int(v)
+
+
+def align_pair(query, subject, matrix, gap_open: int, gap_extend: int, opt: Optional[Options] = None,
+               workspace=None, stream=None) -> dict:
+    """``sw_align_pair``: optimal local alignment of one pair on the device.
+    Blocking (copies the result back): score, 1-based inclusive begin/end
+    positions and the operation string ('M', 'I', 'D') from begin to end."""
+    import torch
+    m, n = int(query.numel()), int(subject.numel())
+    dev = query.device if m else subject.device
+    if workspace is None:
+        workspace = torch.empty(align_workspace_bytes(m, n, opt), dtype=torch.uint8, device=dev)
+    out = torch.zeros(ctypes.sizeof(Alignment), dtype=torch.uint8, device=dev)
+    ops = torch.zeros(max(m + n, 1), dtype=torch.uint8, device=dev)
+    sm = _matrix(matrix)
+    o = ctypes.byref(opt) if opt is not None else None
+    rc = lib().sw_align_pair(_dev(query, torch.uint8, "query") if m else None, m,
+                             _dev(subject, torch.uint8, "subject") if n else None, n, sm.ctypes.data,
+                             int(gap_open), int(gap_extend), o, _dev(workspace, torch.uint8, "workspace"),
+                             int(workspace.numel()), _dev(out, torch.uint8, "out"), _dev(ops, torch.uint8, "ops"),
+                             _stream(stream))
+    _check(rc, "sw_align_pair")
+    (torch.cuda.current_stream(dev) if stream is None else stream).synchronize()
+    a = Alignment.from_buffer_copy(out.cpu().numpy().tobytes())
+    if a.n_ops < 0:
+        raise SwdbError(-3, "sw_align_pair", "inconsistent direction codes")
+    return {"score": a.score, "q_begin": a.q_begin, "s_begin": a.s_begin, "q_end": a.q_end, "s_end": a.s_end,
+            "ops": ops[:a.n_ops].cpu().numpy().tobytes().decode() if a.n_ops > 0 else ""}
 
 
 class Database:

@@ -113,6 +113,20 @@ struct PairArgs {
     int32_t go, ge;
     int32_t d;                   // anti-diagonal: b + c
     int32_t b_lo, ntiles;        // first band on the diagonal, tiles on it
+    // traceback pass only (8 rows per lane): per cell a 4-bit code, bits 0-1
+    // the source of H (0: H = 0, 1: diagonal, 2: E, 3: F), bit 2 E opened
+    // (from H) rather than extended, bit 3 the same for F; column-major, one
+    // 32-bit word per 8 rows: dir[col * dir_stride + row / 8]
+    uint32_t* dir;
+    int64_t dir_stride;          // words per column: nb * K
+    int64_t m, n;                // real lengths (cells past them are padding)
+    unsigned long long* end_key; // min over cells with H = *score of col << 32 | row
+};
+
+// Alignment found by the traceback pass (device memory, written by the
+// traceback kernel): 1-based inclusive positions, operation count.
+struct AlignOut {
+    int32_t score, q_begin, s_begin, q_end, s_end, n_ops;
 };
 
 // Kernel variants the runtime may launch.
@@ -149,5 +163,11 @@ constexpr int kPairRowChoices[2] = {8, 16};
 hipError_t launch_pair_prep(const uint8_t* subj, int64_t n, int64_t n_pad, uint8_t* dst, int32_t* score,
                             const QueryDesc& qd, QueryDesc* qd_out, int64_t* qoff_out, hipStream_t st);
 hipError_t launch_pair_diag(const PairArgs& a, int rows, int elem, hipStream_t st);
+// Traceback: the direction pass over one anti-diagonal (8 rows per lane, K =
+// 64), the end-key reset, and the single-lane walk that writes the alignment.
+hipError_t launch_trace_diag(const PairArgs& a, int elem, hipStream_t st);
+hipError_t launch_trace_reset(unsigned long long* end_key, hipStream_t st);
+hipError_t launch_traceback(const uint32_t* dir, int64_t dir_stride, const unsigned long long* end_key,
+                            const int32_t* score, char* ops, int64_t cap, AlignOut* out, hipStream_t st);
 
 }  // namespace swdb

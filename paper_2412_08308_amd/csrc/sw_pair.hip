@@ -21,9 +21,15 @@
 
 namespace swdb {
 
-template <int R, int ES>
+// TRACE (8 rows per lane only): also write each cell's 4-bit direction code
+// (PairArgs::dir) and find the first cell, in column-major order, whose H
+// equals the score already computed by a plain pass (PairArgs::end_key).  The
+// codes follow the traceback rules: the diagonal before E before F, a gap
+// opened from H rather than extended when both give its value.
+template <int R, int ES, bool TRACE = false>
 __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
 {
+    static_assert(!TRACE || R == 8, "direction words hold 8 rows");
     constexpr uint32_t CS = code_stride(R, ES);
     constexpr uint32_t BS = kCodes * CS;
     constexpr int NB = R * ES;
@@ -72,6 +78,8 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
         ydiag = head ? (b > 0 ? a.corner[b * 3 + c % 3] : -go) : side[-1].x;
     int ybot = -go, fbot = 0;
     int S = 0;
+    const int s_target = TRACE ? *a.score : 0;
+    unsigned long long key = ~0ull;          // first cell holding s_target (TRACE)
 
     // Lane g works on column step - g.  Its code for the next step is the code
     // lane g - 1 holds now (the head reads it from the residue stream), so the
@@ -125,12 +133,21 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
                     ydiag = yt;
                     int hup = yt, F = ft;
                     int hprev = 0;
+                    uint32_t word = 0, hits = 0;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const int t = dg + pent<ES>(pv, r);
-                        const int e = imax3(E[r] - ge, Y[r], 0);
-                        F = max(F - ge, hup);
+                        const int eo = E[r] - ge;
+                        const int e = imax3(eo, Y[r], 0);
+                        const int fo = F - ge;
+                        F = max(fo, hup);
                         const int h = imax3(t, e, F);
+                        if constexpr (TRACE) {
+                            uint32_t code = h == 0 ? 0u : (h == t ? 1u : (h == e ? 2u : 3u));
+                            code |= (Y[r] >= eo ? 4u : 0u) | (hup >= fo ? 8u : 0u);
+                            word |= code << (4 * r);
+                            hits |= (h == s_target ? 1u : 0u) << r;
+                        }
                         if (r & 1) {
                             S = imax3(S, hprev, h);
                             pin(S);
@@ -146,6 +163,15 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
                     fbot = F;
                     if (put_bottom)
                         top[j] = make_int2(ybot, fbot);
+                    if constexpr (TRACE) {
+                        const int64_t col = c0 + j;
+                        if (valid) {
+                            a.dir[col * a.dir_stride + rb] = word;
+                            const int64_t row = row0 + (hits ? __builtin_ctz(hits) : 0);
+                            if (hits && key == ~0ull && col < a.n && row < a.m)
+                                key = ((unsigned long long)col << 32) | (unsigned long long)row;
+                        }
+                    }
                 }
                 code = cnext;
 #pragma unroll
@@ -164,6 +190,16 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
         if (put_bottom)
             a.corner[(b + 1) * 3 + (c + 1) % 3] = ybot;
     }
+    if constexpr (TRACE) {
+        // first hit of the wave (column, then row), into the pair's end key
+        for (int k = 32; k >= 1; k >>= 1) {
+            const unsigned long long o = __shfl_xor(key, k);
+            key = o < key ? o : key;
+        }
+        if (lane == 0 && key != ~0ull)
+            atomicMin(a.end_key, key);
+        return;
+    }
     // tile maximum into the pair's score
     S = valid ? S : 0;
     for (int k = 32; k >= 1; k >>= 1)
@@ -176,6 +212,114 @@ template <int R, int ES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_pair_diag(PairArgs a)
 {
     pair_tile<R, ES>(a, threadIdx.x & 63);
+}
+
+template <int ES>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_trace_diag(PairArgs a)
+{
+    pair_tile<8, ES, true>(a, threadIdx.x & 63);
+}
+
+__global__ void k_trace_reset(unsigned long long* end_key)
+{
+    if (threadIdx.x == 0)
+        *end_key = ~0ull;
+}
+
+// Walk of the traceback (one lane): from the end cell in state H, follow the
+// direction codes -- the diagonal emits a residue pair and stops when its
+// predecessor holds H = 0 or lies on the border, E emits a subject residue
+// against a gap, F a query residue against a gap, each returning to H where
+// the gap was opened -- then reverse the operations into begin-to-end order.
+__global__ void k_traceback(const uint32_t* __restrict__ dir, int64_t stride,
+                            const unsigned long long* __restrict__ end_key, const int32_t* __restrict__ score,
+                            char* __restrict__ ops, int64_t cap, AlignOut* out)
+{
+    if (threadIdx.x != 0)
+        return;
+    AlignOut r{};
+    r.score = *score;
+    const unsigned long long key = *end_key;
+    int64_t n_ops = 0;
+    if (r.score > 0 && key != ~0ull) {
+        int64_t j = (int64_t)(key >> 32) + 1, i = (int64_t)(key & 0xffffffffull) + 1;   // 1-based
+        r.q_end = (int32_t)i;
+        r.s_end = (int32_t)j;
+        auto code = [&](int64_t ii, int64_t jj) {
+            const uint32_t w = dir[(jj - 1) * stride + ((ii - 1) >> 3)];
+            return (w >> (4 * ((ii - 1) & 7))) & 15u;
+        };
+        int state = 0;
+        bool ok = false;
+        while (n_ops < cap && i >= 1 && j >= 1) {
+            const uint32_t c = code(i, j);
+            if (state == 0) {
+                const uint32_t src = c & 3u;
+                if (src == 1u) {
+                    ops[n_ops++] = 'M';
+                    if (i == 1 || j == 1 || (code(i - 1, j - 1) & 3u) == 0u) {
+                        ok = true;
+                        break;
+                    }
+                    --i;
+                    --j;
+                } else if (src == 2u) {
+                    state = 1;
+                } else if (src == 3u) {
+                    state = 2;
+                } else {
+                    break;                        // H = 0 on the path: inconsistent codes
+                }
+            } else if (state == 1) {
+                ops[n_ops++] = 'D';
+                if (c & 4u)
+                    state = 0;
+                --j;
+            } else {
+                ops[n_ops++] = 'I';
+                if (c & 8u)
+                    state = 0;
+                --i;
+            }
+        }
+        if (ok) {
+            r.q_begin = (int32_t)i;
+            r.s_begin = (int32_t)j;
+            for (int64_t x = 0, y = n_ops - 1; x < y; ++x, --y) {
+                const char t = ops[x];
+                ops[x] = ops[y];
+                ops[y] = t;
+            }
+        } else {
+            n_ops = -1;                           // reported as an error by the host
+        }
+    }
+    r.n_ops = (int32_t)n_ops;
+    *out = r;
+}
+
+hipError_t launch_trace_diag(const PairArgs& a, int elem, hipStream_t st)
+{
+    const int waves = a.ntiles;                   // K = 64: one tile per wave
+    const int blocks = (waves + 3) / 4;
+    if (elem == 1)
+        hipLaunchKernelGGL((k_trace_diag<1>), dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_trace_diag<2>), dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_reset(unsigned long long* end_key, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_trace_reset, dim3(1), dim3(64), 0, st, end_key);
+    return hipGetLastError();
+}
+
+hipError_t launch_traceback(const uint32_t* dir, int64_t dir_stride, const unsigned long long* end_key,
+                            const int32_t* score, char* ops, int64_t cap, AlignOut* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_traceback, dim3(1), dim3(64), 0, st, dir, dir_stride, end_key, score, ops, cap, out);
+    return hipGetLastError();
 }
 
 // Padded subject copy (codes taken modulo 32, pad code past the end) and the

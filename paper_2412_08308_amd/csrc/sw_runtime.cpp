@@ -1449,34 +1449,43 @@ int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, 
     return SW_OK;
 }
 
-int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n, const int32_t* sm,
-                  int32_t go, int32_t ge, const sw_options* opt, void* ws, size_t ws_bytes, int32_t* score_out,
-                  hipStream_t stream)
+}  // extern "C"
+
+namespace {
+
+int pair_args_check(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n, const int32_t* sm,
+                    int32_t go, int32_t ge, const sw_options* opt, void* ws, int& fit)
 {
     std::string why;
     if (!validate_pair(m, n, opt, why)) return fail(SW_EINVAL, why);
     if (m > 0 && !query) return fail(SW_EINVAL, "null query");
     if (n > 0 && !subject) return fail(SW_EINVAL, "null subject");
     if (!sm) return fail(SW_EINVAL, "null substitution matrix");
-    if (!score_out) return fail(SW_EINVAL, "null score_out");
     if (go < 0 || ge < 0 || go > SW_MAX_GAP || ge > SW_MAX_GAP)
         return fail(SW_EINVAL, "gap penalties must be in [0, SW_MAX_GAP]");
-    const int fit = matrix_elem(sm, go, why);
+    fit = matrix_elem(sm, go, why);
     if (!fit) return fail(SW_EINVAL, why);
     if (!ws) return fail(SW_EINVAL, "null workspace");
     if (((uintptr_t)ws & 255) != 0) return fail(SW_EINVAL, "workspace must be 256-byte aligned");
-    const size_t need = sw_pair_workspace_bytes(m, n, opt);
-    if (ws_bytes < need)
-        return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
-    int dev = 0, cu = 256;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
-    const PairPlanC p = pair_plan(m, n, cu, opt);
-    const PairLayout L = pair_layout(m, n, &p);
-    if (L.total > need) return fail(SW_EINVAL, "internal error: pair layout exceeds the workspace size");
-    uint8_t* w = static_cast<uint8_t*>(ws);
-    const int elem = (fit == kFitS8 || fit == kFitU8) ? 1 : 2;
+    return SW_OK;
+}
 
+int device_cu(int* cu)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(cu, hipDeviceAttributeMultiprocessorCount, dev));
+    return SW_OK;
+}
+
+// Everything one pass over a pair enqueues: padded subject, cleared score,
+// profile, then the anti-diagonal launches (score pass), and for an alignment
+// a second pass of the same tiles writing direction codes and the end key.
+int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint8_t* query, int64_t m,
+                 const uint8_t* subject, int64_t n, const int32_t* sm, int32_t go, int32_t ge, int elem,
+                 int32_t* score_out, uint32_t* dir, unsigned long long* end_key, hipEvent_t ev0, hipEvent_t ev1,
+                 hipStream_t stream)
+{
     QueryDesc qd{};
     qd.prof_off = 0;
     qd.m = (int32_t)m;
@@ -1517,17 +1526,125 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     a.wc = p.wc;
     a.go = go;
     a.ge = ge;
-    const bool ev = opt && opt->ev_search_begin;
-    if (ev) HIPCHK(hipEventRecord(opt->ev_search_begin, stream));
-    for (int64_t d = 0; d < p.nb + p.nc - 1; ++d) {
-        const int64_t b_lo = std::max<int64_t>(0, d - (p.nc - 1));
-        const int64_t b_hi = std::min<int64_t>(d, p.nb - 1);
-        a.d = (int32_t)d;
-        a.b_lo = (int32_t)b_lo;
-        a.ntiles = (int32_t)(b_hi - b_lo + 1);
-        HIPCHK(launch_pair_diag(a, p.R, elem, stream));
+    a.dir = dir;
+    a.dir_stride = p.nb * p.K;
+    a.m = m;
+    a.n = n;
+    a.end_key = end_key;
+    if (ev0) HIPCHK(hipEventRecord(ev0, stream));
+    for (int pass = 0; pass < (dir ? 2 : 1); ++pass) {
+        if (pass == 1)
+            HIPCHK(launch_trace_reset(end_key, stream));
+        for (int64_t d = 0; d < p.nb + p.nc - 1; ++d) {
+            const int64_t b_lo = std::max<int64_t>(0, d - (p.nc - 1));
+            const int64_t b_hi = std::min<int64_t>(d, p.nb - 1);
+            a.d = (int32_t)d;
+            a.b_lo = (int32_t)b_lo;
+            a.ntiles = (int32_t)(b_hi - b_lo + 1);
+            if (pass == 0)
+                HIPCHK(launch_pair_diag(a, p.R, elem, stream));
+            else
+                HIPCHK(launch_trace_diag(a, elem, stream));
+        }
     }
-    if (opt && opt->ev_search_end) HIPCHK(hipEventRecord(opt->ev_search_end, stream));
+    if (ev1) HIPCHK(hipEventRecord(ev1, stream));
+    return SW_OK;
+}
+
+constexpr int64_t kAlignMaxCells = int64_t(1) << 32;   // direction codes: half a byte per cell
+
+// Alignment schedule: 8 rows per lane, 64 lanes per band (direction words of
+// 8 rows), the planner's chunk width for that.
+PairPlanC align_plan(int64_t m, int64_t n, int cu, const sw_options* opt)
+{
+    sw_options o = opt ? *opt : sw_options{};
+    o.pair_rows = 8;
+    o.max_lanes = 64;
+    return pair_plan(m, n, cu, &o);
+}
+
+// direction words (bound over every chunk width) and the end key
+size_t align_extra_bytes(int64_t m, int64_t n, const PairPlanC* p)
+{
+    const int64_t words = p ? p->nb * p->K * p->nc * p->wc
+                            : ceil_div(std::max<int64_t>(m, 1), 512) * 64 * (align_up(n, 16) + 8192);
+    return (size_t)align_up(words * 4, 256) + 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n, const int32_t* sm,
+                  int32_t go, int32_t ge, const sw_options* opt, void* ws, size_t ws_bytes, int32_t* score_out,
+                  hipStream_t stream)
+{
+    int fit = 0;
+    int rc = pair_args_check(query, m, subject, n, sm, go, ge, opt, ws, fit);
+    if (rc) return rc;
+    if (!score_out) return fail(SW_EINVAL, "null score_out");
+    const size_t need = sw_pair_workspace_bytes(m, n, opt);
+    if (ws_bytes < need)
+        return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    int cu = 256;
+    rc = device_cu(&cu);
+    if (rc) return rc;
+    const PairPlanC p = pair_plan(m, n, cu, opt);
+    const PairLayout L = pair_layout(m, n, &p);
+    if (L.total > need) return fail(SW_EINVAL, "internal error: pair layout exceeds the workspace size");
+    const int elem = (fit == kFitS8 || fit == kFitU8) ? 1 : 2;
+    return pair_enqueue(p, L, static_cast<uint8_t*>(ws), query, m, subject, n, sm, go, ge, elem, score_out,
+                        nullptr, nullptr, opt ? opt->ev_search_begin : nullptr,
+                        opt ? opt->ev_search_end : nullptr, stream);
+}
+
+size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt)
+{
+    std::string why;
+    if (!validate_pair(m, n, opt, why)) { fail(SW_EINVAL, why); return 0; }
+    if (m * n > kAlignMaxCells) { fail(SW_EINVAL, "alignment matrix larger than 2^32 cells"); return 0; }
+    size_t t = pair_layout(m, n, nullptr).total + align_extra_bytes(m, n, nullptr);
+    if (opt && opt->pair_cols > 8192)
+        t += (size_t)align_up((int64_t)opt->pair_cols * 9, 256) +
+             (size_t)ceil_div(std::max<int64_t>(m, 1), 512) * 64 * opt->pair_cols * 4;
+    return t;
+}
+
+int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n, const int32_t* sm,
+                  int32_t go, int32_t ge, const sw_options* opt, void* ws, size_t ws_bytes, sw_alignment* out,
+                  char* ops, hipStream_t stream)
+{
+    int fit = 0;
+    int rc = pair_args_check(query, m, subject, n, sm, go, ge, opt, ws, fit);
+    if (rc) return rc;
+    if (!out) return fail(SW_EINVAL, "null alignment output");
+    if (m > 0 && n > 0 && !ops) return fail(SW_EINVAL, "null operation buffer");
+    const size_t need = sw_align_workspace_bytes(m, n, opt);
+    if (need == 0) return SW_EINVAL;
+    if (ws_bytes < need)
+        return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    int cu = 256;
+    rc = device_cu(&cu);
+    if (rc) return rc;
+    const PairPlanC p = align_plan(m, n, cu, opt);
+    const PairLayout L = pair_layout(m, n, &p);
+    const size_t dir_off = align_up(L.total, 256);
+    if (dir_off + align_extra_bytes(m, n, &p) > need)
+        return fail(SW_EINVAL, "internal error: alignment layout exceeds the workspace size");
+    uint8_t* w = static_cast<uint8_t*>(ws);
+    auto* dir = reinterpret_cast<uint32_t*>(w + dir_off);
+    auto* end_key = reinterpret_cast<unsigned long long*>(w + dir_off + align_extra_bytes(m, n, &p) - 256);
+    auto* o = reinterpret_cast<AlignOut*>(out);
+    const int elem = (fit == kFitS8 || fit == kFitU8) ? 1 : 2;
+    rc = pair_enqueue(p, L, w, query, m, subject, n, sm, go, ge, elem, &o->score, dir, end_key,
+                      opt ? opt->ev_search_begin : nullptr, opt ? opt->ev_search_end : nullptr, stream);
+    if (rc) return rc;
+    if (m == 0 || n == 0) {
+        HIPCHK(launch_trace_reset(end_key, stream));
+        HIPCHK(launch_traceback(dir, 1, end_key, &o->score, ops, 0, o, stream));
+        return SW_OK;
+    }
+    HIPCHK(launch_traceback(dir, p.nb * p.K, end_key, &o->score, ops, m + n, o, stream));
     return SW_OK;
 }
 

@@ -1,0 +1,83 @@
+"""Alignment of one pair (direction-code pass + traceback walk) against the
+oracle's traceback (GPU required).  Equality of the whole result: score,
+begin and end positions, and every operation -- the tie-breaks are part of
+the definition (see oracle.align)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpuhelp import announce, have_gpu
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="needs a GPU")]
+
+DNA = (synth.dna_matrix(synth.DNA_MATCH, synth.DNA_MISMATCH), synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND)
+
+
+def _gpu_align(a, b, sm, go, ge, **kw):
+    import torch
+    import paper_2412_08308_amd as swdb
+    qa = torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint8)).cuda()
+    qb = torch.from_numpy(np.ascontiguousarray(b, dtype=np.uint8)).cuda()
+    return swdb.align_pair(qa, qb, sm, go, ge, opt=swdb.options(**kw) if kw else None)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 50), (50, 1), (31, 33), (300, 400), (1000, 1500), (2000, 2000)])
+def test_dna_alignments(m, n):
+    a, b = synth.dna_pair(m, n, seed=3 * m + n, identity=0.75, indel_rate=0.02)
+    sm, go, ge = DNA
+    announce(f"align m={m} n={n}")
+    assert _gpu_align(a, b, sm, go, ge) == oracle.align(a, b, sm, go, ge)
+
+
+@pytest.mark.parametrize("go,ge", [(10, 2), (0, 3), (4, 4), (120, 1)])
+def test_protein_alignments(go, ge):
+    # (120, 1): 16-bit profile entries; the others 8-bit
+    rng = np.random.default_rng(go + 17 * ge)
+    sm = synth.blosum_style_matrix()
+    a = synth.residues(rng, 600)
+    b = np.concatenate([synth.residues(rng, 100), synth.mutate(rng, a[150:500], 0.6), synth.residues(rng, 80)])
+    announce(f"align protein go={go} ge={ge}")
+    assert _gpu_align(a, b, sm, go, ge) == oracle.align(a, b, sm, go, ge)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tie_heavy_alignments(seed):
+    """Two-letter sequences with free gaps: many optimal alignments; the rules
+    pick one."""
+    rng = np.random.default_rng(100 + seed)
+    a = rng.integers(0, 2, int(rng.integers(50, 300))).astype(np.uint8)
+    b = rng.integers(0, 2, int(rng.integers(50, 300))).astype(np.uint8)
+    sm = synth.dna_matrix(1, -1)
+    go, ge = int(rng.integers(0, 2)), int(rng.integers(0, 2))
+    announce(f"align ties seed={seed}")
+    assert _gpu_align(a, b, sm, go, ge) == oracle.align(a, b, sm, go, ge)
+
+
+@pytest.mark.parametrize("wc", [16, 64, 512])
+def test_chunk_widths(wc):
+    a, b = synth.dna_pair(1500, 1700, seed=9, identity=0.7, indel_rate=0.03)
+    sm, go, ge = DNA
+    announce(f"align cols={wc}")
+    assert _gpu_align(a, b, sm, go, ge, pair_cols=wc) == oracle.align(a, b, sm, go, ge)
+
+
+def test_empty_and_zero():
+    sm, go, ge = DNA
+    a = np.zeros(40, np.uint8)
+    b = np.full(30, 1, np.uint8)                     # all mismatches: score 0
+    empty = {"score": 0, "q_begin": 0, "s_begin": 0, "q_end": 0, "s_end": 0, "ops": ""}
+    announce("align empty")
+    assert _gpu_align(a, b, sm, go, ge) == empty == oracle.align(a, b, sm, go, ge)
+    assert _gpu_align(a[:0], b, sm, go, ge) == empty
+
+
+def test_large_self_alignment():
+    """A 50,000-base sequence against itself: the whole diagonal (closed form),
+    2.5e9 cells of direction codes and a 50,000-step walk."""
+    sm, go, ge = DNA
+    rng = np.random.default_rng(5)
+    a = synth.residues(rng, 50_000, synth.DNA_FREQS)
+    announce("align 50k self")
+    r = _gpu_align(a, a, sm, go, ge)
+    assert r == {"score": 50_000, "q_begin": 1, "s_begin": 1, "q_end": 50_000, "s_end": 50_000, "ops": "M" * 50_000}
