@@ -11,7 +11,8 @@ residues / step time (the paper's Section 3.2 definition).
 Printed (one JSON line): the headline GCUPS of the default exact mode, the
 int32-lane kernel on the same input, a batched 20-query launch, the 16-bit
 overflow workload, a Poisson serving run, single long DNA pairs at the
-paper's pairwise sizes, the integer-VALU roofline of the search kernel (timed
+paper's pairwise sizes, alignments (traceback) of the best hits, the
+integer-VALU roofline of the search kernel (timed
 live with HIP events on its stream), and the CPU oracle timed on a bounded
 sample on this host.
 
@@ -293,6 +294,43 @@ def pairwise(args, ev):
                         "+1/-3, gaps 5/2), int32 lanes, anti-diagonal tile launches", "runs": runs}
 
 
+def alignments(args, w, scores):
+    """Traceback of the best hits (the paper's optional step after the score):
+    the query against its 16 highest-scoring subjects, one sw_align_pair call
+    each (score pass, direction-code pass, walk), and one 50,000-base DNA pair
+    against a homolog; wall time per call."""
+    import numpy as np
+    import torch
+
+    import paper_2412_08308_amd as swdb
+    import synth
+    q = torch.from_numpy(w.queries[0]).cuda()
+    top = torch.topk(scores.to(torch.int64), 16).indices.cpu().numpy()
+    subs = [torch.from_numpy(np.ascontiguousarray(w.db.subject(int(i)))).cuda() for i in top]
+    ws = torch.empty(max(swdb.align_workspace_bytes(len(w.queries[0]), int(s.numel())) for s in subs),
+                     dtype=torch.uint8, device="cuda")
+    swdb.align_pair(q, subs[0], w.matrix, w.gap_open, w.gap_extend, workspace=ws)      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [swdb.align_pair(q, s, w.matrix, w.gap_open, w.gap_extend, workspace=ws) for s in subs]
+    dt = time.perf_counter() - t0
+    cells = len(w.queries[0]) * sum(int(s.numel()) for s in subs)
+    a, b = synth.dna_pair(50_000, 50_000, seed=11)
+    qa, qb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    sm = synth.dna_matrix(synth.DNA_MATCH, synth.DNA_MISMATCH)
+    wsd = torch.empty(swdb.align_workspace_bytes(50_000, 50_000), dtype=torch.uint8, device="cuda")
+    swdb.align_pair(qa, qb, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND, workspace=wsd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r = swdb.align_pair(qa, qb, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND, workspace=wsd)
+    dt2 = time.perf_counter() - t1
+    return {"top_hits": {"alignments": len(subs), "ms_per_alignment": round(dt / len(subs) * 1e3, 2),
+                         "cells": cells, "best": {k: res[0][k] for k in ("score", "q_begin", "s_begin", "q_end", "s_end")},
+                         "best_ops": len(res[0]["ops"])},
+            "dna_50k": {"ms": round(dt2 * 1e3, 1), "gcups_two_passes": round(2 * 50_000 ** 2 / dt2 / 1e9, 1),
+                        "score": r["score"], "ops": len(r["ops"])}}
+
+
 def cpu_baseline(w, seconds: float):
     """The oracle (plain C, int64, threads over subjects) on a random sample of
     the same database, sized for about ``seconds`` of host time."""
@@ -348,6 +386,7 @@ def main(argv=None):
     ap.add_argument("--no-planted", action="store_true")
     ap.add_argument("--planted-steps", type=int, default=3)
     ap.add_argument("--no-pair", action="store_true")
+    ap.add_argument("--no-align", action="store_true")
     ap.add_argument("--pair-sizes", type=int, nargs="+", default=[0, 1, 2, 3, 4],
                     help="indices into the paper's DNA pair sizes (162Kx172K .. 7Mx5M)")
     ap.add_argument("--pair-steps", type=int, default=2)
@@ -435,6 +474,7 @@ def main(argv=None):
                            "flagged": b["flagged"]}
         batched["gcups"] = max(v["gcups"] for k, v in batched.items() if isinstance(v, dict))
 
+    traceback = None if args.no_align else alignments(args, w, main_run["out"])
     overflow = None if args.no_planted else planted(args, ev)
     pair = None if args.no_pair else pairwise(args, ev)
     latency = None if args.no_serve else serving(args, gcups, args.mode)
@@ -481,6 +521,7 @@ def main(argv=None):
         "overflow": overflow,
         "batched": batched,
         "pairwise": pair,
+        "traceback": traceback,
         "latency": latency,
         "parity": parity,
         "plan": {k: main_run["plan"][k] for k in ("lane_cells", "items", "launches", "grid", "rows")},
