@@ -226,17 +226,24 @@ __global__ void k_trace_reset(unsigned long long* end_key)
         *end_key = ~0ull;
 }
 
-// Walk of the traceback (one lane): from the end cell in state H, follow the
-// direction codes -- the diagonal emits a residue pair and stops when its
-// predecessor holds H = 0 or lies on the border, E emits a subject residue
-// against a gap, F a query residue against a gap, each returning to H where
-// the gap was opened -- then reverse the operations into begin-to-end order.
-__global__ void k_traceback(const uint32_t* __restrict__ dir, int64_t stride,
-                            const unsigned long long* __restrict__ end_key, const int32_t* __restrict__ score,
-                            char* __restrict__ ops, int64_t cap, AlignOut* out)
+// Walk of the traceback: from the end cell in state H, follow the direction
+// codes -- the diagonal emits a residue pair and stops when its predecessor
+// holds H = 0 or lies on the border, E emits a subject residue against a gap,
+// F a query residue against a gap, each returning to H where the gap was
+// opened -- then reverse the operations into begin-to-end order.  One
+// wavefront: the codes of a window of 64 columns x 128 rows around the walk
+// sit in LDS (each lane loads one column), every lane runs the same walk on
+// them (uniform control flow; lane 0 writes the operations), and the wave
+// reloads the window when the walk leaves it.
+constexpr int kWinCols = 64, kWinWords = 16;   // 16 words of 8 rows = 128 rows
+
+__global__ void __launch_bounds__(64) k_traceback(const uint32_t* __restrict__ dir, int64_t stride,
+                                                  const unsigned long long* __restrict__ end_key,
+                                                  const int32_t* __restrict__ score, char* __restrict__ ops,
+                                                  int64_t cap, AlignOut* out)
 {
-    if (threadIdx.x != 0)
-        return;
+    __shared__ uint32_t win[kWinCols][kWinWords];
+    const int lane = threadIdx.x;
     AlignOut r{};
     r.score = *score;
     const unsigned long long key = *end_key;
@@ -245,24 +252,45 @@ __global__ void k_traceback(const uint32_t* __restrict__ dir, int64_t stride,
         int64_t j = (int64_t)(key >> 32) + 1, i = (int64_t)(key & 0xffffffffull) + 1;   // 1-based
         r.q_end = (int32_t)i;
         r.s_end = (int32_t)j;
-        auto code = [&](int64_t ii, int64_t jj) {
-            const uint32_t w = dir[(jj - 1) * stride + ((ii - 1) >> 3)];
-            return (w >> (4 * ((ii - 1) & 7))) & 15u;
+        int64_t c0 = -1, w0 = 0;     // window: columns c0..c0+63, words w0..w0+15 (0-based)
+        // code of 1-based cell (ii, jj), reloading the window around it if needed
+        auto code = [&](int64_t ii, int64_t jj) -> uint32_t {
+            const int64_t col = jj - 1, row = ii - 1;
+            if (c0 < 0 || col < c0 || col >= c0 + kWinCols || (row >> 3) < w0 || (row >> 3) >= w0 + kWinWords) {
+                __syncthreads();
+                c0 = col - (kWinCols - 1) > 0 ? col - (kWinCols - 1) : 0;
+                w0 = (row >> 3) - (kWinWords - 4) > 0 ? (row >> 3) - (kWinWords - 4) : 0;
+                const int64_t cc = c0 + lane;
+                if (cc <= col) {
+#pragma unroll
+                    for (int k = 0; k < kWinWords; ++k)
+                        win[lane][k] = (w0 + k < stride) ? dir[cc * stride + w0 + k] : 0u;
+                }
+                __syncthreads();
+            }
+            const uint32_t w = win[col - c0][(row >> 3) - w0];
+            return (w >> (4 * (row & 7))) & 15u;
         };
         int state = 0;
         bool ok = false;
         while (n_ops < cap && i >= 1 && j >= 1) {
             const uint32_t c = code(i, j);
+            char op = 0;
             if (state == 0) {
                 const uint32_t src = c & 3u;
                 if (src == 1u) {
-                    ops[n_ops++] = 'M';
-                    if (i == 1 || j == 1 || (code(i - 1, j - 1) & 3u) == 0u) {
+                    op = 'M';
+                    const bool stop = i == 1 || j == 1 || (code(i - 1, j - 1) & 3u) == 0u;
+                    if (lane == 0)
+                        ops[n_ops] = op;
+                    ++n_ops;
+                    if (stop) {
                         ok = true;
                         break;
                     }
                     --i;
                     --j;
+                    continue;
                 } else if (src == 2u) {
                     state = 1;
                 } else if (src == 3u) {
@@ -270,22 +298,28 @@ __global__ void k_traceback(const uint32_t* __restrict__ dir, int64_t stride,
                 } else {
                     break;                        // H = 0 on the path: inconsistent codes
                 }
-            } else if (state == 1) {
-                ops[n_ops++] = 'D';
+                continue;
+            }
+            if (state == 1) {
+                op = 'D';
                 if (c & 4u)
                     state = 0;
                 --j;
             } else {
-                ops[n_ops++] = 'I';
+                op = 'I';
                 if (c & 8u)
                     state = 0;
                 --i;
             }
+            if (lane == 0)
+                ops[n_ops] = op;
+            ++n_ops;
         }
         if (ok) {
             r.q_begin = (int32_t)i;
             r.s_begin = (int32_t)j;
-            for (int64_t x = 0, y = n_ops - 1; x < y; ++x, --y) {
+            __syncthreads();                      // the walk's writes before the reversal
+            for (int64_t x = lane, y = n_ops - 1 - lane; x < y; x += 64, y -= 64) {
                 const char t = ops[x];
                 ops[x] = ops[y];
                 ops[y] = t;
@@ -295,7 +329,8 @@ __global__ void k_traceback(const uint32_t* __restrict__ dir, int64_t stride,
         }
     }
     r.n_ops = (int32_t)n_ops;
-    *out = r;
+    if (lane == 0)
+        *out = r;
 }
 
 hipError_t launch_trace_diag(const PairArgs& a, int elem, hipStream_t st)
@@ -318,7 +353,7 @@ hipError_t launch_trace_reset(unsigned long long* end_key, hipStream_t st)
 hipError_t launch_traceback(const uint32_t* dir, int64_t dir_stride, const unsigned long long* end_key,
                             const int32_t* score, char* ops, int64_t cap, AlignOut* out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_traceback, dim3(1), dim3(64), 0, st, dir, dir_stride, end_key, score, ops, cap, out);
+    hipLaunchKernelGGL(k_traceback, dim3(1), dim3(kWinCols), 0, st, dir, dir_stride, end_key, score, ops, cap, out);
     return hipGetLastError();
 }
 
