@@ -19,6 +19,8 @@ constexpr int kAlpha = 32;           // residue codes 0..31 accepted at the ABI
 constexpr int kCodes = 33;           // + internal pad code
 constexpr uint8_t kPad = 32;         // pad code: subject tails and chunk fill
 constexpr int kWave = 64;
+constexpr int kRescoreMaxWaves = 8; // wavefronts of a rescore workgroup, at most
+constexpr int kFlagSortCap = 4096;   // overflow lists up to this length are sorted by cost
 constexpr int kI16Rows = 24;       // query rows per lane of the packed 16-bit variant
 
 // Bytes between the profile entries of consecutive residue codes inside a row
@@ -70,7 +72,7 @@ struct SearchArgs {
     // outputs and scratch
     int32_t* scores;             // [nq][out_stride]
     int64_t out_stride;
-    int32_t* counters;           // [1] overflow-flag count
+    int32_t* counters;           // [1] overflow-flag count, [2] rescore queue head
     int2* bnd;                   // slots
     int64_t slot_elems;          // int2 entries per slot
     int2* flags;                 // (q, sorted subject) of 16-bit overflows
@@ -148,6 +150,7 @@ LaunchInfo variant_info(Variant v);
 // Host-side launchers (defined with the kernels).
 hipError_t launch_profile(const ProfileArgs& a, int rows, int elem, int max_entries, hipStream_t st);
 hipError_t launch_search(Variant v, const SearchArgs& a, int grid, int waves, int lds_bytes, hipStream_t st);
+hipError_t launch_flag_sort(const SearchArgs& a, hipStream_t st);
 hipError_t launch_rescore(Variant v, const SearchArgs& a, int grid, int waves, hipStream_t st);
 hipError_t launch_interleave(const uint8_t* src, const int64_t* src_off, const int32_t* perm,
                              const int32_t* slen, const int64_t* chunk_off, int32_t nseq,

@@ -53,7 +53,7 @@ constexpr int64_t kMinLaneCells = 24 * 1024;
 constexpr int64_t kMaxLaneCells = 192 * 1024;
 constexpr int kDefaultLdsLimit = 64 * 1024;
 constexpr int kLdsPerCU = 160 * 1024;
-constexpr int kRescoreWaves = 4;      // workgroup size of the rescore kernel
+constexpr int kRescoreWavesPerCU = 16; // resident rescore wavefronts per CU (the grid)
 constexpr int kMaxWavesPerCU = 16;      // 4 per SIMD: kernels are built for <= 128 VGPRs
 constexpr int kLdsWavesPerCU = 12;      // resident waves per CU when every profile is in LDS
 
@@ -311,6 +311,7 @@ struct Layout {
     std::vector<std::shared_ptr<QPlan>> plans;   // by position in the call
     std::vector<int32_t> order;       // queue position -> position in the call
     int64_t grid = 0, rgrid = 0;
+    int rwaves = 1;               // wavefronts per rescore workgroup
     int64_t slot_elems = 0, rslot_elems = 0;
     int lds_bytes = 0;
     int64_t cells = 0, lane_cells = 0, nitems = 0;
@@ -390,7 +391,13 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
         L.grid = std::min<int64_t>(L.grid, r.grid_limit);
     L.slot_elems = align_up(std::max<int64_t>(slot_need, 4), 4);
     if (r.i16) {
-        L.rgrid = std::max<int64_t>(1, (int64_t)db->cu * 2);
+        // rescore: a workgroup per listed subject, one wavefront per 64-lane
+        // pass of the longest query (at most kRescoreMaxWaves)
+        int maxp = 1;
+        for (int32_t p = 0; p < nq; ++p)
+            maxp = std::max<int>(maxp, (int)ceil_div(L.qd[p].nbr, kWave));
+        L.rwaves = std::min(maxp, kRescoreMaxWaves);
+        L.rgrid = std::max<int64_t>(1, (int64_t)db->cu * kRescoreWavesPerCU / L.rwaves);
         L.rslot_elems = align_up(std::max<int64_t>(align_up(db->max_len, 16), 4), 4);
         L.flag_cap = (int64_t)nq * db->nseq;
     }
@@ -407,7 +414,7 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
     L.off_flags = off; off += align_up(sizeof(int2) * L.flag_cap, 256);
     L.off_slots = off;
     const int64_t main_slots = nslots * L.slot_elems * (int64_t)sizeof(int2);
-    const int64_t res_slots = L.rgrid * kRescoreWaves * L.rslot_elems * (int64_t)sizeof(int2);
+    const int64_t res_slots = L.rgrid * L.rwaves * L.rslot_elems * (int64_t)sizeof(int2);
     off += align_up(std::max(main_slots, res_slots), 256);
     L.total = off;
     return SW_OK;
@@ -604,7 +611,7 @@ void fill_blob(const Layout& L, const int64_t* q_offsets, uint8_t* h)
 
 // Everything a search puts on `stream`: plan upload from pinned host memory,
 // profile kernel (also clears the queue head and flag count), search kernel,
-// rescore kernel.  No memset: the sequence may be captured into a graph.
+// flag-list sort and rescore kernel.  No memset: the sequence may be captured into a graph.
 int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8_t* queries,
                    const int32_t* sm, int32_t go, int32_t ge, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2,
                    void* ws, int32_t* scores, hipStream_t stream)
@@ -655,7 +662,8 @@ int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8
     if (r.i16 && L.grid > 0) {
         SearchArgs b = a;
         b.slot_elems = L.rslot_elems;
-        HIPCHK(launch_rescore(r.v, b, (int)L.rgrid, kRescoreWaves, stream));
+        HIPCHK(launch_flag_sort(b, stream));
+        HIPCHK(launch_rescore(r.v, b, (int)L.rgrid, L.rwaves, stream));
     }
     if (e2) HIPCHK(hipEventRecord(e2, stream));
     return SW_OK;

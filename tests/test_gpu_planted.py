@@ -56,3 +56,50 @@ def test_planted_full_scale_sampled():
         assert _flagged(gdb, ctrl, w.matrix, w.gap_open, w.gap_extend) == 0
     finally:
         gdb.release()
+
+
+def _pass_crossing_case(P: int, seed: int):
+    """A query of P 64-lane rescore passes (1,536 rows each) and near-homologs
+    of query windows that straddle pass boundaries (one window spans several
+    when P >= 4), inside random flanks, plus random subjects."""
+    rng = np.random.default_rng(seed)
+    m = 1536 * P - 77
+    q = synth.residues(rng, m)
+    seqs = []
+    for k in range(1, P):
+        b = 1536 * k
+        lo = max(0, b - int(rng.integers(200, 1200)))
+        hi = min(m, b + int(rng.integers(200, 1200)))
+        h = synth.mutate(rng, q[lo:hi], float(rng.uniform(0.7, 0.95)))
+        seqs.append(np.concatenate([synth.residues(rng, int(rng.integers(0, 300))), h,
+                                    synth.residues(rng, int(rng.integers(0, 300)))]))
+    if P >= 4:
+        seqs.append(synth.mutate(rng, q[1536 - 300:1536 * 3 + 300], 0.8))
+    seqs += [synth.residues(rng, int(n)) for n in rng.integers(10, 600, size=40)]
+    order = rng.permutation(len(seqs))
+    return q, synth.Database.from_list([seqs[i] for i in order])
+
+
+@pytest.mark.parametrize("P", [2, 5, 10])
+@pytest.mark.parametrize("scale,go,ge,variant", [(8, 32, 6, 3), (11, 40, 8, 2)])
+def test_rescore_passes_across_wavefronts(P, scale, go, ge, variant):
+    # The rescore splits a subject's query rows into 64-lane passes over the
+    # wavefronts of a workgroup (at most 8, so P = 10 reuses boundary
+    # buffers); homologs whose best alignment crosses pass boundaries catch a
+    # wrong hand-over.  Scaled matrices push their scores past 32,767.
+    import paper_2412_08308_amd as swdb
+    sm = synth.blosum_style_matrix() * scale
+    assert swdb.select_variant(sm, go) == variant
+    q, db = _pass_crossing_case(P, seed=100 + P)
+    exp = oracle_scores(db, q, sm, go, ge)
+    n_over = int(np.sum(exp >= 32767))
+    assert n_over >= P - 1
+    gdb = gpu_db(db)
+    try:
+        for mode in ("i16", "auto", "i32"):
+            announce(f"rescore passes P={P} m={len(q)} scale={scale} mode={mode}")
+            got = gpu_scores(gdb, q, sm, go, ge, mode=mode)
+            assert np.array_equal(got, exp), f"{mode}: " + mismatch_report(got, exp)
+        assert _flagged(gdb, q, sm, go, ge) == n_over
+    finally:
+        gdb.release()
