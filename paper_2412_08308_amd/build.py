@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswdb.so")
-SOURCES = ["sw_k_i32p8.hip", "sw_k_i32p16.hip", "sw_k_i16.hip", "sw_k_i16p8.hip", "sw_k_prep.hip", "sw_pair.hip",
+SOURCES = ["sw_k_i32p8.hip", "sw_k_i32p16.hip", "sw_k_i16.hip", "sw_k_i16p8.hip", "sw_k_rescore.hip", "sw_k_prep.hip", "sw_pair.hip",
            "sw_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

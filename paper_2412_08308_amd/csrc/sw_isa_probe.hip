@@ -37,7 +37,5 @@ template __global__ void isa_i16<24, 1, true, false>(SearchArgs);
 template __global__ void isa_i16<24, 1, true, true>(SearchArgs);
 template __global__ void isa_i16<24, 1, false, false>(SearchArgs);
 template __global__ void isa_i16<24, 1, false, true>(SearchArgs);
-template __global__ void isa_i32<24, 2, false, true>(SearchArgs);
-template __global__ void isa_i32<24, 1, false, true>(SearchArgs);
 
 }  // namespace swdb

@@ -7,8 +7,6 @@ hipError_t launch_search_i32p8(const SearchArgs& a, int grid, int waves, int lds
 hipError_t launch_search_i32p16(const SearchArgs& a, int grid, int waves, int lds, hipStream_t st);
 hipError_t launch_search_i16(const SearchArgs& a, int grid, int waves, int lds, hipStream_t st);
 hipError_t launch_search_i16p8(const SearchArgs& a, int grid, int waves, int lds, hipStream_t st);
-hipError_t launch_rescore_i16(const SearchArgs& a, int grid, int waves, hipStream_t st);
-hipError_t launch_rescore_i16p8(const SearchArgs& a, int grid, int waves, hipStream_t st);
 int occupancy_i32p8(int waves, int lds);
 int occupancy_i32p16(int waves, int lds);
 int occupancy_i16(int waves, int lds);
@@ -126,81 +124,6 @@ hipError_t launch_search(Variant v, const SearchArgs& a, int grid, int waves, in
     case kI16_P8: return launch_search_i16p8(a, grid, waves, lds_bytes, st);
     }
     return hipErrorInvalidValue;
-}
-
-// Order the overflow list (query, subject) by rescore cost, largest first, so
-// that the rescore workgroups, which take entries in list order, start the
-// longest subjects first and the shortest fill the tail.  One workgroup; a
-// bitonic sort in LDS of (cost, position) keys, then an in-place permutation
-// of the list.  Lists longer than kFlagSortCap are left in append order (only
-// the balance of the rescore depends on the order).
-__global__ void __launch_bounds__(1024) k_flag_sort(SearchArgs a)
-{
-    __shared__ uint64_t key[kFlagSortCap];
-    const int cnt = min(a.counters[1], a.flag_cap);
-    if (cnt <= 1 || cnt > kFlagSortCap)
-        return;
-    int n = 1;
-    while (n < cnt)
-        n <<= 1;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        float cost = 0.f;
-        if (i < cnt) {
-            const int2 e = a.flags[i];
-            if (e.x >= 0 && e.x < a.nq && e.y >= 0 && e.y < a.nseq)
-                cost = (float)a.qd[e.x].nbr * (float)a.slen[e.y] + 1.f;
-        }
-        // a non-negative float orders like its bit pattern
-        key[i] = ((uint64_t)__float_as_uint(cost) << 32) | (uint32_t)i;
-    }
-    __syncthreads();
-    for (int k = 2; k <= n; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint64_t x = key[i], y = key[l];
-                    // descending runs where (i & k) == 0, so the final order is descending
-                    if (((i & k) == 0) ? x < y : x > y) {
-                        key[i] = y;
-                        key[l] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    // gather every thread's new entries before any is overwritten
-    constexpr int kPer = kFlagSortCap / 1024;
-    int2 v[kPer];
-#pragma unroll
-    for (int t = 0; t < kPer; ++t) {
-        const int i = threadIdx.x + t * blockDim.x;
-        if (i < cnt)
-            v[t] = a.flags[(uint32_t)key[i]];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < kPer; ++t) {
-        const int i = threadIdx.x + t * blockDim.x;
-        if (i < cnt)
-            a.flags[i] = v[t];
-    }
-}
-
-hipError_t launch_flag_sort(const SearchArgs& a, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_flag_sort, dim3(1), dim3(1024), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_rescore(Variant v, const SearchArgs& a, int grid, int waves, hipStream_t st)
-{
-    if (v == kI16)
-        return launch_rescore_i16(a, grid, waves, st);
-    if (v == kI16_P8)
-        return launch_rescore_i16p8(a, grid, waves, st);
-    return hipErrorInvalidValue;   // int32 variants never flag subjects
 }
 
 int search_occupancy(Variant v, int waves, int lds_bytes)

@@ -1,11 +1,12 @@
 """VALU instructions per DP cell in the hot loops of the search kernels.
 
 Compiles ``csrc/sw_isa_probe.hip`` (each hot-loop variant alone in a kernel,
-same flags as the library) and ``csrc/sw_pair.hip`` to AMD assembly of this
-build, finds each kernel's innermost loop -- one trip sweeps four subject
-columns of R query rows, i.e. 4*R cells per lane (8*R for the packed 16-bit
-variant, two subjects per lane) -- and counts its instructions by class.  The VALU count per cell is the ISA
-operation count of the integer-VALU roofline.
+same flags as the library), ``csrc/sw_pair.hip`` and ``csrc/sw_k_rescore.hip``
+to AMD assembly of this build, finds each kernel's hot loop -- one trip sweeps
+four subject columns of R query rows, i.e. 4*R cells per lane (8*R for the
+packed 16-bit variant, two subjects per lane) -- and counts its instructions by
+class.  The VALU count per cell is the ISA operation count of the integer-VALU
+roofline.
 """
 from __future__ import annotations
 
@@ -37,20 +38,23 @@ VARIANTS = {
     "i16_p8_lds_kn": ("isa_i16ILi24ELi1ELb1ELb1E", 24, 2),
     "i16_p8_glb_k1": ("isa_i16ILi24ELi1ELb0ELb0E", 24, 2),
     "i16_p8_glb_kn": ("isa_i16ILi24ELi1ELb0ELb1E", 24, 2),
-    "rescore_i32_r24": ("isa_i32ILi24ELi2ELb0ELb1E", 24, 1),
-    "rescore_i32_r24_p8": ("isa_i32ILi24ELi1ELb0ELb1E", 24, 1),
+    # int32 rescore pass (csrc/sw_k_rescore.hip): 64 lanes x 24 rows, 16- / 8-bit profile
+    "rescore_i32_r24": ("k_rescoreILi24ELi2E", 24, 1),
+    "rescore_i32_r24_p8": ("k_rescoreILi24ELi1E", 24, 1),
     # single long pair (csrc/sw_pair.hip): R rows per lane, 8- / 16-bit profile
     "pair_r8_p8": ("k_pair_diagILi8ELi1E", 8, 1),
     "pair_r8_p16": ("k_pair_diagILi8ELi2E", 8, 1),
     "pair_r16_p8": ("k_pair_diagILi16ELi1E", 16, 1),
     "pair_r16_p16": ("k_pair_diagILi16ELi2E", 16, 1),
 }
-SOURCES = ["sw_isa_probe.hip", "sw_pair.hip"]
+SOURCES = ["sw_isa_probe.hip", "sw_pair.hip", "sw_k_rescore.hip"]
 
 
-def _innermost_loop(lines):
-    """Lines of the blocks of the deepest loop: its header block and every
-    block the compiler annotates as inside it, wherever they are placed."""
+def _hot_loop(lines):
+    """Lines of the blocks of the hot loop: of the loops in the function, the
+    one whose own blocks (its header block and every block the compiler
+    annotates as directly inside it, wherever they are placed; not the blocks
+    of loops nested in it) hold the most VALU instructions."""
     blocks = []            # (label, annotation, start, end)
     starts = [i for i, ln in enumerate(lines) if re.match(r"^\.LBB\w+:", ln)]
     for n, i in enumerate(starts):
@@ -61,20 +65,20 @@ def _innermost_loop(lines):
             ann.append(lines[k])
             k += 1
         blocks.append((lines[i].split(":")[0], " ".join(ann), i, end))
-    best = None
-    for label, ann, i, end in blocks:
+    best, best_valu = [], -1
+    for hdr, ann, _, _ in blocks:
         m = re.search(r"Loop Header: Depth=(\d+)", ann)
-        if m and (best is None or int(m.group(1)) > best[1]):
-            best = (label, int(m.group(1)))
-    if best is None:
-        return []
-    hdr, depth = best
-    tag = "Header=" + hdr[2:] + " Depth=" + str(depth)        # ".LBB1_2" -> "BB1_2"
-    out = []
-    for label, ann, i, end in blocks:
-        if label == hdr or tag in ann:
-            out.extend(lines[i:end])
-    return out
+        if not m:
+            continue
+        tag = "Header=" + hdr[2:] + " Depth=" + m.group(1)      # ".LBB1_2" -> "BB1_2"
+        body = []
+        for label, ann2, i, end in blocks:
+            if label == hdr or tag in ann2:
+                body.extend(lines[i:end])
+        valu = sum(1 for l in body if l.strip().startswith("v_"))
+        if valu > best_valu:
+            best, best_valu = body, valu
+    return best
 
 
 def count(asm_text: str) -> dict:
@@ -84,7 +88,7 @@ def count(asm_text: str) -> dict:
         body = next((f for f in funcs if f.startswith("_Z") and frag in f.split(":")[0]), None)
         if body is None:
             continue
-        loop = _innermost_loop(body.split("\n"))
+        loop = _hot_loop(body.split("\n"))
         ins = [l.strip().split()[0] for l in loop
                if l.strip() and not l.strip().startswith((".", ";")) and not l.strip().endswith(":")]
         c = collections.Counter(ins)
