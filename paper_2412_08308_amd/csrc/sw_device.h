@@ -57,6 +57,12 @@ __device__ __forceinline__ int shr1(int v)
     return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);
 }
 
+__device__ __forceinline__ int ror1(int v)
+{
+    // lane i receives lane i-1, lane 0 receives lane 63 (DPP wave_ror:1)
+    return __builtin_amdgcn_update_dpp(v, v, 0x13c, 0xf, 0xf, false);
+}
+
 template <bool LDSP>
 __device__ __forceinline__ uint4 ld16(const uint8_t* __restrict__ g, uint32_t off)
 {
@@ -276,8 +282,51 @@ __device__ __forceinline__ void item_i32(const SearchArgs& a, const Item it, con
 
 // ------------------------------------------------------------------ packed 16-bit item
 
-// ES = profile entry bytes: 2 (signed 16-bit) or 1 (8-bit entries in
-// [0, 127], zero-extended while the two subjects' entries are paired).
+// One column of R rows in both 16-bit halves of a lane (low half: profile
+// vector pa, high half: pb).  yt / ft enter the top row (H - Go and F of the
+// row above), ydiag is H - Go of the row above in the previous column; ybot /
+// fbot leave the bottom row.  ES = profile entry bytes: 2 (signed 16-bit) or 1
+// (8-bit entries in [0, 127], zero-extended while the halves are paired).
+template <int R, int ES, int NV>
+__device__ __forceinline__ void column_i16(const uint4 (&pa)[NV], const uint4 (&pb)[NV], uint32_t (&Y)[R],
+                                           uint32_t (&E)[R], uint32_t& ydiag, uint32_t yt, uint32_t ft,
+                                           uint32_t& ybot, uint32_t& fbot, v2s& S, v2s vge, v2s vgo)
+{
+    const v2s zero = {0, 0};
+    v2s dg = as2(ydiag);
+    ydiag = yt;
+    v2s hup = as2(yt), F = as2(ft);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        // (low-half entry, high-half entry) of row r; selector bytes 0-3 pick
+        // from xa, 4-7 from xb, 0x0c gives 0x00
+        uint32_t pr;
+        if constexpr (ES == 2) {
+            const uint32_t xa = comp(pa[r >> 3], (r >> 1) & 3);
+            const uint32_t xb = comp(pb[r >> 3], (r >> 1) & 3);
+            pr = __builtin_amdgcn_perm(xb, xa, (r & 1) ? 0x07060302u : 0x05040100u);
+        } else {
+            const uint32_t xa = comp(pa[r >> 4], (r >> 2) & 3);
+            const uint32_t xb = comp(pb[r >> 4], (r >> 2) & 3);
+            pr = __builtin_amdgcn_perm(xb, xa, 0x0c000c00u | (uint32_t)(r & 3) | ((uint32_t)(4 + (r & 3)) << 16));
+        }
+        const v2s t = __builtin_elementwise_add_sat(dg, as2(pr));
+        const v2s e = __builtin_elementwise_max(__builtin_elementwise_sub_sat(as2(E[r]), vge), as2(Y[r]));
+        F = __builtin_elementwise_max(__builtin_elementwise_sub_sat(F, vge), hup);
+        const v2s h = __builtin_elementwise_max(__builtin_elementwise_max(t, e), __builtin_elementwise_max(F, zero));
+        S = __builtin_elementwise_max(S, h);
+        if (r & 1)
+            pin(S);
+        dg = as2(Y[r]);
+        hup = h - vgo;
+        Y[r] = asu(hup);
+        E[r] = asu(e);
+    }
+    ybot = asu(hup);
+    fbot = asu(F);
+}
+
+// Two subjects per lane (low and high halves); ES as for column_i16.
 template <int R, int ES, bool LDSP, bool MULTI>
 __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, const QueryDesc& qd,
                                          int2* __restrict__ slot, int lane)
@@ -366,39 +415,7 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
                     ldprof<NB, LDSP>(pa, gprof, pbase + (uint32_t)(code & 0xff) * CS);
                     ldprof<NB, LDSP>(pb, gprof, pbase + (uint32_t)(code >> 8) * CS);
 
-                    v2s dg = as2(ydiag);
-                    ydiag = yt;
-                    v2s hup = as2(yt), F = as2(ft);
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        // (subject A entry, subject B entry) of row r; selector
-                        // bytes 0-3 pick from xa, 4-7 from xb, 0x0c gives 0x00
-                        uint32_t pr;
-                        if constexpr (ES == 2) {
-                            const uint32_t xa = comp(pa[r >> 3], (r >> 1) & 3);
-                            const uint32_t xb = comp(pb[r >> 3], (r >> 1) & 3);
-                            pr = __builtin_amdgcn_perm(xb, xa, (r & 1) ? 0x07060302u : 0x05040100u);
-                        } else {
-                            const uint32_t xa = comp(pa[r >> 4], (r >> 2) & 3);
-                            const uint32_t xb = comp(pb[r >> 4], (r >> 2) & 3);
-                            pr = __builtin_amdgcn_perm(xb, xa, 0x0c000c00u | (uint32_t)(r & 3) |
-                                                                   ((uint32_t)(4 + (r & 3)) << 16));
-                        }
-                        const v2s t = __builtin_elementwise_add_sat(dg, as2(pr));
-                        const v2s e = __builtin_elementwise_max(__builtin_elementwise_sub_sat(as2(E[r]), vge), as2(Y[r]));
-                        F = __builtin_elementwise_max(__builtin_elementwise_sub_sat(F, vge), hup);
-                        const v2s h = __builtin_elementwise_max(__builtin_elementwise_max(t, e),
-                                                                __builtin_elementwise_max(F, zero));
-                        S = __builtin_elementwise_max(S, h);
-                        if (r & 1)
-                            pin(S);
-                        dg = as2(Y[r]);
-                        hup = h - vgo;
-                        Y[r] = asu(hup);
-                        E[r] = asu(e);
-                    }
-                    ybot = asu(hup);
-                    fbot = asu(F);
+                    column_i16<R, ES>(pa, pb, Y, E, ydiag, yt, ft, ybot, fbot, S, vge, vgo);
                     code_prev = code;
                     wY[u] = ybot;
                     wF[u] = fbot;
@@ -453,6 +470,114 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
     }
 }
 
+// Self-paired item (packed variant, the longest subjects): one subject per
+// wavefront, and the two halves of lane g hold two row blocks of it -- the
+// low half row block pass*128 + g, the high half pass*128 + 64 + g -- so one
+// pass covers 128 row blocks and the per-lane work of the subject (the
+// critical path of its item) is half that of 64-lane groups carrying two
+// subjects.  Low halves run as a 64-lane pipeline (lane g one column behind
+// lane g-1); the high halves continue it 64 columns later: a DPP wave
+// rotation hands lane 63's low-half bottom row (and residue code) to lane 0's
+// high half, and lane 63's high half writes the pass's bottom row to the slot
+// (linear, one (H - Go, F) entry per column, value in the low 16 bits).
+template <int R, int ES, bool LDSP>
+__device__ __forceinline__ void item_i16_self(const SearchArgs& a, const Item it, const QueryDesc& qd,
+                                              int2* __restrict__ slot, int lane)
+{
+    constexpr uint32_t CS = code_stride(R, ES);
+    constexpr uint32_t BS = kCodes * CS;
+    constexpr int NB = R * ES;
+    constexpr int NV = (NB + 15) / 16;
+    constexpr int D = 2 * kWave;                  // row blocks per pass; pipeline depth
+
+    const int s = it.s0;
+    const bool head = lane == 0;
+    const bool tail = lane == kWave - 1;
+    const uint4* __restrict__ resp = reinterpret_cast<const uint4*>(a.res + a.chunk_off[s >> 6]) + (s & 63);
+    const int own = (a.slen[s] + 15) & ~15;
+    const int ncols = it.ncols;
+    const int nbr = qd.nbr;
+    const int P = (nbr + D - 1) / D;
+    const int nsteps = (ncols + D - 1 + 3) & ~3;
+    const uint32_t go2 = (uint32_t)(a.go & 0xffff) * 0x10001u;
+    const uint32_t ge2 = (uint32_t)(a.ge & 0xffff) * 0x10001u;
+    const uint32_t ngo2 = (uint32_t)((-a.go) & 0xffff) * 0x10001u;
+    const uint8_t* __restrict__ gprof = a.prof + qd.prof_off;
+    const v2s vge = as2(ge2), vgo = as2(go2);
+
+    v2s S = {0, 0};
+    for (int pass = 0; pass < P; ++pass) {
+        const uint32_t pbA = (uint32_t)min(pass * D + lane, nbr) * BS;          // row block nbr is padding
+        const uint32_t pbB = (uint32_t)min(pass * D + kWave + lane, nbr) * BS;
+        const bool rd = pass > 0;
+        const bool wr = pass < P - 1;
+        uint32_t Y[R], E[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) { Y[r] = ngo2; E[r] = 0; }
+        uint32_t ydiag = ngo2, ybot = ngo2, fbot = 0;
+        int code_prev = kPad | (kPad << 8);
+
+        uint4 rv = (head && 0 < own) ? resp[0] : pad16();
+        for (int blk = 0; blk < nsteps; blk += 16) {
+            const uint4 rvn = (head && blk + 16 < own) ? resp[(blk + 16) * 4] : pad16();
+            const int n4 = min(4, (nsteps - blk) >> 2);
+#pragma unroll 1
+            for (int k4 = 0; k4 < n4; ++k4) {
+                const int col0 = blk + 4 * k4;
+                const uint32_t w = rv.x;
+                rv = make_uint4(rv.y, rv.z, rv.w, 0u);
+                uint32_t ringY[4], ringF[4];
+                if (rd && col0 < ncols && head) {
+                    const uint4* p4 = reinterpret_cast<const uint4*>(slot + col0);
+                    const uint4 v0 = p4[0], v1 = p4[1];
+                    ringY[0] = v0.x; ringF[0] = v0.y; ringY[1] = v0.z; ringF[1] = v0.w;
+                    ringY[2] = v1.x; ringF[2] = v1.y; ringY[3] = v1.z; ringF[3] = v1.w;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) { ringY[k] = ngo2; ringF[k] = 0; }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    // lane g-1's values of the previous column (lane 0: lane 63's)
+                    int rc = ror1(code_prev);
+                    int ry = ror1((int)ybot), rf = ror1((int)fbot);
+                    pin(rc);
+                    pin(ry);
+                    pin(rf);
+                    const int fresh = (int)((w >> (8 * u)) & 0xffu);
+                    const int code = head ? (fresh | ((rc & 0xff) << 8)) : rc;
+                    const uint32_t yt = head ? ((ringY[u] & 0xffffu) | ((uint32_t)ry << 16)) : (uint32_t)ry;
+                    const uint32_t ft = head ? ((ringF[u] & 0xffffu) | ((uint32_t)rf << 16)) : (uint32_t)rf;
+                    uint4 pa[NV], pb[NV];
+                    ldprof<NB, LDSP>(pa, gprof, pbA + (uint32_t)(code & 0xff) * CS);
+                    ldprof<NB, LDSP>(pb, gprof, pbB + (uint32_t)(code >> 8) * CS);
+                    column_i16<R, ES>(pa, pb, Y, E, ydiag, yt, ft, ybot, fbot, S, vge, vgo);
+                    code_prev = code;
+                    const int j = col0 + u - (D - 1);
+                    if (wr && tail && j >= 0 && j < ncols)
+                        slot[j] = make_int2((int)(ybot >> 16), (int)(fbot >> 16));
+                }
+            }
+            rv = rvn;
+        }
+        // this pass's bottom row must be visible to the next pass's first rows
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    const uint32_t Su = asu(S);
+    int best = max((int)(int16_t)(Su & 0xffff), (int)(int16_t)(Su >> 16));
+    for (int off = 32; off > 0; off >>= 1)
+        best = max(best, __shfl_xor(best, off));
+    if (head) {
+        if (best == 32767) {
+            const int k = atomicAdd(&a.counters[1], 1);
+            if (k < a.flag_cap) a.flags[k] = make_int2(it.q, s);
+        } else {
+            a.scores[(int64_t)qd.out_row * a.out_stride + a.perm[s]] = best;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ persistent kernels
 
 // Defence against a work item inconsistent with the launch: every index the
@@ -464,6 +589,9 @@ __device__ __forceinline__ bool item_fits(const SearchArgs& a, const Item& it, c
     const int K = (it.meta >> 16) & 0xff;
     if (nsub <= 0 || K < 1 || K > kWave || it.s0 < 0 || it.ncols < 0)
         return false;
+    if ((it.meta >> 25) & 1)   // self-paired: packed lanes, one subject, 64 lanes, linear slot
+        return I16 && nsub == 1 && K == kWave && it.s0 < a.nseq &&
+               (qd.nbr <= 2 * kWave || (int64_t)it.ncols <= a.slot_elems);
     if (nsub > (kWave / K) * (I16 ? 2 : 1) || (int64_t)it.s0 + nsub > a.nseq)
         return false;
     return qd.nbr <= K || (int64_t)it.ncols * (kWave / K) <= a.slot_elems;
@@ -489,10 +617,14 @@ __device__ __forceinline__ void run_item(const SearchArgs& a, const Item& it, co
 {
     const bool multi = ((it.meta >> 16) & 0xff) > 1;
     const bool crit = (it.meta >> 24) & 1;
+    const bool self = (it.meta >> 25) & 1;
     if (crit)
         __builtin_amdgcn_s_setprio(2);
     if constexpr (I16) {
-        if (qd.lds) {
+        if (self) {
+            if (qd.lds) item_i16_self<R, ES, true>(a, it, qd, slot, lane);
+            else item_i16_self<R, ES, false>(a, it, qd, slot, lane);
+        } else if (qd.lds) {
             if (multi) item_i16<R, ES, true, true>(a, it, qd, slot, lane);
             else item_i16<R, ES, true, false>(a, it, qd, slot, lane);
         } else {

@@ -244,7 +244,23 @@ int choose_k(int64_t n, int nbr, const Resolved& r)
     return best > 0 ? best : shortest;
 }
 
-std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, const Resolved& r)
+// Per-lane cells of a self-paired item (packed lanes, one subject per
+// wavefront, 128 row blocks per pass, a 128-column pipeline).
+int64_t lane_work_self(int64_t n, int nbr, int rows)
+{
+    const int64_t passes = nbr == 0 ? 0 : ceil_div(nbr, 2 * kWave);
+    return std::max<int64_t>(align_up(n + 2 * kWave - 1, 4), 4) * passes * rows;
+}
+
+// Work items of one query.  Subjects in length order are grouped floor(64/K)
+// x spl to an item with the lane-group size chosen per length.  In the packed
+// variant, an item whose per-lane work exceeds the mean work of a resident
+// wavefront (the longest subjects against a long query) would end the launch
+// late however it is scheduled; its subjects become self-paired items instead,
+// one subject per wavefront with both halves of every lane on its rows, which
+// halves the per-lane work (the critical path) for the same total work.
+std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, const Resolved& r,
+                                  int64_t resident_waves)
 {
     auto p = std::make_shared<QPlan>();
     const int64_t N = (int64_t)slen.size();
@@ -253,6 +269,7 @@ std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, con
     int64_t s = 0;
     int64_t last_n = -1;
     int K = 1;
+    double total = 0;
     while (s < N) {
         const int64_t n = slen[s];
         if (n != last_n) {
@@ -265,14 +282,42 @@ std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, con
         it.s0 = (int32_t)s;
         it.ncols = (int32_t)align_up(n, 4);
         it.q = 0;
+        it.meta = (int32_t)take | (K << 16);
         const int64_t lw = lane_work(n, K, nbr, r.rows);
-        // bit 24: critical-path item (per-lane work well above the target)
-        it.meta = (int32_t)take | (K << 16) | ((lw >= 2 * r.target) ? (1 << 24) : 0);
         wis.push_back({it, lw});
-        p->lane_cells += lw * kWave;
-        if (nbr > K)
-            p->slot_elems = std::max<int64_t>(p->slot_elems, (int64_t)it.ncols * (kWave / K));
+        total += (double)lw;
         s += take;
+    }
+    if (r.spl == 2 && nbr > kWave) {
+        const double mean = total / (double)std::max<int64_t>(resident_waves, 1);
+        std::vector<WItem> out;
+        out.reserve(wis.size());
+        for (const WItem& w : wis) {
+            if ((double)w.cost < mean) {
+                out.push_back(w);
+                continue;
+            }
+            const int nsub = w.it.meta & 0xffff;
+            for (int k = 0; k < nsub; ++k) {
+                Item it;
+                it.s0 = w.it.s0 + k;
+                it.ncols = (int32_t)align_up(slen[it.s0], 4);
+                it.q = 0;
+                it.meta = 1 | (kWave << 16) | (1 << 25);   // bit 25: self-paired
+                out.push_back({it, lane_work_self(slen[it.s0], nbr, r.rows)});
+            }
+        }
+        wis.swap(out);
+    }
+    for (WItem& w : wis) {
+        const int K = (w.it.meta >> 16) & 0xff;
+        const bool self = (w.it.meta >> 25) & 1;
+        // bit 24: critical-path item (per-lane work well above the target)
+        if (w.cost >= 2 * r.target)
+            w.it.meta |= 1 << 24;
+        p->lane_cells += w.cost * kWave;
+        if (self ? nbr > 2 * kWave : nbr > K)
+            p->slot_elems = std::max<int64_t>(p->slot_elems, (int64_t)w.it.ncols * (self ? 1 : kWave / K));
     }
     // longest-processing-time order: largest per-lane work first
     std::stable_sort(wis.begin(), wis.end(), [](const WItem& a, const WItem& b) { return a.cost > b.cost; });
@@ -293,7 +338,7 @@ std::shared_ptr<QPlan> get_plan(sw_db_s* db, int nbr, const Resolved& r)
     auto f = db->plans.find(key);
     if (f != db->plans.end())
         return f->second;
-    auto p = build_plan(db->slen, nbr, r);
+    auto p = build_plan(db->slen, nbr, r, (int64_t)std::max(db->cu, 1) * kMaxWavesPerCU);
     db->plans[key] = p;
     db->plan_order.push_back(key);
     while (db->plan_order.size() > 512) {
@@ -353,8 +398,11 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
     // queue: largest query first; descriptors stored in queue order
     L.order.resize(nq);
     std::iota(L.order.begin(), L.order.end(), 0);
-    std::stable_sort(L.order.begin(), L.order.end(),
-                     [&](int a, int b) { return L.plans[a]->cost > L.plans[b]->cost; });
+    std::stable_sort(L.order.begin(), L.order.end(), [&](int a, int b) {
+        if (L.plans[a]->cost != L.plans[b]->cost)
+            return L.plans[a]->cost > L.plans[b]->cost;
+        return q_lens[a] > q_lens[b];
+    });
     std::vector<QueryDesc> by_call = L.qd;
     int64_t nit = 0;
     for (int32_t p = 0; p < nq; ++p) {

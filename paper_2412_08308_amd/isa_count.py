@@ -39,6 +39,11 @@ VARIANTS = {
     "i16_p8_glb_k1": ("isa_i16ILi24ELi1ELb0ELb0E", 24, 2),
     "i16_p8_glb_kn": ("isa_i16ILi24ELi1ELb0ELb1E", 24, 2),
     # int32 rescore pass (csrc/sw_k_rescore.hip): 64 lanes x 24 rows, 16- / 8-bit profile
+    # self-paired packed items (both halves of a lane on one subject's rows)
+    "i16_self_lds": ("isa_i16_selfILi24ELi2ELb1E", 24, 2),
+    "i16_self_glb": ("isa_i16_selfILi24ELi2ELb0E", 24, 2),
+    "i16_p8_self_lds": ("isa_i16_selfILi24ELi1ELb1E", 24, 2),
+    "i16_p8_self_glb": ("isa_i16_selfILi24ELi1ELb0E", 24, 2),
     "rescore_i32_r24": ("k_rescoreILi24ELi2E", 24, 1),
     "rescore_i32_r24_p8": ("k_rescoreILi24ELi1E", 24, 1),
     # single long pair (csrc/sw_pair.hip): R rows per lane, 8- / 16-bit profile

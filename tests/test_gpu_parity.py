@@ -115,6 +115,35 @@ def test_long_query_global_profile():
     _check(db, q, synth.blosum_style_matrix(), 10, 2)
 
 
+@pytest.mark.parametrize("m,lds", [(1537, 0), (1537, 131072), (3073, 0), (6200, 0)])
+def test_self_paired_items(m, lds):
+    # Packed lanes with both halves on one subject's rows (the longest items
+    # of long queries): 1537 rows = 65 row blocks, one pass whose high halves
+    # hold a single block (LDS or global profile); 3073 = 129 blocks, two
+    # passes; 6200 = 259 blocks, three passes.  Homologs of query windows
+    # across the half boundary (row 1536) and the pass boundary (row 3072),
+    # ragged subject lengths around the 16-column blocks and the 128-column
+    # pipeline depth.
+    import paper_2412_08308_amd as swdb
+    rng = np.random.default_rng(m + lds)
+    q = synth.residues(rng, m)
+    seqs = [synth.residues(rng, n) for n in (1, 5, 15, 16, 17, 63, 64, 65, 127, 128, 129, 500, 2000, 9000)]
+    for lo, hi in ((1300, 1800), (2900, 3300), (100, 6000)):
+        if hi <= m:
+            seqs.append(synth.mutate(rng, q[lo:hi], 0.8))
+    seqs += [synth.residues(rng, int(n)) for n in rng.integers(10, 700, size=120)]
+    db = synth.Database.from_list([seqs[i] for i in rng.permutation(len(seqs))])
+    plan = swdb.Database.describe(db.lengths)
+    try:
+        for mode, spl in (("auto", 2), ("i32", 1)):
+            items = plan.plan_items([m], swdb.options(mode=mode, lds_limit=lds))
+            n_self = int(np.sum((items[:, 3] >> 25) & 1))
+            assert (n_self > 0) == (spl == 2), (mode, n_self)
+    finally:
+        plan.release()
+    _check(db, q, synth.blosum_style_matrix(), 10, 2, modes=["i16", "i16w", "auto"], lds_limit=lds)
+
+
 @pytest.mark.parametrize("top,low", [(127, -128), (117, -10)])
 def test_int16_overflow_boundary(top, low):
     # (127, -128): 16-bit profile entries; (117, -10) with Go = 10: every

@@ -37,12 +37,17 @@ def check_plan(db, qlens, opt, spl):
     rows = 32 if spl == 1 else 24
     last = None
     for s0, ncols, q, meta in items:
-        nsub, K = meta & 0xFFFF, (meta >> 16) & 0xFF
+        nsub, K, self_paired = meta & 0xFFFF, (meta >> 16) & 0xFF, (meta >> 25) & 1
         assert nsub > 0, "no empty items"
         assert 1 <= K <= 64
         nbr = -(-qlens[q] // rows)
-        cols = ncols if K == 1 else (int(slen[s0]) + K - 1 + 3) // 4 * 4
-        lw = max(cols, 4) * -(-nbr // K) * rows        # per-lane cells of the item
+        if self_paired:
+            # packed lanes only: one subject, 64 lanes, both halves on its rows
+            assert spl == 2 and nsub == 1 and K == WAVE and nbr > WAVE
+            lw = max((int(slen[s0]) + 2 * WAVE - 1 + 3) // 4 * 4, 4) * -(-nbr // (2 * WAVE)) * rows
+        else:
+            cols = ncols if K == 1 else (int(slen[s0]) + K - 1 + 3) // 4 * 4
+            lw = max(cols, 4) * -(-nbr // K) * rows        # per-lane cells of the item
         if last is not None and last[0] == q:
             assert lw <= last[1], "items of a query not in decreasing per-lane work"
         last = (q, lw)
@@ -50,7 +55,10 @@ def check_plan(db, qlens, opt, spl):
         assert ncols % 4 == 0 and ncols == (int(slen[s0]) + 3) // 4 * 4
         assert np.all(slen[s0:s0 + nsub] <= ncols)
         seen[q, s0:s0 + nsub] += 1
-        if nbr > K:
+        if self_paired:
+            if nbr > 2 * WAVE:
+                slot_need = max(slot_need, ncols * 8)
+        elif nbr > K:
             slot_need = max(slot_need, ncols * (WAVE // K) * 8)
     assert np.all(seen == 1), "every subject exactly once per query"
     info = db.plan_info(qlens, opt)
