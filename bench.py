@@ -297,8 +297,9 @@ def pairwise(args, ev):
 def alignments(args, w, scores):
     """Traceback of the best hits (the paper's optional step after the score):
     the query against its 16 highest-scoring subjects, one sw_align_pair call
-    each (score pass, direction-code pass, walk), and one 50,000-base DNA pair
-    against a homolog; wall time per call."""
+    each (score pass, direction-code pass, walk), one 50,000-base DNA pair
+    against a homolog and the paper's smallest DNA pair (162K x 172K); wall
+    time per call."""
     import numpy as np
     import torch
 
@@ -324,11 +325,43 @@ def alignments(args, w, scores):
     t1 = time.perf_counter()
     r = swdb.align_pair(qa, qb, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND, workspace=wsd)
     dt2 = time.perf_counter() - t1
+    del wsd
+    # the paper's smallest pairwise size (the pair of the pairwise leg): 2.8e10
+    # cells, 14 GB of direction codes; the operations are re-scored on the host
+    m, n = synth.DNA_PAIR_SIZES[0]
+    a, b = synth.dna_pair(m, n, seed=0)
+    qa, qb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    wsd = torch.empty(swdb.align_workspace_bytes(m, n), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    big = swdb.align_pair(qa, qb, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND, workspace=wsd)
+    dt3 = time.perf_counter() - t2
+    ws_gb = wsd.numel() / 1e9
+    del wsd
     return {"top_hits": {"alignments": len(subs), "ms_per_alignment": round(dt / len(subs) * 1e3, 2),
                          "cells": cells, "best": {k: res[0][k] for k in ("score", "q_begin", "s_begin", "q_end", "s_end")},
                          "best_ops": len(res[0]["ops"])},
             "dna_50k": {"ms": round(dt2 * 1e3, 1), "gcups_two_passes": round(2 * 50_000 ** 2 / dt2 / 1e9, 1),
-                        "score": r["score"], "ops": len(r["ops"])}}
+                        "score": r["score"], "ops": len(r["ops"])},
+            "dna_162k_x_172k": {"ms": round(dt3 * 1e3, 1), "cells": m * n, "workspace_gb": round(ws_gb, 1),
+                                "score": big["score"], "ops": len(big["ops"]),
+                                "begin": [big["q_begin"], big["s_begin"]], "end": [big["q_end"], big["s_end"]],
+                                "ops_rescore": ops_score(a, b, big, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND)}}
+
+
+def ops_score(a, b, r, sm, go, ge):
+    """Score of an alignment's operations (a gap of length L costs
+    go + (L - 1) * ge); equals r["score"] for a consistent alignment."""
+    i, j, total, prev = r["q_begin"] - 1, r["s_begin"] - 1, 0, "M"
+    for op in r["ops"]:
+        if op == "M":
+            total += int(sm[a[i], b[j]])
+            i, j = i + 1, j + 1
+        else:
+            total -= ge if op == prev else go
+            i, j = (i + 1, j) if op == "I" else (i, j + 1)
+        prev = op
+    return total
 
 
 def cpu_baseline(w, seconds: float):

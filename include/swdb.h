@@ -345,7 +345,8 @@ typedef struct sw_alignment {
 } sw_alignment;
 
 /* Workspace bytes sw_align_pair needs (0 on invalid input, or when m * n
-   exceeds 2^32 cells: the direction codes take half a byte per cell). */
+   exceeds 2^39 cells): the direction codes take half a byte per cell, so
+   the workspace is about m * n / 2 bytes (14 GB for 162K x 172K). */
 size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt);
 
 /*

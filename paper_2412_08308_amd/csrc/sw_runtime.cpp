@@ -1607,7 +1607,7 @@ int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint
     return SW_OK;
 }
 
-constexpr int64_t kAlignMaxCells = int64_t(1) << 32;   // direction codes: half a byte per cell
+constexpr int64_t kAlignMaxCells = int64_t(1) << 39;   // direction codes: half a byte per cell (256 GiB)
 
 // Alignment schedule: 8 rows per lane, 64 lanes per band (direction words of
 // 8 rows), the planner's chunk width for that.
@@ -1658,7 +1658,7 @@ size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt)
 {
     std::string why;
     if (!validate_pair(m, n, opt, why)) { fail(SW_EINVAL, why); return 0; }
-    if (m * n > kAlignMaxCells) { fail(SW_EINVAL, "alignment matrix larger than 2^32 cells"); return 0; }
+    if (m * n > kAlignMaxCells) { fail(SW_EINVAL, "alignment matrix larger than 2^39 cells"); return 0; }
     size_t t = pair_layout(m, n, nullptr).total + align_extra_bytes(m, n, nullptr);
     if (opt && opt->pair_cols > 8192)
         t += (size_t)align_up((int64_t)opt->pair_cols * 9, 256) +

@@ -81,3 +81,16 @@ def test_large_self_alignment():
     announce("align 50k self")
     r = _gpu_align(a, a, sm, go, ge)
     assert r == {"score": 50_000, "q_begin": 1, "s_begin": 1, "q_end": 50_000, "s_end": 50_000, "ops": "M" * 50_000}
+
+
+def test_alignment_beyond_2_32_cells():
+    """1e10 cells (5 GB of direction codes, byte offsets past 2^32): a
+    100,000-base sequence against its suffix from position 501 -- the whole
+    suffix matches on one diagonal (closed form: begin 501 / 1, 99,500 pairs)."""
+    sm, go, ge = DNA
+    rng = np.random.default_rng(6)
+    a = synth.residues(rng, 100_000, synth.DNA_FREQS)
+    announce("align 100k vs suffix")
+    r = _gpu_align(a, a[500:], sm, go, ge)
+    assert r == {"score": 99_500, "q_begin": 501, "s_begin": 1, "q_end": 100_000, "s_end": 99_500,
+                 "ops": "M" * 99_500}
