@@ -298,8 +298,9 @@ def alignments(args, w, scores):
     """Traceback of the best hits (the paper's optional step after the score):
     the query against its 16 highest-scoring subjects, one sw_align_pair call
     each (score pass, direction-code pass, walk), one 50,000-base DNA pair
-    against a homolog and the paper's smallest DNA pair (162K x 172K); wall
-    time per call."""
+    against a homolog, the paper's smallest DNA pair (162K x 172K, codes for
+    the whole matrix) and its 1M x 1M pair (codes recomputed block by block);
+    wall time per call."""
     import numpy as np
     import torch
 
@@ -338,6 +339,18 @@ def alignments(args, w, scores):
     dt3 = time.perf_counter() - t2
     ws_gb = wsd.numel() / 1e9
     del wsd
+    # the paper's 1M x 1M pair: whole-matrix codes would take 500 GB, so the
+    # codes are recomputed block by block (65536 x 65536) from checkpoints
+    m2, n2 = synth.DNA_PAIR_SIZES[2]
+    a2, b2 = synth.dna_pair(m2, n2, seed=2)
+    qa, qb = torch.from_numpy(a2).cuda(), torch.from_numpy(b2).cuda()
+    wsd = torch.empty(swdb.align_workspace_bytes(m2, n2), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    huge = swdb.align_pair(qa, qb, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND, workspace=wsd)
+    dt4 = time.perf_counter() - t3
+    ws2_gb = wsd.numel() / 1e9
+    del wsd
     return {"top_hits": {"alignments": len(subs), "ms_per_alignment": round(dt / len(subs) * 1e3, 2),
                          "cells": cells, "best": {k: res[0][k] for k in ("score", "q_begin", "s_begin", "q_end", "s_end")},
                          "best_ops": len(res[0]["ops"])},
@@ -346,7 +359,12 @@ def alignments(args, w, scores):
             "dna_162k_x_172k": {"ms": round(dt3 * 1e3, 1), "cells": m * n, "workspace_gb": round(ws_gb, 1),
                                 "score": big["score"], "ops": len(big["ops"]),
                                 "begin": [big["q_begin"], big["s_begin"]], "end": [big["q_end"], big["s_end"]],
-                                "ops_rescore": ops_score(a, b, big, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND)}}
+                                "ops_rescore": ops_score(a, b, big, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND)},
+            "dna_1m_x_1m_blocked": {"ms": round(dt4 * 1e3, 1), "cells": m2 * n2, "workspace_gb": round(ws2_gb, 2),
+                                    "score": huge["score"], "ops": len(huge["ops"]),
+                                    "begin": [huge["q_begin"], huge["s_begin"]], "end": [huge["q_end"], huge["s_end"]],
+                                    "ops_rescore": ops_score(a2, b2, huge, sm, synth.DNA_GAP_OPEN,
+                                                             synth.DNA_GAP_EXTEND)}}
 
 
 def ops_score(a, b, r, sm, go, ge):

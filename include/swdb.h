@@ -77,7 +77,11 @@ typedef struct sw_options {
                               lanes per band there (a power of two)              */
     int32_t pair_rows;     /* sw_pair_score: query rows per lane, 8 or 16
                               (0 = planner)                                      */
-    int32_t reserved[7];
+    int32_t align_block;   /* sw_align_pair: 0 = direction codes for the whole
+                              matrix up to 2^35 cells, blocks of 65536 x 65536
+                              beyond; > 0 = always blocks of this side (rounded
+                              up to 512 rows and to the chunk width), <= 2^24  */
+    int32_t reserved[6];
     /* Optional timing events (created by the caller, may be NULL): recorded on
        the search stream immediately before the search kernel, immediately
        after it, and after the int32 rescore (16-bit modes).                   */

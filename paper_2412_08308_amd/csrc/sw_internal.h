@@ -119,16 +119,47 @@ struct PairArgs {
     // the source of H (0: H = 0, 1: diagonal, 2: E, 3: F), bit 2 E opened
     // (from H) rather than extended, bit 3 the same for F; column-major, one
     // 32-bit word per 8 rows: dir[col * dir_stride + row / 8]
+    // dir may be null (end key only).  A block run writes the codes of the
+    // block alone: dir[(col - dir_col0) * dir_stride + row / 8 - dir_rb0].
     uint32_t* dir;
-    int64_t dir_stride;          // words per column: nb * K
+    int64_t dir_stride;          // words per column: nb * K (a block: its bands * K)
     int64_t m, n;                // real lengths (cells past them are padding)
     unsigned long long* end_key; // min over cells with H = *score of col << 32 | row
+    int64_t dir_col0;
+    int32_t dir_rb0;
+    // Checkpointed alignment.  The checkpointing score pass stores, below
+    // every ckpt_gb-th band, its bottom row (H - Go, F) per column:
+    // ckpt_row[k * ckpt_row_stride + col], k = (b + 1) / ckpt_gb - 1; right of
+    // every ckpt_gc-th chunk, its last column (H - Go, E) per row:
+    // ckpt_col[k * ckpt_col_stride + row], k = (c + 1) / ckpt_gc - 1; and the
+    // largest H of every chunk (chunk_max[c], atomicMax).  A block run (the
+    // direction pass over bands from b_org, chunks from a checkpoint column)
+    // starts from buffers filled from those checkpoints; the corners of its
+    // first band come from top_ckpt (the checkpoint row above b_org, by
+    // absolute column), null when b_org = 0.
+    int2* ckpt_row;
+    int2* ckpt_col;
+    int64_t ckpt_row_stride, ckpt_col_stride;
+    int32_t ckpt_gb, ckpt_gc;
+    int32_t* chunk_max;
+    int32_t b_org;
+    const int2* top_ckpt;
 };
 
 // Alignment found by the traceback pass (device memory, written by the
 // traceback kernel): 1-based inclusive positions, operation count.
 struct AlignOut {
     int32_t score, q_begin, s_begin, q_end, s_end, n_ops;
+};
+
+// State of the traceback walk between blocks (device memory): the current
+// 1-based cell and state (0: H, 1: in a gap of the query (E), 2: in a gap of
+// the subject (F)), whether the last step was a diagonal one, operations so
+// far, and, once done, the begin cell and whether the codes were consistent.
+struct WalkState {
+    int64_t i, j, n_ops, bi, bj;
+    int32_t st, prev_m, done, ok;
+    int32_t q_end, s_end;
 };
 
 // Kernel variants the runtime may launch.
@@ -170,7 +201,19 @@ hipError_t launch_pair_diag(const PairArgs& a, int rows, int elem, hipStream_t s
 // 64), the end-key reset, and the single-lane walk that writes the alignment.
 hipError_t launch_trace_diag(const PairArgs& a, int elem, hipStream_t st);
 hipError_t launch_trace_reset(unsigned long long* end_key, hipStream_t st);
-hipError_t launch_traceback(const uint32_t* dir, int64_t dir_stride, const unsigned long long* end_key,
-                            const int32_t* score, char* ops, int64_t cap, AlignOut* out, hipStream_t st);
+// Checkpointing score pass (8 rows per lane, K = 64) and the fill of the
+// boundary buffers of a block run from the checkpoints.
+hipError_t launch_pair_diag_ckpt(const PairArgs& a, int elem, hipStream_t st);
+hipError_t launch_block_init(const PairArgs& a, int64_t kb, int64_t kc, int64_t b_hi, int64_t c_org,
+                             int64_t c_hi, hipStream_t st);
+// Walk: start from the end key, continue inside a block of codes (rows
+// [r_lo, r_hi), columns [c_lo, c_hi), 0-based) until it leaves the block or
+// ends, finish (reverse the operations, write the result).
+hipError_t launch_walk_init(const unsigned long long* end_key, const int32_t* score, WalkState* w,
+                            hipStream_t st);
+hipError_t launch_walk(const uint32_t* dir, int64_t dir_stride, int64_t r_lo, int64_t c_lo, int64_t r_hi,
+                       int64_t c_hi, WalkState* w, char* ops, int64_t cap, hipStream_t st);
+hipError_t launch_walk_finish(const WalkState* w, const int32_t* score, char* ops, AlignOut* out,
+                              hipStream_t st);
 
 }  // namespace swdb

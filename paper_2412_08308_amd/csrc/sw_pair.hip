@@ -26,10 +26,13 @@ namespace swdb {
 // equals the score already computed by a plain pass (PairArgs::end_key).  The
 // codes follow the traceback rules: the diagonal before E before F, a gap
 // opened from H rather than extended when both give its value.
-template <int R, int ES, bool TRACE = false>
+// CKPT (score pass of a checkpointed alignment): also store the checkpoint
+// rows and columns and the chunk maxima (PairArgs).
+template <int R, int ES, bool TRACE = false, bool CKPT = false>
 __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
 {
     static_assert(!TRACE || R == 8, "direction words hold 8 rows");
+    static_assert(!(TRACE && CKPT), "checkpoints come from the score pass");
     constexpr uint32_t CS = code_stride(R, ES);
     constexpr uint32_t BS = kCodes * CS;
     constexpr int NB = R * ES;
@@ -58,6 +61,15 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
     const bool put_right = valid && c < a.nc - 1;
     int2* __restrict__ top = a.rowbuf + c0;
     int2* __restrict__ side = a.colbuf + row0;
+    // checkpoint row below this band / column right of this chunk (CKPT)
+    int2* __restrict__ ck_bottom = nullptr;
+    int2* __restrict__ ck_right = nullptr;
+    if constexpr (CKPT) {
+        if (put_bottom && (b + 1) % a.ckpt_gb == 0)
+            ck_bottom = a.ckpt_row + (int64_t)((b + 1) / a.ckpt_gb - 1) * a.ckpt_row_stride + c0;
+        if (put_right && (c + 1) % a.ckpt_gc == 0)
+            ck_right = a.ckpt_col + (int64_t)((c + 1) / a.ckpt_gc - 1) * a.ckpt_col_stride + row0;
+    }
     const uint4* __restrict__ resp = reinterpret_cast<const uint4*>(a.subj + c0);
 
     int Y[R], E[R];
@@ -74,8 +86,12 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
     // H - Go of the cell above-left of this lane's first row: the previous
     // lane's last row in the chunk to the left, or the corner for the head
     int ydiag = -go;
-    if (has_left)
-        ydiag = head ? (b > 0 ? a.corner[b * 3 + c % 3] : -go) : side[-1].x;
+    if (has_left) {
+        if (!head)
+            ydiag = side[-1].x;
+        else if (b > 0)
+            ydiag = (TRACE && b == a.b_org && a.top_ckpt) ? a.top_ckpt[c0 - 1].x : a.corner[b * 3 + c % 3];
+    }
     int ybot = -go, fbot = 0;
     int S = 0;
     const int s_target = TRACE ? *a.score : 0;
@@ -163,10 +179,15 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
                     fbot = F;
                     if (put_bottom)
                         top[j] = make_int2(ybot, fbot);
+                    if constexpr (CKPT) {
+                        if (ck_bottom)
+                            ck_bottom[j] = make_int2(ybot, fbot);
+                    }
                     if constexpr (TRACE) {
                         const int64_t col = c0 + j;
                         if (valid) {
-                            a.dir[col * a.dir_stride + rb] = word;
+                            if (a.dir)
+                                a.dir[(col - a.dir_col0) * a.dir_stride + (rb - a.dir_rb0)] = word;
                             const int64_t row = row0 + (hits ? __builtin_ctz(hits) : 0);
                             if (hits && key == ~0ull && col < a.n && row < a.m)
                                 key = ((unsigned long long)col << 32) | (unsigned long long)row;
@@ -189,6 +210,13 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
             *reinterpret_cast<int4*>(side + r) = make_int4(Y[r], E[r], Y[r + 1], E[r + 1]);
         if (put_bottom)
             a.corner[(b + 1) * 3 + (c + 1) % 3] = ybot;
+        if constexpr (CKPT) {
+            if (ck_right) {
+#pragma unroll
+                for (int r = 0; r < R; r += 2)
+                    *reinterpret_cast<int4*>(ck_right + r) = make_int4(Y[r], E[r], Y[r + 1], E[r + 1]);
+            }
+        }
     }
     if constexpr (TRACE) {
         // first hit of the wave (column, then row), into the pair's end key
@@ -200,18 +228,27 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
             atomicMin(a.end_key, key);
         return;
     }
-    // tile maximum into the pair's score
+    // tile maximum into the pair's score (and its chunk's maximum)
     S = valid ? S : 0;
     for (int k = 32; k >= 1; k >>= 1)
         S = max(S, __shfl_xor(S, k));
-    if (lane == 0 && S > 0)
+    if (lane == 0 && S > 0) {
         atomicMax(a.score, S);
+        if constexpr (CKPT)
+            atomicMax(a.chunk_max + c, S);
+    }
 }
 
 template <int R, int ES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_pair_diag(PairArgs a)
 {
     pair_tile<R, ES>(a, threadIdx.x & 63);
+}
+
+template <int ES>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_pair_diag_ckpt(PairArgs a)
+{
+    pair_tile<8, ES, false, true>(a, threadIdx.x & 63);
 }
 
 template <int ES>
@@ -227,108 +264,150 @@ __global__ void k_trace_reset(unsigned long long* end_key)
 }
 
 // Walk of the traceback: from the end cell in state H, follow the direction
-// codes -- the diagonal emits a residue pair and stops when its predecessor
-// holds H = 0 or lies on the border, E emits a subject residue against a gap,
-// F a query residue against a gap, each returning to H where the gap was
-// opened -- then reverse the operations into begin-to-end order.  One
-// wavefront: the codes of a window of 64 columns x 128 rows around the walk
-// sit in LDS (each lane loads one column), every lane runs the same walk on
-// them (uniform control flow; lane 0 writes the operations), and the wave
-// reloads the window when the walk leaves it.
+// codes -- the diagonal emits a residue pair, E a subject residue against a
+// gap, F a query residue against a gap, each gap returning to H where it was
+// opened -- until a diagonal step reaches a cell holding H = 0 (the alignment
+// began at the cell before it) or the border; then reverse the operations
+// into begin-to-end order.  The codes may come one block of the matrix at a
+// time: the walk stops when it leaves the block in hand, keeping its state in
+// a WalkState, and the host supplies the block holding the next cell.
+//
+// One wavefront per walk call: the codes of a window of 64 columns x 128 rows
+// around the walk sit in LDS (each lane loads one column), every lane runs the
+// same walk on them (uniform control flow; lane 0 writes the operations), and
+// the wave reloads the window when the walk leaves it.
 constexpr int kWinCols = 64, kWinWords = 16;   // 16 words of 8 rows = 128 rows
 
-__global__ void __launch_bounds__(64) k_traceback(const uint32_t* __restrict__ dir, int64_t stride,
-                                                  const unsigned long long* __restrict__ end_key,
-                                                  const int32_t* __restrict__ score, char* __restrict__ ops,
-                                                  int64_t cap, AlignOut* out)
+__global__ void k_walk_init(const unsigned long long* __restrict__ end_key, const int32_t* __restrict__ score,
+                            WalkState* w)
+{
+    if (threadIdx.x != 0)
+        return;
+    const unsigned long long key = *end_key;
+    WalkState s{};
+    s.ok = 1;
+    if (*score > 0 && key != ~0ull) {
+        s.j = (int64_t)(key >> 32) + 1;            // 1-based
+        s.i = (int64_t)(key & 0xffffffffull) + 1;
+        s.q_end = (int32_t)s.i;
+        s.s_end = (int32_t)s.j;
+    } else {
+        s.done = 1;                                // empty alignment
+    }
+    *w = s;
+}
+
+__global__ void __launch_bounds__(64) k_walk(const uint32_t* __restrict__ dir, int64_t stride, int64_t r_lo,
+                                             int64_t c_lo, int64_t r_hi, int64_t c_hi, WalkState* wst,
+                                             char* __restrict__ ops, int64_t cap)
 {
     __shared__ uint32_t win[kWinCols][kWinWords];
     const int lane = threadIdx.x;
-    AlignOut r{};
-    r.score = *score;
-    const unsigned long long key = *end_key;
-    int64_t n_ops = 0;
-    if (r.score > 0 && key != ~0ull) {
-        int64_t j = (int64_t)(key >> 32) + 1, i = (int64_t)(key & 0xffffffffull) + 1;   // 1-based
-        r.q_end = (int32_t)i;
-        r.s_end = (int32_t)j;
-        int64_t c0 = -1, w0 = 0;     // window: columns c0..c0+63, words w0..w0+15 (0-based)
-        // code of 1-based cell (ii, jj), reloading the window around it if needed
-        auto code = [&](int64_t ii, int64_t jj) -> uint32_t {
-            const int64_t col = jj - 1, row = ii - 1;
-            if (c0 < 0 || col < c0 || col >= c0 + kWinCols || (row >> 3) < w0 || (row >> 3) >= w0 + kWinWords) {
-                __syncthreads();
-                c0 = col - (kWinCols - 1) > 0 ? col - (kWinCols - 1) : 0;
-                w0 = (row >> 3) - (kWinWords - 4) > 0 ? (row >> 3) - (kWinWords - 4) : 0;
-                const int64_t cc = c0 + lane;
-                if (cc <= col) {
+    WalkState s = *wst;
+    if (s.done)
+        return;
+    const int64_t w_lo = r_lo >> 3;            // r_lo is a multiple of 8
+    int64_t c0 = -1, w0 = 0;                   // window: block columns c0.., block words w0..
+    // code of 1-based cell (ii, jj) inside the block, reloading the window if needed
+    auto code = [&](int64_t ii, int64_t jj) -> uint32_t {
+        const int64_t col = jj - 1 - c_lo, row = ii - 1, wd = (row >> 3) - w_lo;
+        if (c0 < 0 || col < c0 || col >= c0 + kWinCols || wd < w0 || wd >= w0 + kWinWords) {
+            __syncthreads();
+            c0 = col - (kWinCols - 1) > 0 ? col - (kWinCols - 1) : 0;
+            w0 = wd - (kWinWords - 4) > 0 ? wd - (kWinWords - 4) : 0;
+            const int64_t cc = c0 + lane;
+            if (cc <= col) {
 #pragma unroll
-                    for (int k = 0; k < kWinWords; ++k)
-                        win[lane][k] = (w0 + k < stride) ? dir[cc * stride + w0 + k] : 0u;
-                }
-                __syncthreads();
+                for (int k = 0; k < kWinWords; ++k)
+                    win[lane][k] = (w0 + k < stride) ? dir[cc * stride + w0 + k] : 0u;
             }
-            const uint32_t w = win[col - c0][(row >> 3) - w0];
-            return (w >> (4 * (row & 7))) & 15u;
-        };
-        int state = 0;
-        bool ok = false;
-        while (n_ops < cap && i >= 1 && j >= 1) {
-            const uint32_t c = code(i, j);
-            char op = 0;
-            if (state == 0) {
-                const uint32_t src = c & 3u;
-                if (src == 1u) {
-                    op = 'M';
-                    const bool stop = i == 1 || j == 1 || (code(i - 1, j - 1) & 3u) == 0u;
-                    if (lane == 0)
-                        ops[n_ops] = op;
-                    ++n_ops;
-                    if (stop) {
-                        ok = true;
-                        break;
-                    }
-                    --i;
-                    --j;
-                    continue;
-                } else if (src == 2u) {
-                    state = 1;
-                } else if (src == 3u) {
-                    state = 2;
-                } else {
-                    break;                        // H = 0 on the path: inconsistent codes
+            __syncthreads();
+        }
+        const uint32_t word = win[col - c0][wd - w0];
+        return (word >> (4 * (row & 7))) & 15u;
+    };
+    while (!s.done) {
+        if (s.i < 1 || s.j < 1 || s.n_ops >= cap) {          // off the matrix: inconsistent codes
+            s.done = 1;
+            s.ok = 0;
+            break;
+        }
+        if (s.i - 1 < r_lo || s.j - 1 < c_lo || s.i - 1 >= r_hi || s.j - 1 >= c_hi)
+            break;                                            // the next cell is in another block
+        const uint32_t c = code(s.i, s.j);
+        if (s.st == 0) {
+            const uint32_t src = c & 3u;
+            if (src == 0u) {
+                // H = 0: after a diagonal step the alignment began at the
+                // previous cell; anywhere else the codes are inconsistent
+                s.done = 1;
+                s.ok = s.prev_m;
+                s.bi = s.i + 1;
+                s.bj = s.j + 1;
+                break;
+            }
+            if (src == 1u) {
+                if (lane == 0)
+                    ops[s.n_ops] = 'M';
+                ++s.n_ops;
+                s.prev_m = 1;
+                if (s.i == 1 || s.j == 1) {               // border
+                    s.done = 1;
+                    s.bi = s.i;
+                    s.bj = s.j;
+                    break;
                 }
+                --s.i;
+                --s.j;
                 continue;
             }
-            if (state == 1) {
-                op = 'D';
-                if (c & 4u)
-                    state = 0;
-                --j;
-            } else {
-                op = 'I';
-                if (c & 8u)
-                    state = 0;
-                --i;
-            }
-            if (lane == 0)
-                ops[n_ops] = op;
-            ++n_ops;
+            s.prev_m = 0;
+            s.st = src == 2u ? 1 : 2;
+            continue;
         }
-        if (ok) {
-            r.q_begin = (int32_t)i;
-            r.s_begin = (int32_t)j;
-            __syncthreads();                      // the walk's writes before the reversal
-            for (int64_t x = lane, y = n_ops - 1 - lane; x < y; x += 64, y -= 64) {
+        if (lane == 0)
+            ops[s.n_ops] = s.st == 1 ? 'D' : 'I';
+        ++s.n_ops;
+        s.prev_m = 0;
+        if (s.st == 1) {
+            if (c & 4u)
+                s.st = 0;
+            --s.j;
+        } else {
+            if (c & 8u)
+                s.st = 0;
+            --s.i;
+        }
+    }
+    __syncthreads();
+    if (lane == 0)
+        *wst = s;
+}
+
+__global__ void __launch_bounds__(64) k_walk_finish(const WalkState* __restrict__ wst,
+                                                    const int32_t* __restrict__ score, char* __restrict__ ops,
+                                                    AlignOut* out)
+{
+    const int lane = threadIdx.x;
+    const WalkState s = *wst;
+    AlignOut r{};
+    r.score = *score;
+    if (s.n_ops > 0 || s.q_end > 0) {
+        r.q_end = s.q_end;
+        r.s_end = s.s_end;
+        if (s.done && s.ok) {
+            r.q_begin = (int32_t)s.bi;
+            r.s_begin = (int32_t)s.bj;
+            r.n_ops = (int32_t)s.n_ops;
+            for (int64_t x = lane, y = s.n_ops - 1 - lane; x < y; x += 64, y -= 64) {
                 const char t = ops[x];
                 ops[x] = ops[y];
                 ops[y] = t;
             }
         } else {
-            n_ops = -1;                           // reported as an error by the host
+            r.n_ops = -1;                                  // reported as an error by the host
         }
     }
-    r.n_ops = (int32_t)n_ops;
     if (lane == 0)
         *out = r;
 }
@@ -350,10 +429,70 @@ hipError_t launch_trace_reset(unsigned long long* end_key, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_traceback(const uint32_t* dir, int64_t dir_stride, const unsigned long long* end_key,
-                            const int32_t* score, char* ops, int64_t cap, AlignOut* out, hipStream_t st)
+hipError_t launch_walk_init(const unsigned long long* end_key, const int32_t* score, WalkState* w,
+                            hipStream_t st)
 {
-    hipLaunchKernelGGL(k_traceback, dim3(1), dim3(kWinCols), 0, st, dir, dir_stride, end_key, score, ops, cap, out);
+    hipLaunchKernelGGL(k_walk_init, dim3(1), dim3(64), 0, st, end_key, score, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk(const uint32_t* dir, int64_t dir_stride, int64_t r_lo, int64_t c_lo, int64_t r_hi,
+                       int64_t c_hi, WalkState* w, char* ops, int64_t cap, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_walk, dim3(1), dim3(kWinCols), 0, st, dir, dir_stride, r_lo, c_lo, r_hi, c_hi, w, ops,
+                       cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_finish(const WalkState* w, const int32_t* score, char* ops, AlignOut* out,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(k_walk_finish, dim3(1), dim3(64), 0, st, w, score, ops, out);
+    return hipGetLastError();
+}
+
+// Boundary buffers of a block run (bands [b_org, b_hi], chunks [c_org, c_hi]
+// of the tile grid, kb / kc its checkpoint row / column indices): colbuf over
+// the block's rows from checkpoint column kc - 1, rowbuf over its columns from
+// checkpoint row kb - 1, and the corners of the first chunk's bands below the
+// first from checkpoint column kc - 1 (the first band's corners come from the
+// checkpoint row through PairArgs::top_ckpt).
+__global__ void __launch_bounds__(256) k_block_init(PairArgs a, int64_t kb, int64_t kc, int64_t b_hi, int64_t c_org,
+                                                    int64_t c_hi)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    const int64_t band_rows = (int64_t)a.K * 8;
+    const int64_t r0 = (int64_t)a.b_org * band_rows, r1 = (b_hi + 1) * band_rows;
+    const int64_t col0 = c_org * a.wc, col1 = (c_hi + 1) * a.wc;
+    if (kc > 0) {
+        const int2* src = a.ckpt_col + (kc - 1) * a.ckpt_col_stride;
+        for (int64_t r = r0 + t; r < r1; r += nt)
+            a.colbuf[r] = src[r];
+        for (int64_t b = a.b_org + 1 + t; b <= b_hi; b += nt)
+            a.corner[b * 3 + c_org % 3] = src[b * band_rows - 1].x;
+    }
+    if (kb > 0) {
+        const int2* src = a.ckpt_row + (kb - 1) * a.ckpt_row_stride;
+        for (int64_t c = col0 + t; c < col1; c += nt)
+            a.rowbuf[c] = src[c];
+    }
+}
+
+hipError_t launch_block_init(const PairArgs& a, int64_t kb, int64_t kc, int64_t b_hi, int64_t c_org,
+                             int64_t c_hi, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_block_init, dim3(1024), dim3(256), 0, st, a, kb, kc, b_hi, c_org, c_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_diag_ckpt(const PairArgs& a, int elem, hipStream_t st)
+{
+    const int blocks = (a.ntiles + 3) / 4;        // K = 64: one tile per wave
+    if (elem == 1)
+        hipLaunchKernelGGL((k_pair_diag_ckpt<1>), dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_pair_diag_ckpt<2>), dim3(blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

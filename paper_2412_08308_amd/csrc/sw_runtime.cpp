@@ -137,6 +137,7 @@ bool validate_options(const sw_options* opt, std::string& why)
     if (opt->grid_limit < 0) { why = "options.grid_limit"; return false; }
     if (opt->pair_cols < 0) { why = "options.pair_cols"; return false; }
     if (opt->pair_rows < 0) { why = "options.pair_rows"; return false; }
+    if (opt->align_block < 0 || opt->align_block > (1 << 24)) { why = "options.align_block must be 0..2^24"; return false; }
     return true;
 }
 
@@ -1534,13 +1535,12 @@ int device_cu(int* cu)
     return SW_OK;
 }
 
-// Everything one pass over a pair enqueues: padded subject, cleared score,
-// profile, then the anti-diagonal launches (score pass), and for an alignment
-// a second pass of the same tiles writing direction codes and the end key.
-int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint8_t* query, int64_t m,
-                 const uint8_t* subject, int64_t n, const int32_t* sm, int32_t go, int32_t ge, int elem,
-                 int32_t* score_out, uint32_t* dir, unsigned long long* end_key, hipEvent_t ev0, hipEvent_t ev1,
-                 hipStream_t stream)
+// Buffers and arguments shared by every pass over a pair: padded subject,
+// cleared score, the query's profile.  `empty` is set (and nothing but the
+// cleared score enqueued) when either sequence is empty.
+int pair_setup(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint8_t* query, int64_t m,
+               const uint8_t* subject, int64_t n, const int32_t* sm, int32_t go, int32_t ge, int elem,
+               int32_t* score_out, hipStream_t stream, PairArgs& a, bool& empty)
 {
     QueryDesc qd{};
     qd.prof_off = 0;
@@ -1551,7 +1551,8 @@ int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint
     auto* qoff_dev = reinterpret_cast<int64_t*>(w + L.qoff);
     HIPCHK(launch_pair_prep(subject, n, (m > 0 && n > 0) ? L.n_pad : 0, w + L.subj, score_out, qd, qd_dev,
                             qoff_dev, stream));
-    if (m == 0 || n == 0)
+    empty = m == 0 || n == 0;
+    if (empty)
         return SW_OK;      // score 0, written by the preparation kernel
 
     ProfileArgs pa{};
@@ -1568,7 +1569,7 @@ int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint
         pa.sm.v[i] = (int8_t)sm[i];
     HIPCHK(launch_profile(pa, p.R, elem, (int)std::min<int64_t>((p.nbr + 1) * kCodes * p.R, INT32_MAX), stream));
 
-    PairArgs a{};
+    a = PairArgs{};
     a.subj = w + L.subj;
     a.prof = w + L.prof;
     a.rowbuf = reinterpret_cast<int2*>(w + L.rowbuf);
@@ -1582,35 +1583,69 @@ int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint
     a.wc = p.wc;
     a.go = go;
     a.ge = ge;
-    a.dir = dir;
     a.dir_stride = p.nb * p.K;
     a.m = m;
     a.n = n;
+    return SW_OK;
+}
+
+enum class PairPass { kScore, kScoreCkpt, kTrace };
+
+// The anti-diagonal launches of one pass over bands [b0, b1] x chunks [c0, c1]
+// of the tile grid, in order on the stream.
+int pair_diagonals(PairArgs a, PairPass kind, int R, int elem, int64_t b0, int64_t b1, int64_t c0, int64_t c1,
+                   hipStream_t stream)
+{
+    const int64_t nbb = b1 - b0 + 1, ncc = c1 - c0 + 1;
+    for (int64_t dr = 0; dr < nbb + ncc - 1; ++dr) {
+        const int64_t lo = b0 + std::max<int64_t>(0, dr - (ncc - 1));
+        const int64_t hi = b0 + std::min<int64_t>(dr, nbb - 1);
+        a.d = (int32_t)(dr + b0 + c0);
+        a.b_lo = (int32_t)lo;
+        a.ntiles = (int32_t)(hi - lo + 1);
+        if (kind == PairPass::kScore)
+            HIPCHK(launch_pair_diag(a, R, elem, stream));
+        else if (kind == PairPass::kScoreCkpt)
+            HIPCHK(launch_pair_diag_ckpt(a, elem, stream));
+        else
+            HIPCHK(launch_trace_diag(a, elem, stream));
+    }
+    return SW_OK;
+}
+
+// Everything one pass over a pair enqueues: setup, then the anti-diagonal
+// launches (score pass), and for an alignment with direction codes for the
+// whole matrix a second pass of the same tiles writing the codes and the end key.
+int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint8_t* query, int64_t m,
+                 const uint8_t* subject, int64_t n, const int32_t* sm, int32_t go, int32_t ge, int elem,
+                 int32_t* score_out, uint32_t* dir, unsigned long long* end_key, hipEvent_t ev0, hipEvent_t ev1,
+                 hipStream_t stream)
+{
+    PairArgs a{};
+    bool empty = false;
+    int rc = pair_setup(p, L, w, query, m, subject, n, sm, go, ge, elem, score_out, stream, a, empty);
+    if (rc || empty)
+        return rc;
+    a.dir = dir;
     a.end_key = end_key;
     if (ev0) HIPCHK(hipEventRecord(ev0, stream));
-    for (int pass = 0; pass < (dir ? 2 : 1); ++pass) {
-        if (pass == 1)
-            HIPCHK(launch_trace_reset(end_key, stream));
-        for (int64_t d = 0; d < p.nb + p.nc - 1; ++d) {
-            const int64_t b_lo = std::max<int64_t>(0, d - (p.nc - 1));
-            const int64_t b_hi = std::min<int64_t>(d, p.nb - 1);
-            a.d = (int32_t)d;
-            a.b_lo = (int32_t)b_lo;
-            a.ntiles = (int32_t)(b_hi - b_lo + 1);
-            if (pass == 0)
-                HIPCHK(launch_pair_diag(a, p.R, elem, stream));
-            else
-                HIPCHK(launch_trace_diag(a, elem, stream));
-        }
+    rc = pair_diagonals(a, PairPass::kScore, p.R, elem, 0, p.nb - 1, 0, p.nc - 1, stream);
+    if (rc) return rc;
+    if (dir) {
+        HIPCHK(launch_trace_reset(end_key, stream));
+        rc = pair_diagonals(a, PairPass::kTrace, p.R, elem, 0, p.nb - 1, 0, p.nc - 1, stream);
+        if (rc) return rc;
     }
     if (ev1) HIPCHK(hipEventRecord(ev1, stream));
     return SW_OK;
 }
 
-constexpr int64_t kAlignMaxCells = int64_t(1) << 39;   // direction codes: half a byte per cell (256 GiB)
-
 // Alignment schedule: 8 rows per lane, 64 lanes per band (direction words of
 // 8 rows), the planner's chunk width for that.
+constexpr int64_t kBandRows = 8 * 64;
+constexpr int64_t kAlignFullCells = int64_t(1) << 35;   // automatic: whole-matrix codes up to 16 GiB
+constexpr int64_t kAlignBlockSide = 65536;              // automatic block side beyond that
+
 PairPlanC align_plan(int64_t m, int64_t n, int cu, const sw_options* opt)
 {
     sw_options o = opt ? *opt : sw_options{};
@@ -1619,12 +1654,140 @@ PairPlanC align_plan(int64_t m, int64_t n, int cu, const sw_options* opt)
     return pair_plan(m, n, cu, &o);
 }
 
-// direction words (bound over every chunk width) and the end key
-size_t align_extra_bytes(int64_t m, int64_t n, const PairPlanC* p)
+bool align_blocked(int64_t m, int64_t n, const sw_options* opt)
 {
-    const int64_t words = p ? p->nb * p->K * p->nc * p->wc
-                            : ceil_div(std::max<int64_t>(m, 1), 512) * 64 * (align_up(n, 16) + 8192);
-    return (size_t)align_up(words * 4, 256) + 256;
+    return (opt && opt->align_block > 0) || m * n > kAlignFullCells;
+}
+
+// Workspace past the pair buffers.  Whole matrix: the direction words.
+// Blocks: checkpoint rows (below every gb-th band) and columns (right of
+// every gc-th chunk), chunk maxima and the direction words of one block of gb
+// bands x gc chunks.  Both: the end key and the walk state.  Without a plan,
+// the bound over every chunk width.
+struct AlignLayout {
+    size_t ckpt_row = 0, ckpt_col = 0, chunk_max = 0, dir = 0, tail = 0, total = 0;
+    int64_t row_stride = 0, col_stride = 0, n_ckrow = 0, n_ckcol = 0, gb = 1, gc = 1;
+};
+
+AlignLayout align_layout(int64_t m, int64_t n, const sw_options* opt, const PairPlanC* p)
+{
+    AlignLayout A;
+    const int64_t nb = p ? p->nb : ceil_div(std::max<int64_t>(m, 1), kBandRows);
+    const int64_t wide = std::max<int64_t>(8192, opt ? opt->pair_cols : 0);   // widest chunk
+    const int64_t cols = p ? p->nc * p->wc : align_up(n, 16) + wide;          // padded columns
+    size_t off = 0;
+    if (!align_blocked(m, n, opt)) {
+        A.dir = off;
+        off += align_up(nb * 64 * cols * 4, 256);
+    } else {
+        const int64_t B = (opt && opt->align_block > 0) ? opt->align_block : kAlignBlockSide;
+        A.gb = ceil_div(B, kBandRows);
+        A.gc = p ? ceil_div(B, p->wc) : 1;
+        // (nc - 1) / gc < n / B for every chunk width, and gc * wc < B + wc
+        A.n_ckrow = (nb - 1) / A.gb;
+        A.n_ckcol = p ? (p->nc - 1) / A.gc : n / B + 1;
+        A.row_stride = cols;
+        A.col_stride = nb * kBandRows;
+        const int64_t nchunks = p ? p->nc : ceil_div(std::max<int64_t>(n, 1), 16) + 1;
+        const int64_t blk_cols = p ? A.gc * p->wc : B + wide;
+        A.ckpt_row = off; off += align_up(A.n_ckrow * A.row_stride * 8, 256);
+        A.ckpt_col = off; off += align_up(A.n_ckcol * A.col_stride * 8, 256);
+        A.chunk_max = off; off += align_up(nchunks * 4, 256);
+        A.dir = off; off += align_up(A.gb * 64 * blk_cols * 4, 256);
+    }
+    A.tail = off;                 // end key, spare key, walk state
+    off += 512;
+    A.total = off;
+    return A;
+}
+
+// Blocked alignment: score pass with checkpoints and chunk maxima; the end
+// cell from a direction pass (codes not kept) over the checkpoint block
+// column holding the first chunk whose maximum is the score; then, block by
+// block along the walk, the direction codes of the block holding the walk's
+// cell (recomputed from its checkpoint row and column, up to that cell) and
+// the walk through it.  The host reads the walk's position after each block,
+// so the call returns with the stream drained.
+int align_blocks(const PairPlanC& p, const PairLayout& L, const AlignLayout& A, uint8_t* w, uint8_t* x,
+                 const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n, const int32_t* sm, int32_t go,
+                 int32_t ge, int elem, AlignOut* o, char* ops, const sw_options* opt, hipStream_t stream)
+{
+    auto* end_key = reinterpret_cast<unsigned long long*>(x + A.tail);
+    auto* spare_key = end_key + 1;
+    auto* walk = reinterpret_cast<WalkState*>(x + A.tail + 256);
+    PairArgs a{};
+    bool empty = false;
+    int rc = pair_setup(p, L, w, query, m, subject, n, sm, go, ge, elem, &o->score, stream, a, empty);
+    if (rc) return rc;
+    HIPCHK(launch_trace_reset(end_key, stream));
+    if (empty) {
+        HIPCHK(launch_walk_init(end_key, &o->score, walk, stream));
+        HIPCHK(launch_walk_finish(walk, &o->score, ops, o, stream));
+        return SW_OK;
+    }
+    auto* ckrow = reinterpret_cast<int2*>(x + A.ckpt_row);
+    auto* cmax = reinterpret_cast<int32_t*>(x + A.chunk_max);
+    auto* dir = reinterpret_cast<uint32_t*>(x + A.dir);
+    a.ckpt_row = ckrow;
+    a.ckpt_col = reinterpret_cast<int2*>(x + A.ckpt_col);
+    a.ckpt_row_stride = A.row_stride;
+    a.ckpt_col_stride = A.col_stride;
+    a.ckpt_gb = (int32_t)A.gb;
+    a.ckpt_gc = (int32_t)A.gc;
+    a.chunk_max = cmax;
+    HIPCHK(hipMemsetAsync(cmax, 0, sizeof(int32_t) * p.nc, stream));
+    if (opt && opt->ev_search_begin) HIPCHK(hipEventRecord(opt->ev_search_begin, stream));
+    rc = pair_diagonals(a, PairPass::kScoreCkpt, 8, elem, 0, p.nb - 1, 0, p.nc - 1, stream);
+    if (rc) return rc;
+    int32_t S = 0;
+    std::vector<int32_t> cm((size_t)p.nc);
+    HIPCHK(hipMemcpyAsync(&S, &o->score, sizeof S, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(cm.data(), cmax, sizeof(int32_t) * p.nc, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    a.chunk_max = nullptr;
+    if (S > 0) {
+        int64_t cs = 0;
+        while (cs < p.nc && cm[(size_t)cs] != S)
+            ++cs;
+        if (cs == p.nc)
+            return fail(SW_EINVAL, "internal error: no chunk holds the score");
+        const int64_t kc = cs / A.gc, c_org = kc * A.gc;
+        a.b_org = 0;
+        a.top_ckpt = nullptr;
+        a.dir = nullptr;
+        a.end_key = end_key;
+        HIPCHK(launch_block_init(a, 0, kc, p.nb - 1, c_org, cs, stream));
+        rc = pair_diagonals(a, PairPass::kTrace, 8, elem, 0, p.nb - 1, c_org, cs, stream);
+        if (rc) return rc;
+    }
+    HIPCHK(launch_walk_init(end_key, &o->score, walk, stream));
+    WalkState st{};
+    HIPCHK(hipMemcpyAsync(&st, walk, sizeof st, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    a.end_key = spare_key;        // block passes look for no end cell
+    a.dir = dir;
+    while (!st.done) {
+        const int64_t row = st.i - 1, col = st.j - 1;
+        const int64_t kb = row / (A.gb * kBandRows), kc = col / (A.gc * p.wc);
+        const int64_t b_org = kb * A.gb, b_hi = row / kBandRows, c_org = kc * A.gc, c_hi = col / p.wc;
+        a.b_org = (int32_t)b_org;
+        a.top_ckpt = kb > 0 ? ckrow + (kb - 1) * A.row_stride : nullptr;
+        a.dir_col0 = c_org * p.wc;
+        a.dir_rb0 = (int32_t)(b_org * p.K);
+        a.dir_stride = (b_hi - b_org + 1) * p.K;
+        HIPCHK(launch_block_init(a, kb, kc, b_hi, c_org, c_hi, stream));
+        rc = pair_diagonals(a, PairPass::kTrace, 8, elem, b_org, b_hi, c_org, c_hi, stream);
+        if (rc) return rc;
+        HIPCHK(launch_walk(dir, a.dir_stride, b_org * kBandRows, c_org * p.wc, (b_hi + 1) * kBandRows,
+                           (c_hi + 1) * p.wc, walk, ops, m + n, stream));
+        HIPCHK(hipMemcpyAsync(&st, walk, sizeof st, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        if (!st.done && st.i - 1 == row && st.j - 1 == col)
+            return fail(SW_EINVAL, "internal error: the traceback walk did not advance");
+    }
+    if (opt && opt->ev_search_end) HIPCHK(hipEventRecord(opt->ev_search_end, stream));
+    HIPCHK(launch_walk_finish(walk, &o->score, ops, o, stream));
+    return SW_OK;
 }
 
 }  // namespace
@@ -1658,11 +1821,9 @@ size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt)
 {
     std::string why;
     if (!validate_pair(m, n, opt, why)) { fail(SW_EINVAL, why); return 0; }
-    if (m * n > kAlignMaxCells) { fail(SW_EINVAL, "alignment matrix larger than 2^39 cells"); return 0; }
-    size_t t = pair_layout(m, n, nullptr).total + align_extra_bytes(m, n, nullptr);
+    size_t t = pair_layout(m, n, nullptr).total + 256 + align_layout(m, n, opt, nullptr).total;
     if (opt && opt->pair_cols > 8192)
-        t += (size_t)align_up((int64_t)opt->pair_cols * 9, 256) +
-             (size_t)ceil_div(std::max<int64_t>(m, 1), 512) * 64 * opt->pair_cols * 4;
+        t += (size_t)align_up((int64_t)opt->pair_cols * 9, 256);
     return t;
 }
 
@@ -1684,23 +1845,29 @@ int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     if (rc) return rc;
     const PairPlanC p = align_plan(m, n, cu, opt);
     const PairLayout L = pair_layout(m, n, &p);
-    const size_t dir_off = align_up(L.total, 256);
-    if (dir_off + align_extra_bytes(m, n, &p) > need)
+    const size_t x_off = align_up(L.total, 256);
+    const AlignLayout A = align_layout(m, n, opt, &p);
+    if (x_off + A.total > need)
         return fail(SW_EINVAL, "internal error: alignment layout exceeds the workspace size");
     uint8_t* w = static_cast<uint8_t*>(ws);
-    auto* dir = reinterpret_cast<uint32_t*>(w + dir_off);
-    auto* end_key = reinterpret_cast<unsigned long long*>(w + dir_off + align_extra_bytes(m, n, &p) - 256);
+    uint8_t* x = w + x_off;
     auto* o = reinterpret_cast<AlignOut*>(out);
     const int elem = (fit == kFitS8 || fit == kFitU8) ? 1 : 2;
+    if (align_blocked(m, n, opt))
+        return align_blocks(p, L, A, w, x, query, m, subject, n, sm, go, ge, elem, o, ops, opt, stream);
+    auto* dir = reinterpret_cast<uint32_t*>(x + A.dir);
+    auto* end_key = reinterpret_cast<unsigned long long*>(x + A.tail);
+    auto* walk = reinterpret_cast<WalkState*>(x + A.tail + 256);
     rc = pair_enqueue(p, L, w, query, m, subject, n, sm, go, ge, elem, &o->score, dir, end_key,
                       opt ? opt->ev_search_begin : nullptr, opt ? opt->ev_search_end : nullptr, stream);
     if (rc) return rc;
     if (m == 0 || n == 0) {
         HIPCHK(launch_trace_reset(end_key, stream));
-        HIPCHK(launch_traceback(dir, 1, end_key, &o->score, ops, 0, o, stream));
-        return SW_OK;
     }
-    HIPCHK(launch_traceback(dir, p.nb * p.K, end_key, &o->score, ops, m + n, o, stream));
+    HIPCHK(launch_walk_init(end_key, &o->score, walk, stream));
+    if (m > 0 && n > 0)
+        HIPCHK(launch_walk(dir, p.nb * p.K, 0, 0, INT64_MAX, INT64_MAX, walk, ops, m + n, stream));
+    HIPCHK(launch_walk_finish(walk, &o->score, ops, o, stream));
     return SW_OK;
 }
 

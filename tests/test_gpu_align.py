@@ -94,3 +94,59 @@ def test_alignment_beyond_2_32_cells():
     r = _gpu_align(a, a[500:], sm, go, ge)
     assert r == {"score": 99_500, "q_begin": 501, "s_begin": 1, "q_end": 100_000, "s_end": 99_500,
                  "ops": "M" * 99_500}
+
+
+# Blocked traceback: the score pass keeps checkpoint rows and columns, and the
+# direction codes are recomputed one block at a time along the walk.  Small
+# forced blocks put block edges (rows, columns, corners) across the paths;
+# the result must equal the oracle's exactly, as with whole-matrix codes.
+@pytest.mark.parametrize("block,wc", [(512, 0), (700, 64), (1024, 16), (1536, 512)])
+@pytest.mark.parametrize("m,n", [(2000, 2000), (1300, 3100), (3100, 900)])
+def test_blocked_dna_alignments(block, wc, m, n):
+    a, b = synth.dna_pair(m, n, seed=m + 7 * n + block, identity=0.72, indel_rate=0.03)
+    sm, go, ge = DNA
+    announce(f"align blocked block={block} cols={wc} m={m} n={n}")
+    assert _gpu_align(a, b, sm, go, ge, align_block=block, pair_cols=wc) == oracle.align(a, b, sm, go, ge)
+
+
+@pytest.mark.parametrize("go,ge", [(10, 2), (0, 3), (120, 1)])
+def test_blocked_protein_alignments(go, ge):
+    rng = np.random.default_rng(3 * go + ge)
+    sm = synth.blosum_style_matrix()
+    a = synth.residues(rng, 1800)
+    b = np.concatenate([synth.residues(rng, 300), synth.mutate(rng, a[200:1600], 0.55), synth.residues(rng, 200)])
+    announce(f"align blocked protein go={go} ge={ge}")
+    assert _gpu_align(a, b, sm, go, ge, align_block=512, pair_cols=64) == oracle.align(a, b, sm, go, ge)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_blocked_tie_heavy(seed):
+    rng = np.random.default_rng(200 + seed)
+    a = rng.integers(0, 2, int(rng.integers(600, 1400))).astype(np.uint8)
+    b = rng.integers(0, 2, int(rng.integers(600, 1400))).astype(np.uint8)
+    sm = synth.dna_matrix(1, -1)
+    go, ge = int(rng.integers(0, 2)), int(rng.integers(0, 2))
+    announce(f"align blocked ties seed={seed}")
+    assert _gpu_align(a, b, sm, go, ge, align_block=512, pair_cols=16) == oracle.align(a, b, sm, go, ge)
+
+
+def test_blocked_empty_and_zero():
+    sm, go, ge = DNA
+    empty = {"score": 0, "q_begin": 0, "s_begin": 0, "q_end": 0, "s_end": 0, "ops": ""}
+    a = np.zeros(700, np.uint8)
+    b = np.full(900, 1, np.uint8)
+    announce("align blocked empty")
+    assert _gpu_align(a, b, sm, go, ge, align_block=512) == empty
+    assert _gpu_align(a[:0], b, sm, go, ge, align_block=512) == empty
+
+
+def test_blocked_large_suffix():
+    """120,000 x 119,000 cells in 16,384-side blocks: the suffix matches on
+    one diagonal across 8 x 8 blocks (closed form)."""
+    sm, go, ge = DNA
+    rng = np.random.default_rng(8)
+    a = synth.residues(rng, 120_000, synth.DNA_FREQS)
+    announce("align blocked 120k vs suffix")
+    r = _gpu_align(a, a[1000:], sm, go, ge, align_block=16384)
+    assert r == {"score": 119_000, "q_begin": 1001, "s_begin": 1, "q_end": 120_000, "s_end": 119_000,
+                 "ops": "M" * 119_000}
