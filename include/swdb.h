@@ -334,7 +334,10 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
  * one pair, not only its score.  Two passes of the pair tiles (8 query rows
  * per lane, 64 lanes per band): the score, then the same cells again writing a
  * 4-bit direction code per cell and finding the end cell; one lane then walks
- * the codes back.  Tie-breaks (the paper gives none): the end is the first
+ * the codes back.  Beyond 2^35 cells (or with options.align_block) the score
+ * pass also keeps checkpoint rows and columns at block edges, and the codes
+ * are recomputed one block at a time along the walk; the alignment is the
+ * same.  Tie-breaks (the paper gives none): the end is the first
  * cell holding the score in column-major order (smallest subject position,
  * then smallest query position); walking back, the diagonal is taken before E
  * before F, a gap is opened (from H) rather than extended when both give its
@@ -348,24 +351,28 @@ typedef struct sw_alignment {
     int32_t n_ops;             /* operations written (-1: inconsistent codes)  */
 } sw_alignment;
 
-/* Workspace bytes sw_align_pair needs (0 on invalid input, or when m * n
-   exceeds 2^39 cells): the direction codes take half a byte per cell, so
-   the workspace is about m * n / 2 bytes (14 GB for 162K x 172K). */
+/* Workspace bytes sw_align_pair needs (0 on invalid input).  Whole-matrix
+   direction codes (m * n <= 2^35 and options.align_block = 0) take half a
+   byte per cell: about m * n / 2 bytes (14.6 GB for 162K x 172K).  Blocks of
+   side B take about 16 * m * n / B + B^2 / 2 bytes (2.8 GB for 1M x 1M with
+   B = 65536). */
 size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt);
 
 /*
  * Optimal local alignment of query[m] (rows) against subject[n] (columns).
  *   query, subject  device, uint8 codes (read modulo 32)
  *   subst_matrix    HOST, int32[32*32]; gap_open/extend as in sw_db_search
- *   opt             NULL or options (pair_cols; ev_search_begin/end around
- *                   the tile passes)
+ *   opt             NULL or options (pair_cols; align_block; ev_search_begin
+ *                   / end around the tile passes)
  *   workspace       device, >= sw_align_workspace_bytes(m, n, opt), 256-byte aligned
  *   out             device, one sw_alignment
  *   ops             device, char[m + n]: 'M' (query residue paired with a
  *                   subject residue), 'I' (query residue against a gap), 'D'
  *                   (subject residue against a gap), begin to end; out->n_ops
  *                   of them are written
- * Asynchronous on `stream`.  Returns SW_EINVAL, SW_ENOMEM or SW_EHIP.
+ * Asynchronous on `stream` with whole-matrix codes; with blocks the call
+ * reads the walk's position after each block and returns with the stream
+ * drained.  Returns SW_EINVAL, SW_ENOMEM or SW_EHIP.
  */
 int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n,
                   const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
