@@ -317,9 +317,15 @@ __global__ void __launch_bounds__(64) k_walk(const uint32_t* __restrict__ dir, i
             w0 = wd - (kWinWords - 4) > 0 ? wd - (kWinWords - 4) : 0;
             const int64_t cc = c0 + lane;
             if (cc <= col) {
+                // all loads in flight at once: clamped addresses, words past
+                // the column's end read as zero afterwards
+                uint32_t v[kWinWords];
 #pragma unroll
                 for (int k = 0; k < kWinWords; ++k)
-                    win[lane][k] = (w0 + k < stride) ? dir[cc * stride + w0 + k] : 0u;
+                    v[k] = dir[cc * stride + min(w0 + k, stride - 1)];
+#pragma unroll
+                for (int k = 0; k < kWinWords; ++k)
+                    win[lane][k] = (w0 + k < stride) ? v[k] : 0u;
             }
             __syncthreads();
         }
