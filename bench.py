@@ -300,71 +300,66 @@ def alignments(args, w, scores):
     each (score pass, direction-code pass, walk), one 50,000-base DNA pair
     against a homolog, the paper's smallest DNA pair (162K x 172K, codes for
     the whole matrix) and its 1M x 1M pair (codes recomputed block by block);
-    wall time per call."""
+    wall time per call.  ``args.align_legs`` selects among top, 50k, 162k, 1m."""
     import numpy as np
     import torch
 
     import paper_2412_08308_amd as swdb
     import synth
-    q = torch.from_numpy(w.queries[0]).cuda()
-    top = torch.topk(scores.to(torch.int64), 16).indices.cpu().numpy()
-    subs = [torch.from_numpy(np.ascontiguousarray(w.db.subject(int(i)))).cuda() for i in top]
-    ws = torch.empty(max(swdb.align_workspace_bytes(len(w.queries[0]), int(s.numel())) for s in subs),
-                     dtype=torch.uint8, device="cuda")
-    swdb.align_pair(q, subs[0], w.matrix, w.gap_open, w.gap_extend, workspace=ws)      # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = [swdb.align_pair(q, s, w.matrix, w.gap_open, w.gap_extend, workspace=ws) for s in subs]
-    dt = time.perf_counter() - t0
-    cells = len(w.queries[0]) * sum(int(s.numel()) for s in subs)
-    a, b = synth.dna_pair(50_000, 50_000, seed=11)
-    qa, qb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    legs = set(args.align_legs.split(","))
+    out = {}
     sm = synth.dna_matrix(synth.DNA_MATCH, synth.DNA_MISMATCH)
-    wsd = torch.empty(swdb.align_workspace_bytes(50_000, 50_000), dtype=torch.uint8, device="cuda")
-    swdb.align_pair(qa, qb, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND, workspace=wsd)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    r = swdb.align_pair(qa, qb, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND, workspace=wsd)
-    dt2 = time.perf_counter() - t1
-    del wsd
+    go, ge = synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND
+    if "top" in legs:
+        q = torch.from_numpy(w.queries[0]).cuda()
+        top = torch.topk(scores.to(torch.int64), 16).indices.cpu().numpy()
+        subs = [torch.from_numpy(np.ascontiguousarray(w.db.subject(int(i)))).cuda() for i in top]
+        ws = torch.empty(max(swdb.align_workspace_bytes(len(w.queries[0]), int(s.numel())) for s in subs),
+                         dtype=torch.uint8, device="cuda")
+        swdb.align_pair(q, subs[0], w.matrix, w.gap_open, w.gap_extend, workspace=ws)      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [swdb.align_pair(q, s, w.matrix, w.gap_open, w.gap_extend, workspace=ws) for s in subs]
+        dt = time.perf_counter() - t0
+        cells = len(w.queries[0]) * sum(int(s.numel()) for s in subs)
+        out["top_hits"] = {"alignments": len(subs), "ms_per_alignment": round(dt / len(subs) * 1e3, 2),
+                           "cells": cells,
+                           "best": {k: res[0][k] for k in ("score", "q_begin", "s_begin", "q_end", "s_end")},
+                           "best_ops": len(res[0]["ops"])}
+        del ws
+    if "50k" in legs:
+        a, b = synth.dna_pair(50_000, 50_000, seed=11)
+        qa, qb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        wsd = torch.empty(swdb.align_workspace_bytes(50_000, 50_000), dtype=torch.uint8, device="cuda")
+        swdb.align_pair(qa, qb, sm, go, ge, workspace=wsd)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = swdb.align_pair(qa, qb, sm, go, ge, workspace=wsd)
+        dt2 = time.perf_counter() - t1
+        del wsd
+        out["dna_50k"] = {"ms": round(dt2 * 1e3, 1), "gcups_two_passes": round(2 * 50_000 ** 2 / dt2 / 1e9, 1),
+                          "score": r["score"], "ops": len(r["ops"])}
     # the paper's smallest pairwise size (the pair of the pairwise leg): 2.8e10
-    # cells, 14 GB of direction codes; the operations are re-scored on the host
-    m, n = synth.DNA_PAIR_SIZES[0]
-    a, b = synth.dna_pair(m, n, seed=0)
-    qa, qb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
-    wsd = torch.empty(swdb.align_workspace_bytes(m, n), dtype=torch.uint8, device="cuda")
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    big = swdb.align_pair(qa, qb, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND, workspace=wsd)
-    dt3 = time.perf_counter() - t2
-    ws_gb = wsd.numel() / 1e9
-    del wsd
-    # the paper's 1M x 1M pair: whole-matrix codes would take 500 GB, so the
-    # codes are recomputed block by block (65536 x 65536) from checkpoints
-    m2, n2 = synth.DNA_PAIR_SIZES[2]
-    a2, b2 = synth.dna_pair(m2, n2, seed=2)
-    qa, qb = torch.from_numpy(a2).cuda(), torch.from_numpy(b2).cuda()
-    wsd = torch.empty(swdb.align_workspace_bytes(m2, n2), dtype=torch.uint8, device="cuda")
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    huge = swdb.align_pair(qa, qb, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND, workspace=wsd)
-    dt4 = time.perf_counter() - t3
-    ws2_gb = wsd.numel() / 1e9
-    del wsd
-    return {"top_hits": {"alignments": len(subs), "ms_per_alignment": round(dt / len(subs) * 1e3, 2),
-                         "cells": cells, "best": {k: res[0][k] for k in ("score", "q_begin", "s_begin", "q_end", "s_end")},
-                         "best_ops": len(res[0]["ops"])},
-            "dna_50k": {"ms": round(dt2 * 1e3, 1), "gcups_two_passes": round(2 * 50_000 ** 2 / dt2 / 1e9, 1),
-                        "score": r["score"], "ops": len(r["ops"])},
-            "dna_162k_x_172k": {"ms": round(dt3 * 1e3, 1), "cells": m * n, "workspace_gb": round(ws_gb, 1),
-                                "score": big["score"], "ops": len(big["ops"]),
-                                "begin": [big["q_begin"], big["s_begin"]], "end": [big["q_end"], big["s_end"]],
-                                "ops_rescore": ops_score(a, b, big, sm, synth.DNA_GAP_OPEN, synth.DNA_GAP_EXTEND)},
-            "dna_1m_x_1m_blocked": {"ms": round(dt4 * 1e3, 1), "cells": m2 * n2, "workspace_gb": round(ws2_gb, 2),
-                                    "score": huge["score"], "ops": len(huge["ops"]),
-                                    "begin": [huge["q_begin"], huge["s_begin"]], "end": [huge["q_end"], huge["s_end"]],
-                                    "ops_rescore": ops_score(a2, b2, huge, sm, synth.DNA_GAP_OPEN,
-                                                             synth.DNA_GAP_EXTEND)}}
+    # cells, 14 GB of direction codes; and its 1M x 1M pair, whose codes for the
+    # whole matrix would take 500 GB, recomputed block by block (65536 x 65536)
+    # from checkpoints.  The operations are re-scored on the host.
+    for leg, k, name in (("162k", 0, "dna_162k_x_172k"), ("1m", 2, "dna_1m_x_1m_blocked")):
+        if leg not in legs:
+            continue
+        m, n = synth.DNA_PAIR_SIZES[k]
+        a, b = synth.dna_pair(m, n, seed=k)
+        qa, qb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        wsd = torch.empty(swdb.align_workspace_bytes(m, n), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        big = swdb.align_pair(qa, qb, sm, go, ge, workspace=wsd)
+        dt3 = time.perf_counter() - t2
+        out[name] = {"ms": round(dt3 * 1e3, 1), "cells": m * n, "workspace_gb": round(wsd.numel() / 1e9, 2),
+                     "score": big["score"], "ops": len(big["ops"]),
+                     "begin": [big["q_begin"], big["s_begin"]], "end": [big["q_end"], big["s_end"]],
+                     "ops_rescore": ops_score(a, b, big, sm, go, ge)}
+        del wsd
+    return out
 
 
 def ops_score(a, b, r, sm, go, ge):
@@ -438,6 +433,8 @@ def main(argv=None):
     ap.add_argument("--planted-steps", type=int, default=3)
     ap.add_argument("--no-pair", action="store_true")
     ap.add_argument("--no-align", action="store_true")
+    ap.add_argument("--align-legs", default="top,50k,162k,1m",
+                    help="alignment cases: top (16 best hits), 50k, 162k, 1m (DNA pairs)")
     ap.add_argument("--pair-sizes", type=int, nargs="+", default=[0, 1, 2, 3, 4],
                     help="indices into the paper's DNA pair sizes (162Kx172K .. 7Mx5M)")
     ap.add_argument("--pair-steps", type=int, default=2)
