@@ -60,3 +60,49 @@ def test_pair_argument_checks():
         swdb.pair_workspace_bytes(1 << 25, 10)
     with pytest.raises(swdb.SwdbError):
         swdb.pair_plan(10, 10, swdb.options(pair_rows=32))
+
+
+def _a256(x):
+    return (x + 255) // 256 * 256
+
+
+def _align_extra(m, n, p, block):
+    """Workspace past the pair buffers for the alignment schedule p: whole-
+    matrix direction words, or checkpoint rows / columns, chunk maxima and one
+    block's direction words (8 rows x 64 lanes per band); then the end key and
+    walk state."""
+    nb, nc, wc = p["bands"], p["chunks"], p["cols"]
+    cols = nc * wc
+    if block == 0 and m * n <= 1 << 35:
+        return _a256(nb * 64 * cols * 4) + 512
+    B = block or 65536
+    gb, gc = -(-B // 512), -(-B // wc)
+    return (_a256((nb - 1) // gb * cols * 8) + _a256((nc - 1) // gc * nb * 512 * 8) + _a256(nc * 4)
+            + _a256(gb * 64 * gc * wc * 4) + 512)
+
+
+@pytest.mark.parametrize("m,n", [(3000, 4000), (162_000, 172_000), (1_000_000, 1_000_000), (7_000_000, 5_000_000)])
+def test_align_workspace_covers_every_tiling(m, n):
+    """sw_align_workspace_bytes bounds the alignment layout of every chunk width
+    the device's planner may pick (any CU count, any explicit width), for
+    whole-matrix codes and for blocks."""
+    for block in (0, 512, 700, 65536):
+        for wc in (0, 16, 512, 8192, 65536):
+            o = swdb.options(align_block=block, pair_cols=wc)
+            need = swdb.align_workspace_bytes(m, n, o)
+            for cu in (1, 32, 256, 1024):
+                p = swdb.pair_plan(m, n, swdb.options(pair_rows=8, max_lanes=64, pair_cols=wc), cu_count=cu)
+                assert (p["rows"], p["lanes"]) == (8, 64)
+                assert swdb.pair_workspace_bytes(m, n, o) + 256 + _align_extra(m, n, p, block) <= need, (block, wc, cu)
+
+
+def test_align_workspace_blocks_beyond_whole_matrix_codes():
+    # whole-matrix codes: half a byte per cell; blocks: checkpoints + one block
+    assert swdb.align_workspace_bytes(162_000, 172_000) > 162_000 * 172_000 // 2
+    assert swdb.align_workspace_bytes(1_000_000, 1_000_000) < 4 << 30
+    assert swdb.align_workspace_bytes(7_000_000, 5_000_000) < 24 << 30
+    small = swdb.align_workspace_bytes(3000, 4000, swdb.options(align_block=512))
+    assert small < swdb.align_workspace_bytes(3000, 4000)
+    for bad in (-1, (1 << 24) + 1):
+        with pytest.raises(swdb.SwdbError):
+            swdb.align_workspace_bytes(100, 100, swdb.options(align_block=bad))
