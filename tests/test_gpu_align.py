@@ -150,3 +150,28 @@ def test_blocked_large_suffix():
     r = _gpu_align(a, a[1000:], sm, go, ge, align_block=16384)
     assert r == {"score": 119_000, "q_begin": 1001, "s_begin": 1, "q_end": 120_000, "s_end": 119_000,
                  "ops": "M" * 119_000}
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_alignments(seed):
+    """Seeded sweep: sizes, signed matrices (symmetric or not), gap penalties,
+    whole-matrix or blocked codes and chunk widths drawn together; the whole
+    alignment must equal the oracle's."""
+    rng = np.random.default_rng(500 + seed)
+    m, n = int(rng.integers(1, 2600)), int(rng.integers(1, 2600))
+    if seed % 3 == 0:
+        sm = rng.integers(-128, 128, size=(32, 32)).astype(np.int32)
+        a = rng.integers(0, 32, m).astype(np.uint8)
+        b = rng.integers(0, 32, n).astype(np.uint8)
+    elif seed % 3 == 1:
+        sm, a = synth.blosum_style_matrix(), synth.residues(rng, m)
+        lo = int(rng.integers(0, m))
+        b = np.concatenate([synth.residues(rng, int(rng.integers(0, 400))),
+                            synth.mutate(rng, a[lo:], float(rng.uniform(0.4, 0.95)))])[:max(n, 1)]
+    else:
+        sm = synth.dna_matrix(int(rng.integers(1, 6)), -int(rng.integers(1, 6)))
+        a, b = synth.dna_pair(m, n, seed=seed, identity=float(rng.uniform(0.5, 0.95)), indel_rate=0.03)
+    go, ge = int(rng.integers(0, 40)), int(rng.integers(0, 8))
+    kw = dict(align_block=int(rng.choice([0, 512, 1100])), pair_cols=int(rng.choice([0, 16, 48, 256])))
+    announce(f"align random seed={seed} m={len(a)} n={len(b)} go={go} ge={ge} {kw}")
+    assert _gpu_align(a, b, sm, go, ge, **kw) == oracle.align(a, b, sm, go, ge)
