@@ -23,10 +23,15 @@ constexpr int kRescoreMaxWaves = 8; // wavefronts of a rescore workgroup, at mos
 constexpr int kFlagSortCap = 4096;   // overflow lists up to this length are sorted by cost
 constexpr int kI16Rows = 24;       // query rows per lane of the packed 16-bit variant
 
-// Bytes between the profile entries of consecutive residue codes inside a row
-// block: R entries of ES bytes, rounded up to a multiple of 16 with at least 8
-// spare bytes (16-byte aligned loads, codes spread over the LDS banks).
-__host__ __device__ constexpr int code_stride(int R, int ES) { return (R * ES + 8 + 15) / 16 * 16; }
+// Bytes between the profile entries of consecutive residue codes in one row
+// block: R entries of ES bytes plus at least 8 spare bytes, rounded up to an
+// odd number of 16-byte units (16-byte aligned loads; the reads of lanes with
+// different codes start on different LDS bank groups for every code
+// difference below 16 -- an even number of units aliased codes 8 apart).
+__host__ __device__ constexpr int code_stride(int R, int ES)
+{
+    return ((R * ES + 8 + 15) / 16 | 1) * 16;
+}
 
 // Work item (one wavefront).  meta = nsub | K << 16 | critical << 24 (K =
 // lanes per subject, 1..64, floor(64 / K) lane groups per wavefront; critical

@@ -223,12 +223,19 @@ double subject_cost(int64_t n, int K, int nbr, const Resolved& r)
 
 // Lane group size for a subject of length n: the cheapest (in swept cells per
 // subject) K whose per-lane work fits the target; if none fits, the K with the
-// least per-lane work.  K > nbr would only add idle row blocks.
+// least per-lane work.  K > nbr would only add idle row blocks.  A K with up
+// to twice the target's per-lane work is taken instead when it sweeps at
+// least kRelaxGain fewer cells per subject: typically the long subjects of a
+// short query, where the only group that fits (all row blocks in one pass)
+// leaves lanes idle (64 mod K) and half as large a group with two passes does
+// not.  Such items are few and, being large, run early in queue order.
+constexpr double kRelaxGain = 0.10;
+
 int choose_k(int64_t n, int nbr, const Resolved& r)
 {
     const int kmax = std::max(1, std::min(r.kmax, nbr));
-    int best = -1, shortest = 1;
-    double best_cost = 0;
+    int best = -1, shortest = 1, relaxed = -1;
+    double best_cost = 0, relaxed_cost = 0;
     int64_t best_lw = lane_work(n, 1, nbr, r.rows);
     for (int K = 1; K <= kmax; ++K) {
         const int64_t lw = lane_work(n, K, nbr, r.rows);
@@ -237,11 +244,17 @@ int choose_k(int64_t n, int nbr, const Resolved& r)
             best = K;
             best_cost = c;
         }
+        if (lw <= 2 * r.target && (relaxed < 0 || c < relaxed_cost)) {
+            relaxed = K;
+            relaxed_cost = c;
+        }
         if (lw < best_lw) {
             best_lw = lw;
             shortest = K;
         }
     }
+    if (best > 0 && relaxed > 0 && relaxed_cost <= (1.0 - kRelaxGain) * best_cost)
+        return relaxed;
     return best > 0 ? best : shortest;
 }
 

@@ -84,10 +84,12 @@ def test_q567_vs_200k_plan_padding():
     """Swept cells over real cells for the benchmark workload stay small (power-of-two
     groups alone gave 1.29 for int32 lanes): the
     lane-group size is chosen per subject length so that row blocks divide
-    evenly over the group (567 rows = 18 blocks of 32 or 36 of 16)."""
+    evenly over the group (567 rows = 18 blocks of 32 or 24 of 24), and a group
+    twice the per-item target is taken where the one that fits leaves lanes
+    idle (24-lane groups: 16 of 64 lanes; 1.091 -> 1.053 for packed lanes)."""
     db = swdb.Database.describe(_lengths("q567_vs_200k"))
     try:
-        for mode, spl, bound in (("i32", 1, 1.13), ("i16", 2, 1.12)):
+        for mode, spl, bound in (("i32", 1, 1.07), ("i16", 2, 1.07)):
             info = check_plan(db, [567], swdb.options(mode=mode), spl)
             eff = info["lane_cells"] * spl / info["cells"]
             assert eff < bound, (mode, eff)
