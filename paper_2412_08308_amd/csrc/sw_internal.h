@@ -24,13 +24,16 @@ constexpr int kFlagSortCap = 4096;   // overflow lists up to this length are sor
 constexpr int kI16Rows = 24;       // query rows per lane of the packed 16-bit variant
 
 // Bytes between the profile entries of consecutive residue codes in one row
-// block: R entries of ES bytes plus at least 8 spare bytes, rounded up to an
-// odd number of 16-byte units (16-byte aligned loads; the reads of lanes with
-// different codes start on different LDS bank groups for every code
-// difference below 16 -- an even number of units aliased codes 8 apart).
+// block: R entries of ES bytes plus at least 8 spare bytes, in 16-byte units
+// (aligned loads).  For the database search's row blocks (R * ES >= 24: 24 or
+// 32 rows), whose profile is staged in LDS, an odd number of units, so that
+// the reads of lanes with different codes start on different LDS bank groups
+// for every code difference below 16 (an even number aliased codes 8 apart).
+// The single-pair kernel's short row blocks read their profile through the
+// cache hierarchy, where a wider stride would only grow the footprint.
 __host__ __device__ constexpr int code_stride(int R, int ES)
 {
-    return ((R * ES + 8 + 15) / 16 | 1) * 16;
+    return (R * ES >= 24 ? ((R * ES + 8 + 15) / 16 | 1) : (R * ES + 8 + 15) / 16) * 16;
 }
 
 // Work item (one wavefront).  meta = nsub | K << 16 | critical << 24 (K =
