@@ -25,15 +25,18 @@ constexpr int kI16Rows = 24;       // query rows per lane of the packed 16-bit v
 
 // Bytes between the profile entries of consecutive residue codes in one row
 // block: R entries of ES bytes plus at least 8 spare bytes, in 16-byte units
-// (aligned loads).  For the database search's row blocks (R * ES >= 24: 24 or
-// 32 rows), whose profile is staged in LDS, an odd number of units, so that
-// the reads of lanes with different codes start on different LDS bank groups
-// for every code difference below 16 (an even number aliased codes 8 apart).
-// The single-pair kernel's short row blocks read their profile through the
-// cache hierarchy, where a wider stride would only grow the footprint.
+// (aligned loads).  For the database search's 8-bit row blocks (24 or 32
+// rows), whose profile is staged in LDS, an odd number of units, so that the
+// reads of lanes with different codes start on different LDS bank groups for
+// every code difference below 16 (an even number aliased codes 8 apart).
+// 16-bit row blocks keep the narrower stride: the wider one pushed the
+// 567-residue query's packed profile past the 64 KiB a workgroup stages in
+// LDS by default, and measured 4% slower.  The single-pair kernel's short row
+// blocks read their profile through the cache hierarchy, where a wider stride
+// would only grow the footprint.
 __host__ __device__ constexpr int code_stride(int R, int ES)
 {
-    return (R * ES >= 24 ? ((R * ES + 8 + 15) / 16 | 1) : (R * ES + 8 + 15) / 16) * 16;
+    return (ES == 1 && R >= 24 ? ((R + 8 + 15) / 16 | 1) : (R * ES + 8 + 15) / 16) * 16;
 }
 
 // Work item (one wavefront).  meta = nsub | K << 16 | critical << 24 (K =
