@@ -155,6 +155,13 @@ struct PairArgs {
     int32_t* chunk_max;
     int32_t b_org;
     const int2* top_ckpt;
+    // Skewed score pass: lane g of band b covers, in chunk c, columns
+    // [c*wc - b*kr - g, +wc) (kr: K rounded up to 16); carry[row block] holds
+    // (H - Go, F) of the lane's bottom row at its last column and the H - Go
+    // above that column, for the lane's next tile.  n_pad: bytes of subj.
+    int32_t kr;
+    int4* carry;                 // [nb * K]
+    int64_t n_pad;
 };
 
 // Alignment found by the traceback pass (device memory, written by the
@@ -207,7 +214,8 @@ int search_occupancy(Variant v, int waves, int lds_bytes);   // workgroups per C
 constexpr int kPairRowChoices[2] = {8, 16};
 hipError_t launch_pair_prep(const uint8_t* subj, int64_t n, int64_t n_pad, uint8_t* dst, int32_t* score,
                             const QueryDesc& qd, QueryDesc* qd_out, int64_t* qoff_out, hipStream_t st);
-hipError_t launch_pair_diag(const PairArgs& a, int rows, int elem, hipStream_t st);
+// The plain score pass over skewed tiles (one anti-diagonal of them).
+hipError_t launch_pair_skew(const PairArgs& a, int rows, int elem, hipStream_t st);
 // Traceback: the direction pass over one anti-diagonal (8 rows per lane, K =
 // 64), the end-key reset, and the single-lane walk that writes the alignment.
 hipError_t launch_trace_diag(const PairArgs& a, int elem, hipStream_t st);

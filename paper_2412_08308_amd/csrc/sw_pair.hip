@@ -16,7 +16,11 @@
 // pipeline fill steps leave its state alone), the group head reads the band's
 // top boundary from rowbuf, the tail writes the band's bottom row back into it,
 // and after the sweep every lane writes its rows of the chunk's last column
-// into colbuf.
+// into colbuf.  These rectangular tiles serve the passes that write direction
+// codes or checkpoints, whose layouts follow rows and columns; the plain score
+// pass runs skewed tiles without the pipeline fill (pair_skew_tile).
+#include <type_traits>
+
 #include "sw_device.h"
 
 namespace swdb {
@@ -239,10 +243,178 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
     }
 }
 
+// Score pass over skewed tiles.  Lane g of band b covers, in chunk c, the
+// columns [c*wc - b*kr - g, +wc) (kr = K rounded up to 16): a lane's row block
+// starts one column after the row block above it, as the DPP pipeline needs,
+// so every lane has a column on every step -- a tile has no pipeline fill or
+// drain -- and the head's first column is a multiple of 16.  Only columns in
+// [0, n) are computed.  Tile (b, c) reads the band above's bottom row from
+// rowbuf (written by tiles (b-1, c' <= c)), and its own lanes' state at the
+// end of tile (b, c-1): colbuf (H - Go and E per row) and carry (per row
+// block: H - Go and F of the bottom row at the lane's last column, which the
+// lane below takes on its first step, and the H - Go of the cell above the
+// lane's last column, its diagonal for the next column).  With kr >= K no two
+// tiles of one anti-diagonal touch the same rowbuf entry, and every entry a
+// tile reads is written on an earlier anti-diagonal and overwritten only on a
+// later one (checked with a model of this schedule against the oracle).
 template <int R, int ES>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_pair_diag(PairArgs a)
+__device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
 {
-    pair_tile<R, ES>(a, threadIdx.x & 63);
+    constexpr uint32_t CS = code_stride(R, ES);
+    constexpr uint32_t BS = kCodes * CS;
+    constexpr int NB = R * ES;
+    constexpr int NV = (NB + 15) / 16;
+
+    const int K = a.K;
+    const int nsubw = kWave / K;
+    const int sub = lane / K;
+    const int g = lane - sub * K;
+    const bool inb = sub < nsubw;
+    const int tile = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * nsubw) + (inb ? sub : 0);
+    const bool valid = inb && tile < a.ntiles;
+    const int b = a.b_lo + (valid ? tile : 0);
+    const int c = a.d - b;
+    const bool head = g == 0;
+    const int wc = a.wc;
+    const int n = (int)a.n;                                    // lengths are below 2^24
+    const int jh = c * wc - b * a.kr;                          // the head's first column
+    const int j0 = jh - g;                                     // this lane's first column
+    const int rb = b * K + g;
+    const int64_t row0 = (int64_t)rb * R;
+    const uint32_t pbase = (uint32_t)min(rb, a.nbr) * BS;
+    const int go = a.go, ge = a.ge;
+    const bool has_top = valid && b > 0;
+    const bool put_bottom = valid && g == K - 1 && b < a.nb - 1;
+    // this lane computed column j0 - 1 in tile (b, c - 1)
+    const bool has_left = valid && j0 >= 1 && j0 <= n;
+    int2* __restrict__ top = a.rowbuf;
+    int2* __restrict__ side = a.colbuf + row0;
+    const uint4* __restrict__ resp = reinterpret_cast<const uint4*>(a.subj);
+    const int nblk = (int)(a.n_pad >> 4);
+
+    int Y[R], E[R];
+    int ybot = -go, fbot = 0, ydiag = -go;
+    if (has_left) {
+#pragma unroll
+        for (int r = 0; r < R; r += 2) {
+            const int4 v = *reinterpret_cast<const int4*>(side + r);
+            Y[r] = v.x; E[r] = v.y; Y[r + 1] = v.z; E[r + 1] = v.w;
+        }
+        const int4 cv = a.carry[rb];
+        ybot = cv.x; fbot = cv.y; ydiag = cv.z;
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) { Y[r] = -go; E[r] = 0; }
+    }
+    int S = 0;
+
+    // every lane of the wave inside [0, n) on every step: no per-column predicate
+    const bool inner = !valid || (j0 >= 0 && j0 + wc <= n);
+    auto block_at = [&](int col) {            // 16 codes from column col (a multiple of 16)
+        const int i = col >> 4;
+        return (i >= 0 && i < nblk) ? resp[i] : pad16();
+    };
+
+    auto sweep = [&](auto edge) {
+        constexpr bool EDGE = decltype(edge)::value;
+        uint4 rv = head ? block_at(jh) : pad16();
+        int code = head ? (int)(rv.x & 0xffu) : ((valid && j0 >= 0 && j0 < n) ? (int)a.subj[j0] : kPad);
+        uint4 pv[NV];
+        ldprof<NB, false>(pv, a.prof, pbase + (uint32_t)code * CS);
+        for (int blk = 0; blk < wc; blk += 16) {
+            const uint4 rvn = head ? block_at(jh + blk + 16) : pad16();
+#pragma unroll 1
+            for (int k4 = 0; k4 < 4; ++k4) {
+                const int col0 = blk + 4 * k4;
+                const uint32_t w = rv.x;                      // codes of columns col0 .. col0 + 3
+                const uint32_t wn = k4 == 3 ? rvn.x : rv.y;   // col0 + 4 .. col0 + 7
+                rv = make_uint4(rv.y, rv.z, rv.w, 0u);
+                int ringY[4], ringF[4];
+                const int hc = jh + col0;                     // head's column, a multiple of 4
+                if (has_top && head && hc >= 0 && hc < n) {
+                    const int4* p4 = reinterpret_cast<const int4*>(top + hc);
+                    const int4 v0 = p4[0], v1 = p4[1];
+                    ringY[0] = v0.x; ringF[0] = v0.y; ringY[1] = v0.z; ringF[1] = v0.w;
+                    ringY[2] = v1.x; ringF[2] = v1.y; ringY[3] = v1.z; ringF[3] = v1.w;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) { ringY[k] = -go; ringF[k] = 0; }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    // shifts with the whole wave active; the values are pinned so
+                    // that no shift is folded into a select under a partial mask
+                    int cd = shr1(code), yd = shr1(ybot), fd = shr1(fbot);
+                    pin(cd);
+                    pin(yd);
+                    pin(fd);
+                    const uint32_t wsrc = u < 3 ? w : wn;
+                    const int shift = u < 3 ? 8 * (u + 1) : 0;
+                    const int cnext = head ? (int)((wsrc >> shift) & 0xffu) : cd;
+                    uint4 pvn[NV];
+                    ldprof<NB, false>(pvn, a.prof, pbase + (uint32_t)cnext * CS);
+                    const int j = j0 + col0 + u;              // this lane's column
+                    if (!EDGE || (j >= 0 && j < n)) {
+                        const int yt = head ? ringY[u] : yd;
+                        const int ft = head ? ringF[u] : fd;
+                        int dg = ydiag;
+                        ydiag = yt;
+                        int hup = yt, F = ft;
+                        int hprev = 0;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const int t = dg + pent<ES>(pv, r);
+                            const int e = imax3(E[r] - ge, Y[r], 0);
+                            F = max(F - ge, hup);
+                            const int h = imax3(t, e, F);
+                            if (r & 1) {
+                                S = imax3(S, hprev, h);
+                                pin(S);
+                            } else {
+                                hprev = h;
+                            }
+                            dg = Y[r];
+                            hup = h - go;
+                            Y[r] = hup;
+                            E[r] = e;
+                        }
+                        ybot = hup;
+                        fbot = F;
+                        if (put_bottom)
+                            top[j] = make_int2(ybot, fbot);
+                    }
+                    code = cnext;
+#pragma unroll
+                    for (int i = 0; i < NV; ++i)
+                        pv[i] = pvn[i];
+                }
+            }
+            rv = rvn;
+        }
+    };
+    if (__all(inner))
+        sweep(std::integral_constant<bool, false>{});
+    else
+        sweep(std::integral_constant<bool, true>{});
+
+    // state after this lane's last column, for tile (b, c + 1)
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < R; r += 2)
+            *reinterpret_cast<int4*>(side + r) = make_int4(Y[r], E[r], Y[r + 1], E[r + 1]);
+        a.carry[rb] = make_int4(ybot, fbot, ydiag, 0);
+    }
+    S = valid ? S : 0;
+    for (int k = 32; k >= 1; k >>= 1)
+        S = max(S, __shfl_xor(S, k));
+    if (lane == 0 && S > 0)
+        atomicMax(a.score, S);
+}
+
+template <int R, int ES>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_pair_skew(PairArgs a)
+{
+    pair_skew_tile<R, ES>(a, threadIdx.x & 63);
 }
 
 template <int ES>
@@ -529,22 +701,22 @@ hipError_t launch_pair_prep(const uint8_t* subj, int64_t n, int64_t n_pad, uint8
 }
 
 template <int R>
-void launch_pair_rows(const PairArgs& a, int elem, int blocks, hipStream_t st)
+void launch_skew_rows(const PairArgs& a, int elem, int blocks, hipStream_t st)
 {
     if (elem == 1)
-        hipLaunchKernelGGL((k_pair_diag<R, 1>), dim3(blocks), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_pair_skew<R, 1>), dim3(blocks), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL((k_pair_diag<R, 2>), dim3(blocks), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_pair_skew<R, 2>), dim3(blocks), dim3(256), 0, st, a);
 }
 
-hipError_t launch_pair_diag(const PairArgs& a, int rows, int elem, hipStream_t st)
+hipError_t launch_pair_skew(const PairArgs& a, int rows, int elem, hipStream_t st)
 {
     const int groups_per_wave = kWave / a.K;
     const int waves = (a.ntiles + groups_per_wave - 1) / groups_per_wave;
     const int blocks = (waves + 3) / 4;
     switch (rows) {
-    case 8: launch_pair_rows<8>(a, elem, blocks, st); break;
-    case 16: launch_pair_rows<16>(a, elem, blocks, st); break;
+    case 8: launch_skew_rows<8>(a, elem, blocks, st); break;
+    case 16: launch_skew_rows<16>(a, elem, blocks, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1344,13 +1344,21 @@ int sw_db_search(const uint8_t* query, int32_t qlen, const uint8_t* residues, co
 namespace {
 
 // Schedule of one pair: R query rows per lane, K lanes per band (K*R query
-// rows), wc columns per chunk.  Time model: anti-diagonal launches in order;
-// a launch's waves spread over the device's SIMDs, each wave's instructions
-// issued back to back (one wave64 VALU instruction per 4 cycles per SIMD),
-// times a factor fitted to MI355X measurements of this kernel: about 1.25
-// with 1.5 to 3 waves per SIMD, more with fewer (latency shows) or more (the
-// waves' profile and boundary lines no longer fit the caches); plus a fixed
-// cost per launch.  The candidate with the least total wins.
+// rows), wc columns per chunk.  The score pass runs skewed tiles: lane g of
+// band b covers, in chunk c, columns [c*wc - b*kr - g, +wc) with kr = K
+// rounded up to 16, so band b's chunks run from floor(b*kr / wc) (the first
+// with a column >= 0 for its head) to ceil((n + b*kr + K - 1) / wc) - 1 (the
+// last whose tail starts below n), and tile (b, c) is launched with
+// anti-diagonal b + c.  Time model (fitted to MI355X measurements of this
+// pass on DNA pairs of 162K x 172K to 7M x 5M cells, 8 and 16 rows, lane
+// groups of 2 to 64, chunks of 64 to 4096 columns; within 6% on those):
+// anti-diagonal launches in order, each lasting its busiest SIMD's time plus a
+// fixed cost.  A step (one column for every lane of a tile) costs a wave alone
+// on its SIMD a latency-bound time, about twice its VALU issue time plus a
+// share per lane group (boundary loads and stores); k waves sharing a SIMD
+// cost k times their issue time, 32% more per wave beyond three (their
+// profile and boundary lines no longer fit the caches), or the latency-bound
+// time if that is longer.  The candidate with the least total wins.
 struct PairPlanC {
     int R = 0, K = 0, wc = 0;
     int64_t nb = 0, nc = 0, nbr = 0;
@@ -1358,58 +1366,123 @@ struct PairPlanC {
 };
 
 constexpr int64_t kPairMaxCols = 1 << 20;
-constexpr double kPairLaunchS = 4e-6;
+constexpr double kPairLaunchS = 11e-6;      // fixed cost of a launch
+constexpr double kPairIssueCycles = 5.44;   // per VALU instruction of a wave sharing its SIMD
+constexpr double kPairGroupCycles = 57.7;   // per lane group of a wave and step
+constexpr double kPairCacheSlope = 0.316;   // per wave on a SIMD beyond three
+
+struct SkewGrid {
+    int64_t nb = 0, n = 0, K = 1, kr = 16, wc = 16;
+    int64_t c_lo(int64_t b) const { return b * kr / wc; }
+    int64_t c_hi(int64_t b) const { return ceil_div(n + b * kr + K - 1, wc) - 1; }
+    int64_t diagonals() const { return nb > 0 ? nb + c_hi(nb - 1) : 0; }
+};
+
+SkewGrid skew_grid(int64_t m, int64_t n, int R, int K, int wc)
+{
+    SkewGrid G;
+    G.nb = ceil_div(std::max<int64_t>(m, 1), (int64_t)K * R);
+    G.n = std::max<int64_t>(n, 1);
+    G.K = K;
+    G.kr = align_up(K, 16);
+    G.wc = wc;
+    return G;
+}
+
+// f(d, first band, tiles) for every anti-diagonal holding tiles: bands b with
+// b + c_lo(b) <= d <= b + c_hi(b), a contiguous range since both bounds grow
+// with b.
+template <class F>
+void skew_walk(const SkewGrid& G, F&& f)
+{
+    int64_t lo = 0, hi = -1;
+    const int64_t D = G.diagonals();
+    for (int64_t d = 0; d < D; ++d) {
+        while (lo < G.nb && lo + G.c_hi(lo) < d) ++lo;
+        while (hi + 1 < G.nb && hi + 1 + G.c_lo(hi + 1) <= d) ++hi;
+        if (hi >= lo) f(d, lo, hi - lo + 1);
+    }
+}
 
 // hot-loop VALU instructions per cell of the pair kernel by rows per lane
 // (counted in the gfx950 assembly of this code)
 double pair_instr_per_cell(int R)
 {
-    return R == 8 ? 10.8 : 9.66;
+    return R == 8 ? 9.97 : 8.98;
 }
 
-double pair_slowdown(double waves_per_simd)
+// cycles of one step of a wave alone on its SIMD, lane groups aside
+double pair_latency_cycles(int R)
 {
-    const double w = waves_per_simd;
-    if (w <= 1.0) return 1.45;
-    if (w <= 1.5) return 1.45 - 0.4 * (w - 1.0);
-    if (w <= 3.0) return 1.25;
-    return 1.25 + 0.28 * (w - 3.0);
+    return R == 8 ? 514.0 : 803.0;
 }
 
 double pair_time(int64_t m, int64_t n, int R, int K, int wc, int cu)
+{
+    const SkewGrid G = skew_grid(m, n, R, K, wc);
+    const double per_wave = (double)(kWave / K);
+    const double simds = 4.0 * std::max(cu, 1);
+    const double valu = pair_instr_per_cell(R) * R;               // per lane and step
+    const double lat = pair_latency_cycles(R) + kPairGroupCycles * per_wave;
+    double t = 0;
+    skew_walk(G, [&](int64_t, int64_t, int64_t tiles) {
+        const double k = std::ceil(std::ceil((double)tiles / per_wave) / simds);
+        const double issue = k * kPairIssueCycles * valu * (1.0 + kPairCacheSlope * std::max(0.0, k - 3.0));
+        t += (double)wc * std::max(lat, issue) / 2.4e9 + kPairLaunchS;
+    });
+    return t;
+}
+
+// The passes of an alignment that write direction codes or checkpoints run
+// rectangular tiles (lane g of a tile on column step - g, K - 1 steps of
+// pipeline fill): their chunk width is chosen with the model fitted to those
+// tiles on MI355X (launches of 4 us; a wave's VALU time, 1.45x alone on its
+// SIMD, 1.25x with 1.5 to 3 waves, 0.28x more per wave beyond; 10.8 VALU per
+// cell with 8 rows per lane).
+double pair_time_rect(int64_t m, int64_t n, int R, int K, int wc, int cu)
 {
     const int64_t nb = ceil_div(std::max<int64_t>(m, 1), (int64_t)K * R);
     const int64_t nc = ceil_div(std::max<int64_t>(n, 1), wc);
     const double per_wave = (double)(kWave / K);
     const double simds = 4.0 * std::max(cu, 1);
-    const double wave_s = R * (double)align_up(wc + K - 1, 4) * pair_instr_per_cell(R) * 4.0 / 2.4e9;
+    const double wave_s = R * (double)align_up(wc + K - 1, 4) * (R == 8 ? 10.8 : 9.66) * 4.0 / 2.4e9;
+    auto slowdown = [](double w) {
+        if (w <= 1.0) return 1.45;
+        if (w <= 1.5) return 1.45 - 0.4 * (w - 1.0);
+        if (w <= 3.0) return 1.25;
+        return 1.25 + 0.28 * (w - 3.0);
+    };
     // anti-diagonal d holds min(d + 1, lo, nb + nc - 1 - d) tiles: two ramps of
     // 1..lo-1 tiles and max(nb, nc) - lo + 1 diagonals of lo tiles
     const int64_t lo = std::min(nb, nc), hi = std::max(nb, nc);
     auto launch = [&](int64_t tiles) {
         const double w = std::ceil(tiles / per_wave) / simds;
-        return std::ceil(w) * wave_s * pair_slowdown(w);
+        return std::ceil(w) * wave_s * slowdown(w);
     };
     double t = (double)(hi - lo + 1) * launch(lo);
     for (int64_t tiles = 1; tiles < lo; ++tiles)
         t += 2 * launch(tiles);
-    return t + (double)(nb + nc - 1) * kPairLaunchS;
+    return t + (double)(nb + nc - 1) * 4e-6;
 }
 
-PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt)
+PairPlanC pair_plan_search(int64_t m, int64_t n, int cu, int fixR, int fixK, int fixW, bool rect)
 {
+    auto model = [&](int R, int K, int wc) {
+        return rect ? pair_time_rect(m, n, R, K, wc, cu) : pair_time(m, n, R, K, wc, cu);
+    };
     PairPlanC best;
     best.est_s = 1e300;
-    const int fixR = opt ? opt->pair_rows : 0;
-    const int fixK = opt ? opt->max_lanes : 0;
-    const int fixW = opt ? opt->pair_cols : 0;
     for (int R : kPairRowChoices) {
         if (fixR && R != fixR) continue;
+        // lane groups below a quarter of the query's row blocks (or of 64)
+        // only add launches and boundary traffic
+        int kmin = 1;
+        while (kmin < 16 && 4 * kmin < ceil_div(m, R)) kmin *= 2;
         for (int K : {1, 2, 4, 8, 16, 32, 64}) {
-            if (fixK && K != fixK) continue;
+            if (fixK ? K != fixK : K < kmin) continue;
             for (int wc : {64, 128, 256, 512, 1024, 2048, 4096, 8192}) {
                 if (fixW && wc != fixW) continue;
-                const double t = pair_time(m, n, R, K, wc, cu);
+                const double t = model(R, K, wc);
                 if (t < best.est_s) {
                     best.est_s = t;
                     best.R = R;
@@ -1423,7 +1496,7 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt)
         best.wc = fixW;
         best.R = fixR ? fixR : 16;
         best.K = fixK ? fixK : 64;
-        best.est_s = pair_time(m, n, best.R, best.K, best.wc, cu);
+        best.est_s = model(best.R, best.K, best.wc);
     }
     best.nb = ceil_div(std::max<int64_t>(m, 1), (int64_t)best.K * best.R);
     best.nc = ceil_div(std::max<int64_t>(n, 1), best.wc);
@@ -1431,19 +1504,54 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt)
     return best;
 }
 
+// The planner evaluates every candidate over its anti-diagonals (a few
+// milliseconds for the largest pairs); the last plans are kept, since callers
+// often repeat one pair size.  rect: plan for the rectangular tiles of an
+// alignment's code and checkpoint passes.
+PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool rect = false)
+{
+    struct Entry {
+        int64_t m = -1, n = -1;
+        int cu = 0, R = 0, K = 0, W = 0;
+        bool rect = false;
+        PairPlanC p;
+    };
+    static std::mutex mu;
+    static Entry cache[8];
+    static int next = 0;
+    const int fixR = opt ? opt->pair_rows : 0;
+    const int fixK = opt ? opt->max_lanes : 0;
+    const int fixW = opt ? opt->pair_cols : 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const Entry& e : cache)
+            if (e.m == m && e.n == n && e.cu == cu && e.R == fixR && e.K == fixK && e.W == fixW && e.rect == rect)
+                return e.p;
+    }
+    const PairPlanC p = pair_plan_search(m, n, cu, fixR, fixK, fixW, rect);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[next] = Entry{m, n, cu, fixR, fixK, fixW, rect, p};
+    next = (next + 1) % 8;
+    return p;
+}
+
 // Workspace of a pair, sized for every schedule (so the size does not depend
 // on the device or the matrix): padded subject, 16-bit profile, rowbuf,
-// colbuf, corners, profile descriptor and counters.
+// colbuf, carry, corners, profile descriptor and counters.  The columns of
+// rowbuf and the padded subject cover both tilings: rectangular tiles reach
+// nc * wc < n + wc, skewed ones n + K - 1 + wc.
 struct PairLayout {
-    size_t subj = 0, prof = 0, rowbuf = 0, colbuf = 0, corner = 0, qd = 0, qoff = 0, counters = 0, total = 0;
+    size_t subj = 0, prof = 0, rowbuf = 0, colbuf = 0, carry = 0, corner = 0, qd = 0, qoff = 0, counters = 0,
+           total = 0;
     int64_t n_pad = 0;
 };
 
-PairLayout pair_layout(int64_t m, int64_t n, const PairPlanC* p)
+PairLayout pair_layout(int64_t m, int64_t n, const PairPlanC* p, int64_t wc_max)
 {
     PairLayout L;
-    // without a plan: the bound over every schedule (rows per lane 8..32)
-    const int64_t cols = p ? p->nc * p->wc : align_up(n, 16) + 8192;
+    // without a plan: the bound over every schedule (chunk width up to wc_max)
+    const int64_t wc = p ? p->wc : wc_max;
+    const int64_t cols = align_up(n, 16) + 2 * wc + 128;
     int64_t prof = 0, rows_pad = 0, blocks = 0;
     for (int R : kPairRowChoices) {
         if (p && R != p->R) continue;
@@ -1461,8 +1569,16 @@ PairLayout pair_layout(int64_t m, int64_t n, const PairPlanC* p)
     L.prof = off; off += align_up(prof, 256);
     L.rowbuf = off; off += align_up(cols * (int64_t)sizeof(int2), 256);
     L.colbuf = off; off += align_up(rows_pad * (int64_t)sizeof(int2), 256);
+    L.carry = off; off += align_up((blocks + kWave) * (int64_t)sizeof(int4), 256);
     L.total = off;
     return L;
+}
+
+// The generic bound's widest chunk: every planner choice (at most 8192), or
+// an explicit width.
+int64_t pair_wc_max(const sw_options* opt)
+{
+    return std::max<int64_t>(8192, opt ? opt->pair_cols : 0);
 }
 
 int validate_pair(int64_t m, int64_t n, const sw_options* opt, std::string& why)
@@ -1492,13 +1608,9 @@ size_t sw_pair_workspace_bytes(int64_t m, int64_t n, const sw_options* opt)
 {
     std::string why;
     if (!validate_pair(m, n, opt, why)) { fail(SW_EINVAL, why); return 0; }
-    // the padded subject and rowbuf of the chosen schedule never exceed the
-    // generic bound: nc * wc < n + wc <= n + 8192 for planner choices, and an
-    // explicit pair_cols adds its own width
-    size_t t = pair_layout(m, n, nullptr).total;
-    if (opt && opt->pair_cols > 8192)
-        t += (size_t)align_up((int64_t)opt->pair_cols * 9, 256);
-    return t;
+    // every buffer of the chosen schedule's layout is at most its generic
+    // bound: its chunk width is at most pair_wc_max
+    return pair_layout(m, n, nullptr, pair_wc_max(opt)).total;
 }
 
 int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, sw_pair_stats* out)
@@ -1513,7 +1625,10 @@ int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, 
     out->cols = p.wc;
     out->bands = p.nb;
     out->chunks = p.nc;
-    out->launches = (m > 0 && n > 0) ? p.nb + p.nc - 1 : 0;
+    int64_t launches = 0;
+    if (m > 0 && n > 0)
+        skew_walk(skew_grid(m, n, p.R, p.K, p.wc), [&](int64_t, int64_t, int64_t) { ++launches; });
+    out->launches = launches;
     out->est_ms = p.est_s * 1e3;
     out->workspace = (int64_t)sw_pair_workspace_bytes(m, n, opt);
     return SW_OK;
@@ -1599,10 +1714,28 @@ int pair_setup(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint8_
     a.dir_stride = p.nb * p.K;
     a.m = m;
     a.n = n;
+    a.kr = align_up(p.K, 16);
+    a.carry = reinterpret_cast<int4*>(w + L.carry);
+    a.n_pad = L.n_pad;
     return SW_OK;
 }
 
-enum class PairPass { kScore, kScoreCkpt, kTrace };
+enum class PairPass { kScoreCkpt, kTrace };
+
+// The plain score pass: the anti-diagonals of skewed tiles, in order.
+int pair_skew_diagonals(PairArgs a, const PairPlanC& p, int elem, hipStream_t stream)
+{
+    hipError_t e = hipSuccess;
+    skew_walk(skew_grid(a.m, a.n, p.R, p.K, p.wc), [&](int64_t d, int64_t b_lo, int64_t tiles) {
+        if (e != hipSuccess) return;
+        a.d = (int32_t)d;
+        a.b_lo = (int32_t)b_lo;
+        a.ntiles = (int32_t)tiles;
+        e = launch_pair_skew(a, p.R, elem, stream);
+    });
+    HIPCHK(e);
+    return SW_OK;
+}
 
 // The anti-diagonal launches of one pass over bands [b0, b1] x chunks [c0, c1]
 // of the tile grid, in order on the stream.
@@ -1616,9 +1749,7 @@ int pair_diagonals(PairArgs a, PairPass kind, int R, int elem, int64_t b0, int64
         a.d = (int32_t)(dr + b0 + c0);
         a.b_lo = (int32_t)lo;
         a.ntiles = (int32_t)(hi - lo + 1);
-        if (kind == PairPass::kScore)
-            HIPCHK(launch_pair_diag(a, R, elem, stream));
-        else if (kind == PairPass::kScoreCkpt)
+        if (kind == PairPass::kScoreCkpt)
             HIPCHK(launch_pair_diag_ckpt(a, elem, stream));
         else
             HIPCHK(launch_trace_diag(a, elem, stream));
@@ -1642,7 +1773,7 @@ int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint
     a.dir = dir;
     a.end_key = end_key;
     if (ev0) HIPCHK(hipEventRecord(ev0, stream));
-    rc = pair_diagonals(a, PairPass::kScore, p.R, elem, 0, p.nb - 1, 0, p.nc - 1, stream);
+    rc = pair_skew_diagonals(a, p, elem, stream);
     if (rc) return rc;
     if (dir) {
         HIPCHK(launch_trace_reset(end_key, stream));
@@ -1664,7 +1795,7 @@ PairPlanC align_plan(int64_t m, int64_t n, int cu, const sw_options* opt)
     sw_options o = opt ? *opt : sw_options{};
     o.pair_rows = 8;
     o.max_lanes = 64;
-    return pair_plan(m, n, cu, &o);
+    return pair_plan(m, n, cu, &o, true);
 }
 
 bool align_blocked(int64_t m, int64_t n, const sw_options* opt)
@@ -1822,7 +1953,7 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     rc = device_cu(&cu);
     if (rc) return rc;
     const PairPlanC p = pair_plan(m, n, cu, opt);
-    const PairLayout L = pair_layout(m, n, &p);
+    const PairLayout L = pair_layout(m, n, &p, p.wc);
     if (L.total > need) return fail(SW_EINVAL, "internal error: pair layout exceeds the workspace size");
     const int elem = (fit == kFitS8 || fit == kFitU8) ? 1 : 2;
     return pair_enqueue(p, L, static_cast<uint8_t*>(ws), query, m, subject, n, sm, go, ge, elem, score_out,
@@ -1834,10 +1965,7 @@ size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt)
 {
     std::string why;
     if (!validate_pair(m, n, opt, why)) { fail(SW_EINVAL, why); return 0; }
-    size_t t = pair_layout(m, n, nullptr).total + 256 + align_layout(m, n, opt, nullptr).total;
-    if (opt && opt->pair_cols > 8192)
-        t += (size_t)align_up((int64_t)opt->pair_cols * 9, 256);
-    return t;
+    return pair_layout(m, n, nullptr, pair_wc_max(opt)).total + 256 + align_layout(m, n, opt, nullptr).total;
 }
 
 int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n, const int32_t* sm,
@@ -1857,7 +1985,7 @@ int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     rc = device_cu(&cu);
     if (rc) return rc;
     const PairPlanC p = align_plan(m, n, cu, opt);
-    const PairLayout L = pair_layout(m, n, &p);
+    const PairLayout L = pair_layout(m, n, &p, p.wc);
     const size_t x_off = align_up(L.total, 256);
     const AlignLayout A = align_layout(m, n, opt, &p);
     if (x_off + A.total > need)

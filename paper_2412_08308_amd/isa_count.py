@@ -46,20 +46,25 @@ VARIANTS = {
     "i16_p8_self_glb": ("isa_i16_selfILi24ELi1ELb0E", 24, 2),
     "rescore_i32_r24": ("k_rescoreILi24ELi2E", 24, 1),
     "rescore_i32_r24_p8": ("k_rescoreILi24ELi1E", 24, 1),
-    # single long pair (csrc/sw_pair.hip): R rows per lane, 8- / 16-bit profile
-    "pair_r8_p8": ("k_pair_diagILi8ELi1E", 8, 1),
-    "pair_r8_p16": ("k_pair_diagILi8ELi2E", 8, 1),
-    "pair_r16_p8": ("k_pair_diagILi16ELi1E", 16, 1),
-    "pair_r16_p16": ("k_pair_diagILi16ELi2E", 16, 1),
+    # single long pair (csrc/sw_pair.hip), score pass over skewed tiles: R rows
+    # per lane, 8- / 16-bit profile; the loop of tiles inside the matrix
+    "pair_r8_p8": ("k_pair_skewILi8ELi1E", 8, 1),
+    "pair_r8_p16": ("k_pair_skewILi8ELi2E", 8, 1),
+    "pair_r16_p8": ("k_pair_skewILi16ELi1E", 16, 1),
+    "pair_r16_p16": ("k_pair_skewILi16ELi2E", 16, 1),
 }
+# kernels with two copies of the hot loop (tiles at the matrix edge with a
+# per-column predicate, tiles inside without): count the copy inside
+INTERIOR = {"pair_r8_p8", "pair_r8_p16", "pair_r16_p8", "pair_r16_p16"}
 SOURCES = ["sw_isa_probe.hip", "sw_pair.hip", "sw_k_rescore.hip"]
 
 
-def _hot_loop(lines):
+def _hot_loop(lines, interior=False):
     """Lines of the blocks of the hot loop: of the loops in the function, the
     one whose own blocks (its header block and every block the compiler
     annotates as directly inside it, wherever they are placed; not the blocks
-    of loops nested in it) hold the most VALU instructions."""
+    of loops nested in it) hold the most VALU instructions.  interior: of the
+    loops holding at least 70% of that count, the one with the fewest."""
     blocks = []            # (label, annotation, start, end)
     starts = [i for i, ln in enumerate(lines) if re.match(r"^\.LBB\w+:", ln)]
     for n, i in enumerate(starts):
@@ -70,7 +75,7 @@ def _hot_loop(lines):
             ann.append(lines[k])
             k += 1
         blocks.append((lines[i].split(":")[0], " ".join(ann), i, end))
-    best, best_valu = [], -1
+    loops = []
     for hdr, ann, _, _ in blocks:
         m = re.search(r"Loop Header: Depth=(\d+)", ann)
         if not m:
@@ -80,10 +85,13 @@ def _hot_loop(lines):
         for label, ann2, i, end in blocks:
             if label == hdr or tag in ann2:
                 body.extend(lines[i:end])
-        valu = sum(1 for l in body if l.strip().startswith("v_"))
-        if valu > best_valu:
-            best, best_valu = body, valu
-    return best
+        loops.append((sum(1 for l in body if l.strip().startswith("v_")), body))
+    if not loops:
+        return []
+    top = max(v for v, _ in loops)
+    if interior:
+        return min((lp for lp in loops if lp[0] >= 0.7 * top), key=lambda lp: lp[0])[1]
+    return max(loops, key=lambda lp: lp[0])[1]
 
 
 def count(asm_text: str) -> dict:
@@ -93,7 +101,7 @@ def count(asm_text: str) -> dict:
         body = next((f for f in funcs if f.startswith("_Z") and frag in f.split(":")[0]), None)
         if body is None:
             continue
-        loop = _hot_loop(body.split("\n"))
+        loop = _hot_loop(body.split("\n"), key in INTERIOR)
         ins = [l.strip().split()[0] for l in loop
                if l.strip() and not l.strip().startswith((".", ";")) and not l.strip().endswith(":")]
         c = collections.Counter(ins)

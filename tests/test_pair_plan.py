@@ -5,6 +5,26 @@ import pytest
 import paper_2412_08308_amd as swdb
 import synth
 
+def _skew_chunks(b, n, K, wc):
+    """Chunks of band b in the skewed score pass: lane g of band b covers, in
+    chunk c, columns [c*wc - b*kr - g, +wc) with kr = K rounded up to 16; the
+    first chunk holds the head's column 0, the last the tail's column n - 1."""
+    kr = -(-K // 16) * 16
+    return range(b * kr // wc, -(-(n + b * kr + K - 1) // wc))
+
+
+def _skew_launches(m, n, R, K, wc):
+    """Anti-diagonals b + c holding at least one tile (band intervals merged)."""
+    nb = -(-m // (K * R))
+    count, end = 0, -1
+    for b in range(nb):
+        ch = _skew_chunks(b, n, K, wc)
+        lo, hi = b + ch.start, b + ch.stop - 1
+        count += max(0, hi - max(lo, end + 1) + 1)
+        end = max(end, hi)
+    return count
+
+
 @pytest.mark.parametrize("m,n", [(1, 1), (1, 5000), (5000, 1), (2047, 2049), (2048, 512), (20000, 15000)]
                          + synth.DNA_PAIR_SIZES)
 def test_pair_plan_covers_matrix(m, n):
@@ -12,9 +32,28 @@ def test_pair_plan_covers_matrix(m, n):
     R, K, wc = p["rows"], p["lanes"], p["cols"]
     assert R in (8, 16) and K in (1, 2, 4, 8, 16, 32, 64) and wc % 16 == 0
     assert p["bands"] == -(-m // (K * R)) and p["chunks"] == -(-n // wc)
-    assert p["launches"] == p["bands"] + p["chunks"] - 1
+    assert p["launches"] == _skew_launches(m, n, R, K, wc)
     assert p["workspace"] == swdb.pair_workspace_bytes(m, n) > 0
     assert p["est_ms"] > 0
+
+
+@pytest.mark.parametrize("n,K,wc", [(1, 1, 16), (5, 64, 16), (100, 2, 16), (1000, 64, 64), (777, 16, 48),
+                                    (4096, 8, 512), (33, 32, 16)])
+def test_skewed_tiles_cover_each_row_block_once(n, K, wc):
+    """Every lane's chunks of the skewed tiling cover columns 0..n-1 of its row
+    block exactly once, and the launch count matches the planner's for forced
+    tilings."""
+    for b in range(6):
+        for g in range(K):
+            seen = []
+            for c in _skew_chunks(b, n, K, wc):
+                lo = c * wc - b * (-(-K // 16) * 16) - g
+                seen.extend(j for j in range(lo, lo + wc) if 0 <= j < n)
+            assert seen == list(range(n)), (b, g)
+    for R in (8, 16):
+        m = 6 * K * R
+        o = swdb.options(pair_rows=R, max_lanes=K, pair_cols=wc)
+        assert swdb.pair_plan(m, n, o)["launches"] == _skew_launches(m, n, R, K, wc)
 
 
 def test_pair_plan_options_fix_the_tiling():
