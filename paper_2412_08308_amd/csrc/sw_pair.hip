@@ -310,36 +310,56 @@ __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
 
     // every lane of the wave inside [0, n) on every step: no per-column predicate
     const bool inner = !valid || (j0 >= 0 && j0 + wc <= n);
-    auto block_at = [&](int col) {            // 16 codes from column col (a multiple of 16)
-        const int i = col >> 4;
-        return (i >= 0 && i < nblk) ? resp[i] : pad16();
+    // 16 codes from column col (a multiple of 16), read by every lane of the
+    // group at its head's column (one address per group), the index clamped
+    // into the buffer; blocks outside it hold no column that is computed
+    auto block_at = [&](int col) { return resp[min(max(col >> 4, 0), nblk - 1)]; };
+
+    // The last lane's bottom row goes to rowbuf through a buffer store that
+    // every lane issues: the others aim past the buffer's range (n entries),
+    // where the hardware drops the store, at an offset that still lies in the
+    // workspace's spare rowbuf columns.  Without a branch around the store the
+    // compiler's count of outstanding memory operations is exact, so the wait
+    // for a profile load no longer includes the store issued just before it.
+    typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+    const __amdgpu_buffer_rsrc_t rows_out = __builtin_amdgcn_make_buffer_rsrc(top, (short)0, n * 8, 0x00020000);
+    const int sink = (n + 64) * 8;
+    // the band above's bottom row for the head, 4 columns per load pair, read
+    // by every lane of the group at the head's (clamped) column one group of 4
+    // steps ahead, so that no wait depends on a load just issued
+    auto ring_load = [&](int col, int4& v0, int4& v1) {
+        const int4* p4 = reinterpret_cast<const int4*>(top + max(col, 0));
+        v0 = p4[0];
+        v1 = p4[1];
     };
+
+    const int tmask = has_top ? -1 : 0;
 
     auto sweep = [&](auto edge) {
         constexpr bool EDGE = decltype(edge)::value;
-        uint4 rv = head ? block_at(jh) : pad16();
+        int4 rn0, rn1;
+        ring_load(jh, rn0, rn1);
+        uint4 rv = block_at(jh);
         int code = head ? (int)(rv.x & 0xffu) : ((valid && j0 >= 0 && j0 < n) ? (int)a.subj[j0] : kPad);
         uint4 pv[NV];
         ldprof<NB, false>(pv, a.prof, pbase + (uint32_t)code * CS);
         for (int blk = 0; blk < wc; blk += 16) {
-            const uint4 rvn = head ? block_at(jh + blk + 16) : pad16();
-#pragma unroll 1
+            const uint4 rvn = block_at(jh + blk + 16);
+            // the 16 steps of a residue block unrolled, so that every wait
+            // counts exactly the loads and stores issued after the one it needs
+#pragma unroll
             for (int k4 = 0; k4 < 4; ++k4) {
                 const int col0 = blk + 4 * k4;
                 const uint32_t w = rv.x;                      // codes of columns col0 .. col0 + 3
                 const uint32_t wn = k4 == 3 ? rvn.x : rv.y;   // col0 + 4 .. col0 + 7
                 rv = make_uint4(rv.y, rv.z, rv.w, 0u);
+                // (H - Go, F) of the band above, or the matrix's top border
                 int ringY[4], ringF[4];
-                const int hc = jh + col0;                     // head's column, a multiple of 4
-                if (has_top && head && hc >= 0 && hc < n) {
-                    const int4* p4 = reinterpret_cast<const int4*>(top + hc);
-                    const int4 v0 = p4[0], v1 = p4[1];
-                    ringY[0] = v0.x; ringF[0] = v0.y; ringY[1] = v0.z; ringF[1] = v0.w;
-                    ringY[2] = v1.x; ringF[2] = v1.y; ringY[3] = v1.z; ringF[3] = v1.w;
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) { ringY[k] = -go; ringF[k] = 0; }
-                }
+                ringY[0] = (rn0.x & tmask) | (-go & ~tmask); ringF[0] = rn0.y & tmask;
+                ringY[1] = (rn0.z & tmask) | (-go & ~tmask); ringF[1] = rn0.w & tmask;
+                ringY[2] = (rn1.x & tmask) | (-go & ~tmask); ringF[2] = rn1.y & tmask;
+                ringY[3] = (rn1.z & tmask) | (-go & ~tmask); ringF[3] = rn1.w & tmask;
+                ring_load(jh + col0 + 4, rn0, rn1);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     // shifts with the whole wave active; the values are pinned so
@@ -380,8 +400,8 @@ __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
                         }
                         ybot = hup;
                         fbot = F;
-                        if (put_bottom)
-                            top[j] = make_int2(ybot, fbot);
+                        const u32x2 v = {(unsigned)ybot, (unsigned)fbot};
+                        __builtin_amdgcn_raw_buffer_store_b64(v, rows_out, put_bottom ? j * 8 : sink, 0, 0);
                     }
                     code = cnext;
 #pragma unroll
@@ -411,8 +431,10 @@ __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
         atomicMax(a.score, S);
 }
 
+// 16-row lanes keep their state in up to 168 registers (three waves per SIMD,
+// more than long pairs put on one); 8-row lanes fit four
 template <int R, int ES>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_pair_skew(PairArgs a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 8 ? 4 : 3))) k_pair_skew(PairArgs a)
 {
     pair_skew_tile<R, ES>(a, threadIdx.x & 63);
 }

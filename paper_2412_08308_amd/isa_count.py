@@ -4,8 +4,8 @@ Compiles ``csrc/sw_isa_probe.hip`` (each hot-loop variant alone in a kernel,
 same flags as the library), ``csrc/sw_pair.hip`` and ``csrc/sw_k_rescore.hip``
 to AMD assembly of this build, finds each kernel's hot loop -- one trip sweeps
 four subject columns of R query rows, i.e. 4*R cells per lane (8*R for the
-packed 16-bit variant, two subjects per lane) -- and counts its instructions by
-class.  The VALU count per cell is the ISA operation count of the integer-VALU
+packed 16-bit variant, two subjects per lane; 16 columns for the pair kernel)
+-- and counts its instructions by class.  The VALU count per cell is the ISA operation count of the integer-VALU
 roofline.
 """
 from __future__ import annotations
@@ -56,6 +56,9 @@ VARIANTS = {
 # kernels with two copies of the hot loop (tiles at the matrix edge with a
 # per-column predicate, tiles inside without): count the copy inside
 INTERIOR = {"pair_r8_p8", "pair_r8_p16", "pair_r16_p8", "pair_r16_p16"}
+# subject columns one trip of the hot loop sweeps, where not four (the pair
+# kernel unrolls the 16 columns of a residue block)
+TRIP_COLS = {"pair_r8_p8": 16, "pair_r8_p16": 16, "pair_r16_p8": 16, "pair_r16_p16": 16}
 SOURCES = ["sw_isa_probe.hip", "sw_pair.hip", "sw_k_rescore.hip"]
 
 
@@ -105,7 +108,7 @@ def count(asm_text: str) -> dict:
         ins = [l.strip().split()[0] for l in loop
                if l.strip() and not l.strip().startswith((".", ";")) and not l.strip().endswith(":")]
         c = collections.Counter(ins)
-        cells = 4 * rows * per
+        cells = TRIP_COLS.get(key, 4) * rows * per
         valu = sum(v for k, v in c.items() if k.startswith("v_"))
         out[key] = {
             "valu_per_cell": round(valu / cells, 4),
