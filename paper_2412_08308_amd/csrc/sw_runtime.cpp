@@ -1351,14 +1351,15 @@ namespace {
 // last whose tail starts below n), and tile (b, c) is launched with
 // anti-diagonal b + c.  Time model (fitted to MI355X measurements of this
 // pass on DNA pairs of 162K x 172K to 7M x 5M cells, 8 and 16 rows, lane
-// groups of 2 to 64, chunks of 64 to 4096 columns; within 6% on those):
-// anti-diagonal launches in order, each lasting its busiest SIMD's time plus a
-// fixed cost.  A step (one column for every lane of a tile) costs a wave alone
-// on its SIMD a latency-bound time, about twice its VALU issue time plus a
-// share per lane group (boundary loads and stores); k waves sharing a SIMD
-// cost k times their issue time, 32% more per wave beyond three (their
-// profile and boundary lines no longer fit the caches), or the latency-bound
-// time if that is longer.  The candidate with the least total wins.
+// groups of 16 to 64, chunks of 64 to 4096 columns, and smaller pairs down to
+// 3,000 x 3,500; within 5% RMS on those): anti-diagonal launches in order,
+// each lasting its busiest SIMD's time plus a dispatch cost per wave.  A step (one column for every lane of a tile) costs
+// a wave alone on its SIMD a latency-bound time, about 1.2x its VALU issue
+// time plus a share per lane group (boundary loads and stores); k waves
+// sharing a SIMD cost k times their issue time, 8.3% more per wave beyond
+// three (their profile and boundary lines no longer fit the caches), or the
+// latency-bound time if that is longer.  The candidate with the least total
+// wins.
 struct PairPlanC {
     int R = 0, K = 0, wc = 0;
     int64_t nb = 0, nc = 0, nbr = 0;
@@ -1366,10 +1367,11 @@ struct PairPlanC {
 };
 
 constexpr int64_t kPairMaxCols = 1 << 20;
-constexpr double kPairLaunchS = 11e-6;      // fixed cost of a launch
-constexpr double kPairIssueCycles = 5.44;   // per VALU instruction of a wave sharing its SIMD
-constexpr double kPairGroupCycles = 57.7;   // per lane group of a wave and step
-constexpr double kPairCacheSlope = 0.316;   // per wave on a SIMD beyond three
+constexpr double kPairLaunchS = 2e-6;       // fixed cost of a launch
+constexpr double kPairWaveS = 1.17e-8;      // dispatch cost per wave of a launch
+constexpr double kPairIssueCycles = 4.60;   // per VALU instruction of a wave sharing its SIMD
+constexpr double kPairGroupCycles = 41.9;   // per lane group of a wave and step
+constexpr double kPairCacheSlope = 0.083;   // per wave on a SIMD beyond three
 
 struct SkewGrid {
     int64_t nb = 0, n = 0, K = 1, kr = 16, wc = 16;
@@ -1408,13 +1410,13 @@ void skew_walk(const SkewGrid& G, F&& f)
 // (counted in the gfx950 assembly of this code)
 double pair_instr_per_cell(int R)
 {
-    return R == 8 ? 9.97 : 8.98;
+    return R == 8 ? 9.80 : 8.91;
 }
 
 // cycles of one step of a wave alone on its SIMD, lane groups aside
 double pair_latency_cycles(int R)
 {
-    return R == 8 ? 514.0 : 803.0;
+    return R == 8 ? 386.0 : 627.0;
 }
 
 double pair_time(int64_t m, int64_t n, int R, int K, int wc, int cu)
@@ -1426,9 +1428,10 @@ double pair_time(int64_t m, int64_t n, int R, int K, int wc, int cu)
     const double lat = pair_latency_cycles(R) + kPairGroupCycles * per_wave;
     double t = 0;
     skew_walk(G, [&](int64_t, int64_t, int64_t tiles) {
-        const double k = std::ceil(std::ceil((double)tiles / per_wave) / simds);
+        const double waves = std::ceil((double)tiles / per_wave);
+        const double k = std::ceil(waves / simds);
         const double issue = k * kPairIssueCycles * valu * (1.0 + kPairCacheSlope * std::max(0.0, k - 3.0));
-        t += (double)wc * std::max(lat, issue) / 2.4e9 + kPairLaunchS;
+        t += (double)wc * std::max(lat, issue) / 2.4e9 + waves * kPairWaveS + kPairLaunchS;
     });
     return t;
 }
