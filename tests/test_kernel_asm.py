@@ -23,24 +23,44 @@ def _asm(unit, tmp_path):
     return out.read_text()
 
 
+def _full_mask_at(body, i, seen):
+    """Whether every path reaching line i of a kernel body arrives with the
+    whole wave active, judged from the nearest change of the execution mask
+    before it on each path: a restore (s_or_b64 / s_mov_b64 exec) or the
+    kernel's entry counts as full, a saveexec as narrowed.  At a label the
+    paths are its fall-through (unless the line before ends the flow) and
+    every branch to it; a label already under examination counts as full, the
+    other paths into the loop deciding."""
+    for k in range(i - 1, -1, -1):
+        u = body[k].strip()
+        if u.startswith(("s_or_b64 exec", "s_mov_b64 exec")):
+            return True
+        if "saveexec" in u:
+            return False
+        if u.startswith(".LBB") and u.split()[0].endswith(":"):
+            label = u.split(":")[0]
+            if label in seen:
+                return True
+            seen = seen | {label}
+            srcs = [n for n, ln in enumerate(body)
+                    if re.match(r"\s*s_(c)?branch\w*\s+" + re.escape(label) + r"\s*$", ln)]
+            prev = next((body[q].strip() for q in range(k - 1, -1, -1)
+                         if body[q].strip() and not body[q].strip().startswith(";")), "")
+            falls = not prev.startswith(("s_branch", "s_endpgm", "s_setpc"))
+            return all(_full_mask_at(body, n, seen) for n in srcs) and (not falls or _full_mask_at(body, k, seen))
+    return True
+
+
 def dpp_under_partial_exec(asm: str):
-    """(kernel, line) of each DPP move whose nearest preceding change of the
-    execution mask narrows it (a saveexec) or is a branch target, before any
-    restore of the full mask."""
+    """(kernel, line) of each DPP move that some path reaches with part of the
+    wave masked off (see _full_mask_at)."""
     found = []
     for name in re.findall(r"^(_ZN4swdb\w*):", asm, re.M):
         m = re.search(r"^" + re.escape(name) + r":.*?s_endpgm", asm, re.S | re.M)
         body = m.group(0).split("\n")
         for i, line in enumerate(body):
-            if "_dpp" not in line:
-                continue
-            for k in range(i - 1, max(0, i - 80), -1):
-                u = body[k].strip()
-                if u.startswith(("s_or_b64 exec", "s_mov_b64 exec")):
-                    break
-                if u.startswith(".LBB") or "saveexec" in u:
-                    found.append((name, line.strip()))
-                    break
+            if "_dpp" in line and not _full_mask_at(body, i, frozenset()):
+                found.append((name, line.strip()))
     return found
 
 
@@ -58,3 +78,20 @@ def test_scanner_flags_a_shift_in_a_branch():
                      ".LBB1_43:", "v_mov_b32_dpp v59, v59 wave_shr:1 row_mask:0xf bank_mask:0xf",
                      "s_or_b64 exec, exec, s[4:5]", "v_mov_b32_dpp v1, v1 wave_shr:1", "s_endpgm"])
     assert len(dpp_under_partial_exec(asm)) == 1
+
+
+def test_dpp_check_follows_paths():
+    """The checker flags a shift after a narrowing saveexec and a shift at a
+    label that some branch reaches with a narrowed mask, and passes a loop
+    header whose back edge restores the mask first."""
+    narrowed = ("_ZN4swdb1aEv:\n s_and_saveexec_b64 s[0:1], vcc\n v_mov_b32_dpp v1, v1 wave_shr:1\n"
+                " s_or_b64 exec, exec, s[0:1]\n s_endpgm\n")
+    assert len(dpp_under_partial_exec(narrowed)) == 1
+    loop_ok = ("_ZN4swdb1bEv:\n v_mov_b32 v1, 0\n.LBB0_1:\n v_mov_b32_dpp v1, v1 wave_shr:1\n"
+               " s_and_saveexec_b64 s[0:1], vcc\n v_add_u32 v2, v1, v2\n s_or_b64 exec, exec, s[0:1]\n"
+               " s_cbranch_scc1 .LBB0_1\n s_endpgm\n")
+    assert dpp_under_partial_exec(loop_ok) == []
+    loop_bad = ("_ZN4swdb1cEv:\n v_mov_b32 v1, 0\n.LBB0_1:\n v_mov_b32_dpp v1, v1 wave_shr:1\n"
+                " s_and_saveexec_b64 s[0:1], vcc\n v_add_u32 v2, v1, v2\n s_cbranch_scc1 .LBB0_1\n"
+                " s_or_b64 exec, exec, s[0:1]\n s_endpgm\n")
+    assert len(dpp_under_partial_exec(loop_bad)) == 1
