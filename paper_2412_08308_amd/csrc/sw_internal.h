@@ -162,6 +162,9 @@ struct PairArgs {
     int32_t kr;
     int4* carry;                 // [nb * K]
     int64_t n_pad;
+    // 64 bytes per wavefront of a launch: where lanes of no tile store their
+    // direction words (skewed trace pass)
+    uint8_t* sink;
 };
 
 // Alignment found by the traceback pass (device memory, written by the
@@ -214,8 +217,10 @@ int search_occupancy(Variant v, int waves, int lds_bytes);   // workgroups per C
 constexpr int kPairRowChoices[2] = {8, 16};
 hipError_t launch_pair_prep(const uint8_t* subj, int64_t n, int64_t n_pad, uint8_t* dst, int32_t* score,
                             const QueryDesc& qd, QueryDesc* qd_out, int64_t* qoff_out, hipStream_t st);
-// The plain score pass over skewed tiles (one anti-diagonal of them).
+// The plain score pass over skewed tiles (one anti-diagonal of them), and the
+// direction-code pass of an alignment with whole-matrix codes (8 rows per lane).
 hipError_t launch_pair_skew(const PairArgs& a, int rows, int elem, hipStream_t st);
+hipError_t launch_trace_skew(const PairArgs& a, int elem, hipStream_t st);
 // Traceback: the direction pass over one anti-diagonal (8 rows per lane, K =
 // 64), the end-key reset, and the single-lane walk that writes the alignment.
 hipError_t launch_trace_diag(const PairArgs& a, int elem, hipStream_t st);

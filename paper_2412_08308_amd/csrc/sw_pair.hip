@@ -257,9 +257,16 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
 // tiles of one anti-diagonal touch the same rowbuf entry, and every entry a
 // tile reads is written on an earlier anti-diagonal and overwritten only on a
 // later one (checked with a model of this schedule against the oracle).
-template <int R, int ES>
+//
+// TRACE (8 rows per lane, whole-matrix direction codes): also write each
+// cell's direction code into dir and find the first cell, in column-major
+// order, holding the score of the plain pass, as the rectangular tiles do;
+// lanes of no tile write their words into their wave's sink slot, so that the
+// store needs no branch either.
+template <int R, int ES, bool TRACE = false>
 __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
 {
+    static_assert(!TRACE || R == 8, "direction words hold 8 rows");
     constexpr uint32_t CS = code_stride(R, ES);
     constexpr uint32_t BS = kCodes * CS;
     constexpr int NB = R * ES;
@@ -307,6 +314,10 @@ __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
         for (int r = 0; r < R; ++r) { Y[r] = -go; E[r] = 0; }
     }
     int S = 0;
+    const int s_target = TRACE ? *a.score : 0;
+    unsigned long long key = ~0ull;          // first cell holding s_target (TRACE)
+    uint32_t* const dsink =
+        reinterpret_cast<uint32_t*>(a.sink + (int64_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64);
 
     // every lane of the wave inside [0, n) on every step: no per-column predicate
     const bool inner = !valid || (j0 >= 0 && j0 + wc <= n);
@@ -381,12 +392,21 @@ __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
                         ydiag = yt;
                         int hup = yt, F = ft;
                         int hprev = 0;
+                        uint32_t word = 0, hits = 0;
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const int t = dg + pent<ES>(pv, r);
-                            const int e = imax3(E[r] - ge, Y[r], 0);
-                            F = max(F - ge, hup);
+                            const int eo = E[r] - ge;
+                            const int e = imax3(eo, Y[r], 0);
+                            const int fo = F - ge;
+                            F = max(fo, hup);
                             const int h = imax3(t, e, F);
+                            if constexpr (TRACE) {
+                                uint32_t cc = h == 0 ? 0u : (h == t ? 1u : (h == e ? 2u : 3u));
+                                cc |= (Y[r] >= eo ? 4u : 0u) | (hup >= fo ? 8u : 0u);
+                                word |= cc << (4 * r);
+                                hits |= (h == s_target ? 1u : 0u) << r;
+                            }
                             if (r & 1) {
                                 S = imax3(S, hprev, h);
                                 pin(S);
@@ -402,6 +422,13 @@ __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
                         fbot = F;
                         const u32x2 v = {(unsigned)ybot, (unsigned)fbot};
                         __builtin_amdgcn_raw_buffer_store_b64(v, rows_out, put_bottom ? j * 8 : sink, 0, 0);
+                        if constexpr (TRACE) {
+                            *((valid && a.dir) ? a.dir + ((int64_t)j - a.dir_col0) * a.dir_stride + (rb - a.dir_rb0)
+                                               : dsink) = word;
+                            const int64_t row = row0 + (hits ? __builtin_ctz(hits) : 0);
+                            const bool first = valid && hits && key == ~0ull && row < a.m;
+                            key = first ? ((unsigned long long)j << 32) | (unsigned long long)row : key;
+                        }
                     }
                     code = cnext;
 #pragma unroll
@@ -424,6 +451,15 @@ __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
             *reinterpret_cast<int4*>(side + r) = make_int4(Y[r], E[r], Y[r + 1], E[r + 1]);
         a.carry[rb] = make_int4(ybot, fbot, ydiag, 0);
     }
+    if constexpr (TRACE) {
+        for (int k = 32; k >= 1; k >>= 1) {
+            const unsigned long long o = __shfl_xor(key, k);
+            key = o < key ? o : key;
+        }
+        if (lane == 0 && key != ~0ull)
+            atomicMin(a.end_key, key);
+        return;
+    }
     S = valid ? S : 0;
     for (int k = 32; k >= 1; k >>= 1)
         S = max(S, __shfl_xor(S, k));
@@ -437,6 +473,13 @@ template <int R, int ES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 8 ? 4 : 3))) k_pair_skew(PairArgs a)
 {
     pair_skew_tile<R, ES>(a, threadIdx.x & 63);
+}
+
+// the direction codes and the end-cell search take about 175 registers
+template <int ES>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_trace_skew(PairArgs a)
+{
+    pair_skew_tile<8, ES, true>(a, threadIdx.x & 63);
 }
 
 template <int ES>
@@ -729,6 +772,18 @@ void launch_skew_rows(const PairArgs& a, int elem, int blocks, hipStream_t st)
         hipLaunchKernelGGL((k_pair_skew<R, 1>), dim3(blocks), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((k_pair_skew<R, 2>), dim3(blocks), dim3(256), 0, st, a);
+}
+
+hipError_t launch_trace_skew(const PairArgs& a, int elem, hipStream_t st)
+{
+    const int groups_per_wave = kWave / a.K;
+    const int waves = (a.ntiles + groups_per_wave - 1) / groups_per_wave;
+    const int blocks = (waves + 3) / 4;
+    if (elem == 1)
+        hipLaunchKernelGGL((k_trace_skew<1>), dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_trace_skew<2>), dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_pair_skew(const PairArgs& a, int rows, int elem, hipStream_t st)

@@ -1540,12 +1540,12 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool re
 
 // Workspace of a pair, sized for every schedule (so the size does not depend
 // on the device or the matrix): padded subject, 16-bit profile, rowbuf,
-// colbuf, carry, corners, profile descriptor and counters.  The columns of
+// colbuf, carry, store sinks, corners, profile descriptor and counters.  The columns of
 // rowbuf and the padded subject cover both tilings: rectangular tiles reach
 // nc * wc < n + wc, skewed ones n + K - 1 + wc.
 struct PairLayout {
-    size_t subj = 0, prof = 0, rowbuf = 0, colbuf = 0, carry = 0, corner = 0, qd = 0, qoff = 0, counters = 0,
-           total = 0;
+    size_t subj = 0, prof = 0, rowbuf = 0, colbuf = 0, carry = 0, sink = 0, corner = 0, qd = 0, qoff = 0,
+           counters = 0, total = 0;
     int64_t n_pad = 0;
 };
 
@@ -1573,6 +1573,7 @@ PairLayout pair_layout(int64_t m, int64_t n, const PairPlanC* p, int64_t wc_max)
     L.rowbuf = off; off += align_up(cols * (int64_t)sizeof(int2), 256);
     L.colbuf = off; off += align_up(rows_pad * (int64_t)sizeof(int2), 256);
     L.carry = off; off += align_up((blocks + kWave) * (int64_t)sizeof(int4), 256);
+    L.sink = off; off += align_up((blocks + kWave) * 64, 256);     // a launch has at most nb + 3 waves
     L.total = off;
     return L;
 }
@@ -1720,13 +1721,15 @@ int pair_setup(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint8_
     a.kr = align_up(p.K, 16);
     a.carry = reinterpret_cast<int4*>(w + L.carry);
     a.n_pad = L.n_pad;
+    a.sink = w + L.sink;
     return SW_OK;
 }
 
 enum class PairPass { kScoreCkpt, kTrace };
 
-// The plain score pass: the anti-diagonals of skewed tiles, in order.
-int pair_skew_diagonals(PairArgs a, const PairPlanC& p, int elem, hipStream_t stream)
+// A pass over skewed tiles: the anti-diagonals in order; the plain score pass
+// or (trace) the direction-code pass of whole-matrix codes.
+int pair_skew_diagonals(PairArgs a, const PairPlanC& p, int elem, hipStream_t stream, bool trace = false)
 {
     hipError_t e = hipSuccess;
     skew_walk(skew_grid(a.m, a.n, p.R, p.K, p.wc), [&](int64_t d, int64_t b_lo, int64_t tiles) {
@@ -1734,7 +1737,7 @@ int pair_skew_diagonals(PairArgs a, const PairPlanC& p, int elem, hipStream_t st
         a.d = (int32_t)d;
         a.b_lo = (int32_t)b_lo;
         a.ntiles = (int32_t)tiles;
-        e = launch_pair_skew(a, p.R, elem, stream);
+        e = trace ? launch_trace_skew(a, elem, stream) : launch_pair_skew(a, p.R, elem, stream);
     });
     HIPCHK(e);
     return SW_OK;
@@ -1780,7 +1783,7 @@ int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint
     if (rc) return rc;
     if (dir) {
         HIPCHK(launch_trace_reset(end_key, stream));
-        rc = pair_diagonals(a, PairPass::kTrace, p.R, elem, 0, p.nb - 1, 0, p.nc - 1, stream);
+        rc = pair_skew_diagonals(a, p, elem, stream, true);
         if (rc) return rc;
     }
     if (ev1) HIPCHK(hipEventRecord(ev1, stream));
