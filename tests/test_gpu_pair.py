@@ -46,6 +46,21 @@ def test_tilings(R, K, wc):
     assert _gpu_pair(a, b, sm, go, ge, pair_rows=R, max_lanes=K, pair_cols=wc) == exp
 
 
+@pytest.mark.parametrize("m,n", [(1, 700), (700, 1), (7, 3), (600, 20), (20, 600), (513, 17), (17, 513),
+                                 (1100, 1030)])
+@pytest.mark.parametrize("R,K,wc", [(8, 1, 16), (8, 64, 16), (16, 64, 32), (16, 4, 48), (8, 16, 128)])
+def test_skewed_tile_edges(m, n, R, K, wc):
+    """Skewed tiles at the matrix's edges: sequences shorter than a band or a
+    chunk, very unequal lengths, chunks narrower than the band-to-band skew
+    (K = 64 with 16 columns: several chunks of a band lie wholly left of
+    column 0), and lane groups below 16 (the skew is rounded up to 16)."""
+    a, b = synth.dna_pair(m, n, seed=3 * m + n, identity=0.8, indel_rate=0.03)
+    sm, go, ge = DNA
+    exp = oracle_pair(a, b, sm, go, ge)
+    announce(f"pair skewed edges m={m} n={n} R={R} K={K} cols={wc}")
+    assert _gpu_pair(a, b, sm, go, ge, pair_rows=R, max_lanes=K, pair_cols=wc) == exp
+
+
 @pytest.mark.parametrize("go,ge", [(10, 2), (0, 3), (3, 5), (120, 1)])
 def test_protein_pairs_profile_widths(go, ge):
     # (10, 2) and (0, 3): 8-bit profile entries; (120, 1): 16-bit (11 + 120 > 127)
