@@ -281,11 +281,14 @@ const char* sw_version(void);
  * Intra-task alignment (paper Section 2.2, Fig. 1; the pairwise DNA workload
  * of Section 4.1): the score of ONE pair, query `query[m]` along the rows and
  * subject `subject[n]` along the columns, with the whole device working on the
- * single matrix.  The matrix is tiled into bands of K*R query rows (R = 8 or 16 rows
- * per lane, K lanes pipelined per band, int32 lanes) by chunks of `cols`
- * subject columns; the tiles of each anti-diagonal run in one launch and pass
- * their boundary rows and columns to the next launch through the workspace.
- * Same recurrence, borders and result as sw_db_search; int32 score.
+ * single matrix.  The matrix is cut into bands of K*R query rows (R = 8 or 16
+ * rows per lane, K lanes pipelined per band, int32 lanes) and each band into
+ * chunks of `cols` subject columns, every lane's chunk starting one column
+ * after the row block above it (skewed tiles: lane g of band b covers columns
+ * [c*cols - b*kr - g, +cols) in chunk c, kr = K rounded up to 16); the tiles of
+ * each anti-diagonal b + c run in one launch and pass their boundary rows and
+ * columns to the next launch through the workspace.  Same recurrence, borders
+ * and result as sw_db_search; int32 score.
  */
 typedef struct sw_pair_stats {
     int32_t rows;          /* R: query rows per lane (8 or 16)                    */
@@ -294,7 +297,7 @@ typedef struct sw_pair_stats {
     int32_t pad;
     int64_t bands;         /* ceil(m / (R*K))                                     */
     int64_t chunks;        /* ceil(n / cols)                                      */
-    int64_t launches;      /* anti-diagonals: bands + chunks - 1                  */
+    int64_t launches;      /* anti-diagonals holding tiles (one launch each)      */
     double est_ms;         /* the planner's time model                            */
     int64_t workspace;     /* sw_pair_workspace_bytes                             */
 } sw_pair_stats;
@@ -319,8 +322,8 @@ int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, 
  *   workspace       device, >= sw_pair_workspace_bytes(m, n, opt), 256-byte aligned
  *   score_out       device, int32[1]
  * Asynchronous on `stream`; enqueues one preparation kernel, the profile
- * kernel and bands + chunks - 1 tile launches.  Returns SW_EINVAL, SW_ENOMEM
- * (workspace too small) or SW_EHIP.
+ * kernel and one tile launch per anti-diagonal (sw_pair_stats.launches).
+ * Returns SW_EINVAL, SW_ENOMEM (workspace too small) or SW_EHIP.
  */
 int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n,
                   const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
@@ -334,7 +337,9 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
  * one pair, not only its score.  Two passes of the pair tiles (8 query rows
  * per lane, 64 lanes per band): the score, then the same cells again writing a
  * 4-bit direction code per cell and finding the end cell; one lane then walks
- * the codes back.  Beyond 2^35 cells (or with options.align_block) the score
+ * the codes back.  With whole-matrix codes both passes run the skewed tiles;
+ * the passes of a blocked alignment run rectangular tiles (lane g on column
+ * step - g of its chunk), whose checkpoint columns and blocks follow columns.  Beyond 2^35 cells (or with options.align_block) the score
  * pass also keeps checkpoint rows and columns at block edges, and the codes
  * are recomputed one block at a time along the walk; the alignment is the
  * same.  Tie-breaks (the paper gives none): the end is the first
