@@ -256,7 +256,9 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
 // lane's last column, its diagonal for the next column).  With kr >= K no two
 // tiles of one anti-diagonal touch the same rowbuf entry, and every entry a
 // tile reads is written on an earlier anti-diagonal and overwritten only on a
-// later one (checked with a model of this schedule against the oracle).
+// later one (tests/test_skew_schedule.py steps through this schedule on the
+// CPU, checks each launch's reads against the same launch's writes, and
+// compares the scores with the oracle).
 //
 // TRACE (8 rows per lane, whole-matrix direction codes): also write each
 // cell's direction code into dir and find the first cell, in column-major
