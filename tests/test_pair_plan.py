@@ -145,3 +145,20 @@ def test_align_workspace_blocks_beyond_whole_matrix_codes():
     for bad in (-1, (1 << 24) + 1):
         with pytest.raises(swdb.SwdbError):
             swdb.align_workspace_bytes(100, 100, swdb.options(align_block=bad))
+
+
+def test_pair_plan_cache_keys_every_option():
+    """Plans are cached per (lengths, device size, forced options): repeated
+    calls agree, and a forced option never returns another call's plan."""
+    m, n = 543_000, 536_000
+    base = swdb.pair_plan(m, n, cu_count=256)
+    assert swdb.pair_plan(m, n, cu_count=256) == base
+    for R in (8, 16):
+        for K in (16, 64):
+            for wc in (128, 1024):
+                p = swdb.pair_plan(m, n, swdb.options(pair_rows=R, max_lanes=K, pair_cols=wc), cu_count=256)
+                assert (p["rows"], p["lanes"], p["cols"]) == (R, K, wc)
+    assert swdb.pair_plan(m, n, cu_count=256) == base
+    small = swdb.pair_plan(m, n, cu_count=32)
+    assert small["est_ms"] > base["est_ms"]        # fewer compute units: a slower plan
+    assert swdb.pair_plan(m, n, cu_count=256) == base
