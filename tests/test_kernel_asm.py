@@ -95,3 +95,20 @@ def test_dpp_check_follows_paths():
                 " s_and_saveexec_b64 s[0:1], vcc\n v_add_u32 v2, v1, v2\n s_cbranch_scc1 .LBB0_1\n"
                 " s_or_b64 exec, exec, s[0:1]\n s_endpgm\n")
     assert len(dpp_under_partial_exec(loop_bad)) == 1
+
+
+@pytest.mark.skipif(not shutil.which(HIPCC) and not os.path.exists(HIPCC), reason="hipcc not available")
+def test_hot_loop_counts_are_sane(tmp_path):
+    """The roofline's VALU-per-cell figures come from isa_count.py's choice of
+    hot loop; a change in the kernels' loop structure must not make it count a
+    fragment or the wrong copy (the ranges bracket the counted loops), and the
+    counted loops of the default variants keep their state in registers."""
+    from paper_2412_08308_amd import isa_count
+    r = isa_count.run(out=str(tmp_path / "counts.json"))
+    # the pair kernel's edge copy of its loop counts about 1 VALU per cell more
+    # than the copy inside the matrix: the pair bounds exclude it
+    bounds = {"i16_p8_lds_k1": (5.2, 6.2), "i16_p8_lds_kn": (5.2, 6.5), "i32_p8_lds_k1": (7.6, 8.8),
+              "pair_r8_p8": (9.3, 10.3), "pair_r16_p8": (8.5, 9.4), "rescore_i32_r24_p8": (8.3, 9.5)}
+    for key, (lo, hi) in bounds.items():
+        assert lo <= r[key]["valu_per_cell"] <= hi, (key, r[key])
+        assert r[key]["scratch"] == 0, (key, r[key])
