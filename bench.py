@@ -116,6 +116,41 @@ def traffic_bytes(mode: str):
     return {"bytes": int(fetch + write), "fetch_bytes": int(fetch), "write_bytes": int(write)}
 
 
+_DIGESTS = {}
+
+
+def digests():
+    """The oracle's digests of the full workloads (tests/golden/oracle_digests.json,
+    written by tests/golden/make_digests.py from oracle/ and synth/ only)."""
+    if not _DIGESTS:
+        path = os.path.join(ROOT, "tests", "golden", "oracle_digests.json")
+        if os.path.exists(path):
+            with open(path) as fh:
+                _DIGESTS.update(json.load(fh))
+    return _DIGESTS
+
+
+def digest_parity(name, rows, first_row=0):
+    """Compare GPU score rows (int32, caller's order) with the stored oracle
+    digests of workload ``name``: rows and 4,096-subject blocks that differ."""
+    import hashlib
+    import numpy as np
+    e = digests().get("workloads", {}).get(name)
+    if e is None:
+        return {"status": "no stored digests"}
+    bad_rows, bad_blocks, n = 0, 0, 0
+    for k, r in enumerate(rows):
+        want = e["rows"][first_row + k]
+        b = np.ascontiguousarray(np.asarray(r)).astype("<i4")
+        n += len(b)
+        if hashlib.sha256(b.tobytes()).hexdigest() != want["sha256"]:
+            bad_rows += 1
+            blk = e["block"]
+            bad_blocks += sum(hashlib.sha256(b[i:i + blk].tobytes()).hexdigest()[:16] != want["blocks"][i // blk]
+                              for i in range(0, len(b), blk))
+    return {"rows": len(rows), "scores": n, "rows_mismatched": bad_rows, "blocks_mismatched": bad_blocks}
+
+
 def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False):
     """Run warmup + steps searches; wall time per step and the search kernel's
     own time (HIP events recorded by the library around its launch)."""
@@ -134,9 +169,9 @@ def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False)
 
     def one(opt):
         if batch:
-            gdb.search_batch(qarg, sm, go, ge, opt=opt, out=out, workspace=ws)
+            gdb.search_batch(qarg, sm, go, ge, opt=opt, out=out, workspace=ws, check=False)
         else:
-            gdb.search(queries[0], sm, go, ge, opt=opt, out=out, workspace=ws)
+            gdb.search(queries[0], sm, go, ge, opt=opt, out=out, workspace=ws, check=False)
 
     for _ in range(warmup):
         one(base)
@@ -158,7 +193,8 @@ def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False)
     for _, e in evs:
         for x in e:
             ev.destroy(x)
-    flagged = gdb.flagged_count(ws) if mode != "i32" else 0
+    status = gdb.status(ws, raise_on_error=True)     # the last timed search's status words
+    flagged = status["flagged"]
     plan = gdb.plan_info(lens, base)
     plan["variant"] = swdb.select_variant(sm, go, base)   # plan_info reports the 16-bit sizing variant
     return dict(wall_ms=wall * 1e3, kernel_ms=sum(k) / len(k), kernel_min_ms=min(k),
@@ -177,17 +213,16 @@ def serving(args, capacity_gcups, mode):
 
     w5 = synth.workload("serve_500k", scale=args.serve_scale)
     gdb = swdb.Database.from_host(w5.db)
-    rng = np.random.default_rng(77)
     n = args.serve_requests
-    qlens = synth.lognormal_lengths(rng, n, 350, 0.75, 50, 5000)
-    qs = [synth.residues(rng, int(m)) for m in qlens]
+    qs = synth.serve_requests(n)
+    qlens = np.array([len(q) for q in qs])
     be = GpuBackend(gdb, w5.matrix, w5.gap_open, w5.gap_extend, mode=mode, n_streams=4, **KNOBS)
     with Server(be, max_batch=16) as srv:                    # warm-up: plans, allocator, code
         for f in [srv.submit(q) for q in qs[:8]]:
             f.result()
     torch.cuda.synchronize()
     mean_m = float(np.mean(qlens))
-    runs = []
+    runs, checks = [], []
     rate = capacity_gcups * 1e9
     for policy in args.serve_policies:
         arng = np.random.default_rng(78)          # the same arrival times for every policy
@@ -202,10 +237,16 @@ def serving(args, capacity_gcups, mode):
                 if dt > 0:
                     time.sleep(dt)
                 futs.append(srv.submit(q))
-            for f in futs:
-                f.result()
+            res = [f.result() for f in futs]
             srv.stop()
             st = srv.stats()
+            if args.serve_scale == 1.0:
+                # every score of the first requests against the oracle's digests,
+                # and a seeded sample of other requests on sampled subjects
+                nd = len(digests().get("workloads", {}).get("serve_500k", {}).get("rows", []))
+                checks.append(("digest", digest_parity("serve_500k", res[:nd])))
+                checks.append(("sample", sample_parity(w5.db, qs, res, w5.matrix, w5.gap_open, w5.gap_extend,
+                                                       seed=len(runs))))
             print(f"[bench] serving {policy} rho={rho}: p50 {st['p50_s'] * 1e3:.1f} ms p99 {st['p99_s'] * 1e3:.1f} ms",
                   file=sys.stderr, flush=True)
             runs.append({"policy": policy, "rho": rho, "rate_per_s": round(lam, 2), "requests": n,
@@ -213,9 +254,34 @@ def serving(args, capacity_gcups, mode):
                          "sustained_gcups": round(st["sustained_gcups"], 1),
                          "mean_batch": round(st["mean_batch"], 2), "max_batch": st["max_batch"]})
     gdb.release()
+    parity = None
+    if checks:
+        dg = [c for k, c in checks if k == "digest" and "rows" in c]
+        sp = [c for k, c in checks if k == "sample"]
+        parity = {"digest_requests": sum(c["rows"] for c in dg), "digest_rows_mismatched":
+                  sum(c["rows_mismatched"] for c in dg),
+                  "sampled_requests": sum(c["requests"] for c in sp),
+                  "sampled_scores": sum(c["scores"] for c in sp), "sample_mismatches": sum(c["mismatches"] for c in sp)}
     return {"workload": f"{w5.db.nseq} subjects ({w5.db.total} residues); {n} queries log-normal median 350 "
                         "clamped 50-5000; Poisson arrivals at rho x single-query capacity",
-            "capacity_gcups": round(capacity_gcups, 1), "runs": runs}
+            "capacity_gcups": round(capacity_gcups, 1), "runs": runs, "parity": parity}
+
+
+def sample_parity(db, qs, res, sm, go, ge, seed=0, nreq=6, nsub=64):
+    """The oracle on a seeded sample of requests, each on a seeded sample of
+    subjects (the longest ones included)."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(900 + seed)
+    reqs = rng.choice(len(qs), size=min(nreq, len(qs)), replace=False)
+    longest = np.argsort(-db.lengths, kind="stable")[:8]
+    bad, n = 0, 0
+    for k in reqs:
+        ids = np.unique(np.concatenate([longest, rng.choice(db.nseq, nsub, replace=False)]))
+        exp = oracle.search_db(qs[k], db, sm, go, ge, ids=ids)
+        bad += int(np.sum(np.asarray(res[k])[ids] != exp))
+        n += len(ids)
+    return {"requests": len(reqs), "scores": n, "mismatches": bad}
 
 
 def planted(args, ev):
@@ -231,13 +297,17 @@ def planted(args, ev):
     cells = len(w4.queries[0]) * w4.db.total
     a = timed_search(gdb, [q], w4.matrix, w4.gap_open, w4.gap_extend, "auto", args.planted_steps, 1, ev)
     b = timed_search(gdb, [q], w4.matrix, w4.gap_open, w4.gap_extend, "i32", args.planted_steps, 1, ev)
+    parity = None
+    if args.scale == 1.0:
+        parity = {"auto": digest_parity("q8000_planted_vs_200k", [a["out"].cpu().numpy()]),
+                  "i32": digest_parity("q8000_planted_vs_200k", [b["out"].cpu().numpy()])}
     gdb.release()
     return {"workload": f"query 8000 vs {w4.db.nseq} subjects ({w4.db.total} residues): 0.5% long "
                         "10,000-35,000, 1% near-homologs 30-90% identity",
             "i16_rescore_gcups": round(cells / (a["wall_ms"] / 1e3) / 1e9, 1),
             "i16_search_ms": round(a["kernel_ms"], 2), "rescore_ms": round(a["rescore_ms"], 2),
             "flagged": a["flagged"], "i32_gcups": round(cells / (b["wall_ms"] / 1e3) / 1e9, 1),
-            "i32_search_ms": round(b["kernel_ms"], 2), "cells": cells}
+            "i32_search_ms": round(b["kernel_ms"], 2), "cells": cells, "parity": parity}
 
 
 def pairwise(args, ev):
@@ -377,13 +447,62 @@ def ops_score(a, b, r, sm, go, ge):
     return total
 
 
+def paper_model(cells, kernel_s, variant):
+    """Algorithm 1's 12 operations per cell against the lane-operation peak of
+    the kernel's own arithmetic: 39.32 T 32-bit lane-ops/s for int32 lanes,
+    twice that for packed 16-bit lanes (each 32-bit lane-op carries two
+    16-bit operations)."""
+    lanes_per_op = 2 if variant in (2, 3) else 1
+    peak = PEAK_VALU_TOPS * lanes_per_op
+    achieved = cells * PAPER_OPS_PER_CELL / kernel_s / 1e12
+    return {"ops_per_cell": PAPER_OPS_PER_CELL, "achieved": round(achieved, 3), "peak": round(peak, 3),
+            "unit": "TOP/s", "frac": round(achieved / peak, 4),
+            "peak_gcups": round(peak * 1e3 / PAPER_OPS_PER_CELL, 1),
+            "peak_basis": "16-bit lane-ops (two per 32-bit lane)" if lanes_per_op == 2 else "32-bit lane-ops"}
+
+
+def timed_graph(gdb, queries, sm, go, ge, steps, ev):
+    """The batch as a captured HIP graph (sw_graph_create): one warm-up replay,
+    then ``steps`` replays timed by wall clock and by HIP events around each
+    replay on its stream."""
+    import numpy as np
+    import torch
+    import paper_2412_08308_amd as swdb
+    lens = [int(q.numel()) for q in queries]
+    cat = torch.cat([q.reshape(-1) for q in queries])
+    offs = np.concatenate([[0], np.cumsum(lens[:-1])]).astype(np.int64)
+    g = gdb.capture((cat, offs, lens), sm, go, ge, opt=swdb.options(mode="auto", **KNOBS))
+    s = torch.cuda.current_stream()
+    g.launch()
+    g.status()
+    pairs = [(ev.create(), ev.create()) for _ in range(steps)]
+    h = ev.h
+    h.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in pairs:
+        h.hipEventRecord(a, ctypes.c_void_p(s.cuda_stream))
+        g.launch()
+        h.hipEventRecord(b, ctypes.c_void_p(s.cuda_stream))
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    replay = sum(ev.ms(a, b) for a, b in pairs) / steps
+    for a, b in pairs:
+        ev.destroy(a)
+        ev.destroy(b)
+    g.status()
+    out = g.out.cpu().numpy()
+    g.destroy()
+    return {"wall_ms": wall * 1e3, "replay_ms": replay, "out": out}
+
+
 def cpu_baseline(w, seconds: float):
     """The oracle (plain C, int64, threads over subjects) on a random sample of
     the same database, sized for about ``seconds`` of host time."""
     import numpy as np
     import oracle
     q = w.queries[0]
-    threads = os.cpu_count() or 1
+    threads = min(16, len(os.sched_getaffinity(0)))      # the host cores this process may use (at most 16)
     rng = np.random.default_rng(123)
     n = w.db.nseq
     ids = rng.permutation(n)
@@ -396,7 +515,7 @@ def cpu_baseline(w, seconds: float):
     sel = ids[:want]
     cells = len(q) * int(w.db.lengths[sel].sum())
     t0 = time.perf_counter()
-    oracle.search_db(q, w.db, w.matrix, w.gap_open, w.gap_extend, ids=sel, threads=threads)
+    scores = oracle.search_db(q, w.db, w.matrix, w.gap_open, w.gap_extend, ids=sel, threads=threads)
     dt = time.perf_counter() - t0
     cpu = "unknown"
     try:
@@ -406,9 +525,9 @@ def cpu_baseline(w, seconds: float):
                 break
     except OSError:
         pass
-    return {"value": round(cells / dt / 1e9, 3), "unit": "GCUPS", "cores": threads, "kind": "oracle",
-            "sample": f"query 567 vs {want} of {n} subjects drawn at random ({cells:.3e} cells, {dt:.1f} s)",
-            "cpu": cpu, "calibration_gcups": round(rate / 1e9, 3)}
+    return ({"value": round(cells / dt / 1e9, 3), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+             "sample": f"query 567 vs {want} of {n} subjects drawn at random ({cells:.3e} cells, {dt:.1f} s)",
+             "cpu": cpu, "calibration_gcups": round(rate / 1e9, 3)}, sel, scores)
 
 
 def main(argv=None):
@@ -486,17 +605,15 @@ def main(argv=None):
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    # parity of every config at its stated size: the stored oracle digests of
+    # every score (tests/golden/make_digests.py), plus the oracle run of the
+    # CPU-baseline leg compared with the same GPU outputs subject by subject
     parity = None
-    if not args.no_check:
-        import oracle
-        rng = np.random.default_rng(5)
-        order = np.argsort(-w.db.lengths, kind="stable")
-        ids = np.unique(np.concatenate([order[:64], rng.choice(w.db.nseq, 448, replace=False)]))
-        exp = oracle.search_db(w.queries[0], w.db, w.matrix, w.gap_open, w.gap_extend, ids=ids)
-        g1 = main_run["out"].cpu().numpy()[ids]
-        g2 = i32_run["out"].cpu().numpy()[ids]
-        parity = {"sampled_subjects": int(len(ids)),
-                  "mismatches": int(np.sum(g1 != exp) + np.sum(g2 != exp))}
+    outs = {args.mode: main_run["out"].cpu().numpy(), "i32": i32_run["out"].cpu().numpy()}
+    if tuned_run is not None:
+        outs["tuned"] = tuned_run["out"].cpu().numpy()
+    if not args.no_check and args.scale == 1.0:
+        parity = {"q567_vs_200k": {m: digest_parity("q567_vs_200k", [o]) for m, o in outs.items()}}
 
     traffic = traffic_bytes(args.mode)
     variant = main_run["plan"]["variant"]
@@ -514,19 +631,39 @@ def main(argv=None):
         bcells = sum(len(x) for x in w3.queries) * w.db.total
         batched = {"workload": "20 queries 144-5478 vs the same 200,000 subjects, one persistent launch "
                                "per schedule", "cells": bcells}
+        bpar = {}
         for bm in (["auto", "i32"] + (["tuned"] if tuning is not None else [])):
             b = timed_search(gdb, qs, w3.matrix, w3.gap_open, w3.gap_extend, bm, args.batch_steps, 1, ev,
                              batch=True)
             batched[bm] = {"gcups": round(bcells / (b["wall_ms"] / 1e3) / 1e9, 1),
                            "ms_per_batch": round(b["wall_ms"], 2), "search_kernel_ms": round(b["kernel_ms"], 2),
                            "flagged": b["flagged"]}
+            if args.scale == 1.0:
+                bpar[bm] = digest_parity("20q_vs_200k", b["out"].cpu().numpy())
+        g = timed_graph(gdb, qs, w3.matrix, w3.gap_open, w3.gap_extend, args.batch_steps, ev)
+        batched["graph"] = {"gcups": round(bcells / (g["wall_ms"] / 1e3) / 1e9, 1),
+                            "ms_per_batch": round(g["wall_ms"], 2), "replay_ms": round(g["replay_ms"], 2)}
+        if args.scale == 1.0:
+            bpar["graph"] = digest_parity("20q_vs_200k", g["out"])
         batched["gcups"] = max(v["gcups"] for k, v in batched.items() if isinstance(v, dict))
+        if parity is not None and bpar:
+            parity["20q_vs_200k"] = bpar
 
     traceback = None if args.no_align else alignments(args, w, main_run["out"])
     overflow = None if args.no_planted else planted(args, ev)
     pair = None if args.no_pair else pairwise(args, ev)
     latency = None if args.no_serve else serving(args, gcups, args.mode)
-    cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_seconds)
+    cpu = None
+    if not args.no_cpu:
+        cpu, sel, exp = cpu_baseline(w, args.cpu_seconds)
+        if parity is not None:
+            parity["q567_vs_200k"]["cpu_oracle_run"] = {
+                "subjects": int(len(sel)),
+                "mismatches": {m: int(np.sum(o[sel] != exp)) for m, o in outs.items()}}
+    if parity is not None and overflow is not None and overflow.get("parity"):
+        parity["q8000_planted_vs_200k"] = overflow["parity"]
+    if parity is not None and latency is not None and latency.get("parity"):
+        parity["serve_500k"] = latency["parity"]
 
     rec = {
         "metric": "GCUPS per MI355X (int32 vs packed-int16+batched), bit-exact; p50/p99 query latency",
@@ -553,8 +690,7 @@ def main(argv=None):
                      "kernel": kname,
                      "isa_valu_per_cell": ops, "search_kernel_ms": round(main_run["kernel_ms"], 3),
                      "isa_peak_gcups": round(PEAK_VALU_TOPS * 1e3 / ops, 1),
-                     "paper_model_peak_gcups": round(PEAK_VALU_TOPS * 1e3 / PAPER_OPS_PER_CELL, 1),
-                     "paper_model_frac": round(cells / kernel_s / 1e9 / (PEAK_VALU_TOPS * 1e3 / PAPER_OPS_PER_CELL), 4)},
+                     "paper_model": paper_model(cells, kernel_s, variant)},
         "int32": {"gcups": round(cells / (i32_run["wall_ms"] / 1e3) / 1e9, 1),
                   "ms_per_step": round(i32_run["wall_ms"], 3),
                   "search_kernel_ms": round(i32_run["kernel_ms"], 3),

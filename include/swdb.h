@@ -17,8 +17,16 @@
  * Conventions for every call:
  *   - "device" pointers are HIP device memory of the current device (for
  *     example torch tensors' data_ptr()); "host" pointers are ordinary memory;
- *   - the caller owns every buffer it passes; the library owns only what a
- *     database handle allocates (see sw_db_prepare);
+ *   - the caller owns every device buffer: inputs, outputs, the prepared
+ *     database's layout (sw_db_prepare) and every search workspace; a
+ *     database handle owns only host memory (its sorted lengths, plan cache
+ *     and pinned plan-upload buffers).  The one-shot sw_db_search and the
+ *     autotuner are the only calls that take device memory of their own, as
+ *     stream-ordered allocations released before they return;
+ *   - the substitution matrix is read from HOST memory by every call: the
+ *     library picks the kernel variant from its values (8- or 16-bit profile
+ *     entries) and passes it to the profile kernel by value, so a search needs
+ *     no device-to-host copy and stays capturable in a graph;
  *   - searches are asynchronous on `stream` (a hipStream_t, NULL = default
  *     stream); results are valid once the stream has been synchronised;
  *   - every call returns SW_OK (0) or a negative SW_E* code and validates its
@@ -49,7 +57,12 @@ extern "C" {
 #define SW_ENOMEM (-2)     /* workspace too small, or an allocation failed        */
 #define SW_EHIP (-3)       /* a HIP runtime call failed; see sw_last_error()      */
 #define SW_EUNSUP (-4)     /* the current device is not gfx950                    */
-#define SW_EBADRES (-5)    /* a database residue code is >= SW_ALPHA              */
+#define SW_EBADRES (-5)    /* a residue code is >= SW_ALPHA (database: from
+                              sw_db_prepare; query: from the search status)      */
+#define SW_ERESCORE (-6)   /* the exact int32 rescore gave up on a subject (its
+                              score is stored as -1); from the search status      */
+#define SW_EINTERNAL (-7)  /* a search skipped a work item inconsistent with its
+                              launch (a library bug); from the search status      */
 
 /* Arithmetic mode of a search.  All modes give identical scores. */
 #define SW_MODE_AUTO 0     /* packed 16-bit lanes + exact int32 rescore           */
@@ -123,9 +136,12 @@ typedef struct sw_plan_stats {
  *   db_lengths   device, int32[nseq], each >= 0
  *   subst_matrix HOST, int32[32*32], [query residue][subject residue]
  *   scores_out   device, int32[nseq], in the caller's subject order
- * Prepares a temporary database, allocates its own workspace, searches in
- * SW_MODE_AUTO and synchronises `stream` before returning (this call is
- * blocking).  qlen = 0, nseq = 0 and empty subjects are legal (score 0).
+ * Prepares a temporary database and a workspace in stream-ordered device
+ * memory of its own (hipMallocAsync on `stream`, freed before returning),
+ * searches in SW_MODE_AUTO, checks the search status and synchronises
+ * `stream` (this call is blocking: the length sort runs on the host).
+ * qlen = 0, nseq = 0 and empty subjects are legal (score 0).  Returns
+ * SW_EBADRES for a residue code >= 32 in the query or the database.
  */
 int sw_db_search(const uint8_t* query, int32_t qlen,
                  const uint8_t* db_residues, const int64_t* db_offsets,
@@ -134,18 +150,35 @@ int sw_db_search(const uint8_t* query, int32_t qlen,
                  int32_t* scores_out, hipStream_t stream);
 
 /*
+ * Device bytes sw_db_prepare needs for a database of nseq subjects holding
+ * total_residues residues, the longest of them max_len residues (host only,
+ * no HIP call; 0 on invalid or inconsistent input).  An upper bound of the
+ * layout: residues padded per 64-subject chunk to its longest member, plus
+ * 12 bytes per subject; monotone in each argument.  (The padded size depends
+ * on the longest subject, hence max_len beside the total and the count.)
+ */
+size_t sw_db_prepare_bytes(int64_t total_residues, int32_t nseq, int32_t max_len);
+
+/*
  * Resident database (paper Section 3.1: the database is split by length; here
  * it is sorted by length, descending, and lane-interleaved 64 subjects to a
- * chunk).  Arguments as for sw_db_search.  Blocking: copies the lengths to
- * the host, sorts, then builds the device layout on `stream` and waits for
- * it.  The handle owns that device memory (about sum of lengths + padding,
- * plus 12 bytes per subject) until sw_db_release().  Returns SW_EBADRES if a
- * residue code is >= 32, SW_EUNSUP off gfx950.  A handle may be used by
- * several streams at once if each call has its own workspace.
+ * chunk).
+ *   db_residues, db_offsets, db_lengths, nseq   as for sw_db_search (device)
+ *   workspace   device, 256-byte aligned, at least
+ *               sw_db_prepare_bytes(sum of lengths, nseq, longest length)
+ *               bytes; owned by the caller, holds the database layout for
+ *               the handle's lifetime (do not free or reuse it before
+ *               sw_db_release)
+ * Blocking: copies the lengths to the host, sorts, then builds the layout in
+ * `workspace` on `stream` and waits for it.  Returns SW_ENOMEM if the
+ * workspace is too small (checked before any HIP call against the layout's
+ * metadata, then against the exact layout once the lengths are read),
+ * SW_EBADRES if a residue code is >= 32, SW_EUNSUP off gfx950.  A handle may
+ * be used by several streams at once if each call has its own workspace.
  */
 int sw_db_prepare(const uint8_t* db_residues, const int64_t* db_offsets,
-                  const int32_t* db_lengths, int32_t nseq, hipStream_t stream,
-                  sw_db_t* out);
+                  const int32_t* db_lengths, int32_t nseq, void* workspace, size_t ws_bytes,
+                  hipStream_t stream, sw_db_t* out);
 
 /*
  * Host-only handle for planning (no device memory, no HIP call): subject
@@ -157,10 +190,12 @@ int sw_db_prepare(const uint8_t* db_residues, const int64_t* db_offsets,
 int sw_db_describe(const int32_t* lengths_host, int32_t nseq, int32_t cu_count, int32_t lds_bytes,
                    sw_db_t* out);
 
-/* Frees the handle's device memory.  No search may still be in flight. */
+/* Frees the handle (host memory).  No search may still be in flight; the
+   caller's database workspace may be reused afterwards. */
 int sw_db_release(sw_db_t db);
 
-/* nseq, residues and device bytes held by the handle (any pointer may be NULL). */
+/* nseq, residues, and the bytes of the caller's database workspace the
+   handle keeps using (any pointer may be NULL). */
 int sw_db_info(sw_db_t db, int64_t* nseq, int64_t* residues, int64_t* device_bytes);
 
 /*
@@ -204,6 +239,8 @@ int sw_db_sorted_lengths(sw_db_t db, int32_t* out);
  *               256-byte aligned; must not be shared by concurrent calls
  *   scores_out  device, int32[nseq], caller's subject order
  * Asynchronous on `stream`; the host returns once the work is enqueued.
+ * Errors found on the device (a query residue code >= 32, an incomplete
+ * rescore) are reported by sw_search_status on the workspace afterwards.
  */
 int sw_db_search_ex(sw_db_t db, const uint8_t* query, int32_t qlen,
                     const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
@@ -267,8 +304,44 @@ int sw_tune_set(sw_db_t db, const sw_tune_entry* entries, int32_t n);
 int32_t sw_tune_get(sw_db_t db, sw_tune_entry* out, int32_t cap);
 
 /*
+ * Status of the last search that used `workspace` (the first 16 bytes of the
+ * workspace; cleared at the start of every search call, graph launches
+ * included, and accumulated over a call's launch groups).  A search call
+ * returns once its work is enqueued, so errors found on the device are
+ * reported here:
+ *   bad_query       nonzero if a query residue code was >= 32 (the search read
+ *                   it modulo 32; its scores are meaningless)
+ *   rescore_failed  subjects the exact int32 rescore gave up on (a bounded
+ *                   wait timed out, or the subject exceeded the rescore
+ *                   buffers); their score is stored as -1
+ *   flagged         subjects the 16-bit pass sent to the int32 rescore
+ *   bad_items       work items skipped as inconsistent with the launch (a
+ *                   library bug; their subjects keep no score)
+ */
+typedef struct sw_status {
+    int32_t bad_query;
+    int32_t rescore_failed;
+    int32_t flagged;
+    int32_t bad_items;
+} sw_status;
+
+/* Enqueue on `stream` a copy of the status words into `out` (HOST memory,
+   pinned for an asynchronous copy); read it once the stream has passed the
+   copy.  Ordered after the search when enqueued on the search's stream. */
+int sw_search_status_async(const void* workspace, sw_status* out, hipStream_t stream);
+
+/* Error code of a status: SW_EBADRES (bad query code), else SW_ERESCORE
+   (rescore incomplete), else SW_EINTERNAL (skipped items), else SW_OK. */
+int sw_status_code(const sw_status* status);
+
+/* Blocking form: copy the status words, synchronise `stream`, fill `out`
+   (may be NULL) and return sw_status_code of it (or SW_EHIP). */
+int sw_search_status(const void* workspace, hipStream_t stream, sw_status* out);
+
+/*
  * Number of subjects the last search that used `workspace` sent to the int32
- * rescore (16-bit modes).  Synchronises `stream`.  Negative on error.
+ * rescore (16-bit modes; the status's `flagged`).  Synchronises `stream`.
+ * Negative on error.
  */
 int64_t sw_flagged_count(const void* workspace, hipStream_t stream);
 

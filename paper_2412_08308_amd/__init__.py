@@ -9,10 +9,16 @@ and streams.  If the library is missing, every entry point raises
 Names mirror the C-ABI in ``include/swdb.h``:
 
 * ``search`` -> ``sw_db_search`` (one-shot, blocking);
-* ``Database`` -> ``sw_db_prepare`` / ``sw_db_release`` (resident database),
+* ``Database`` -> ``sw_db_prepare_bytes`` / ``sw_db_prepare`` /
+  ``sw_db_release`` (resident database in a torch-allocated layout tensor),
   with ``search`` -> ``sw_db_search_ex`` and ``search_batch`` ->
-  ``sw_db_search_batch`` (asynchronous on the current stream), and
-  ``workspace_bytes`` / ``plan_info``.
+  ``sw_db_search_batch`` (asynchronous on the current stream), ``status`` ->
+  ``sw_search_status``, and ``workspace_bytes`` / ``plan_info``.
+
+Searches check their status (``sw_search_status``: a query residue code >= 32,
+an incomplete exact rescore) before returning unless ``check=False`` is
+passed; the check synchronises the stream.  ``check=False`` callers read
+``Database.status`` themselves.
 """
 from __future__ import annotations
 
@@ -88,6 +94,15 @@ class PairStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Status(ctypes.Structure):
+    """``sw_status``: the status words of a search workspace."""
+    _fields_ = [("bad_query", ctypes.c_int32), ("rescore_failed", ctypes.c_int32),
+                ("flagged", ctypes.c_int32), ("bad_items", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Alignment(ctypes.Structure):
     _fields_ = [("score", ctypes.c_int32), ("q_begin", ctypes.c_int32), ("s_begin", ctypes.c_int32),
                 ("q_end", ctypes.c_int32), ("s_end", ctypes.c_int32), ("n_ops", ctypes.c_int32)]
@@ -108,7 +123,15 @@ def lib():
     L.sw_db_search.restype = ctypes.c_int
     L.sw_db_search.argtypes = [vp, i32, vp, vp, vp, i32, vp, i32, i32, vp, vp]
     L.sw_db_prepare.restype = ctypes.c_int
-    L.sw_db_prepare.argtypes = [vp, vp, vp, i32, vp, ctypes.POINTER(vp)]
+    L.sw_db_prepare.argtypes = [vp, vp, vp, i32, vp, sz, vp, ctypes.POINTER(vp)]
+    L.sw_db_prepare_bytes.restype = sz
+    L.sw_db_prepare_bytes.argtypes = [i64, i32, i32]
+    L.sw_search_status.restype = ctypes.c_int
+    L.sw_search_status.argtypes = [vp, vp, ctypes.POINTER(Status)]
+    L.sw_search_status_async.restype = ctypes.c_int
+    L.sw_search_status_async.argtypes = [vp, vp, vp]
+    L.sw_status_code.restype = ctypes.c_int
+    L.sw_status_code.argtypes = [ctypes.POINTER(Status)]
     L.sw_db_release.restype = ctypes.c_int
     L.sw_db_release.argtypes = [vp]
     L.sw_db_info.restype = ctypes.c_int
@@ -212,6 +235,38 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _on_stream(stream, *tensors):
+    """Tensors allocated on torch's current stream but used by work on another
+    ``stream``: tell the caching allocator, so that it does not hand their
+    memory out again before that work is done."""
+    import torch
+    if stream is None or stream == torch.cuda.current_stream():
+        return
+    for t in tensors:
+        if t is not None and t.numel():
+            t.record_stream(stream)
+
+
+def status_error(host) -> Optional["SwdbError"]:
+    """``sw_status_code`` of status words copied to the host (a 4-element int32
+    tensor or array): None, or the ``SwdbError`` the status reports."""
+    a = np.ascontiguousarray(np.asarray(host.numpy() if hasattr(host, "numpy") else host, dtype=np.int32))
+    st = Status.from_buffer_copy(a[:4].tobytes())
+    rc = lib().sw_status_code(ctypes.byref(st))
+    if rc == SW_OK:
+        return None
+    L = lib()
+    return SwdbError(rc, "search status", f"{L.sw_strerror(rc).decode()}: {L.sw_last_error().decode()}")
+
+
+def prepare_bytes(total_residues: int, nseq: int, max_len: int) -> int:
+    """``sw_db_prepare_bytes``: device bytes of a prepared database's layout."""
+    v = lib().sw_db_prepare_bytes(int(total_residues), int(nseq), int(max_len))
+    if v == 0:
+        raise SwdbError(-1, "sw_db_prepare_bytes", lib().sw_last_error().decode())
+    return int(v)
+
+
 def _dev(t, dtype, name):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -234,8 +289,13 @@ class SearchGraph:
         self.queries, self.workspace, self.out = queries, workspace, out
 
     def launch(self, stream=None):
+        """Replay the search on ``stream`` (asynchronous; ``status`` checks it)."""
         _check(lib().sw_graph_launch(self._g, _stream(stream)), "sw_graph_launch")
         return self.out
+
+    def status(self, stream=None, raise_on_error: bool = True) -> dict:
+        """Status words of the last replay (synchronises ``stream``)."""
+        return self.db.status(self.workspace, stream, raise_on_error=raise_on_error)
 
     def destroy(self):
         if getattr(self, "_g", None) is not None:
@@ -373,14 +433,27 @@ class Database:
         _check(lib().sw_db_sorted_lengths(self._handle(), out.ctypes.data), "sw_db_sorted_lengths")
         return out[:self.nseq]
 
-    def __init__(self, residues, offsets, lengths, stream=None):
+    def __init__(self, residues, offsets, lengths, stream=None, total=None, max_len=None, layout=None):
+        """``sw_db_prepare`` into a caller-owned layout tensor: ``layout`` (a
+        device uint8 tensor of at least ``prepare_bytes`` bytes) or one
+        allocated here from torch's allocator.  ``total`` / ``max_len``
+        (residues, longest subject) size it; computed from ``lengths`` when
+        not given."""
         import torch
+        self._h = None
         self.nseq = int(lengths.numel())
         self.device = lengths.device
+        if total is None or max_len is None:
+            total = int(lengths.sum().item()) if self.nseq else 0
+            max_len = int(lengths.max().item()) if self.nseq else 0
+        if layout is None:
+            layout = torch.empty(prepare_bytes(total, self.nseq, max_len), dtype=torch.uint8, device=self.device)
+        self.layout = layout
         h = ctypes.c_void_p()
         rc = lib().sw_db_prepare(_dev(residues, torch.uint8, "residues"),
                                  _dev(offsets, torch.int64, "offsets"),
                                  _dev(lengths, torch.int32, "lengths"), self.nseq,
+                                 _dev(layout, torch.uint8, "layout"), int(layout.numel()),
                                  _stream(stream), ctypes.byref(h))
         _check(rc, "sw_db_prepare")
         self._h = h
@@ -390,13 +463,16 @@ class Database:
         self.device_bytes = int(b.value)
 
     @classmethod
-    def from_host(cls, db, device="cuda", stream=None):
+    def from_host(cls, db, device="cuda", stream=None, layout=None):
         """From a ``synth.Database``-like object with numpy arrays."""
         import torch
+        lens = np.ascontiguousarray(db.lengths, dtype=np.int32)
         res = torch.from_numpy(np.ascontiguousarray(db.residues)).to(device)
         off = torch.from_numpy(np.ascontiguousarray(db.offsets, dtype=np.int64)).to(device)
-        ln = torch.from_numpy(np.ascontiguousarray(db.lengths, dtype=np.int32)).to(device)
-        return cls(res, off, ln, stream)
+        ln = torch.from_numpy(lens).to(device)
+        total = int(lens.sum(dtype=np.int64)) if len(lens) else 0
+        mx = int(lens.max()) if len(lens) else 0
+        return cls(res, off, ln, stream, total=total, max_len=mx, layout=layout)
 
     def _handle(self):
         if self._h is None:
@@ -407,6 +483,7 @@ class Database:
         if getattr(self, "_h", None) is not None:
             lib().sw_db_release(self._h)
             self._h = None
+        self.layout = None
 
     def __del__(self):
         try:
@@ -436,14 +513,17 @@ class Database:
         return torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
 
     def search(self, query, matrix, gap_open: int, gap_extend: int, opt: Optional[Options] = None,
-               out=None, workspace=None, stream=None):
-        """``sw_db_search_ex``: one device query; asynchronous on ``stream``."""
+               out=None, workspace=None, stream=None, check: bool = True):
+        """``sw_db_search_ex``: one device query on ``stream``.  With ``check``
+        the call waits for the search and raises ``SwdbError`` if its status
+        reports an error; without it the call is asynchronous."""
         import torch
         m = int(query.numel())
         if workspace is None:
             workspace = self.alloc_workspace([m], opt)
         if out is None:
             out = torch.empty(self.nseq, dtype=torch.int32, device=self.device)
+        _on_stream(stream, query, workspace, out)
         sm = _matrix(matrix)
         rc = lib().sw_db_search_ex(self._handle(), _dev(query, torch.uint8, "query"), m, sm.ctypes.data,
                                    int(gap_open), int(gap_extend),
@@ -451,13 +531,16 @@ class Database:
                                    _dev(workspace, torch.uint8, "workspace"), int(workspace.numel()),
                                    _dev(out, torch.int32, "out"), _stream(stream))
         _check(rc, "sw_db_search_ex")
-        self._last_ws = workspace
+        if check and self.nseq:
+            self.status(workspace, stream, raise_on_error=True)
         return out
 
     def search_batch(self, queries, matrix, gap_open: int, gap_extend: int,
-                     opt: Optional[Options] = None, out=None, workspace=None, stream=None):
+                     opt: Optional[Options] = None, out=None, workspace=None, stream=None,
+                     check: bool = True):
         """``sw_db_search_batch``.  ``queries``: a list of device uint8 tensors,
-        or a tuple (concatenated device tensor, host offsets, host lengths)."""
+        or a tuple (concatenated device tensor, host offsets, host lengths).
+        ``check`` as for ``search``."""
         import torch
         cat, offs, lens = self._batch_args(queries)
         nq = len(lens)
@@ -465,6 +548,7 @@ class Database:
             workspace = self.alloc_workspace(lens, opt)
         if out is None:
             out = torch.empty((nq, self.nseq), dtype=torch.int32, device=self.device)
+        _on_stream(stream, cat, workspace, out)
         sm = _matrix(matrix)
         rc = lib().sw_db_search_batch(self._handle(), _dev(cat, torch.uint8, "queries"),
                                       offs.ctypes.data if nq else None, lens.ctypes.data if nq else None,
@@ -473,7 +557,8 @@ class Database:
                                       _dev(workspace, torch.uint8, "workspace"), int(workspace.numel()),
                                       _dev(out, torch.int32, "out"), _stream(stream))
         _check(rc, "sw_db_search_batch")
-        self._keep = (cat, workspace)
+        if check and nq and self.nseq:
+            self.status(workspace, stream, raise_on_error=True)
         return out
 
     def capture(self, queries, matrix, gap_open: int, gap_extend: int, opt: Optional[Options] = None,
@@ -532,6 +617,31 @@ class Database:
         arr = (TuneEntry * max(n, 1))()
         lib().sw_tune_get(self._handle(), arr, n)
         return [arr[k].as_dict() for k in range(n)]
+
+    def status(self, workspace, stream=None, raise_on_error: bool = False) -> dict:
+        """``sw_search_status``: the status words of the last search that used
+        ``workspace`` (synchronises ``stream``).  With ``raise_on_error`` a
+        status error raises ``SwdbError``."""
+        import torch
+        st = Status()
+        rc = lib().sw_search_status(_dev(workspace, torch.uint8, "workspace"), _stream(stream),
+                                    ctypes.byref(st))
+        if raise_on_error or rc == -3:
+            _check(rc, "search status")
+        d = st.as_dict()
+        d["code"] = int(rc)
+        return d
+
+    def status_async(self, workspace, host, stream=None):
+        """``sw_search_status_async``: enqueue on ``stream`` a copy of the status
+        words into ``host`` (a pinned int32 CPU tensor of 4 elements);
+        ``status_error(host)`` decodes it once the stream has passed the copy."""
+        import torch
+        if host.dtype != torch.int32 or host.numel() < 4 or host.is_cuda or not host.is_contiguous():
+            raise TypeError("host status buffer must be a contiguous CPU int32 tensor of 4 elements")
+        _check(lib().sw_search_status_async(_dev(workspace, torch.uint8, "workspace"),
+                                            ctypes.c_void_p(host.data_ptr()), _stream(stream)),
+               "sw_search_status_async")
 
     def flagged_count(self, workspace, stream=None) -> int:
         import torch

@@ -455,6 +455,7 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
             if (lo == 32767) {
                 const int k = atomicAdd(&a.counters[1], 1);
                 if (k < a.flag_cap) a.flags[k] = make_int2(it.q, sA);
+                else atomicAdd(&a.status[kStatusRescoreFailed], 1);
             } else {
                 a.scores[ob + a.perm[sA]] = lo;
             }
@@ -463,6 +464,7 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
             if (hi == 32767) {
                 const int k = atomicAdd(&a.counters[1], 1);
                 if (k < a.flag_cap) a.flags[k] = make_int2(it.q, sB);
+                else atomicAdd(&a.status[kStatusRescoreFailed], 1);
             } else {
                 a.scores[ob + a.perm[sB]] = hi;
             }
@@ -572,6 +574,7 @@ __device__ __forceinline__ void item_i16_self(const SearchArgs& a, const Item it
         if (best == 32767) {
             const int k = atomicAdd(&a.counters[1], 1);
             if (k < a.flag_cap) a.flags[k] = make_int2(it.q, s);
+            else atomicAdd(&a.status[kStatusRescoreFailed], 1);
         } else {
             a.scores[(int64_t)qd.out_row * a.out_stride + a.perm[s]] = best;
         }
@@ -681,6 +684,8 @@ k_search(SearchArgs a)
             const Item it = a.items[ix];
             if (it.q == p && item_fits<I16>(a, it, qd))
                 run_item<R, ES, I16>(a, it, qd, slot, lane);
+            else if (lane == 0)
+                atomicAdd(&a.status[kStatusBadItems], 1);
         }
     }
 }

@@ -62,6 +62,17 @@ struct QueryDesc {
     int32_t pad;
 };
 
+// Status words at the start of a search workspace, cleared by the first
+// launch group of every search call and accumulated over its groups (int32
+// each): a query residue code >= 32 was seen; subjects the exact rescore gave
+// up on (their score is stored as -1); subjects sent to the rescore; work
+// items the search kernel skipped as inconsistent with its launch.
+constexpr int kStatusBytes = 256;
+constexpr int kStatusBadQuery = 0;
+constexpr int kStatusRescoreFailed = 1;
+constexpr int kStatusFlagged = 2;
+constexpr int kStatusBadItems = 3;
+
 struct Matrix8 {
     int8_t v[kAlpha * kAlpha];   // [query residue][subject residue]
 };
@@ -83,7 +94,8 @@ struct SearchArgs {
     // outputs and scratch
     int32_t* scores;             // [nq][out_stride]
     int64_t out_stride;
-    int32_t* counters;           // [1] overflow-flag count, [2] rescore queue head
+    int32_t* counters;           // [1] overflow-flag count, [2] rescore queue head (per launch group)
+    int32_t* status;             // status words (kStatus*)
     int2* bnd;                   // slots
     int64_t slot_elems;          // int2 entries per slot
     int2* flags;                 // (q, sorted subject) of 16-bit overflows
@@ -96,8 +108,7 @@ struct ProfileArgs {
     const int64_t* q_off;        // device copy of offsets
     const QueryDesc* qd;
     uint8_t* prof;
-    int32_t* counters;
-    int32_t* heads;
+    int32_t* bad;                // set to 1 if a query residue code is >= 32 (null: read codes modulo 32)
     int32_t nq;
     int32_t go;
     int32_t pad;                 // entry of pad codes and pad rows

@@ -30,15 +30,12 @@ LaunchInfo variant_info(Variant v)
 // profile of the packed lanes: a pad cell then adds -Go to its diagonal, so it
 // never exceeds the real cells it derives from); row block nbr is entirely
 // padding.
-// Block (0, 0) also clears the flag count, block (0, q) query q's queue head.
+// A query residue code >= 32 sets *a.bad (when given) and is read modulo 32,
+// so that every profile read stays inside the matrix.
 template <typename PE>
 __global__ void __launch_bounds__(256) k_profile(ProfileArgs a, int R)
 {
     const int q = blockIdx.y;
-    if (blockIdx.x == 0 && q == 0 && threadIdx.x < 4)
-        a.counters[threadIdx.x] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        a.heads[q] = 0;
     const QueryDesc qd = a.qd[q];
     const int entries = (qd.nbr + 1) * kCodes * R;
     const int cse = code_stride(R, (int)sizeof(PE)) / (int)sizeof(PE);   // code stride in entries
@@ -52,7 +49,10 @@ __global__ void __launch_bounds__(256) k_profile(ProfileArgs a, int R)
         const int row = rb * R + r;
         PE v = padv;
         if (row < qd.m && c < kAlpha) {
-            const int qc = qs[row] & (kAlpha - 1);
+            const int raw = qs[row];
+            if (c == 0 && raw >= kAlpha && a.bad)
+                atomicOr(a.bad, 1);
+            const int qc = raw & (kAlpha - 1);
             v = (PE)(a.sm.v[qc * kAlpha + c] + a.go);
         }
         out[((int64_t)rb * kCodes + c) * cse + r] = v;

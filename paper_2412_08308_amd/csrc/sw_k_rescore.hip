@@ -17,8 +17,9 @@ namespace swdb {
 // soon as pass p - 1 has published, through a counter in LDS, that the columns
 // it needs are written.  The critical path of a long subject is then one pass
 // instead of all of them.  Every wait is bounded: after kSpinLimit polls the
-// workgroup gives up on the subject and stores -1 (no Smith-Waterman score is
-// negative), so the kernel always drains.
+// workgroup gives up on the subject, stores -1 (no Smith-Waterman score is
+// negative) and counts the subject in the status words, so the kernel always
+// drains and the call's status reports the failure.
 
 constexpr uint32_t kSpinLimit = 1u << 24;
 
@@ -198,13 +199,18 @@ k_rescore(SearchArgs a)
         const int2 e = cur;
         if (e.x < 0)
             break;
-        if (e.x >= a.nq || e.y < 0 || e.y >= a.nseq)
-            continue;                          // not an entry of this launch
+        if (e.x >= a.nq || e.y < 0 || e.y >= a.nseq) {
+            if (threadIdx.x == 0)              // not an entry of this launch
+                atomicAdd(&a.status[kStatusBadItems], 1);
+            continue;
+        }
         const QueryDesc qd = a.qd[e.x];
         const int ncols = (a.slen[e.y] + 15) & ~15;
         if ((int64_t)ncols > a.slot_elems) {   // buffers sized below the subject: no score
-            if (threadIdx.x == 0)
+            if (threadIdx.x == 0) {
                 a.scores[(int64_t)qd.out_row * a.out_stride + a.perm[e.y]] = -1;
+                atomicAdd(&a.status[kStatusRescoreFailed], 1);
+            }
             continue;
         }
         const int P = (qd.nbr + kWave - 1) / kWave;
@@ -218,8 +224,11 @@ k_rescore(SearchArgs a)
         if (lane == 0)
             atomicMax(&smax, S < 0 ? INT_MAX : S);
         __syncthreads();
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
             a.scores[(int64_t)qd.out_row * a.out_stride + a.perm[e.y]] = smax == INT_MAX ? -1 : smax;
+            if (smax == INT_MAX)
+                atomicAdd(&a.status[kStatusRescoreFailed], 1);
+        }
     }
 }
 
@@ -233,6 +242,8 @@ __global__ void __launch_bounds__(1024) k_flag_sort(SearchArgs a)
 {
     __shared__ uint64_t key[kFlagSortCap];
     const int cnt = min(a.counters[1], a.flag_cap);
+    if (threadIdx.x == 0 && cnt > 0)
+        atomicAdd(&a.status[kStatusFlagged], cnt);
     if (cnt <= 1 || cnt > kFlagSortCap)
         return;
     int n = 1;

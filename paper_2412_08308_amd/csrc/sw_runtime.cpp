@@ -375,8 +375,12 @@ struct Layout {
     int lds_bytes = 0;
     int64_t cells = 0, lane_cells = 0, nitems = 0;
     int max_entries = 0;
-    size_t off_counters = 0, off_heads = 0, off_qd = 0, off_qoff = 0, off_items = 0, off_prof = 0,
-           off_flags = 0, off_slots = 0, total = 0, blob = 0;
+    // The plan blob uploaded before a launch group covers [off_status,
+    // off_prof): status words (cleared by the first group of a call only),
+    // per-group counters and queue heads (cleared by every group), query
+    // descriptors, query offsets and work items.
+    size_t off_status = 0, off_counters = 0, off_heads = 0, off_qd = 0, off_qoff = 0, off_items = 0,
+           off_prof = 0, off_flags = 0, off_slots = 0, total = 0, blob = 0;
     int64_t flag_cap = 0;
 };
 
@@ -465,13 +469,14 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
     }
     // byte layout
     size_t off = 0;
+    L.off_status = off; off += kStatusBytes;
     L.off_counters = off; off += 256;
     L.off_heads = off; off += align_up(sizeof(int32_t) * nq, 256);
     L.off_qd = off; off += align_up(sizeof(QueryDesc) * nq, 16);
     L.off_qoff = off; off += align_up(sizeof(int64_t) * nq, 16);
     L.off_items = off;
     off += align_up(sizeof(Item) * nit, 256);
-    L.blob = off - L.off_qd;
+    L.blob = off - L.off_status;
     L.off_prof = off; off += align_up(prof, 256);
     L.off_flags = off; off += align_up(sizeof(int2) * L.flag_cap, 256);
     L.off_slots = off;
@@ -653,12 +658,14 @@ int plan_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, co
     return SW_OK;
 }
 
-// The plan blob (query descriptors, query offsets, work queue) in host memory.
+// The plan blob in host memory: zeroed status words, counters and queue
+// heads, then query descriptors, query offsets and the work queue.
 void fill_blob(const Layout& L, const int64_t* q_offsets, uint8_t* h)
 {
-    std::memcpy(h, L.qd.data(), sizeof(QueryDesc) * L.nq);
-    int64_t* qoff = reinterpret_cast<int64_t*>(h + (L.off_qoff - L.off_qd));
-    Item* items = reinterpret_cast<Item*>(h + (L.off_items - L.off_qd));
+    std::memset(h, 0, L.off_qd - L.off_status);
+    std::memcpy(h + (L.off_qd - L.off_status), L.qd.data(), sizeof(QueryDesc) * L.nq);
+    int64_t* qoff = reinterpret_cast<int64_t*>(h + (L.off_qoff - L.off_status));
+    Item* items = reinterpret_cast<Item*>(h + (L.off_items - L.off_status));
     int64_t pos = 0;
     for (int32_t p = 0; p < L.nq; ++p) {
         const int32_t k = L.order[p];
@@ -671,24 +678,26 @@ void fill_blob(const Layout& L, const int64_t* q_offsets, uint8_t* h)
     }
 }
 
-// Everything a search puts on `stream`: plan upload from pinned host memory,
-// profile kernel (also clears the queue head and flag count), search kernel,
-// flag-list sort and rescore kernel.  No memset: the sequence may be captured into a graph.
+// Everything a search puts on `stream`: plan upload from pinned host memory
+// (which also clears the counters and queue heads, and for the first launch
+// group of a call the status words), profile kernel, search kernel, flag-list
+// sort and rescore kernel.  No memset: the sequence may be captured into a graph.
 int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8_t* queries,
                    const int32_t* sm, int32_t go, int32_t ge, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2,
-                   void* ws, int32_t* scores, hipStream_t stream)
+                   void* ws, int32_t* scores, bool first, hipStream_t stream)
 {
     const Resolved& r = L.r;
     uint8_t* w = static_cast<uint8_t*>(ws);
-    HIPCHK(hipMemcpyAsync(w + L.off_qd, blob, L.blob, hipMemcpyHostToDevice, stream));
+    const size_t skip = first ? 0 : L.off_counters - L.off_status;
+    HIPCHK(hipMemcpyAsync(w + L.off_status + skip, blob + skip, L.blob - skip, hipMemcpyHostToDevice, stream));
+    int32_t* status = reinterpret_cast<int32_t*>(w + L.off_status);
 
     ProfileArgs pa{};
     pa.queries = queries;
     pa.q_off = reinterpret_cast<const int64_t*>(w + L.off_qoff);
     pa.qd = reinterpret_cast<const QueryDesc*>(w + L.off_qd);
     pa.prof = w + L.off_prof;
-    pa.counters = reinterpret_cast<int32_t*>(w + L.off_counters);
-    pa.heads = reinterpret_cast<int32_t*>(w + L.off_heads);
+    pa.bad = status + kStatusBadQuery;
     pa.nq = L.nq;
     pa.go = go;
     pa.pad = r.v == kI16_P8 ? 0 : (r.elem == 1 ? -128 : -32768);
@@ -705,12 +714,13 @@ int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8
     a.items = reinterpret_cast<const Item*>(w + L.off_items);
     a.qd = pa.qd;
     a.nq = L.nq;
-    a.heads = pa.heads;
+    a.heads = reinterpret_cast<int32_t*>(w + L.off_heads);
     a.n_items = L.nitems;
     a.prof = pa.prof;
     a.scores = scores;
     a.out_stride = db->nseq;
-    a.counters = pa.counters;
+    a.counters = reinterpret_cast<int32_t*>(w + L.off_counters);
+    a.status = status;
     a.bnd = reinterpret_cast<int2*>(w + L.off_slots);
     a.slot_elems = L.slot_elems;
     a.flags = reinterpret_cast<int2*>(w + L.off_flags);
@@ -742,7 +752,8 @@ int enqueue_parts(sw_db_t db, const std::vector<Part>& parts, const std::vector<
         const int rc = enqueue_search(db, parts[g].L, blobs[g], queries, sm, go, ge,
                                       first && opt ? opt->ev_search_begin : nullptr,
                                       last && opt ? opt->ev_search_end : nullptr,
-                                      last && opt ? opt->ev_rescore_end : nullptr, ws, scores, stream);
+                                      last && opt ? opt->ev_rescore_end : nullptr, ws, scores, first,
+                                      stream);
         if (rc) return rc;
     }
     return SW_OK;
@@ -787,10 +798,6 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
 void free_db(sw_db_s* db)
 {
     if (!db) return;
-    (void)hipFree(db->d_res);
-    (void)hipFree(db->d_chunk_off);
-    (void)hipFree(db->d_perm);
-    (void)hipFree(db->d_slen);
     for (auto& st : db->staging) {
         if (st.ev) {
             (void)hipEventSynchronize(st.ev);
@@ -801,50 +808,76 @@ void free_db(sw_db_s* db)
     delete db;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* sw_version(void) { return "swdb 0.1.0 (gfx950)"; }
-
-const char* sw_last_error(void) { return g_err.c_str(); }
-
-const char* sw_strerror(int code)
+// Copies a search's status words (the start of its workspace) to the host,
+// synchronises the stream and decodes them (sw_status_code).
+int sw_search_status_get(const void* ws, hipStream_t stream, sw_status* st)
 {
-    switch (code) {
-    case SW_OK: return "ok";
-    case SW_EINVAL: return "invalid argument";
-    case SW_ENOMEM: return "out of memory or workspace too small";
-    case SW_EHIP: return "HIP runtime error";
-    case SW_EUNSUP: return "unsupported device (gfx950 required)";
-    case SW_EBADRES: return "database residue code >= 32";
-    }
-    return "unknown error";
+    if (!ws) return fail(SW_EINVAL, "null workspace");
+    *st = sw_status{};
+    HIPCHK(hipMemcpyAsync(st, ws, sizeof(sw_status), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return sw_status_code(st);
 }
 
-int sw_db_prepare(const uint8_t* residues, const int64_t* offsets, const int32_t* lengths,
-                  int32_t nseq, hipStream_t stream, sw_db_t* out)
+// Device layout of a prepared database inside the caller's workspace
+// (256-byte aligned pieces): lane-interleaved residues, chunk offsets, the
+// sort permutation, sorted lengths; then two pieces used only while
+// preparing (the chunk block prefix and the bad-code flag).
+struct DbLayout {
+    size_t res = 0, chunk_off = 0, perm = 0, slen = 0, bprefix = 0, bad = 0, total = 0, resident = 0;
+};
+
+DbLayout db_layout(int64_t res_bytes, int64_t nseq)
 {
-    if (!out) return fail(SW_EINVAL, "null output handle");
-    *out = nullptr;
+    const int64_t nchunks = ceil_div(nseq, 64);
+    DbLayout L;
+    size_t off = 0;
+    L.res = off; off += align_up(std::max<int64_t>(res_bytes, 16), 256);
+    L.chunk_off = off; off += align_up(sizeof(int64_t) * std::max<int64_t>(nchunks, 1), 256);
+    L.perm = off; off += align_up(sizeof(int32_t) * std::max<int64_t>(nseq, 1), 256);
+    L.slen = off; off += align_up(sizeof(int32_t) * std::max<int64_t>(nseq, 1), 256);
+    L.resident = off;
+    L.bprefix = off; off += align_up(sizeof(int64_t) * (nchunks + 1), 256);
+    L.bad = off; off += 256;
+    L.total = off;
+    return L;
+}
+
+// Checks of sw_db_prepare that need no HIP call; the workspace must at least
+// hold the layout's metadata (the residues are checked once the lengths are
+// known).
+int prepare_args_check(const int64_t* offsets, const int32_t* lengths, int32_t nseq, void* ws, size_t ws_bytes)
+{
     if (nseq < 0) return fail(SW_EINVAL, "nseq < 0");
     if (nseq > 0 && (!offsets || !lengths)) return fail(SW_EINVAL, "null offsets or lengths");
     if (nseq > (INT32_MAX / 2)) return fail(SW_EINVAL, "nseq too large");
+    if (!ws) return fail(SW_EINVAL, "null workspace");
+    if (((uintptr_t)ws & 255) != 0) return fail(SW_EINVAL, "workspace must be 256-byte aligned");
+    const size_t least = db_layout(0, nseq).total;
+    if (ws_bytes < least)
+        return fail(SW_ENOMEM, "database workspace too small: need at least " + std::to_string(least) + " bytes");
+    return SW_OK;
+}
 
-    int dev = 0;
-    HIPCHK(hipGetDevice(&dev));
+int gfx950_device(int* dev)
+{
+    HIPCHK(hipGetDevice(dev));
     hipDeviceProp_t prop;
-    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    HIPCHK(hipGetDeviceProperties(&prop, *dev));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(SW_EUNSUP, std::string("device is ") + prop.gcnArchName);
+    return SW_OK;
+}
 
-    std::vector<int32_t> len(nseq);
-    std::vector<int64_t> off(nseq);
-    if (nseq > 0) {
-        HIPCHK(hipMemcpyAsync(len.data(), lengths, sizeof(int32_t) * nseq, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipMemcpyAsync(off.data(), offsets, sizeof(int64_t) * nseq, hipMemcpyDeviceToHost, stream));
-        HIPCHK(hipStreamSynchronize(stream));
-    }
+// Database preparation from host copies of the lengths and offsets: stable
+// sort by length (descending), chunk layout, upload of the metadata and the
+// lane interleaving on `stream`, all inside `ws`.  Blocking (reads back the
+// bad-code flag).
+int prepare_from_host(const uint8_t* residues, const int64_t* offsets, const std::vector<int32_t>& len,
+                      const std::vector<int64_t>& off, int dev, void* ws, size_t ws_bytes, hipStream_t stream,
+                      sw_db_t* out)
+{
+    const int32_t nseq = (int32_t)len.size();
     int64_t total = 0;
     int32_t maxl = 0;
     for (int32_t i = 0; i < nseq; ++i) {
@@ -869,7 +902,13 @@ int sw_db_prepare(const uint8_t* residues, const int64_t* offsets, const int32_t
         coff[c] = bprefix[c] * 1024;
     }
     const int64_t res_bytes = std::max<int64_t>(bprefix[nchunks] * 1024, 16);
+    const DbLayout L = db_layout(res_bytes, nseq);
+    if (ws_bytes < L.total)
+        return fail(SW_ENOMEM, "database workspace too small: need " + std::to_string(L.total) + " bytes");
 
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    uint8_t* w = static_cast<uint8_t*>(ws);
     auto* db = new sw_db_s();
     db->device = dev;
     db->cu = prop.multiProcessorCount;
@@ -880,12 +919,15 @@ int sw_db_prepare(const uint8_t* residues, const int64_t* offsets, const int32_t
     db->max_len = maxl;
     db->res_bytes = res_bytes;
     db->slen = slen;
-    int64_t* d_bprefix = nullptr;
-    int32_t* d_bad = nullptr;
+    db->d_res = w + L.res;
+    db->d_chunk_off = reinterpret_cast<int64_t*>(w + L.chunk_off);
+    db->d_perm = reinterpret_cast<int32_t*>(w + L.perm);
+    db->d_slen = reinterpret_cast<int32_t*>(w + L.slen);
+    db->dev_bytes = (int64_t)L.resident;
+    auto* d_bprefix = reinterpret_cast<int64_t*>(w + L.bprefix);
+    auto* d_bad = reinterpret_cast<int32_t*>(w + L.bad);
     auto cleanup = [&](int code, const std::string& msg) {
         (void)hipStreamSynchronize(stream);
-        (void)hipFree(d_bprefix);
-        (void)hipFree(d_bad);
         free_db(db);
         return fail(code, msg);
     };
@@ -894,19 +936,13 @@ int sw_db_prepare(const uint8_t* residues, const int64_t* offsets, const int32_t
         hipError_t e_ = (x);                                                                    \
         if (e_ != hipSuccess) return cleanup(SW_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
-    PCHK(hipMalloc(&db->d_res, res_bytes));
-    PCHK(hipMalloc(&db->d_chunk_off, sizeof(int64_t) * std::max(nchunks, 1)));
-    PCHK(hipMalloc(&db->d_perm, sizeof(int32_t) * std::max(nseq, 1)));
-    PCHK(hipMalloc(&db->d_slen, sizeof(int32_t) * std::max(nseq, 1)));
-    PCHK(hipMalloc(&d_bprefix, sizeof(int64_t) * (nchunks + 1)));
-    PCHK(hipMalloc(&d_bad, sizeof(int32_t)));
-    db->dev_bytes = res_bytes + sizeof(int64_t) * std::max(nchunks, 1) + 8 * (int64_t)std::max(nseq, 1);
     if (nseq > 0) {
+        const int32_t zero = 0;
         PCHK(hipMemcpyAsync(db->d_chunk_off, coff.data(), sizeof(int64_t) * nchunks, hipMemcpyHostToDevice, stream));
         PCHK(hipMemcpyAsync(db->d_perm, perm.data(), sizeof(int32_t) * nseq, hipMemcpyHostToDevice, stream));
         PCHK(hipMemcpyAsync(db->d_slen, slen.data(), sizeof(int32_t) * nseq, hipMemcpyHostToDevice, stream));
         PCHK(hipMemcpyAsync(d_bprefix, bprefix.data(), sizeof(int64_t) * (nchunks + 1), hipMemcpyHostToDevice, stream));
-        PCHK(hipMemsetAsync(d_bad, 0, sizeof(int32_t), stream));
+        PCHK(hipMemcpyAsync(d_bad, &zero, sizeof(int32_t), hipMemcpyHostToDevice, stream));
         PCHK(launch_interleave(residues, offsets, db->d_perm, db->d_slen, db->d_chunk_off, nseq,
                                bprefix[nchunks] * 64, d_bprefix, nchunks, db->d_res, d_bad, stream));
         int32_t bad = 0;
@@ -915,11 +951,73 @@ int sw_db_prepare(const uint8_t* residues, const int64_t* offsets, const int32_t
         if (bad)
             return cleanup(SW_EBADRES, "database residue code >= 32");
     }
-    (void)hipFree(d_bprefix);
-    (void)hipFree(d_bad);
 #undef PCHK
     *out = db;
     return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sw_version(void) { return "swdb 0.1.0 (gfx950)"; }
+
+const char* sw_last_error(void) { return g_err.c_str(); }
+
+const char* sw_strerror(int code)
+{
+    switch (code) {
+    case SW_OK: return "ok";
+    case SW_EINVAL: return "invalid argument";
+    case SW_ENOMEM: return "out of memory or workspace too small";
+    case SW_EHIP: return "HIP runtime error";
+    case SW_EUNSUP: return "unsupported device (gfx950 required)";
+    case SW_EBADRES: return "residue code >= 32";
+    case SW_ERESCORE: return "exact int32 rescore incomplete";
+    case SW_EINTERNAL: return "internal error";
+    }
+    return "unknown error";
+}
+
+int sw_db_prepare(const uint8_t* residues, const int64_t* offsets, const int32_t* lengths,
+                  int32_t nseq, void* workspace, size_t ws_bytes, hipStream_t stream, sw_db_t* out)
+{
+    if (!out) return fail(SW_EINVAL, "null output handle");
+    *out = nullptr;
+    int rc = prepare_args_check(offsets, lengths, nseq, workspace, ws_bytes);
+    if (rc) return rc;
+    int dev = 0;
+    rc = gfx950_device(&dev);
+    if (rc) return rc;
+    std::vector<int32_t> len(nseq);
+    std::vector<int64_t> off(nseq);
+    if (nseq > 0) {
+        HIPCHK(hipMemcpyAsync(len.data(), lengths, sizeof(int32_t) * nseq, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipMemcpyAsync(off.data(), offsets, sizeof(int64_t) * nseq, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+    }
+    return prepare_from_host(residues, offsets, len, off, dev, workspace, ws_bytes, stream, out);
+}
+
+size_t sw_db_prepare_bytes(int64_t total_residues, int32_t nseq, int32_t max_len)
+{
+    if (total_residues < 0 || nseq < 0 || nseq > INT32_MAX / 2 || max_len < 0) {
+        fail(SW_EINVAL, "negative or out-of-range database size");
+        return 0;
+    }
+    if ((nseq == 0 && (total_residues || max_len)) || max_len > total_residues ||
+        (int64_t)nseq * max_len < total_residues) {
+        fail(SW_EINVAL, "inconsistent total_residues, nseq and max_len");
+        return 0;
+    }
+    const int64_t nchunks = ceil_div(nseq, 64);
+    // Chunk c stores 64 lanes of ceil16(longest length of the chunk) bytes.
+    // Lengths are sorted descending, so chunk c's longest subject (c >= 1) is
+    // no longer than any subject of chunk c - 1: 64 * that length is at most
+    // chunk c - 1's residues, and the sum over chunks at most
+    // 64 * ceil16(max_len) + total + 960 per chunk for the rounding.
+    const int64_t bound = 64 * align_up(max_len, 16) + total_residues + 960 * nchunks;
+    return db_layout(bound, nseq).total;
 }
 
 int sw_db_describe(const int32_t* lengths, int32_t nseq, int32_t cu_count, int32_t lds_bytes, sw_db_t* out)
@@ -1151,10 +1249,10 @@ int sw_autotune(sw_db_t db, const int32_t* qlens, int32_t nbins, const int32_t* 
     std::vector<uint8_t> hq(maxm);
     int rc = SW_OK;
     auto cleanup = [&]() {
+        if (d_q) (void)hipFreeAsync(d_q, stream);
+        if (d_ws) (void)hipFreeAsync(d_ws, stream);
+        if (d_sc) (void)hipFreeAsync(d_sc, stream);
         (void)hipStreamSynchronize(stream);
-        (void)hipFree(d_q);
-        (void)hipFree(d_ws);
-        (void)hipFree(d_sc);
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
     };
@@ -1166,9 +1264,10 @@ int sw_autotune(sw_db_t db, const int32_t* qlens, int32_t nbins, const int32_t* 
             return fail(SW_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));             \
         }                                                                                     \
     } while (0)
-    TCHK(hipMalloc(&d_q, std::max<int32_t>(maxm, 1)));
-    TCHK(hipMalloc(&d_ws, std::max<size_t>(ws_need, 256)));
-    TCHK(hipMalloc(&d_sc, sizeof(int32_t) * db->nseq));
+    // the tuner's own buffers: stream-ordered allocations, freed on the stream
+    TCHK(hipMallocAsync((void**)&d_q, std::max<int32_t>(maxm, 1), stream));
+    TCHK(hipMallocAsync(&d_ws, std::max<size_t>(ws_need, 256), stream));
+    TCHK(hipMallocAsync((void**)&d_sc, sizeof(int32_t) * db->nseq, stream));
     TCHK(hipEventCreate(&ev[0]));
     TCHK(hipEventCreate(&ev[1]));
     uint64_t x = 0x9E3779B97F4A7C15ull;              // xorshift64* draws of sample positions
@@ -1296,13 +1395,39 @@ int sw_graph_destroy(sw_graph_t g)
     return SW_OK;
 }
 
-int64_t sw_flagged_count(const void* ws, hipStream_t stream)
+int sw_search_status_async(const void* ws, sw_status* out, hipStream_t stream)
 {
     if (!ws) return fail(SW_EINVAL, "null workspace");
-    int32_t c[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(c, ws, sizeof(c), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    return c[1];
+    if (!out) return fail(SW_EINVAL, "null status output");
+    static_assert(sizeof(sw_status) == 4 * sizeof(int32_t), "status layout");
+    HIPCHK(hipMemcpyAsync(out, ws, sizeof(sw_status), hipMemcpyDeviceToHost, stream));
+    return SW_OK;
+}
+
+int sw_status_code(const sw_status* st)
+{
+    if (!st) return fail(SW_EINVAL, "null status");
+    if (st->bad_query) return fail(SW_EBADRES, "query residue code >= 32");
+    if (st->rescore_failed)
+        return fail(SW_ERESCORE, std::to_string(st->rescore_failed) + " subject(s) without an exact rescore");
+    if (st->bad_items)
+        return fail(SW_EINTERNAL, std::to_string(st->bad_items) + " work item(s) inconsistent with the launch");
+    return SW_OK;
+}
+
+int sw_search_status(const void* ws, hipStream_t stream, sw_status* out)
+{
+    sw_status local{};
+    sw_status* st = out ? out : &local;
+    return sw_search_status_get(ws, stream, st);
+}
+
+int64_t sw_flagged_count(const void* ws, hipStream_t stream)
+{
+    sw_status st{};
+    const int rc = sw_search_status_get(ws, stream, &st);
+    if (rc && rc != SW_EBADRES && rc != SW_ERESCORE && rc != SW_EINTERNAL) return rc;
+    return st.flagged;
 }
 
 int sw_db_search(const uint8_t* query, int32_t qlen, const uint8_t* residues, const int64_t* offsets,
@@ -1316,23 +1441,57 @@ int sw_db_search(const uint8_t* query, int32_t qlen, const uint8_t* residues, co
         return fail(SW_EINVAL, "gap penalties must be in [0, SW_MAX_GAP]");
     if (nseq < 0) return fail(SW_EINVAL, "nseq < 0");
     if (nseq > 0 && !scores) return fail(SW_EINVAL, "null scores_out");
+    if (nseq > 0 && (!offsets || !lengths)) return fail(SW_EINVAL, "null offsets or lengths");
+    if (nseq > (INT32_MAX / 2)) return fail(SW_EINVAL, "nseq too large");
     std::string why;
     if (!matrix_elem(sm, go, why)) return fail(SW_EINVAL, why);
     if (nseq == 0) return SW_OK;
-    sw_db_t db = nullptr;
-    int rc = sw_db_prepare(residues, offsets, lengths, nseq, stream, &db);
+    int dev = 0;
+    int rc = gfx950_device(&dev);
     if (rc) return rc;
+    std::vector<int32_t> len(nseq);
+    std::vector<int64_t> off(nseq);
+    HIPCHK(hipMemcpyAsync(len.data(), lengths, sizeof(int32_t) * nseq, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(off.data(), offsets, sizeof(int64_t) * nseq, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    int64_t total = 0;
+    int32_t maxl = 0;
+    for (int32_t v : len) {
+        if (v < 0) return fail(SW_EINVAL, "negative subject length");
+        total += v;
+        maxl = std::max(maxl, v);
+    }
+    // the one-shot call's own memory: stream-ordered allocations, freed on
+    // the stream before the call returns
+    const size_t dbb = sw_db_prepare_bytes(total, nseq, maxl);
+    void* dbw = nullptr;
+    if (dbb == 0 || hipMallocAsync(&dbw, dbb, stream) != hipSuccess)
+        return fail(SW_ENOMEM, "database allocation failed");
+    sw_db_t db = nullptr;
+    rc = prepare_from_host(residues, offsets, len, off, dev, dbw, dbb, stream, &db);
+    if (rc) {
+        const std::string err = g_err;
+        (void)hipFreeAsync(dbw, stream);
+        (void)hipStreamSynchronize(stream);
+        return fail(rc, err);
+    }
     const size_t need = sw_workspace_bytes(db, 1, &qlen, nullptr);
     void* ws = nullptr;
-    if (need == 0 || hipMalloc(&ws, need) != hipSuccess) {
+    if (need == 0 || hipMallocAsync(&ws, need, stream) != hipSuccess) {
         sw_db_release(db);
+        (void)hipFreeAsync(dbw, stream);
+        (void)hipStreamSynchronize(stream);
         return fail(SW_ENOMEM, "workspace allocation failed");
     }
     rc = sw_db_search_ex(db, query, qlen, sm, go, ge, nullptr, ws, need, scores, stream);
+    sw_status st{};
+    const int src = rc ? rc : sw_search_status_get(ws, stream, &st);   // synchronises the stream
+    const std::string err = g_err;
+    (void)hipFreeAsync(ws, stream);
+    (void)hipFreeAsync(dbw, stream);
     const hipError_t e = hipStreamSynchronize(stream);
-    (void)hipFree(ws);
     sw_db_release(db);
-    if (rc) return rc;
+    if (src) return fail(src, err);
     if (e != hipSuccess) return fail(SW_EHIP, std::string("search: ") + hipGetErrorString(e));
     return SW_OK;
 }
@@ -1540,12 +1699,12 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool re
 
 // Workspace of a pair, sized for every schedule (so the size does not depend
 // on the device or the matrix): padded subject, 16-bit profile, rowbuf,
-// colbuf, carry, store sinks, corners, profile descriptor and counters.  The columns of
+// colbuf, carry, store sinks, corners and the profile descriptor.  The columns of
 // rowbuf and the padded subject cover both tilings: rectangular tiles reach
 // nc * wc < n + wc, skewed ones n + K - 1 + wc.
 struct PairLayout {
     size_t subj = 0, prof = 0, rowbuf = 0, colbuf = 0, carry = 0, sink = 0, corner = 0, qd = 0, qoff = 0,
-           counters = 0, total = 0;
+           total = 0;
     int64_t n_pad = 0;
 };
 
@@ -1564,7 +1723,6 @@ PairLayout pair_layout(int64_t m, int64_t n, const PairPlanC* p, int64_t wc_max)
     }
     L.n_pad = cols + 128;
     size_t off = 0;
-    L.counters = off; off += 256;
     L.qd = off; off += 256;
     L.qoff = off; off += 256;
     L.corner = off; off += align_up((blocks + 2) * 3 * 4, 256);
@@ -1692,8 +1850,7 @@ int pair_setup(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint8_
     pa.q_off = qoff_dev;
     pa.qd = qd_dev;
     pa.prof = w + L.prof;
-    pa.counters = reinterpret_cast<int32_t*>(w + L.counters);
-    pa.heads = pa.counters + 8;
+    pa.bad = nullptr;          // a pair reads residue codes modulo 32
     pa.nq = 1;
     pa.go = go;
     pa.pad = elem == 1 ? -128 : -32768;

@@ -98,18 +98,26 @@ class GpuBackend:
             ws = self.db.alloc_workspace(lens, self.opt)
             out = torch.empty((len(lens), self.nseq), dtype=torch.int32, device=self.device)
             self.db.search_batch((cat, offs, lens), self.matrix, self.go, self.ge, opt=self.opt, out=out,
-                                 workspace=ws, stream=s)
+                                 workspace=ws, stream=s, check=False)
+            status = torch.zeros(4, dtype=torch.int32, pin_memory=True)
+            self.db.status_async(ws, status, stream=s)
             res = torch.empty((len(lens), self.nseq), dtype=torch.int32, pin_memory=True)
             res.copy_(out, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        return {"event": ev, "res": res, "keep": (host, cat, ws, out)}
+        return {"event": ev, "res": res, "status": status, "keep": (host, cat, ws, out)}
 
     def poll(self, handle) -> bool:
         return handle["event"].query()
 
     def results(self, handle) -> List[np.ndarray]:
+        """Score rows of a finished batch; raises the batch's status error (a
+        residue code >= 32, an incomplete exact rescore) instead."""
+        from . import status_error
         handle["event"].synchronize()
+        err = status_error(handle["status"])
+        if err is not None:
+            raise err
         r = handle["res"].numpy()
         return [r[k].copy() for k in range(r.shape[0])]
 
@@ -150,6 +158,7 @@ class Server:
         self.max_in_use = 0
         self.batch_sizes = []
         self.errors = []
+        self._failed = None            # the error that stopped the scheduler, if any
 
     # ------------------------------------------------------------------ client side
 
@@ -168,6 +177,9 @@ class Server:
             req.future.set_exception(MemoryError(f"request needs {need} bytes, budget {self.mem_budget}"))
             return req.future
         with self._cv:
+            if self._failed is not None:
+                req.future.set_exception(RuntimeError(f"server stopped after an error: {self._failed!r}"))
+                return req.future
             if self.first_arrival is None:
                 self.first_arrival = now
             self._pending.append(req)
@@ -301,14 +313,33 @@ class Server:
             launched = True
 
     def _loop(self):
-        while True:
-            progressed = self._complete()
-            progressed |= self._admit()
-            with self._cv:
-                if not self._running and not self._pending and not self._inflight:
-                    return
-                if not progressed:
-                    if self._inflight:
-                        self._cv.wait(self.poll_interval)
-                    else:
-                        self._cv.wait(0.05)
+        try:
+            while True:
+                progressed = self._complete()
+                progressed |= self._admit()
+                with self._cv:
+                    if not self._running and not self._pending and not self._inflight:
+                        return
+                    if not progressed:
+                        if self._inflight:
+                            self._cv.wait(self.poll_interval)
+                        else:
+                            self._cv.wait(0.05)
+        except BaseException as e:          # e.g. an asynchronous device error raised by poll()
+            self._fail_all(e)
+
+    def _fail_all(self, err):
+        """The scheduler cannot go on: fail every pending and in-flight request
+        with ``err`` and stop accepting work."""
+        self.errors.append(err)
+        with self._cv:
+            self._failed = err
+            self._running = False
+            reqs = [r for _, _, batch, _, _ in self._inflight for r in batch] + list(self._pending)
+            self._inflight = []
+            self._pending.clear()
+        for r in reqs:
+            if not r.future.done():
+                if not r.started and not r.future.set_running_or_notify_cancel():
+                    continue
+                r.future.set_exception(err)

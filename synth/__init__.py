@@ -358,6 +358,20 @@ def poisson_arrivals(rng: np.random.Generator, rate: float, n: int) -> np.ndarra
     return np.cumsum(rng.exponential(1.0 / rate, size=int(n)))
 
 
+def serve_requests(n: int, seed: int = 77) -> List[np.ndarray]:
+    """The serving workload's request stream: ``n`` queries with log-normal
+    lengths (median 350, sigma 0.75, clamped 50..5,000), in arrival order.
+    Lengths and residues come from separate streams, drawn in order, so the
+    first k requests are the same for every n >= k (the first requests of the
+    default stream carry stored oracle digests)."""
+    r_len, r_res = _streams(seed, 2)
+    out = []
+    for _ in range(int(n)):
+        m = int(lognormal_lengths(r_len, 1, 350, 0.75, 50, 5000)[0])
+        out.append(residues(r_res, m))
+    return out
+
+
 def random_case(rng: np.random.Generator, m: int, n_list: Sequence[int], alpha: int = 20,
                 matrix: Optional[np.ndarray] = None):
     """A query and a database with given subject lengths over ``alpha`` codes."""

@@ -23,8 +23,9 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ["sw_db_search", "sw_db_prepare", "sw_db_release", "sw_db_search_ex",
-                     "sw_db_search_batch", "sw_workspace_bytes", "sw_strerror", "sw_version"]:
+    for required in ["sw_db_search", "sw_db_prepare", "sw_db_prepare_bytes", "sw_db_release", "sw_db_search_ex",
+                     "sw_db_search_batch", "sw_workspace_bytes", "sw_search_status", "sw_flagged_count",
+                     "sw_strerror", "sw_version"]:
         assert required in names
 
 
@@ -37,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_errors():
     assert "gfx950" in swdb.version()
     L = swdb.lib()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.sw_strerror(code)
     assert L.sw_strerror(-99) == b"unknown error"
 
@@ -84,9 +85,72 @@ def test_handle_calls_reject_null():
                                 None, None) == -1
     assert L.sw_flagged_count(None, None) == -1
     h = ctypes.c_void_p()
-    assert L.sw_db_prepare(None, None, None, -1, None, ctypes.byref(h)) == -1
-    assert L.sw_db_prepare(None, None, None, 3, None, ctypes.byref(h)) == -1
-    assert L.sw_db_prepare(None, None, None, 0, None, None) == -1
+    assert L.sw_db_prepare(None, None, None, -1, ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(h)) == -1
+    assert L.sw_db_prepare(None, None, None, 3, ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(h)) == -1
+    assert L.sw_db_prepare(None, None, None, 0, ctypes.c_void_p(256), 1 << 20, None, None) == -1
+    # the workspace: required, 256-byte aligned
+    assert L.sw_db_prepare(ctypes.c_void_p(1), ctypes.c_void_p(8), ctypes.c_void_p(8), 3, None, 1 << 20, None,
+                           ctypes.byref(h)) == -1
+    assert L.sw_db_prepare(ctypes.c_void_p(1), ctypes.c_void_p(8), ctypes.c_void_p(8), 3, ctypes.c_void_p(264),
+                           1 << 20, None, ctypes.byref(h)) == -1
+    assert L.sw_search_status(None, None, None) == -1
+    assert L.sw_search_status_async(None, None, None) == -1
+    assert L.sw_status_code(None) == -1
+
+
+def test_prepare_bytes_bounds_and_monotone():
+    """sw_db_prepare_bytes: an upper bound of the exact layout (residues padded
+    per 64-subject chunk to its longest member, 1 KiB per 16 columns of a chunk,
+    plus metadata), monotone in each argument, 0 on inconsistent input."""
+    L = swdb.lib()
+    f = L.sw_db_prepare_bytes
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        nseq = int(rng.integers(1, 3000))
+        lens = rng.integers(0, int(rng.choice([5, 60, 400, 5000])), size=nseq)
+        total, mx = int(lens.sum()), int(lens.max())
+        if mx == 0:
+            continue
+        s = np.sort(lens)[::-1]
+        exact_res = sum(64 * ((int(s[c]) + 15) // 16 * 16) for c in range(0, nseq, 64))
+        meta = 12 * nseq
+        got = f(total, nseq, mx)
+        assert got >= exact_res + meta
+        assert got <= exact_res + meta + 64 * 16 * 3 + 1024 * 8 + 960 * ((nseq + 63) // 64) + 64 * mx
+        # monotone in every argument (where the arguments stay consistent)
+        assert f(total + 1, nseq, mx) >= got
+        assert f(total, nseq + 1, mx) >= got
+        if mx + 1 <= total:
+            assert f(total, nseq, mx + 1) >= got
+    assert f(0, 0, 0) > 0                 # an empty database still has a (tiny) layout
+    assert f(-1, 5, 3) == 0
+    assert f(10, 5, 11) == 0              # longest longer than the total
+    assert f(100, 5, 3) == 0              # 5 subjects of at most 3 cannot hold 100
+    assert f(5, 0, 0) == 0
+
+
+def test_prepare_rejects_small_workspace_before_hip():
+    """A workspace below the layout's metadata is SW_ENOMEM before any HIP
+    call (so on a host without a GPU too)."""
+    L = swdb.lib()
+    h = ctypes.c_void_p()
+    nseq = 1000
+    rc = L.sw_db_prepare(ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21), ctypes.c_void_p(1 << 22), nseq,
+                         ctypes.c_void_p(1 << 23), 4096, None, ctypes.byref(h))
+    assert rc == -2 and not h.value
+
+
+def test_status_codes():
+    """sw_status_code decodes the status words in priority order."""
+    L = swdb.lib()
+    for words, code in [((0, 0, 0, 0), 0), ((0, 0, 7, 0), 0), ((1, 0, 0, 0), -5), ((1, 3, 0, 1), -5),
+                        ((0, 2, 5, 0), -6), ((0, 2, 0, 1), -6), ((0, 0, 0, 1), -7)]:
+        st = swdb.Status(*words)
+        assert L.sw_status_code(ctypes.byref(st)) == code
+        err = swdb.status_error(np.array(words, dtype=np.int32))
+        assert (err is None) == (code == 0)
+        if err is not None:
+            assert err.code == code
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

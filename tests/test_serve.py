@@ -168,3 +168,63 @@ def test_percentiles_known_values():
     p50, p99 = percentiles(list(range(1, 101)))
     assert p50 == pytest.approx(50.5) and p99 == pytest.approx(99.01)
     assert percentiles([]) == (None, None)
+
+
+class PollRaises(FakeBackend):
+    """poll() raises on its n-th call, like an asynchronous device error
+    surfacing through Event.query()."""
+
+    def __init__(self, *a, raise_after=3, **kw):
+        super().__init__(*a, **kw)
+        self.calls = 0
+        self.raise_after = raise_after
+
+    def poll(self, h):
+        self.calls += 1
+        if self.calls >= self.raise_after:
+            raise RuntimeError("injected device error")
+        return super().poll(h)
+
+
+def test_scheduler_error_fails_every_request():
+    db, sm = _db(20), synth.blosum_style_matrix()
+    be = PollRaises(db, sm, delay=0.05)
+    srv = Server(be, max_batch=2, mem_budget=10**9).start()
+    rng = np.random.default_rng(9)
+    futs = [srv.submit(rng.integers(0, 20, size=30).astype(np.uint8)) for _ in range(8)]
+    for f in futs:
+        with pytest.raises(RuntimeError):
+            f.result(timeout=10)
+    srv.stop()
+    assert srv.errors and "injected device error" in str(srv.errors[-1])
+    late = srv.submit(np.zeros(5, np.uint8))
+    with pytest.raises(RuntimeError):
+        late.result(timeout=1)
+
+
+class StatusFails(FakeBackend):
+    """results() raises for batches holding a query of a given length, as the
+    GPU backend does when a batch's search status reports an error."""
+
+    def __init__(self, *a, bad_len=None, **kw):
+        super().__init__(*a, **kw)
+        self.bad_len = bad_len
+
+    def results(self, h):
+        if any(len(q) == self.bad_len for q in h["q"]):
+            raise RuntimeError("search status: exact int32 rescore incomplete")
+        return super().results(h)
+
+
+def test_status_error_fails_its_batch_only():
+    db, sm = _db(20), synth.blosum_style_matrix()
+    be = StatusFails(db, sm, delay=0.01, bad_len=13)
+    rng = np.random.default_rng(10)
+    with Server(be, max_batch=1, mem_budget=10**9) as srv:
+        good = [srv.submit(rng.integers(0, 20, size=40).astype(np.uint8)) for _ in range(3)]
+        bad = srv.submit(rng.integers(0, 20, size=13).astype(np.uint8))
+        good.append(srv.submit(rng.integers(0, 20, size=41).astype(np.uint8)))
+        with pytest.raises(RuntimeError):
+            bad.result(timeout=10)
+        for f in good:
+            assert f.result(timeout=10).shape == (db.nseq,)
