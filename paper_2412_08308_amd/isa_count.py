@@ -46,6 +46,9 @@ VARIANTS = {
     "i16_p8_self_glb": ("isa_i16_selfILi24ELi1ELb0E", 24, 2),
     "rescore_i32_r24": ("k_rescoreILi24ELi2E", 24, 1),
     "rescore_i32_r24_p8": ("k_rescoreILi24ELi1E", 24, 1),
+    # probe of an 8-bit lane form (four subjects per lane, byte-wise saturating
+    # arithmetic built from 32-bit operations; not part of the library)
+    "i8x4_probe": ("isa_i8x4ILi16E", 16, 4),
     # single long pair (csrc/sw_pair.hip), score pass over skewed tiles: R rows
     # per lane, 8- / 16-bit profile; the loop of tiles inside the matrix
     "pair_r8_p8": ("k_pair_skewILi8ELi1E", 8, 1),
