@@ -31,9 +31,11 @@ def _run(cmd):
     return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
 
 
-def build(out: str = LIB, extra=None, quiet: bool = True, jobs: int = 0) -> str:
-    """Compile every translation unit (in parallel) and link ``out``."""
+def build(out: str = LIB, extra=None, quiet: bool = True, jobs: int = 0, link_extra=None) -> str:
+    """Compile every translation unit (in parallel) and link ``out``;
+    ``extra`` / ``link_extra``: more compile / link flags."""
     extra = list(extra or [])
+    link_extra = list(link_extra or [])
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
     with tempfile.TemporaryDirectory(prefix="swdb_build_") as td:
         objs, procs, logs = [], [], []
@@ -53,7 +55,7 @@ def build(out: str = LIB, extra=None, quiet: bool = True, jobs: int = 0) -> str:
                 raise RuntimeError(f"hipcc failed on {src}:\n" + " ".join(cmd) + "\n" + text)
             logs.append(text)
         tmp = out + ".tmp"
-        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + link_extra + objs + ["-o", tmp]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("link failed:\n" + " ".join(cmd) + "\n" + r.stdout + r.stderr)
