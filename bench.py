@@ -216,20 +216,30 @@ def serving(args, capacity_gcups, mode):
     n = args.serve_requests
     qs = synth.serve_requests(n)
     qlens = np.array([len(q) for q in qs])
-    be = GpuBackend(gdb, w5.matrix, w5.gap_open, w5.gap_extend, mode=mode, n_streams=4, **KNOBS)
-    with Server(be, max_batch=16) as srv:                    # warm-up: plans, allocator, code
+    slice_mcells = int(capacity_gcups * args.serve_slice_ms) if args.serve_slice_ms > 0 else 0
+    be = GpuBackend(gdb, w5.matrix, w5.gap_open, w5.gap_extend, mode=mode, n_streams=4,
+                    slice_mcells=slice_mcells, **KNOBS)
+    rate = capacity_gcups * 1e9
+    srv_kw = dict(max_batch=16, rate_guess=rate, long_s=args.serve_long_ms / 1e3)
+    with Server(be, **srv_kw) as srv:                    # warm-up: plans, allocator, code
         for f in [srv.submit(q) for q in qs[:8]]:
             f.result()
     torch.cuda.synchronize()
+    # each request alone (the server idle when it arrives): its service time
+    edges = [int(x) for x in np.percentile(qlens, [100 / 3, 200 / 3])]
+    alone = Server(be, **srv_kw).start()
+    for q in qs:
+        alone.submit(q).result()
+    alone.stop()
+    alone_cls = alone.stats_by_length(edges)
     mean_m = float(np.mean(qlens))
     runs, checks = [], []
-    rate = capacity_gcups * 1e9
     for policy in args.serve_policies:
         arng = np.random.default_rng(78)          # the same arrival times for every policy
         for rho in args.serve_rho:
             lam = rho * capacity_gcups * 1e9 / (mean_m * w5.db.total)
             arrivals = synth.poisson_arrivals(arng, lam, n)
-            srv = Server(be, max_batch=16, policy=policy, rate_guess=rate).start()
+            srv = Server(be, policy=policy, **srv_kw).start()
             futs = []
             t0 = time.perf_counter()
             for k, q in enumerate(qs):
@@ -249,10 +259,15 @@ def serving(args, capacity_gcups, mode):
                                                        seed=len(runs))))
             print(f"[bench] serving {policy} rho={rho}: p50 {st['p50_s'] * 1e3:.1f} ms p99 {st['p99_s'] * 1e3:.1f} ms",
                   file=sys.stderr, flush=True)
+            cls = srv.stats_by_length(edges)
             runs.append({"policy": policy, "rho": rho, "rate_per_s": round(lam, 2), "requests": n,
                          "p50_ms": round(st["p50_s"] * 1e3, 2), "p99_ms": round(st["p99_s"] * 1e3, 2),
                          "sustained_gcups": round(st["sustained_gcups"], 1),
-                         "mean_batch": round(st["mean_batch"], 2), "max_batch": st["max_batch"]})
+                         "mean_batch": round(st["mean_batch"], 2), "max_batch": st["max_batch"],
+                         "by_length": [{"qlen": [c["qlen_lo"], c["qlen_hi"]], "requests": c["requests"],
+                                        "p50_ms": round(c["p50_s"] * 1e3, 2), "p99_ms": round(c["p99_s"] * 1e3, 2),
+                                        "p99_over_alone_p99": round(c["p99_s"] / a["p99_s"], 2)}
+                                       for c, a in zip(cls, alone_cls)]})
     gdb.release()
     parity = None
     if checks:
@@ -264,7 +279,13 @@ def serving(args, capacity_gcups, mode):
                   "sampled_scores": sum(c["scores"] for c in sp), "sample_mismatches": sum(c["mismatches"] for c in sp)}
     return {"workload": f"{w5.db.nseq} subjects ({w5.db.total} residues); {n} queries log-normal median 350 "
                         "clamped 50-5000; Poisson arrivals at rho x single-query capacity",
-            "capacity_gcups": round(capacity_gcups, 1), "runs": runs, "parity": parity}
+            "capacity_gcups": round(capacity_gcups, 1),
+            "server": {"slice_mcells": slice_mcells, "slice_ms": args.serve_slice_ms, "long_ms": args.serve_long_ms,
+                       "size_ratio": 4.0, "streams": 4, "max_batch": 16},
+            "alone_by_length": [{"qlen": [c["qlen_lo"], c["qlen_hi"]], "requests": c["requests"],
+                                 "p50_ms": round(c["p50_s"] * 1e3, 2), "p99_ms": round(c["p99_s"] * 1e3, 2)}
+                                for c in alone_cls],
+            "runs": runs, "parity": parity}
 
 
 def sample_parity(db, qs, res, sm, go, ge, seed=0, nreq=6, nsub=64):
@@ -561,6 +582,10 @@ def main(argv=None):
     ap.add_argument("--serve-rho", type=float, nargs="+", default=[0.5, 0.8])
     ap.add_argument("--serve-scale", type=float, default=1.0)
     ap.add_argument("--serve-policies", nargs="+", default=["edf", "fifo"], choices=["edf", "fifo"])
+    ap.add_argument("--serve-slice-ms", type=float, default=3.0,
+                    help="device time per persistent launch of a serving batch (0: one launch)")
+    ap.add_argument("--serve-long-ms", type=float, default=20.0,
+                    help="estimated device time above which a request is long (keeps a slot for short ones)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (traffic calibration)")
     args = ap.parse_args(argv)

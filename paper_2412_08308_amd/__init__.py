@@ -50,7 +50,7 @@ class Options(ctypes.Structure):
                 ("lds_limit", ctypes.c_int32), ("grid_limit", ctypes.c_int32),
                 ("wide_profile", ctypes.c_int32), ("pair_cols", ctypes.c_int32),
                 ("pair_rows", ctypes.c_int32), ("align_block", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6),
+                ("slice_mcells", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
                 ("ev_search_begin", ctypes.c_void_p), ("ev_search_end", ctypes.c_void_p),
                 ("ev_rescore_end", ctypes.c_void_p)]
 
@@ -202,8 +202,9 @@ def version() -> str:
 
 
 def options(mode="auto", waves=0, lane_cells=0, max_lanes=0, lds_limit=0, grid_limit=0,
-            wide_profile=0, pair_cols=0, pair_rows=0, align_block=0) -> Options:
+            wide_profile=0, pair_cols=0, pair_rows=0, align_block=0, slice_mcells=0) -> Options:
     o = Options()
+    o.slice_mcells = int(slice_mcells)
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.waves, o.lane_cells, o.max_lanes = int(waves), int(lane_cells), int(max_lanes)
     o.lds_limit, o.grid_limit = int(lds_limit), int(grid_limit)

@@ -84,6 +84,7 @@ struct PlanKey {
 // Work items of one query (q field 0), largest per-lane work first.
 struct QPlan {
     std::vector<Item> items;
+    std::vector<int64_t> item_cost;   // per-lane work of each item
     int64_t slot_elems = 0;       // int2 entries a multi-pass item needs
     int64_t lane_cells = 0;       // sum over items of 64 * per-lane cells
     int64_t cost = 0;             // sum of per-lane work over items
@@ -138,6 +139,7 @@ bool validate_options(const sw_options* opt, std::string& why)
     if (opt->pair_cols < 0) { why = "options.pair_cols"; return false; }
     if (opt->pair_rows < 0) { why = "options.pair_rows"; return false; }
     if (opt->align_block < 0 || opt->align_block > (1 << 24)) { why = "options.align_block must be 0..2^24"; return false; }
+    if (opt->slice_mcells < 0) { why = "options.slice_mcells"; return false; }
     return true;
 }
 
@@ -337,8 +339,10 @@ std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, con
     std::stable_sort(wis.begin(), wis.end(), [](const WItem& a, const WItem& b) { return a.cost > b.cost; });
     p->nitems = (int64_t)wis.size();
     p->items.resize(wis.size());
+    p->item_cost.resize(wis.size());
     for (size_t i = 0; i < wis.size(); ++i) {
         p->items[i] = wis[i].it;
+        p->item_cost[i] = wis[i].cost;
         p->cost += wis[i].cost;
     }
     p->slot_elems = align_up(p->slot_elems, 4);
@@ -369,6 +373,7 @@ struct Layout {
     std::vector<QueryDesc> qd;        // queue order; out_row = query's position in the call
     std::vector<std::shared_ptr<QPlan>> plans;   // by position in the call
     std::vector<int32_t> order;       // queue position -> position in the call
+    std::vector<std::pair<int64_t, int64_t>> ranges;   // by position: window [begin, end) of the plan's items
     int64_t grid = 0, rgrid = 0;
     int rwaves = 1;               // wavefronts per rescore workgroup
     int64_t slot_elems = 0, rslot_elems = 0;
@@ -384,12 +389,29 @@ struct Layout {
     int64_t flag_cap = 0;
 };
 
-int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& r, Layout& L)
+// Real cells of items [b, e) of a query of m rows.
+int64_t range_cells(const sw_db_s* db, const QPlan& p, int64_t b, int64_t e, int32_t m)
+{
+    int64_t n = 0;
+    for (int64_t i = b; i < e; ++i) {
+        const Item& it = p.items[i];
+        for (int k = 0; k < (it.meta & 0xffff); ++k)
+            n += db->slen[(size_t)it.s0 + k];
+    }
+    return n * m;
+}
+
+// Layout of a launch group of nq queries; `ranges` (by position in the call,
+// may be null for every item) limits each query to a window of its plan's
+// items -- one launch of a sliced search.
+int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& r, Layout& L,
+                const std::vector<std::pair<int64_t, int64_t>>* ranges = nullptr)
 {
     L.r = r;
     L.nq = nq;
     L.qd.assign(nq, QueryDesc{});
     L.plans.assign(nq, nullptr);
+    L.ranges.assign(nq, {0, 0});
     int64_t prof = 0;
     int64_t slot_need = 0;
     for (int32_t k = 0; k < nq; ++k) {
@@ -409,9 +431,20 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
         prof += align_up(pb, 256);
         L.plans[k] = get_plan(db, nbr, r);
         slot_need = std::max(slot_need, L.plans[k]->slot_elems);
-        L.cells += (int64_t)m * db->total;
-        L.lane_cells += L.plans[k]->lane_cells;
-        L.nitems += L.plans[k]->nitems;
+        const QPlan& pl = *L.plans[k];
+        if (ranges) {
+            const auto [b, e] = (*ranges)[k];
+            if (b < 0 || e > pl.nitems || b > e) return fail(SW_EINVAL, "internal error: item window");
+            L.ranges[k] = {b, e};
+            L.cells += range_cells(db, pl, b, e, m);
+            L.lane_cells += kWave * std::accumulate(pl.item_cost.begin() + b, pl.item_cost.begin() + e, int64_t(0));
+            L.nitems += e - b;
+        } else {
+            L.ranges[k] = {0, pl.nitems};
+            L.cells += (int64_t)m * db->total;
+            L.lane_cells += pl.lane_cells;
+            L.nitems += pl.nitems;
+        }
     }
     // queue: largest query first; descriptors stored in queue order
     L.order.resize(nq);
@@ -427,8 +460,8 @@ int make_layout(sw_db_s* db, int32_t nq, const int32_t* q_lens, const Resolved& 
         const int32_t k = L.order[p];
         L.qd[p] = by_call[k];
         L.qd[p].item_begin = (int32_t)nit;
-        L.qd[p].item_count = (int32_t)L.plans[k]->nitems;
-        nit += L.plans[k]->nitems;
+        L.qd[p].item_count = (int32_t)(L.ranges[k].second - L.ranges[k].first);
+        nit += L.qd[p].item_count;
         if (nit > INT32_MAX / 2)
             return fail(SW_EINVAL, "batch too large for one launch");
     }
@@ -568,6 +601,54 @@ sw_options tuned_for(const sw_db_s* db, int32_t m, int* which)
     return o;
 }
 
+// A launch group cut into launches of at most `limit` lane cells each: its
+// queue (queries in queue order, each query's items largest first) is walked
+// in order and every launch takes the next items until the limit would be
+// passed (at least one item).  Each launch keeps the group's schedule, so its
+// items are exactly the group's, and writes its queries' rows.
+int slice_part(sw_db_s* db, const Part& P, int64_t limit, std::vector<Part>& out)
+{
+    const Layout& L = P.L;
+    struct Piece { int32_t k; int64_t b, e; };
+    std::vector<Piece> cur;
+    int64_t acc = 0;
+    auto flush = [&]() -> int {
+        if (cur.empty()) return SW_OK;
+        Part S;
+        std::vector<std::pair<int64_t, int64_t>> ranges;
+        for (const Piece& pc : cur) {         // queue order; make_layout keeps it (same plan costs)
+            S.idx.push_back(P.idx[pc.k]);
+            S.lens.push_back(P.lens[pc.k]);
+            S.offs.push_back(P.offs[pc.k]);
+            ranges.push_back({pc.b, pc.e});
+        }
+        const int rc = make_layout(db, (int32_t)S.idx.size(), S.lens.data(), L.r, S.L, &ranges);
+        if (rc) return rc;
+        for (QueryDesc& d : S.L.qd)
+            d.out_row = S.idx[d.out_row];
+        out.push_back(std::move(S));
+        cur.clear();
+        acc = 0;
+        return SW_OK;
+    };
+    for (int32_t k : L.order) {
+        const QPlan& pl = *L.plans[k];
+        int64_t b = L.ranges[k].first;
+        for (int64_t i = L.ranges[k].first; i < L.ranges[k].second; ++i) {
+            const int64_t c = kWave * pl.item_cost[i];
+            if (acc > 0 && acc + c > limit) {
+                if (i > b) cur.push_back({k, b, i});
+                const int rc = flush();
+                if (rc) return rc;
+                b = i;
+            }
+            acc += c;
+        }
+        if (L.ranges[k].second > b) cur.push_back({k, b, L.ranges[k].second});
+    }
+    return flush();
+}
+
 int build_parts(sw_db_s* db, int32_t nq, const int32_t* q_lens, const int64_t* q_offsets,
                 const sw_options* opt, int elem, std::vector<Part>& parts)
 {
@@ -602,6 +683,14 @@ int build_parts(sw_db_s* db, int32_t nq, const int32_t* q_lens, const int64_t* q
         if (rc) return rc;
         for (QueryDesc& d : P.L.qd)
             d.out_row = P.idx[d.out_row];
+    }
+    if (opt && opt->slice_mcells > 0) {
+        std::vector<Part> sliced;
+        for (const Part& P : parts) {
+            const int rc = slice_part(db, P, (int64_t)opt->slice_mcells * 1000000, sliced);
+            if (rc) return rc;
+        }
+        parts.swap(sliced);
     }
     return SW_OK;
 }
@@ -670,8 +759,8 @@ void fill_blob(const Layout& L, const int64_t* q_offsets, uint8_t* h)
     for (int32_t p = 0; p < L.nq; ++p) {
         const int32_t k = L.order[p];
         qoff[p] = q_offsets[k];
-        for (const Item& it0 : L.plans[k]->items) {
-            Item it = it0;
+        for (int64_t i = L.ranges[k].first; i < L.ranges[k].second; ++i) {
+            Item it = L.plans[k]->items[i];
             it.q = p;
             items[pos++] = it;
         }
@@ -1063,7 +1152,8 @@ int64_t sw_plan_items(sw_db_t db, int32_t nq, const int32_t* q_lens, const sw_op
     int64_t pos = 0;
     for (const Part& P : parts) {
         for (int32_t k : P.L.order) {
-            for (const Item& it : P.L.plans[k]->items) {
+            for (int64_t i = P.L.ranges[k].first; i < P.L.ranges[k].second; ++i) {
+                const Item& it = P.L.plans[k]->items[i];
                 if (pos < cap) {
                     out[4 * pos + 0] = it.s0;
                     out[4 * pos + 1] = it.ncols;
@@ -2122,6 +2212,58 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     return pair_enqueue(p, L, static_cast<uint8_t*>(ws), query, m, subject, n, sm, go, ge, elem, score_out,
                         nullptr, nullptr, opt ? opt->ev_search_begin : nullptr,
                         opt ? opt->ev_search_end : nullptr, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ pair score without allocation
+//
+// Device scratch of sw_pair_score_static: one array per GPU, held until the
+// process ends.  Host code never uses the array's name as an address (it is a
+// host-side stand-in); the device address comes from hipGetSymbolAddress,
+// taken once per device on that device's first call.
+static __device__ __align__(256) uint8_t scratch[SW_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, uint8_t*> g_scratch;      // device -> address of its copy of `scratch`
+
+int static_scratch(uint8_t** out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto f = g_scratch.find(dev);
+    if (f == g_scratch.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SW_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        f = g_scratch.emplace(dev, static_cast<uint8_t*>(p)).first;
+    }
+    *out = f->second;
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_pair_score_static(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n, const int32_t* sm,
+                         int32_t go, int32_t ge, const sw_options* opt, int32_t* score_out, hipStream_t stream)
+{
+    std::string why;
+    if (!validate_pair(m, n, opt, why)) return fail(SW_EINVAL, why);
+    const size_t need = sw_pair_workspace_bytes(m, n, opt);
+    if (need > SW_STATIC_SCRATCH_BYTES)
+        return fail(SW_ENOMEM, "pair needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                                   std::to_string((long long)SW_STATIC_SCRATCH_BYTES) +
+                                   " bytes of the static scratch; use sw_pair_score with a workspace");
+    uint8_t* ws = nullptr;
+    const int rc = static_scratch(&ws);
+    if (rc) return rc;
+    return sw_pair_score(query, m, subject, n, sm, go, ge, opt, ws, SW_STATIC_SCRATCH_BYTES, score_out, stream);
 }
 
 size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt)

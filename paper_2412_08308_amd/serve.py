@@ -10,9 +10,16 @@ scheduler thread
   over the device rate observed on completed batches, so a short request
   overtakes long ones that arrived about as early, while no deadline moves)
   or of arrival (``policy="fifo"``);
-* groups everything admissible into one batched launch
+* groups admissible requests of similar size into one batched launch
   (``sw_db_search_batch``) on a free stream of a small stream pool, so batches
-  that arrive while others run are searched concurrently on the device;
+  that arrive while others run are searched concurrently on the device: a
+  batch takes the first pending request and those within ``size_ratio`` of
+  its cells (a short request never waits for a long one in its own batch),
+  and requests longer than ``long_s`` of estimated device time may hold all
+  but one of the in-flight slots, so a short request always finds a slot;
+* the GPU backend cuts each batch's work into persistent launches of a few
+  milliseconds (``slice_mcells``), so a short batch on another stream gets
+  the device between the launches of a long one instead of after it;
 * records a completion event per batch (after an asynchronous copy of the
   scores to pinned host memory) and resolves each request's future when it
   fires, with the latency (completion - arrival) attached.
@@ -61,7 +68,7 @@ class GpuBackend:
     """Batched searches on a pool of HIP streams through ``Database.search_batch``."""
 
     def __init__(self, db, matrix, gap_open: int, gap_extend: int, mode="auto", n_streams: int = 4,
-                 **opt_kw):
+                 slice_mcells: int = 0, **opt_kw):
         import torch
 
         from . import options
@@ -69,7 +76,7 @@ class GpuBackend:
         self.db = db
         self.matrix = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
         self.go, self.ge = int(gap_open), int(gap_extend)
-        self.opt = options(mode=mode, **opt_kw)
+        self.opt = options(mode=mode, slice_mcells=slice_mcells, **opt_kw)
         self.device = db.device
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.nseq = db.nseq
@@ -127,10 +134,13 @@ class Server:
 
     def __init__(self, backend, max_batch: int = 16, max_inflight: Optional[int] = None,
                  mem_budget: Optional[int] = None, poll_interval: float = 1e-4, clock=time.perf_counter,
-                 policy: str = "edf", rate_guess: float = 1e12):
+                 policy: str = "edf", rate_guess: float = 1e12, size_ratio: float = 4.0,
+                 long_s: float = 0.02):
         if policy not in ("edf", "fifo"):
             raise ValueError("policy must be 'edf' or 'fifo'")
         self.policy = policy
+        self.size_ratio = float(size_ratio)   # 0: batch regardless of size
+        self.long_s = float(long_s)           # estimated device time that makes a request long
         self.rate = float(rate_guess)       # cells per second, updated from completed batches
         self.backend = backend
         self.max_batch = int(max_batch)
@@ -151,6 +161,7 @@ class Server:
         self._running = False
         self._thread = None
         self.latencies = []
+        self.by_qlen = []              # (query length, latency) of completed requests
         self.completed = 0
         self.cells_done = 0
         self.first_arrival = None
@@ -211,6 +222,18 @@ class Server:
     def __exit__(self, *exc):
         self.stop(drain=True)
 
+    def stats_by_length(self, edges: Sequence[int]) -> List[dict]:
+        """p50 / p99 latency per query-length class: lengths below edges[0],
+        between consecutive edges, and from edges[-1] up."""
+        bounds = [0] + [int(e) for e in edges] + [1 << 62]
+        out = []
+        for lo, hi in zip(bounds[:-1], bounds[1:]):
+            lat = [x for m, x in self.by_qlen if lo <= m < hi]
+            p50, p99 = percentiles(lat)
+            out.append({"qlen_lo": lo, "qlen_hi": hi if hi < (1 << 62) else None, "requests": len(lat),
+                        "p50_s": p50, "p99_s": p99})
+        return out
+
     def stats(self) -> dict:
         p50, p99 = percentiles(self.latencies)
         span = (self.last_completion - self.first_arrival) if self.completed else None
@@ -244,6 +267,7 @@ class Server:
                     continue
                 r.future.latency = t - r.arrival
                 self.latencies.append(r.future.latency)
+                self.by_qlen.append((r.qlen, r.future.latency))
                 self.completed += 1
                 r.future.set_result(rows[k])
             if err is None:
@@ -267,19 +291,39 @@ class Server:
                 batch, lens = [], []
                 if self.policy == "edf" and len(self._pending) > 1:
                     self._pending = collections.deque(sorted(self._pending, key=lambda r: (r.deadline, r.id)))
-                while self._pending and len(batch) < self.max_batch:
-                    r = self._pending[0]
-                    if r.future.cancelled():
-                        self._pending.popleft()
-                        continue
-                    need = self.backend.need_bytes(lens + [r.qlen])
-                    if self._in_use + need > self.mem_budget:
-                        break
+                while self._pending and self._pending[0].future.cancelled():
                     self._pending.popleft()
+                if not self._pending:
+                    return launched
+                head = self._pending[0]
+                head_cells = max(self.backend.cells([head.qlen]), 1)
+                if (self.max_inflight >= 2 and self._is_long(head.qlen)
+                        and self._long_inflight() >= self.max_inflight - 1):
+                    # the last free slot stays for a request that is not long
+                    short = next((r for r in self._pending if not self._is_long(r.qlen)
+                                  and not r.future.cancelled()), None)
+                    if short is None:
+                        return launched
+                    head, head_cells = short, max(self.backend.cells([short.qlen]), 1)
+                keep = collections.deque()
+                for r in list(self._pending):
+                    if len(batch) >= self.max_batch or r.future.cancelled():
+                        if not r.future.cancelled():
+                            keep.append(r)
+                        continue
+                    c = self.backend.cells([r.qlen])
+                    similar = r is head or self.size_ratio <= 0 or (
+                        head_cells / self.size_ratio <= c <= head_cells * self.size_ratio
+                        and (not self._is_long(r.qlen) or self._is_long(head.qlen)))
+                    need = self.backend.need_bytes(lens + [r.qlen])
+                    if (not batch and r is not head) or not similar or self._in_use + need > self.mem_budget:
+                        keep.append(r)
+                        continue
                     batch.append(r)
                     lens.append(r.qlen)
                 if not batch:
                     return launched
+                self._pending = keep
                 nbytes = self.backend.need_bytes(lens)
                 slot = self._free_slots.pop()
                 self._in_use += nbytes
@@ -311,6 +355,12 @@ class Server:
             self.batch_sizes.append(len(batch))
             self._inflight.append((slot, h, batch, nbytes, self.clock()))
             launched = True
+
+    def _is_long(self, qlen: int) -> bool:
+        return self.backend.cells([qlen]) / self.rate > self.long_s
+
+    def _long_inflight(self) -> int:
+        return sum(1 for _, _, reqs, _, _ in self._inflight if any(self._is_long(r.qlen) for r in reqs))
 
     def _loop(self):
         try:

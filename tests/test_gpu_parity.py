@@ -218,3 +218,46 @@ def test_q567_vs_200k_sampled():
     ids = np.unique(np.concatenate([order[:200], order[-100:],
                                     rng.choice(w.db.nseq, size=700, replace=False)]))
     _check(w.db, w.queries[0], w.matrix, w.gap_open, w.gap_extend, modes=["i32", "auto"], ids=ids)
+
+
+@pytest.mark.parametrize("mode", ["auto", "i32", "tuned"])
+def test_sliced_launches(mode):
+    """A search cut into many persistent launches (slice_mcells) equals the
+    oracle: single queries, a batch, a tuned table with several launch groups,
+    and 16-bit overflows rescored per launch."""
+    import paper_2412_08308_amd as swdb
+    rng = np.random.default_rng(19)
+    sm = synth.blosum_style_matrix()
+    lens = rng.integers(0, 900, size=1200).tolist() + [0, 1, 6000, 12000]
+    _, db = synth.random_case(rng, 1, lens)
+    qs = [synth.residues(rng, int(m)) for m in [300, 0, 17, 1500, 4000, 64]]
+    gdb = gpu_db(db)
+    try:
+        if mode == "tuned":
+            gdb.set_tuning([{"qlen": 100, "mode": 2, "waves": 8, "lane_cells": 24576},
+                            {"qlen": 2000, "mode": 1, "waves": 4, "lane_cells": 49152},
+                            {"qlen": 9000, "mode": 2, "waves": 4, "lane_cells": 98304}])
+        for mc in (1, 40):
+            announce(f"sliced batch mode={mode} slice_mcells={mc}")
+            got = gpu_batch(gdb, qs, sm, 10, 2, mode=mode, slice_mcells=mc)
+            for k, q in enumerate(qs):
+                exp = oracle_scores(db, q, sm, 10, 2)
+                assert np.array_equal(got[k], exp), f"{mode} {mc} query {k}: " + mismatch_report(got[k], exp)
+            assert gdb.plan_info([len(q) for q in qs], swdb.options(mode=mode, slice_mcells=mc))["launches"] > 1
+    finally:
+        gdb.release()
+    # overflows rescored inside sliced launches
+    sm2 = overflow_matrix(127, -10)
+    subj = [overflow_sequence(t, 127) for t in (32766, 32767, 40000)] * 3
+    subj += [rng.integers(2, 20, size=int(n)).astype(np.uint8) for n in rng.integers(10, 300, size=200)]
+    db2 = synth.Database.from_list(subj)
+    q2 = np.concatenate([np.zeros(400, np.uint8), np.ones(300, np.uint8)])
+    if mode != "tuned":
+        announce(f"sliced overflow mode={mode}")
+        gdb2 = gpu_db(db2)
+        try:
+            got = gpu_scores(gdb2, q2, sm2, 10, 2, mode=mode, slice_mcells=1)
+            exp = oracle_scores(db2, q2, sm2, 10, 2)
+            assert np.array_equal(got, exp), mismatch_report(got, exp)
+        finally:
+            gdb2.release()

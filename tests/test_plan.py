@@ -146,3 +146,40 @@ def test_tuned_mode_splits_batch_by_schedule():
             db.set_tuning([{"qlen": 10, "mode": swdb.MODE_TUNED}])
     finally:
         db.release()
+
+
+@pytest.mark.parametrize("mode", ["auto", "i32", "tuned"])
+@pytest.mark.parametrize("mcells", [1, 7, 60])
+def test_sliced_launches_cover_the_same_items(mode, mcells):
+    """slice_mcells cuts every launch group's queue into launches of at most
+    that many million lane cells (at least one item each): the items are
+    exactly those of the unsliced search, in the same order, and the cells
+    add up to the same total."""
+    db = swdb.Database.describe(_lengths("ragged"), cu_count=256)
+    if mode == "tuned":
+        db.set_tuning([{"qlen": 300, "mode": 2, "waves": 8, "lane_cells": 49152},
+                       {"qlen": 5000, "mode": 1, "waves": 4, "lane_cells": 98304}])
+    qlens = [1000, 0, 17, 300, 2500, 64]
+    base = swdb.options(mode=mode)
+    sl = swdb.options(mode=mode, slice_mcells=mcells)
+    a, b = db.plan_items(qlens, base), db.plan_items(qlens, sl)
+    assert np.array_equal(a, b)
+    pa, pb = db.plan_info(qlens, base), db.plan_info(qlens, sl)
+    assert pb["cells"] == pa["cells"] and pb["items"] == pa["items"]
+    assert pb["lane_cells"] == pa["lane_cells"]
+    assert pb["launches"] >= pa["launches"]
+    # no launch is empty; a limit above the group's work leaves one launch
+    assert pb["launches"] <= pb["items"]
+    if mcells == 1:
+        assert pb["launches"] > 10 * pa["launches"]
+    big = swdb.options(mode=mode, slice_mcells=pa["lane_cells"] // 10**6 + 1)
+    assert db.plan_info(qlens, big)["launches"] == pa["launches"]
+    assert db.workspace_bytes(qlens, sl) <= db.workspace_bytes(qlens, base)
+    db.release()
+
+
+def test_slice_option_validated():
+    db = swdb.Database.describe(_lengths("tiny"))
+    with pytest.raises(swdb.SwdbError):
+        db.plan_info([10], swdb.options(slice_mcells=-1))
+    db.release()

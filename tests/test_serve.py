@@ -228,3 +228,55 @@ def test_status_error_fails_its_batch_only():
             bad.result(timeout=10)
         for f in good:
             assert f.result(timeout=10).shape == (db.nseq,)
+
+
+def test_short_requests_not_batched_with_long():
+    """A batch holds requests within size_ratio of its first request's cells:
+    short and long requests pending together go to different batches."""
+    db, sm = _db(), synth.blosum_style_matrix()
+    be = FakeBackend(db, sm, delay=0.05)
+    rate = be.cells([1]) / 1e-3
+    srv = Server(be, max_batch=8, max_inflight=1, mem_budget=10**9, rate_guess=rate, long_s=10.0).start()
+    blocker = srv.submit(np.ones(30, np.uint8))
+    time.sleep(0.01)
+    futs = [srv.submit(np.ones(m, np.uint8)) for m in (40, 5, 45, 6, 4)]
+    for f in [blocker] + futs:
+        f.result(timeout=10)
+    srv.stop()
+    batches = [sorted(lens) for _, lens in be.launches]
+    assert batches[0] == [30]
+    assert sorted(map(tuple, batches[1:])) == [(4, 5, 6), (40, 45)]
+
+
+def test_one_slot_kept_for_short_requests():
+    """Long requests hold at most all but one in-flight slot: with two slots
+    and two long requests pending, a short one arriving later runs before the
+    second long one starts."""
+    db, sm = _db(), synth.blosum_style_matrix()
+    be = FakeBackend(db, sm, delay=0.08)
+    be.slots = 2
+    rate = be.cells([1]) / 1e-3        # 1 ms per residue: 40 residues = 40 ms > long_s
+    srv = Server(be, max_batch=1, mem_budget=10**9, rate_guess=rate, long_s=0.02).start()
+    l1 = srv.submit(np.ones(40, np.uint8))
+    l2 = srv.submit(np.ones(41, np.uint8))
+    time.sleep(0.02)
+    sh = srv.submit(np.ones(5, np.uint8))
+    for f in (l1, l2, sh):
+        f.result(timeout=10)
+    srv.stop()
+    order = [lens[0] for _, lens in be.launches]
+    assert order == [40, 5, 41]
+    assert be.max_active <= 2
+
+
+def test_latency_by_length_class():
+    db, sm = _db(), synth.blosum_style_matrix()
+    be = FakeBackend(db, sm, delay=0.005)
+    with Server(be, max_batch=4, mem_budget=10**9) as srv:
+        fs = [srv.submit(np.ones(m, np.uint8)) for m in (3, 8, 15, 30, 31, 60)]
+        for f in fs:
+            f.result(timeout=10)
+    cls = srv.stats_by_length([10, 30])
+    assert [c["requests"] for c in cls] == [2, 1, 3]
+    assert cls[0]["qlen_lo"] == 0 and cls[2]["qlen_hi"] is None
+    assert all(c["p50_s"] > 0 and c["p99_s"] >= c["p50_s"] for c in cls)
