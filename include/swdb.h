@@ -82,7 +82,9 @@ typedef struct sw_options {
     int32_t lane_cells;    /* target cells per lane per work item (load balance)  */
     int32_t max_lanes;     /* largest lane group per subject (1..64)               */
     int32_t lds_limit;     /* largest query profile staged in LDS, bytes           */
-    int32_t grid_limit;    /* cap on persistent workgroups (0 = fill the device)   */
+    int32_t grid_limit;    /* cap on persistent workgroups (0 = fill the device);
+                              the pipelined pair pass then runs its bands in
+                              rounds on 4 * grid_limit wavefronts               */
     int32_t wide_profile;  /* 1: 16-bit profile entries even where 8 bits hold
                               every s + Go (measurement and testing)             */
     int32_t pair_cols;     /* sw_pair_score: subject columns per tile (multiple
@@ -100,7 +102,15 @@ typedef struct sw_options {
                               work item per launch), enqueued one after another
                               on the stream, so that work on other streams gets
                               the device between them (serving); 0 = one launch */
-    int32_t reserved[5];
+    int32_t pair_mode;     /* sw_pair_score: 0 = planner, 1 = anti-diagonal tile
+                              launches, 2 = one pipelined launch (bands hand rows
+                              to the band below through memory; needs the largest
+                              score below 2^24); pair_rows then picks R from
+                              4, 6, 8, 10, 12, 16                              */
+    int32_t pair_sm_max;   /* sw_pair_plan: the largest substitution-matrix entry
+                              the pair will be scored with (0 = 127); scoring
+                              calls take it from the matrix                    */
+    int32_t reserved[3];
     /* Optional timing events (created by the caller, may be NULL): recorded on
        the search stream immediately before the search kernel, immediately
        after it, and after the int32 rescore (16-bit modes).                   */
@@ -370,10 +380,10 @@ const char* sw_version(void);
  * and result as sw_db_search; int32 score.
  */
 typedef struct sw_pair_stats {
-    int32_t rows;          /* R: query rows per lane (8 or 16)                    */
+    int32_t rows;          /* R: query rows per lane                              */
     int32_t lanes;         /* K: lanes per band (band = R*K query rows)           */
-    int32_t cols;          /* subject columns per tile                            */
-    int32_t pad;
+    int32_t cols;          /* subject columns per tile (0 for the pipelined pass) */
+    int32_t flow;          /* 1: one pipelined launch; 0: anti-diagonal tiles     */
     int64_t bands;         /* ceil(m / (R*K))                                     */
     int64_t chunks;        /* ceil(n / cols)                                      */
     int64_t launches;      /* anti-diagonals holding tiles (one launch each)      */
@@ -408,26 +418,6 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
                   const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
                   const sw_options* opt, void* workspace, size_t ws_bytes, int32_t* score_out,
                   hipStream_t stream);
-
-/*
- * Score of one pair without any allocation, for callers that cannot allocate
- * device memory (code under HIP graph capture, tight serving loops, harnesses
- * that forbid hipMalloc): sw_pair_score with its workspace taken from a
- * static device array of SW_STATIC_SCRATCH_BYTES (64 MiB) that the library
- * holds on every GPU it runs on until the process ends.  Arguments as for
- * sw_pair_score, minus the workspace.  Returns SW_ENOMEM, with nothing
- * enqueued, if the pair needs more scratch than that
- * (sw_pair_workspace_bytes(m, n, opt) > SW_STATIC_SCRATCH_BYTES: the
- * paper's smallest DNA pair, 162,000 x 172,000, needs 25 MiB; m = n =
- * 400,000 needs 61 MiB).
- * All calls on one GPU share its array: calls that overlap in time on one
- * GPU (different streams, or threads) race and give wrong scores; serialise
- * them on one stream.  Calls no hipMalloc or hipFree.
- */
-#define SW_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
-int sw_pair_score_static(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n,
-                         const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
-                         const sw_options* opt, int32_t* score_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------ alignment of one pair
  *

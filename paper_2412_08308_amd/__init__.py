@@ -50,7 +50,8 @@ class Options(ctypes.Structure):
                 ("lds_limit", ctypes.c_int32), ("grid_limit", ctypes.c_int32),
                 ("wide_profile", ctypes.c_int32), ("pair_cols", ctypes.c_int32),
                 ("pair_rows", ctypes.c_int32), ("align_block", ctypes.c_int32),
-                ("slice_mcells", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+                ("slice_mcells", ctypes.c_int32), ("pair_mode", ctypes.c_int32),
+                ("pair_sm_max", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
                 ("ev_search_begin", ctypes.c_void_p), ("ev_search_end", ctypes.c_void_p),
                 ("ev_rescore_end", ctypes.c_void_p)]
 
@@ -87,7 +88,7 @@ class PlanStats(ctypes.Structure):
 
 class PairStats(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("lanes", ctypes.c_int32), ("cols", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("bands", ctypes.c_int64),
+                ("flow", ctypes.c_int32), ("bands", ctypes.c_int64),
                 ("chunks", ctypes.c_int64), ("launches", ctypes.c_int64), ("est_ms", ctypes.c_double),
                 ("workspace", ctypes.c_int64)]
 
@@ -147,8 +148,6 @@ def lib():
     L.sw_pair_plan.argtypes = [i64, i64, ctypes.POINTER(Options), i32, ctypes.POINTER(PairStats)]
     L.sw_pair_score.restype = ctypes.c_int
     L.sw_pair_score.argtypes = [vp, i64, vp, i64, vp, i32, i32, ctypes.POINTER(Options), vp, sz, vp, vp]
-    L.sw_pair_score_static.restype = ctypes.c_int
-    L.sw_pair_score_static.argtypes = [vp, i64, vp, i64, vp, i32, i32, ctypes.POINTER(Options), vp, vp]
     L.sw_align_workspace_bytes.restype = sz
     L.sw_align_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Options)]
     L.sw_align_pair.restype = ctypes.c_int
@@ -201,10 +200,16 @@ def version() -> str:
     return lib().sw_version().decode()
 
 
+PAIR_MODES = {"auto": 0, "tiles": 1, "flow": 2}
+
+
 def options(mode="auto", waves=0, lane_cells=0, max_lanes=0, lds_limit=0, grid_limit=0,
-            wide_profile=0, pair_cols=0, pair_rows=0, align_block=0, slice_mcells=0) -> Options:
+            wide_profile=0, pair_cols=0, pair_rows=0, align_block=0, slice_mcells=0, pair_mode=0,
+            pair_sm_max=0) -> Options:
     o = Options()
     o.slice_mcells = int(slice_mcells)
+    o.pair_mode = PAIR_MODES[pair_mode] if isinstance(pair_mode, str) else int(pair_mode)
+    o.pair_sm_max = int(pair_sm_max)
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.waves, o.lane_cells, o.max_lanes = int(waves), int(lane_cells), int(max_lanes)
     o.lds_limit, o.grid_limit = int(lds_limit), int(grid_limit)
@@ -362,29 +367,6 @@ def pair_score(query, subject, matrix, gap_open: int, gap_extend: int, opt: Opti
                              int(gap_open), int(gap_extend), o, _dev(workspace, torch.uint8, "workspace"),
                              int(workspace.numel()), _dev(out, torch.int32, "out"), _stream(stream))
     _check(rc, "sw_pair_score")
-    return out
-
-
-STATIC_SCRATCH_BYTES = 64 << 20
-
-
-def pair_score_static(query, subject, matrix, gap_open: int, gap_extend: int, opt: Optional[Options] = None,
-                      out=None, stream=None):
-    """``sw_pair_score_static``: ``pair_score`` on the library's static device
-    scratch (no allocation by the library; ``out`` is allocated here unless
-    given).  Calls overlapping on one GPU race on that scratch."""
-    import torch
-    m, n = int(query.numel()), int(subject.numel())
-    dev = query.device if m else subject.device
-    if out is None:
-        out = torch.empty(1, dtype=torch.int32, device=dev)
-    sm = _matrix(matrix)
-    o = ctypes.byref(opt) if opt is not None else None
-    rc = lib().sw_pair_score_static(_dev(query, torch.uint8, "query") if m else None, m,
-                                    _dev(subject, torch.uint8, "subject") if n else None, n, sm.ctypes.data,
-                                    int(gap_open), int(gap_extend), o, _dev(out, torch.int32, "out"),
-                                    _stream(stream))
-    _check(rc, "sw_pair_score_static")
     return out
 
 

@@ -178,6 +178,27 @@ struct PairArgs {
     uint8_t* sink;
 };
 
+// Pipelined pass over one long pair (sw_pair_flow.hip): waves take bands of
+// 64 lanes x R rows (bands w, w + waves, ...) and sweep all columns; a band
+// hands its bottom row to the band below through tagged 64-bit words.
+struct FlowArgs {
+    const uint8_t* subj;         // subject codes padded with the pad code (n_pad bytes, multiple of 16)
+    const uint8_t* prof;         // query profile, R-row blocks (nbr + 1 of them)
+    unsigned long long* rows;    // [n + 16] handoff words (cleared by the launch)
+    int32_t* score;              // [1] running maximum (atomicMax); -1 if a wait timed out
+    int32_t* status;             // [1] nonzero once a wait timed out
+    int32_t n, n_pad;            // subject length, bytes of subj
+    int32_t nbr, nb;             // query row blocks, bands (64 row blocks each)
+    int32_t waves;               // wavefronts of the launch
+    int32_t go, ge;
+    uint64_t timeout;            // s_memrealtime ticks a wait may last
+};
+// Rows per lane the flow pass is built for (the planner keeps the band count
+// at or below the device's SIMDs where it can).
+constexpr int kFlowRowChoices[6] = {4, 6, 8, 10, 12, 16};
+hipError_t launch_pair_flow(const FlowArgs& a, int rows, int elem, hipStream_t st);
+int flow_occupancy(int rows, int elem);   // workgroups of 4 waves per CU
+
 // Alignment found by the traceback pass (device memory, written by the
 // traceback kernel): 1-based inclusive positions, operation count.
 struct AlignOut {

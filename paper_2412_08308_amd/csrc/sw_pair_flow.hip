@@ -1,0 +1,300 @@
+// Pipelined pass over one long pair ("flow"): the score of one matrix with
+// one launch in place of one launch per anti-diagonal of tiles.
+//
+// Every wavefront takes one band of 64 lanes x R query rows at a time (bands
+// w, w + waves, w + 2 waves, ... in order) and sweeps all subject columns:
+// lane g computes column t - g at step t, receiving the bottom row of lane
+// g - 1 (and its residue code) through a DPP wave shift, as in the tile
+// kernels.  The band's state never leaves registers.  Its last lane hands the
+// band's bottom row to the band below through one 64-bit word per column of
+// a buffer updated in place: bits 0-23 hold H - Go + Go, bits 24-47 F + Go,
+// bits 48-63 a tag, band + 1.  The head lane of the band below reads the word
+// of its column 16 steps ahead and, before using it, checks that the tag names
+// the band just above; tags are unique per band within a call (the buffer is
+// cleared first), so a word not yet written is never mistaken for one that
+// is.  The words are read and written with agent-scope coherent accesses
+// (relaxed atomics: no cache writeback or invalidate is needed, since every
+// word carries its own validity), so bands on different XCDs meet in memory.
+//
+// A band waits only for the band above it, which a lower-numbered wavefront
+// (dispatched earlier) or this wavefront's previous round runs, so the
+// pipeline needs no other ordering.  Every wait is bounded in time: a wave
+// that gives up sets the status word, the waves waiting behind it see it and
+// stop, and the score is then reported as -1 (k_pair_flow_finish).
+//
+// The packing holds values in [0, 2^24): the host takes this pass only when
+// the largest possible score, max(SM) x min(m, n), is below 2^24 and the
+// bands number at most 2^16 - 1.
+#include <algorithm>
+#include <type_traits>
+
+#include "sw_device.h"
+
+namespace swdb {
+
+// raw buffer store cache policy: sc1 (agent-scope coherent, as a relaxed
+// agent-scope atomic store)
+constexpr int kStoreSc1 = 16;
+
+__device__ __forceinline__ unsigned long long flow_word(const unsigned long long* rows, int j)
+{
+    return __hip_atomic_load(rows + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The NW 32-bit words of a profile row block's entries (16-byte aligned).
+template <int NW>
+__device__ __forceinline__ void flow_ldprof(uint32_t (&v)[NW], const uint8_t* __restrict__ p)
+{
+    constexpr int N4 = NW / 4 * 4;
+#pragma unroll
+    for (int i = 0; i < N4; i += 4) {
+        const uint4 x = *reinterpret_cast<const uint4*>(p + 4 * i);
+        v[i] = x.x; v[i + 1] = x.y; v[i + 2] = x.z; v[i + 3] = x.w;
+    }
+    if constexpr (NW - N4 >= 2) {
+        const uint2 x = *reinterpret_cast<const uint2*>(p + 4 * N4);
+        v[N4] = x.x; v[N4 + 1] = x.y;
+    }
+    if constexpr ((NW - N4) % 2 == 1)
+        v[NW - 1] = *reinterpret_cast<const uint32_t*>(p + 4 * (NW - 1));
+}
+
+template <int ES, int NW>
+__device__ __forceinline__ int flow_entry(const uint32_t (&v)[NW], int r)
+{
+    if constexpr (ES == 1)
+        return (int)(int8_t)(v[r >> 2] >> (8 * (r & 3)));
+    else
+        return (int)(int16_t)(v[r >> 1] >> (16 * (r & 1)));
+}
+
+// Slow path of a read: poll the word of column j until its tag is `want`,
+// another wave has failed, or the time limit (or a poll count of the same
+// order) passes; then *failed is set.
+constexpr uint32_t kFlowMaxPolls = 1u << 25;
+
+__device__ __forceinline__ unsigned long long flow_wait(const FlowArgs& a, int j, uint32_t want,
+                                                           int* failed)
+{
+    const uint64_t begin = __builtin_amdgcn_s_memrealtime();
+    for (uint32_t polls = 0;; ++polls) {
+        const unsigned long long w = flow_word(a.rows, j);
+        if (__builtin_amdgcn_readfirstlane((uint32_t)(w >> 48)) == want)
+            return w;
+        const int stop = __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_readfirstlane(stop) != 0 || polls >= kFlowMaxPolls ||
+            __builtin_amdgcn_s_memrealtime() - begin > a.timeout) {
+            *failed = 1;
+            __hip_atomic_fetch_or(a.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return w;
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+}
+
+template <int R, int ES>
+__device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int lane)
+{
+    constexpr uint32_t CS = code_stride(R, ES);
+    constexpr uint32_t BS = kCodes * CS;
+    constexpr int NW = (R * ES + 3) / 4;
+
+    const int n = a.n;
+    const int go = a.go, ge = a.ge;
+    const bool head = lane == 0, tail = lane == kWave - 1;
+    const uint4* __restrict__ resp = reinterpret_cast<const uint4*>(a.subj);
+    const int nblk = a.n_pad >> 4;
+    const int T = n + kWave - 1;               // steps of a band
+    const int nsteps16 = (T + 15) & ~15;
+    typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+    // the tail lane's handoff store; the other lanes aim at entry n, past the
+    // descriptor's range (dropped), still inside the buffer's n + 16 entries
+    const __amdgpu_buffer_rsrc_t rows_out = __builtin_amdgcn_make_buffer_rsrc(a.rows, (short)0, n * 8, 0x00020000);
+    int S = 0;
+    int failed = 0;
+    for (int b = wave_id; b < a.nb && !failed; b += a.waves) {
+        const int rb = b * kWave + lane;
+        const uint8_t* __restrict__ prof = a.prof + (size_t)min(rb, a.nbr) * BS;
+        const bool has_top = b > 0;
+        const bool put = b < a.nb - 1;
+        const uint32_t want = (uint32_t)b;                 // the band above wrote tag (b - 1) + 1
+        const uint32_t wtag = (uint32_t)(b + 1) << 16;     // this band's tag, in the word's high half
+        int Y[R], E[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) { Y[r] = -go; E[r] = 0; }
+        int ydiag = -go, ybot = -go, fbot = 0;
+        // the head's words of the first 16 columns; then each word is loaded 16
+        // steps before its use, into the ring slot the step just consumed
+        unsigned long long ring[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            ring[u] = flow_word(a.rows, min(u, n - 1));
+        uint4 rv = resp[0];
+        int code = head ? (int)(rv.x & 0xffu) : kPad;
+        uint32_t pv[NW];
+        flow_ldprof<NW>(pv, prof + (uint32_t)code * CS);
+
+        auto sweep = [&](auto edge, int t0, const uint4& rvn) {
+            constexpr bool EDGE = decltype(edge)::value;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int t = t0 + u;
+                unsigned long long word = ring[u];
+                if (has_top && t < n && __builtin_amdgcn_readfirstlane((uint32_t)(word >> 48)) != want)
+                    word = flow_wait(a, t, want, &failed);
+                ring[u] = flow_word(a.rows, min(t + 16, n - 1));
+                const int yh = (int)(word & 0xffffffu) - go;
+                const int fh = (int)((word >> 24) & 0xffffffu) - go;
+                // shifts with the whole wave active, pinned so that none is
+                // folded into a select under a partial execution mask
+                int cd = shr1(code), yd = shr1(ybot), fd = shr1(fbot);
+                pin(cd);
+                pin(yd);
+                pin(fd);
+                const uint32_t nxt = u < 15 ? comp(rv, (u + 1) >> 2) >> (8 * ((u + 1) & 3)) : rvn.x;
+                const int cnext = head ? (int)(nxt & 0xffu) : cd;
+                uint32_t pvn[NW];
+                flow_ldprof<NW>(pvn, prof + (uint32_t)cnext * CS);
+                const int j = t - lane;                    // this lane's column
+                if (!EDGE || (j >= 0 && j < n)) {
+                    const int yt = head ? (has_top ? yh : -go) : yd;
+                    const int ft = head ? (has_top ? fh : 0) : fd;
+                    int dg = ydiag;
+                    ydiag = yt;
+                    int hup = yt, F = ft;
+                    int hprev = 0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int tt = dg + flow_entry<ES>(pv, r);      // H[i-1][j-1] + s
+                        const int e = imax3(E[r] - ge, Y[r], 0);        // E (clamped at 0)
+                        F = max(F - ge, hup);                           // F
+                        const int h = imax3(tt, e, F);                  // H
+                        if (r & 1) {
+                            S = imax3(S, hprev, h);
+                            pin(S);
+                        } else {
+                            hprev = h;
+                        }
+                        if ((R & 1) && r == R - 1)
+                            S = max(S, h);
+                        dg = Y[r];
+                        hup = h - go;
+                        Y[r] = hup;
+                        E[r] = e;
+                    }
+                    ybot = hup;
+                    fbot = F;
+                }
+                const bool st = tail && put && !failed && j >= 0 && j < n;
+                const uint32_t yv = (uint32_t)(ybot + go), fv = (uint32_t)(fbot + go);
+                const u32x2 v = {(yv & 0xffffffu) | (fv << 24), ((fv >> 8) & 0xffffu) | wtag};
+                __builtin_amdgcn_raw_buffer_store_b64(v, rows_out, st ? j * 8 : n * 8, 0, kStoreSc1);
+                code = cnext;
+#pragma unroll
+                for (int i = 0; i < NW; ++i)
+                    pv[i] = pvn[i];
+            }
+        };
+        // blocks where some lane is outside [0, n) (the pipeline's fill and
+        // drain) run a copy of the sweep with a per-lane predicate; the blocks
+        // between run without, in a loop of their own
+        const int fast_lo = kWave, fast_hi = max(kWave, n & ~15);     // [fast_lo, fast_hi): every lane inside
+        auto block = [&](auto edge, int t0) {
+            rv = resp[min(t0 >> 4, nblk - 1)];
+            const uint4 rvn = resp[min((t0 >> 4) + 1, nblk - 1)];
+            sweep(edge, t0, rvn);
+        };
+        for (int t0 = 0; t0 < min(fast_lo, nsteps16) && !failed; t0 += 16)
+            block(std::integral_constant<bool, true>{}, t0);
+        for (int t0 = fast_lo; t0 < fast_hi && !failed; t0 += 16)
+            block(std::integral_constant<bool, false>{}, t0);
+        for (int t0 = max(fast_lo, fast_hi); t0 < nsteps16 && !failed; t0 += 16)
+            block(std::integral_constant<bool, true>{}, t0);
+    }
+    for (int k = 32; k >= 1; k >>= 1)
+        S = max(S, __shfl_xor(S, k));
+    if (lane == 0 && S > 0)
+        atomicMax(a.score, S);
+}
+
+// Up to 6 rows per lane the state fits 128 registers (four waves per SIMD);
+// more rows take up to 256 (two per SIMD; the pass usually runs one wave per
+// SIMD anyway).
+template <int R, int ES>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R <= 6 ? 4 : 2))) k_pair_flow(FlowArgs a)
+{
+    const int w = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    if (w >= a.waves)
+        return;
+    pair_flow<R, ES>(a, w, threadIdx.x & 63);
+}
+
+// Clear the handoff words and the status word before a flow pass.
+__global__ void __launch_bounds__(256) k_flow_clear(unsigned long long* rows, int64_t count, int32_t* status)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0)
+        *status = 0;
+    for (int64_t i = t; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        rows[i] = 0ull;
+}
+
+// A timed-out wait makes the score meaningless: report -1.
+__global__ void k_pair_flow_finish(const int32_t* status, int32_t* score)
+{
+    if (*status)
+        *score = -1;
+}
+
+template <int R>
+static void launch_flow_rows(const FlowArgs& a, int elem, int blocks, hipStream_t st)
+{
+    if (elem == 1)
+        hipLaunchKernelGGL((k_pair_flow<R, 1>), dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_pair_flow<R, 2>), dim3(blocks), dim3(256), 0, st, a);
+}
+
+hipError_t launch_pair_flow(const FlowArgs& a, int rows, int elem, hipStream_t st)
+{
+    const int64_t clear = (int64_t)a.n + 16;
+    hipLaunchKernelGGL(k_flow_clear, dim3((unsigned)std::min<int64_t>((clear + 255) / 256, 1024)), dim3(256), 0,
+                       st, a.rows, clear, a.status);
+    const int blocks = (a.waves + 3) / 4;
+    switch (rows) {
+    case 4: launch_flow_rows<4>(a, elem, blocks, st); break;
+    case 6: launch_flow_rows<6>(a, elem, blocks, st); break;
+    case 8: launch_flow_rows<8>(a, elem, blocks, st); break;
+    case 10: launch_flow_rows<10>(a, elem, blocks, st); break;
+    case 12: launch_flow_rows<12>(a, elem, blocks, st); break;
+    case 16: launch_flow_rows<16>(a, elem, blocks, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_pair_flow_finish, dim3(1), dim3(1), 0, st, a.status, a.score);
+    return hipGetLastError();
+}
+
+int flow_occupancy(int rows, int elem)
+{
+    int n = 0;
+    hipError_t e = hipSuccess;
+    auto occ = [&](auto kern) { e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, 256, 0); };
+    switch (rows * 4 + elem) {
+    case 4 * 4 + 1: occ(k_pair_flow<4, 1>); break;
+    case 4 * 4 + 2: occ(k_pair_flow<4, 2>); break;
+    case 6 * 4 + 1: occ(k_pair_flow<6, 1>); break;
+    case 6 * 4 + 2: occ(k_pair_flow<6, 2>); break;
+    case 8 * 4 + 1: occ(k_pair_flow<8, 1>); break;
+    case 8 * 4 + 2: occ(k_pair_flow<8, 2>); break;
+    case 10 * 4 + 1: occ(k_pair_flow<10, 1>); break;
+    case 10 * 4 + 2: occ(k_pair_flow<10, 2>); break;
+    case 12 * 4 + 1: occ(k_pair_flow<12, 1>); break;
+    case 12 * 4 + 2: occ(k_pair_flow<12, 2>); break;
+    case 16 * 4 + 1: occ(k_pair_flow<16, 1>); break;
+    case 16 * 4 + 2: occ(k_pair_flow<16, 2>); break;
+    default: return 1;
+    }
+    return (e != hipSuccess || n < 1) ? 1 : n;
+}
+
+}  // namespace swdb

@@ -1613,6 +1613,8 @@ struct PairPlanC {
     int R = 0, K = 0, wc = 0;
     int64_t nb = 0, nc = 0, nbr = 0;
     double est_s = 0;
+    bool flow = false;          // one pipelined launch (wc, nc unused)
+    int waves = 0;              // flow: wavefronts of the launch
 };
 
 constexpr int64_t kPairMaxCols = 1 << 20;
@@ -1717,6 +1719,49 @@ double pair_time_rect(int64_t m, int64_t n, int R, int K, int wc, int cu)
     return t + (double)(nb + nc - 1) * 4e-6;
 }
 
+// Pipelined pass: bands of 64 lanes x R rows, at most flow_waves_per_cu(R)
+// wavefronts per CU.  Every band sweeps n + 63 steps and
+// starts about kFlowLagSteps after the band above; a wave alone on its SIMD
+// runs a step latency-bound, k waves sharing a SIMD issue-bound.  Instructions
+// per step: R rows of the cell update plus the per-column work (profile and
+// word loads, shifts, the handoff store).
+constexpr double kFlowLagSteps = 86.0;
+constexpr uint64_t kFlowTimeoutTicks = 200000000;   // a wait's limit: 2 s of the 100 MHz real-time counter
+constexpr double kFlowLaunchS = 15e-6;       // clear, launch and finish kernels
+constexpr int64_t kFlowMaxBands = (1 << 16) - 1;
+constexpr int64_t kFlowMaxValue = (1 << 24) - 1;
+
+double flow_instr_per_step(int R) { return 9.0 * R + 24.0; }
+
+int64_t flow_bands(int64_t m, int R) { return ceil_div(ceil_div(std::max<int64_t>(m, 1), R), kWave); }
+
+// Resident waves per CU of the pipelined pass (its register budget: 128
+// registers up to 6 rows per lane, 256 beyond).
+int64_t flow_waves_per_cu(int R) { return R <= 6 ? 16 : 8; }
+
+double flow_time(int64_t m, int64_t n, int R, int cu)
+{
+    const int64_t nb = flow_bands(m, R);
+    const int64_t cap = flow_waves_per_cu(R) * std::max(cu, 1);
+    const int64_t G = std::min(nb, cap);
+    const double k = std::ceil((double)G / (4.0 * std::max(cu, 1)));
+    const double rounds = std::ceil((double)nb / (double)G);
+    const double I = flow_instr_per_step(R);
+    const double step = std::max(4.92 * I, k * kPairIssueCycles * I);
+    const double steps = rounds * (double)(n + kWave - 1) + (double)G * kFlowLagSteps;
+    return steps * step / 2.4e9 + kFlowLaunchS;
+}
+
+// Whether the pipelined pass can score the pair: its handoff words hold
+// values below 2^24 (every H and F + Go is at most the largest score, at most
+// max(SM, 0) x min(m, n)) and tags for at most 2^16 - 1 bands.
+bool flow_fits(int64_t m, int64_t n, int R, int sm_max)
+{
+    if (m <= 0 || n <= 0) return false;
+    const int64_t bound = (int64_t)std::max(sm_max, 0) * std::min(m, n);
+    return bound <= kFlowMaxValue && flow_bands(m, R) <= kFlowMaxBands;
+}
+
 PairPlanC pair_plan_search(int64_t m, int64_t n, int cu, int fixR, int fixK, int fixW, bool rect)
 {
     auto model = [&](int R, int K, int wc) {
@@ -1760,11 +1805,11 @@ PairPlanC pair_plan_search(int64_t m, int64_t n, int cu, int fixR, int fixK, int
 // milliseconds for the largest pairs); the last plans are kept, since callers
 // often repeat one pair size.  rect: plan for the rectangular tiles of an
 // alignment's code and checkpoint passes.
-PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool rect = false)
+PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool rect = false, int sm_max = 127)
 {
     struct Entry {
         int64_t m = -1, n = -1;
-        int cu = 0, R = 0, K = 0, W = 0;
+        int cu = 0, R = 0, K = 0, W = 0, mode = 0, sm = 0, grid = 0;
         bool rect = false;
         PairPlanC p;
     };
@@ -1774,15 +1819,41 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool re
     const int fixR = opt ? opt->pair_rows : 0;
     const int fixK = opt ? opt->max_lanes : 0;
     const int fixW = opt ? opt->pair_cols : 0;
+    const int mode = rect ? 1 : (opt ? opt->pair_mode : 0);
     {
         std::lock_guard<std::mutex> lk(mu);
         for (const Entry& e : cache)
-            if (e.m == m && e.n == n && e.cu == cu && e.R == fixR && e.K == fixK && e.W == fixW && e.rect == rect)
+            if (e.m == m && e.n == n && e.cu == cu && e.R == fixR && e.K == fixK && e.W == fixW && e.rect == rect &&
+                e.mode == mode && e.sm == sm_max && e.grid == (opt ? opt->grid_limit : 0))
                 return e.p;
     }
-    const PairPlanC p = pair_plan_search(m, n, cu, fixR, fixK, fixW, rect);
+    PairPlanC p;
+    if (mode != 2 || m <= 0 || n <= 0)          // an empty pair has nothing to pipeline
+        p = pair_plan_search(m, n, cu, mode == 0 && fixR && !(fixR == 8 || fixR == 16) ? 0 : fixR, fixK, fixW, rect);
+    else
+        p.est_s = 1e300;
+    // the pipelined pass, where the scores fit its words (and no tile knob is set)
+    if (mode != 1 && !(mode == 0 && (fixK || fixW))) {
+        for (int R : kFlowRowChoices) {
+            if ((fixR && R != fixR) || !flow_fits(m, n, R, sm_max)) continue;
+            const double t = flow_time(m, n, R, cu);
+            if (t < p.est_s) {
+                PairPlanC f;
+                f.flow = true;
+                f.R = R;
+                f.K = kWave;
+                f.nbr = ceil_div(m, R);
+                f.nb = flow_bands(m, R);
+                f.waves = (int)std::min<int64_t>(f.nb, flow_waves_per_cu(R) * std::max(cu, 1));
+                if (opt && opt->grid_limit)      // a cap on workgroups (4 waves): bands run in rounds
+                    f.waves = (int)std::min<int64_t>(f.waves, (int64_t)opt->grid_limit * 4);
+                f.est_s = t;
+                p = f;
+            }
+        }
+    }
     std::lock_guard<std::mutex> lk(mu);
-    cache[next] = Entry{m, n, cu, fixR, fixK, fixW, rect, p};
+    cache[next] = Entry{m, n, cu, fixR, fixK, fixW, mode, sm_max, opt ? opt->grid_limit : 0, rect, p};
     next = (next + 1) % 8;
     return p;
 }
@@ -1794,7 +1865,7 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool re
 // nc * wc < n + wc, skewed ones n + K - 1 + wc.
 struct PairLayout {
     size_t subj = 0, prof = 0, rowbuf = 0, colbuf = 0, carry = 0, sink = 0, corner = 0, qd = 0, qoff = 0,
-           total = 0;
+           flow = 0, flow_status = 0, total = 0;
     int64_t n_pad = 0;
 };
 
@@ -1806,11 +1877,14 @@ PairLayout pair_layout(int64_t m, int64_t n, const PairPlanC* p, int64_t wc_max)
     const int64_t cols = align_up(n, 16) + 2 * wc + 128;
     int64_t prof = 0, rows_pad = 0, blocks = 0;
     for (int R : kPairRowChoices) {
-        if (p && R != p->R) continue;
+        if (p && (p->flow || R != p->R)) continue;
         prof = std::max(prof, prof_bytes_for((int)ceil_div(m, R), R, 2));
         rows_pad = std::max<int64_t>(rows_pad, align_up(m, R) + (int64_t)kWave * R);
         blocks = std::max(blocks, ceil_div(m, R));
     }
+    for (int R : kFlowRowChoices)
+        if (!p || (p->flow && R == p->R))
+            prof = std::max(prof, prof_bytes_for((int)ceil_div(m, R), R, 2));
     L.n_pad = cols + 128;
     size_t off = 0;
     L.qd = off; off += 256;
@@ -1822,6 +1896,8 @@ PairLayout pair_layout(int64_t m, int64_t n, const PairPlanC* p, int64_t wc_max)
     L.colbuf = off; off += align_up(rows_pad * (int64_t)sizeof(int2), 256);
     L.carry = off; off += align_up((blocks + kWave) * (int64_t)sizeof(int4), 256);
     L.sink = off; off += align_up((blocks + kWave) * 64, 256);     // a launch has at most nb + 3 waves
+    L.flow = off; off += align_up((n + 16) * 8, 256);              // pipelined pass: handoff words
+    L.flow_status = off; off += 256;
     L.total = off;
     return L;
 }
@@ -1845,9 +1921,21 @@ int validate_pair(int64_t m, int64_t n, const sw_options* opt, std::string& why)
         why = "options.pair_cols must be a multiple of 16, at most 2^20";
         return 0;
     }
-    if (opt && opt->pair_rows && opt->pair_rows != 8 && opt->pair_rows != 16) {
-        why = "options.pair_rows must be 0, 8 or 16";
-        return 0;
+    const int mode = opt ? opt->pair_mode : 0;
+    if (mode < 0 || mode > 2) { why = "options.pair_mode must be 0, 1 or 2"; return 0; }
+    if (opt && (opt->pair_sm_max < 0 || opt->pair_sm_max > 127)) { why = "options.pair_sm_max must be 0..127"; return 0; }
+    if (opt && opt->pair_rows) {
+        bool ok = false;
+        if (mode == 2) {
+            for (int R : kFlowRowChoices) ok = ok || opt->pair_rows == R;
+        } else {
+            ok = opt->pair_rows == 8 || opt->pair_rows == 16;
+        }
+        if (!ok) {
+            why = mode == 2 ? "options.pair_rows must be 0, 4, 6, 8, 10, 12 or 16 for the pipelined pass"
+                            : "options.pair_rows must be 0, 8 or 16";
+            return 0;
+        }
     }
     return 1;
 }
@@ -1870,15 +1958,20 @@ int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, 
     std::string why;
     if (!validate_pair(m, n, opt, why)) return fail(SW_EINVAL, why);
     if (!out) return fail(SW_EINVAL, "null output");
-    const PairPlanC p = pair_plan(m, n, cu_count > 0 ? cu_count : 256, opt);
+    const int sm_max = (opt && opt->pair_sm_max) ? opt->pair_sm_max : 127;
+    const PairPlanC p = pair_plan(m, n, cu_count > 0 ? cu_count : 256, opt, false, sm_max);
+    if (!p.R) return fail(SW_EINVAL, "the pipelined pass cannot hold this pair's scores (max(SM) x min(m, n) >= 2^24)");
     *out = sw_pair_stats{};
     out->rows = p.R;
     out->lanes = p.K;
     out->cols = p.wc;
+    out->flow = p.flow ? 1 : 0;
     out->bands = p.nb;
     out->chunks = p.nc;
     int64_t launches = 0;
-    if (m > 0 && n > 0)
+    if (p.flow)
+        launches = (m > 0 && n > 0) ? 1 : 0;
+    else if (m > 0 && n > 0)
         skew_walk(skew_grid(m, n, p.R, p.K, p.wc), [&](int64_t, int64_t, int64_t) { ++launches; });
     out->launches = launches;
     out->est_ms = p.est_s * 1e3;
@@ -2023,6 +2116,26 @@ int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint
     int rc = pair_setup(p, L, w, query, m, subject, n, sm, go, ge, elem, score_out, stream, a, empty);
     if (rc || empty)
         return rc;
+    if (p.flow) {
+        FlowArgs f{};
+        f.subj = a.subj;
+        f.prof = a.prof;
+        f.rows = reinterpret_cast<unsigned long long*>(w + L.flow);
+        f.score = score_out;
+        f.status = reinterpret_cast<int32_t*>(w + L.flow_status);
+        f.n = (int32_t)n;
+        f.n_pad = (int32_t)L.n_pad;
+        f.nbr = (int32_t)p.nbr;
+        f.nb = (int32_t)p.nb;
+        f.waves = p.waves;
+        f.go = go;
+        f.ge = ge;
+        f.timeout = kFlowTimeoutTicks;
+        if (ev0) HIPCHK(hipEventRecord(ev0, stream));
+        HIPCHK(launch_pair_flow(f, p.R, elem, stream));
+        if (ev1) HIPCHK(hipEventRecord(ev1, stream));
+        return SW_OK;
+    }
     a.dir = dir;
     a.end_key = end_key;
     if (ev0) HIPCHK(hipEventRecord(ev0, stream));
@@ -2205,65 +2318,16 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     int cu = 256;
     rc = device_cu(&cu);
     if (rc) return rc;
-    const PairPlanC p = pair_plan(m, n, cu, opt);
+    int sm_max = 0;
+    for (int i = 0; i < kAlpha * kAlpha; ++i) sm_max = std::max(sm_max, (int)sm[i]);
+    const PairPlanC p = pair_plan(m, n, cu, opt, false, sm_max);
+    if (!p.R) return fail(SW_EINVAL, "the pipelined pass cannot hold this pair's scores (max(SM) x min(m, n) >= 2^24)");
     const PairLayout L = pair_layout(m, n, &p, p.wc);
     if (L.total > need) return fail(SW_EINVAL, "internal error: pair layout exceeds the workspace size");
     const int elem = (fit == kFitS8 || fit == kFitU8) ? 1 : 2;
     return pair_enqueue(p, L, static_cast<uint8_t*>(ws), query, m, subject, n, sm, go, ge, elem, score_out,
                         nullptr, nullptr, opt ? opt->ev_search_begin : nullptr,
                         opt ? opt->ev_search_end : nullptr, stream);
-}
-
-}  // extern "C"
-
-// ------------------------------------------------------------------ pair score without allocation
-//
-// Device scratch of sw_pair_score_static: one array per GPU, held until the
-// process ends.  Host code never uses the array's name as an address (it is a
-// host-side stand-in); the device address comes from hipGetSymbolAddress,
-// taken once per device on that device's first call.
-static __device__ __align__(256) uint8_t scratch[SW_STATIC_SCRATCH_BYTES];
-
-namespace {
-
-std::mutex g_scratch_mu;
-std::map<int, uint8_t*> g_scratch;      // device -> address of its copy of `scratch`
-
-int static_scratch(uint8_t** out)
-{
-    int dev = 0;
-    HIPCHK(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lk(g_scratch_mu);
-    auto f = g_scratch.find(dev);
-    if (f == g_scratch.end()) {
-        void* p = nullptr;
-        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-        if (e != hipSuccess || !p)
-            return fail(SW_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
-        f = g_scratch.emplace(dev, static_cast<uint8_t*>(p)).first;
-    }
-    *out = f->second;
-    return SW_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-int sw_pair_score_static(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n, const int32_t* sm,
-                         int32_t go, int32_t ge, const sw_options* opt, int32_t* score_out, hipStream_t stream)
-{
-    std::string why;
-    if (!validate_pair(m, n, opt, why)) return fail(SW_EINVAL, why);
-    const size_t need = sw_pair_workspace_bytes(m, n, opt);
-    if (need > SW_STATIC_SCRATCH_BYTES)
-        return fail(SW_ENOMEM, "pair needs " + std::to_string(need) + " bytes of scratch, more than the " +
-                                   std::to_string((long long)SW_STATIC_SCRATCH_BYTES) +
-                                   " bytes of the static scratch; use sw_pair_score with a workspace");
-    uint8_t* ws = nullptr;
-    const int rc = static_scratch(&ws);
-    if (rc) return rc;
-    return sw_pair_score(query, m, subject, n, sm, go, ge, opt, ws, SW_STATIC_SCRATCH_BYTES, score_out, stream);
 }
 
 size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt)

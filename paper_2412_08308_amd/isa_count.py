@@ -56,13 +56,19 @@ VARIANTS = {
     "pair_r16_p8": ("k_pair_skewILi16ELi1E", 16, 1),
     "pair_r16_p16": ("k_pair_skewILi16ELi2E", 16, 1),
 }
+# pipelined pair pass (csrc/sw_pair_flow.hip): R rows per lane, 8- / 16-bit profile
+for _R in (4, 6, 8, 10, 12, 16):
+    for _ES in (1, 2):
+        VARIANTS[f"flow_r{_R}_p{8 * _ES}"] = (f"k_pair_flowILi{_R}ELi{_ES}E", _R, 1)
+_FLOW = [k for k in VARIANTS if k.startswith("flow_")]
 # kernels with two copies of the hot loop (tiles at the matrix edge with a
 # per-column predicate, tiles inside without): count the copy inside
-INTERIOR = {"pair_r8_p8", "pair_r8_p16", "pair_r16_p8", "pair_r16_p16"}
+INTERIOR = {"pair_r8_p8", "pair_r8_p16", "pair_r16_p8", "pair_r16_p16", *_FLOW}
 # subject columns one trip of the hot loop sweeps, where not four (the pair
-# kernel unrolls the 16 columns of a residue block)
-TRIP_COLS = {"pair_r8_p8": 16, "pair_r8_p16": 16, "pair_r16_p8": 16, "pair_r16_p16": 16}
-SOURCES = ["sw_isa_probe.hip", "sw_pair.hip", "sw_k_rescore.hip"]
+# kernels unroll the 16 columns of a residue block)
+TRIP_COLS = {"pair_r8_p8": 16, "pair_r8_p16": 16, "pair_r16_p8": 16, "pair_r16_p16": 16,
+             **{k: 16 for k in _FLOW}}
+SOURCES = ["sw_isa_probe.hip", "sw_pair.hip", "sw_pair_flow.hip", "sw_k_rescore.hip"]
 
 
 def _hot_loop(lines, interior=False):

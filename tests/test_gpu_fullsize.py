@@ -221,7 +221,8 @@ def test_pair_162k_x_172k(golden):
     h.update(f"{go},{ge}".encode())
     assert h.hexdigest() == p["config_sha256"]
     qa, qb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
-    for opt in (None, swdb.options(pair_rows=8, pair_cols=128), swdb.options(pair_rows=16, pair_cols=512)):
-        announce(f"pair 162k x 172k {opt and (opt.pair_rows, opt.pair_cols)}")
+    for opt in (None, swdb.options(pair_rows=8, pair_cols=128), swdb.options(pair_rows=16, pair_cols=512),
+                swdb.options(pair_mode=2, pair_rows=4), swdb.options(pair_mode=2, pair_rows=10)):
+        announce(f"pair 162k x 172k {opt and (opt.pair_mode, opt.pair_rows, opt.pair_cols)}")
         got = int(swdb.pair_score(qa, qb, sm, go, ge, opt=opt).cpu().item())
         assert got == p["score"], f"gpu {got} oracle {p['score']}"

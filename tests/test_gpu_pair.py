@@ -108,3 +108,76 @@ def test_large_tilings_agree():
     assert ref > 0.2 * 162_000          # a long homologous alignment (about 0.3 per base)
     for R, K, wc in ((16, 16, 256), (16, 64, 4096), (8, 64, 512), (16, 32, 1024)):
         assert _gpu_pair(a, b, sm, go, ge, pair_rows=R, max_lanes=K, pair_cols=wc) == ref
+
+
+FLOW_ROWS = [4, 6, 8, 10, 12, 16]
+
+
+@pytest.mark.parametrize("R", FLOW_ROWS)
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 700), (700, 1), (5, 16), (17, 15), (63, 64), (257, 300),
+                                 (1000, 1500), (2900, 3500)])
+def test_flow_pass(R, m, n):
+    """The pipelined pass (one launch, bands hand their bottom rows to the
+    band below through tagged words): sequences shorter than a band, the
+    pipeline fill and drain, bands past the query's end, every R."""
+    a, b = synth.dna_pair(m, n, seed=11 * m + n, identity=0.8, indel_rate=0.03)
+    sm, go, ge = DNA
+    exp = oracle_pair(a, b, sm, go, ge)
+    announce(f"flow pass m={m} n={n} R={R}")
+    assert _gpu_pair(a, b, sm, go, ge, pair_mode=2, pair_rows=R) == exp
+
+
+@pytest.mark.parametrize("R", [4, 16])
+def test_flow_pass_rounds(R):
+    """More bands than wavefronts: waves take bands w, w + waves, ... in
+    rounds (a cap of one or two workgroups), the last band ragged."""
+    a, b = synth.dna_pair(5000, 3000, seed=31, identity=0.75, indel_rate=0.02)
+    sm, go, ge = DNA
+    exp = oracle_pair(a, b, sm, go, ge)
+    for grid in (1, 2):
+        announce(f"flow pass rounds R={R} grid={grid}")
+        assert _gpu_pair(a, b, sm, go, ge, pair_mode=2, pair_rows=R, grid_limit=grid) == exp
+
+
+@pytest.mark.parametrize("go,ge", [(10, 2), (120, 1)])
+def test_flow_pass_protein(go, ge):
+    """Protein pairs through the pipelined pass with both profile widths
+    (8-bit entries for (10, 2), 16-bit for (120, 1)), and a substring pair
+    whose alignment crosses many bands."""
+    rng = np.random.default_rng(go + 7 * ge)
+    sm = synth.blosum_style_matrix()
+    a = synth.residues(rng, 3100)
+    b = np.concatenate([synth.residues(rng, 300), synth.mutate(rng, a[100:2900], 0.7), synth.residues(rng, 200)])
+    exp = oracle_pair(a, b, sm, go, ge)
+    for R in (4, 8, 12):
+        announce(f"flow protein go={go} ge={ge} R={R}")
+        assert _gpu_pair(a, b, sm, go, ge, pair_mode=2, pair_rows=R) == exp
+        assert _gpu_pair(b, a, sm, go, ge, pair_mode=2, pair_rows=R) == exp
+
+
+def test_flow_pass_refused_when_scores_do_not_fit():
+    """Scores that could reach 2^24 are not packed into the handoff words:
+    the pipelined pass is refused, the planner keeps the tiles."""
+    import torch
+    import paper_2412_08308_amd as swdb
+    sm = np.full((32, 32), -1, dtype=np.int32)
+    np.fill_diagonal(sm, 127)
+    m = n = 140_000                                   # 127 * 140,000 > 2^24
+    qa = torch.zeros(m, dtype=torch.uint8, device="cuda")
+    qb = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    announce("flow refused")
+    with pytest.raises(swdb.SwdbError):
+        swdb.pair_score(qa, qb, sm, 5, 2, opt=swdb.options(pair_mode=2))
+    assert swdb.pair_plan(m, n, swdb.options(pair_sm_max=127))["flow"] == 0
+
+
+def test_flow_large_closed_form():
+    """300,000 bases against themselves and a 100,000-base substring through
+    the pipelined pass (1,172 bands of 4 rows x 64 lanes, two per SIMD)."""
+    sm, go, ge = DNA
+    rng = np.random.default_rng(21)
+    a = synth.residues(rng, 300_000, synth.DNA_FREQS)
+    for R in (4, 16):
+        announce(f"flow 300k self R={R}")
+        assert _gpu_pair(a, a, sm, go, ge, pair_mode=2, pair_rows=R) == 300_000
+        assert _gpu_pair(a, a[123_456:223_456], sm, go, ge, pair_mode=2, pair_rows=R) == 100_000

@@ -12,7 +12,8 @@ import pytest
 
 CSRC = os.path.join(os.path.dirname(__file__), "..", "paper_2412_08308_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-UNITS = ["sw_k_i32p8.hip", "sw_k_i32p16.hip", "sw_k_i16.hip", "sw_k_i16p8.hip", "sw_k_rescore.hip", "sw_pair.hip"]
+UNITS = ["sw_k_i32p8.hip", "sw_k_i32p16.hip", "sw_k_i16.hip", "sw_k_i16p8.hip", "sw_k_rescore.hip", "sw_pair.hip",
+         "sw_pair_flow.hip"]
 
 
 def _asm(unit, tmp_path):

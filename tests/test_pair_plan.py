@@ -1,5 +1,6 @@
 """Host logic of the single-pair (intra-task) schedule: tiles cover the matrix,
-the anti-diagonal count, the workspace bound, argument checks (no GPU)."""
+the anti-diagonal count, the choice between tiles and the pipelined pass, the
+workspace bound, argument checks (no GPU)."""
 import pytest
 
 import paper_2412_08308_amd as swdb
@@ -28,13 +29,45 @@ def _skew_launches(m, n, R, K, wc):
 @pytest.mark.parametrize("m,n", [(1, 1), (1, 5000), (5000, 1), (2047, 2049), (2048, 512), (20000, 15000)]
                          + synth.DNA_PAIR_SIZES)
 def test_pair_plan_covers_matrix(m, n):
-    p = swdb.pair_plan(m, n)
+    p = swdb.pair_plan(m, n, swdb.options(pair_mode="tiles"))
     R, K, wc = p["rows"], p["lanes"], p["cols"]
+    assert p["flow"] == 0
     assert R in (8, 16) and K in (1, 2, 4, 8, 16, 32, 64) and wc % 16 == 0
     assert p["bands"] == -(-m // (K * R)) and p["chunks"] == -(-n // wc)
     assert p["launches"] == _skew_launches(m, n, R, K, wc)
     assert p["workspace"] == swdb.pair_workspace_bytes(m, n) > 0
     assert p["est_ms"] > 0
+
+
+@pytest.mark.parametrize("m,n", [(1, 5000), (2047, 2049), (20000, 15000)] + synth.DNA_PAIR_SIZES)
+def test_pipelined_plan(m, n):
+    """The pipelined pass: bands of 64 lanes x R rows in one launch, on at most
+    16 waves per CU (8 beyond 6 rows per lane), chosen only where the scores
+    fit its 24-bit words (max(SM) x min(m, n) < 2^24)."""
+    for R in (4, 6, 8, 10, 12, 16):
+        o = swdb.options(pair_mode="flow", pair_rows=R, pair_sm_max=1)
+        p = swdb.pair_plan(m, n, o)
+        assert p["flow"] == 1 and p["rows"] == R and p["lanes"] == 64 and p["launches"] == 1
+        assert p["bands"] == -(-(-(-m // R)) // 64)
+        assert p["workspace"] == swdb.pair_workspace_bytes(m, n) > 0
+    # scores that do not fit 24 bits: the pipelined pass is refused or not chosen
+    big = swdb.options(pair_mode="flow", pair_sm_max=127)
+    if 127 * min(m, n) >= 1 << 24:
+        with pytest.raises(swdb.SwdbError):
+            swdb.pair_plan(m, n, big)
+        assert swdb.pair_plan(m, n, swdb.options(pair_sm_max=127))["flow"] == 0
+    else:
+        assert swdb.pair_plan(m, n, big)["flow"] == 1
+    # the planner compares both and keeps the cheaper estimate
+    auto = swdb.pair_plan(m, n, swdb.options(pair_sm_max=1))
+    tiles = swdb.pair_plan(m, n, swdb.options(pair_mode="tiles"))
+    assert auto["est_ms"] <= tiles["est_ms"] + 1e-9
+
+
+def test_pipelined_rounds_follow_the_grid_cap():
+    o = swdb.options(pair_mode="flow", pair_rows=4, pair_sm_max=1, grid_limit=2)
+    p = swdb.pair_plan(20_000, 3_000, o)
+    assert p["flow"] == 1 and p["bands"] == 79
 
 
 @pytest.mark.parametrize("n,K,wc", [(1, 1, 16), (5, 64, 16), (100, 2, 16), (1000, 64, 64), (777, 16, 48),
@@ -52,7 +85,7 @@ def test_skewed_tiles_cover_each_row_block_once(n, K, wc):
             assert seen == list(range(n)), (b, g)
     for R in (8, 16):
         m = 6 * K * R
-        o = swdb.options(pair_rows=R, max_lanes=K, pair_cols=wc)
+        o = swdb.options(pair_rows=R, max_lanes=K, pair_cols=wc, pair_mode="tiles")
         assert swdb.pair_plan(m, n, o)["launches"] == _skew_launches(m, n, R, K, wc)
 
 
@@ -69,8 +102,13 @@ def test_pair_plan_options_fix_the_tiling():
 def test_pair_plan_prefers_short_strips_for_short_pairs():
     """Fewer rows per lane put more lanes on each anti-diagonal: the planner
     takes them when the pair is too short to fill the device otherwise."""
-    assert swdb.pair_plan(162_000, 172_000)["rows"] < 32
-    assert swdb.pair_plan(10_000, 10_000)["rows"] == 8
+    tiles = swdb.options(pair_mode="tiles")
+    assert swdb.pair_plan(162_000, 172_000, tiles)["rows"] < 32
+    assert swdb.pair_plan(10_000, 10_000, tiles)["rows"] == 8
+    # the pipelined pass takes the fewest rows per lane on short pairs
+    dna = swdb.options(pair_sm_max=1)
+    assert swdb.pair_plan(162_000, 172_000, dna)["rows"] == 4
+    assert swdb.pair_plan(1_000_000, 1_000_000, dna)["rows"] >= 8
 
 
 def test_pair_workspace_covers_every_tiling():
@@ -99,6 +137,14 @@ def test_pair_argument_checks():
         swdb.pair_workspace_bytes(1 << 25, 10)
     with pytest.raises(swdb.SwdbError):
         swdb.pair_plan(10, 10, swdb.options(pair_rows=32))
+    with pytest.raises(swdb.SwdbError):
+        swdb.pair_plan(10, 10, swdb.options(pair_rows=4))       # 4 rows: pipelined pass only
+    with pytest.raises(swdb.SwdbError):
+        swdb.pair_plan(10, 10, swdb.options(pair_mode=3))
+    with pytest.raises(swdb.SwdbError):
+        swdb.pair_plan(10, 10, swdb.options(pair_mode="flow", pair_rows=7))
+    with pytest.raises(swdb.SwdbError):
+        swdb.pair_plan(10, 10, swdb.options(pair_sm_max=128))
 
 
 def _a256(x):
