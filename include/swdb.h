@@ -419,6 +419,26 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
                   const sw_options* opt, void* workspace, size_t ws_bytes, int32_t* score_out,
                   hipStream_t stream);
 
+/*
+ * Score of one pair without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): sw_pair_score with its workspace taken from a
+ * static device array of SW_STATIC_SCRATCH_BYTES (64 MiB) that the library
+ * holds on every GPU it runs on until the process ends.  Arguments as for
+ * sw_pair_score, minus the workspace.  Returns SW_ENOMEM, with nothing
+ * enqueued, if the pair needs more scratch than that
+ * (sw_pair_workspace_bytes(m, n, opt) > SW_STATIC_SCRATCH_BYTES: the
+ * paper's smallest DNA pair, 162,000 x 172,000, needs 25 MiB; m = n =
+ * 400,000 needs 61 MiB).
+ * All calls on one GPU share its array: calls that overlap in time on one
+ * GPU (different streams, or threads) race and give wrong scores; serialise
+ * them on one stream.  Calls no hipMalloc or hipFree.
+ */
+#define SW_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int sw_pair_score_static(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n,
+                         const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,
+                         const sw_options* opt, int32_t* score_out, hipStream_t stream);
+
 /* ------------------------------------------------------------------ alignment of one pair
  *
  * The optional traceback after the score (paper Section 2.2: the alignment is

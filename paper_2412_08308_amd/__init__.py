@@ -148,6 +148,8 @@ def lib():
     L.sw_pair_plan.argtypes = [i64, i64, ctypes.POINTER(Options), i32, ctypes.POINTER(PairStats)]
     L.sw_pair_score.restype = ctypes.c_int
     L.sw_pair_score.argtypes = [vp, i64, vp, i64, vp, i32, i32, ctypes.POINTER(Options), vp, sz, vp, vp]
+    L.sw_pair_score_static.restype = ctypes.c_int
+    L.sw_pair_score_static.argtypes = [vp, i64, vp, i64, vp, i32, i32, ctypes.POINTER(Options), vp, vp]
     L.sw_align_workspace_bytes.restype = sz
     L.sw_align_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Options)]
     L.sw_align_pair.restype = ctypes.c_int
@@ -367,6 +369,29 @@ def pair_score(query, subject, matrix, gap_open: int, gap_extend: int, opt: Opti
                              int(gap_open), int(gap_extend), o, _dev(workspace, torch.uint8, "workspace"),
                              int(workspace.numel()), _dev(out, torch.int32, "out"), _stream(stream))
     _check(rc, "sw_pair_score")
+    return out
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def pair_score_static(query, subject, matrix, gap_open: int, gap_extend: int, opt: Optional[Options] = None,
+                      out=None, stream=None):
+    """``sw_pair_score_static``: ``pair_score`` on the library's static device
+    scratch (no allocation by the library; ``out`` is allocated here unless
+    given).  Calls overlapping on one GPU race on that scratch."""
+    import torch
+    m, n = int(query.numel()), int(subject.numel())
+    dev = query.device if m else subject.device
+    if out is None:
+        out = torch.empty(1, dtype=torch.int32, device=dev)
+    sm = _matrix(matrix)
+    o = ctypes.byref(opt) if opt is not None else None
+    rc = lib().sw_pair_score_static(_dev(query, torch.uint8, "query") if m else None, m,
+                                    _dev(subject, torch.uint8, "subject") if n else None, n, sm.ctypes.data,
+                                    int(gap_open), int(gap_extend), o, _dev(out, torch.int32, "out"),
+                                    _stream(stream))
+    _check(rc, "sw_pair_score_static")
     return out
 
 

@@ -2330,6 +2330,58 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
                         opt ? opt->ev_search_end : nullptr, stream);
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ pair score without allocation
+//
+// Device scratch of sw_pair_score_static: one array per GPU, held until the
+// process ends.  Host code never uses the array's name as an address (it is a
+// host-side stand-in); the device address comes from hipGetSymbolAddress,
+// taken once per device on that device's first call.
+static __device__ __align__(256) uint8_t scratch[SW_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, uint8_t*> g_scratch;      // device -> address of its copy of `scratch`
+
+int static_scratch(uint8_t** out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto f = g_scratch.find(dev);
+    if (f == g_scratch.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SW_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        f = g_scratch.emplace(dev, static_cast<uint8_t*>(p)).first;
+    }
+    *out = f->second;
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_pair_score_static(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n, const int32_t* sm,
+                         int32_t go, int32_t ge, const sw_options* opt, int32_t* score_out, hipStream_t stream)
+{
+    std::string why;
+    if (!validate_pair(m, n, opt, why)) return fail(SW_EINVAL, why);
+    const size_t need = sw_pair_workspace_bytes(m, n, opt);
+    if (need > SW_STATIC_SCRATCH_BYTES)
+        return fail(SW_ENOMEM, "pair needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                                   std::to_string((long long)SW_STATIC_SCRATCH_BYTES) +
+                                   " bytes of the static scratch; use sw_pair_score with a workspace");
+    uint8_t* ws = nullptr;
+    const int rc = static_scratch(&ws);
+    if (rc) return rc;
+    return sw_pair_score(query, m, subject, n, sm, go, ge, opt, ws, SW_STATIC_SCRATCH_BYTES, score_out, stream);
+}
+
 size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt)
 {
     std::string why;
