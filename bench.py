@@ -370,19 +370,35 @@ def pairwise(args, ev):
             ev.destroy(e0)
             ev.destroy(e1)
         wall = sum(walls) / len(walls)
-        plan = swdb.pair_plan(m, n, cu_count=torch.cuda.get_device_properties(0).multi_processor_count)
+        cu = torch.cuda.get_device_properties(0).multi_processor_count
+        plan = swdb.pair_plan(m, n, swdb.options(pair_sm_max=max(int(sm.max()), 1)), cu_count=cu)
         tiles_s = sum(kers) / len(kers) / 1e3
-        ops = isa[f"pair_r{plan['rows']}_p{8 if p8 else 16}"]["valu_per_cell"]
+        kind = "flow" if plan["flow"] else "pair"
+        ops = isa[f"{kind}_r{plan['rows']}_p{8 if p8 else 16}"]["valu_per_cell"]
+        # the anti-diagonal tile launches on the same pair, for comparison
+        cmp = None
+        if plan["flow"] and not big:
+            ot = swdb.options(pair_mode="tiles")
+            swdb.pair_score(qa, qb, sm, go, ge, opt=ot, workspace=ws, out=out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            swdb.pair_score(qa, qb, sm, go, ge, opt=ot, workspace=ws, out=out)
+            torch.cuda.synchronize()
+            cmp = {"tiles_ms": round((time.perf_counter() - t0) * 1e3, 2), "tiles_score": int(out.cpu().item())}
+            swdb.pair_score(qa, qb, sm, go, ge, workspace=ws, out=out)
+            torch.cuda.synchronize()
         runs.append({"m": m, "n": n, "cells": m * n, "gcups": round(m * n / wall / 1e9, 1),
                      "ms": round(wall * 1e3, 2), "tiles_ms": round(tiles_s * 1e3, 2),
                      "score": int(out.cpu().item()), "steps": steps,
-                     "plan": {k2: plan[k2] for k2 in ("rows", "lanes", "cols", "bands", "chunks", "launches")},
+                     "plan": {k2: plan[k2] for k2 in ("flow", "rows", "lanes", "cols", "bands", "chunks", "launches")},
+                     "tile_launches": cmp,
                      "model_ms": round(plan["est_ms"], 1), "isa_valu_per_cell": ops,
                      "roofline_frac": round(m * n * ops / tiles_s / 1e12 / PEAK_VALU_TOPS, 4)})
         print(f"[bench] pair {m}x{n}: {runs[-1]['gcups']} GCUPS", file=sys.stderr, flush=True)
         del qa, qb, ws
     return {"workload": "one DNA pair per size (paper's pairwise sizes, synthetic 80%-identity homologs, "
-                        "+1/-3, gaps 5/2), int32 lanes, anti-diagonal tile launches", "runs": runs}
+                        "+1/-3, gaps 5/2), int32 lanes; the planner's pass: one pipelined launch (flow) or "
+                        "anti-diagonal tile launches", "runs": runs}
 
 
 def alignments(args, w, scores):
