@@ -371,7 +371,8 @@ def pairwise(args, ev):
             ev.destroy(e1)
         wall = sum(walls) / len(walls)
         cu = torch.cuda.get_device_properties(0).multi_processor_count
-        plan = swdb.pair_plan(m, n, swdb.options(pair_sm_max=max(int(sm.max()), 1)), cu_count=cu)
+        plan = swdb.pair_plan(m, n, swdb.options(pair_sm_max=max(int(sm.max()), 1), pair_entry_bytes=1 if p8 else 2),
+                              cu_count=cu)
         tiles_s = sum(kers) / len(kers) / 1e3
         kind = "flow" if plan["flow"] else "pair"
         ops = isa[f"{kind}_r{plan['rows']}_p{8 if p8 else 16}"]["valu_per_cell"]
@@ -390,7 +391,8 @@ def pairwise(args, ev):
         runs.append({"m": m, "n": n, "cells": m * n, "gcups": round(m * n / wall / 1e9, 1),
                      "ms": round(wall * 1e3, 2), "tiles_ms": round(tiles_s * 1e3, 2),
                      "score": int(out.cpu().item()), "steps": steps,
-                     "plan": {k2: plan[k2] for k2 in ("flow", "rows", "lanes", "cols", "bands", "chunks", "launches")},
+                     "plan": {k2: plan[k2] for k2 in ("flow", "rows", "lanes", "cols", "bands", "chunks", "launches",
+                                                      "groups", "group_waves")},
                      "tile_launches": cmp,
                      "model_ms": round(plan["est_ms"], 1), "isa_valu_per_cell": ops,
                      "roofline_frac": round(m * n * ops / tiles_s / 1e12 / PEAK_VALU_TOPS, 4)})

@@ -110,7 +110,20 @@ typedef struct sw_options {
     int32_t pair_sm_max;   /* sw_pair_plan: the largest substitution-matrix entry
                               the pair will be scored with (0 = 127); scoring
                               calls take it from the matrix                    */
-    int32_t reserved[3];
+    int32_t slice_begin;   /* searches with slice_mcells > 0: run only launches
+                              slice_begin .. slice_begin + slice_count - 1 of the
+                              sliced search (slice_count 0 = through the last;
+                              sw_plan_info counts the launches), so a caller can
+                              enqueue a long search launch by launch and put
+                              other work between them.  Calls that cover
+                              0 .. launches - 1 in order, on one workspace and
+                              stream, equal one call: launch 0 zeroes the status
+                              words, later launches add to them.  A begin at or
+                              past the launch count is SW_EINVAL.              */
+    int32_t slice_count;
+    int32_t pair_entry_bytes; /* sw_pair_plan: profile entry bytes the pair will
+                              be scored with, 1 (every s + Go in [-128, 127]) or
+                              2 (0 = 2); scoring calls take it from the matrix  */
     /* Optional timing events (created by the caller, may be NULL): recorded on
        the search stream immediately before the search kernel, immediately
        after it, and after the int32 rescore (16-bit modes).                   */
@@ -389,6 +402,9 @@ typedef struct sw_pair_stats {
     int64_t launches;      /* anti-diagonals holding tiles (one launch each)      */
     double est_ms;         /* the planner's time model                            */
     int64_t workspace;     /* sw_pair_workspace_bytes                             */
+    int32_t groups;        /* pipelined pass: workgroups (one per CU)             */
+    int32_t group_waves;   /* pipelined pass: waves per workgroup, one band each
+                              at a time (group_waves / 4 per SIMD)               */
 } sw_pair_stats;
 
 /* Workspace bytes sw_pair_score needs for lengths m, n (0 on invalid input);

@@ -51,7 +51,8 @@ class Options(ctypes.Structure):
                 ("wide_profile", ctypes.c_int32), ("pair_cols", ctypes.c_int32),
                 ("pair_rows", ctypes.c_int32), ("align_block", ctypes.c_int32),
                 ("slice_mcells", ctypes.c_int32), ("pair_mode", ctypes.c_int32),
-                ("pair_sm_max", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+                ("pair_sm_max", ctypes.c_int32), ("slice_begin", ctypes.c_int32),
+                ("slice_count", ctypes.c_int32), ("pair_entry_bytes", ctypes.c_int32),
                 ("ev_search_begin", ctypes.c_void_p), ("ev_search_end", ctypes.c_void_p),
                 ("ev_rescore_end", ctypes.c_void_p)]
 
@@ -90,7 +91,7 @@ class PairStats(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("lanes", ctypes.c_int32), ("cols", ctypes.c_int32),
                 ("flow", ctypes.c_int32), ("bands", ctypes.c_int64),
                 ("chunks", ctypes.c_int64), ("launches", ctypes.c_int64), ("est_ms", ctypes.c_double),
-                ("workspace", ctypes.c_int64)]
+                ("workspace", ctypes.c_int64), ("groups", ctypes.c_int32), ("group_waves", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -207,9 +208,11 @@ PAIR_MODES = {"auto": 0, "tiles": 1, "flow": 2}
 
 def options(mode="auto", waves=0, lane_cells=0, max_lanes=0, lds_limit=0, grid_limit=0,
             wide_profile=0, pair_cols=0, pair_rows=0, align_block=0, slice_mcells=0, pair_mode=0,
-            pair_sm_max=0) -> Options:
+            pair_sm_max=0, slice_begin=0, slice_count=0, pair_entry_bytes=0) -> Options:
     o = Options()
+    o.pair_entry_bytes = int(pair_entry_bytes)
     o.slice_mcells = int(slice_mcells)
+    o.slice_begin, o.slice_count = int(slice_begin), int(slice_count)
     o.pair_mode = PAIR_MODES[pair_mode] if isinstance(pair_mode, str) else int(pair_mode)
     o.pair_sm_max = int(pair_sm_max)
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)

@@ -178,9 +178,10 @@ struct PairArgs {
     uint8_t* sink;
 };
 
-// Pipelined pass over one long pair (sw_pair_flow.hip): waves take bands of
-// 64 lanes x R rows (bands w, w + waves, ...) and sweep all columns; a band
-// hands its bottom row to the band below through tagged 64-bit words.
+// Pipelined pass over one long pair (sw_pair_flow.hip): one-wave workgroups
+// take bands of 64 lanes x R rows (bands w, w + waves, ...), stage the band's
+// profile in LDS and sweep all columns; a band hands its bottom row to the band
+// below through tagged 64-bit words.
 struct FlowArgs {
     const uint8_t* subj;         // subject codes padded with the pad code (n_pad bytes, multiple of 16)
     const uint8_t* prof;         // query profile, R-row blocks (nbr + 1 of them)
@@ -193,11 +194,23 @@ struct FlowArgs {
     int32_t go, ge;
     uint64_t timeout;            // s_memrealtime ticks a wait may last
 };
+// Bytes per (code, lane) entry group of a band's profile staged in LDS by the
+// flow pass: the lane's R entries rounded up to a power of two (aligned reads).
+__host__ __device__ constexpr int flow_lds_stride(int R, int ES)
+{
+    return R * ES <= 4 ? 4 : (R * ES <= 8 ? 8 : (R * ES <= 16 ? 16 : 32));
+}
 // Rows per lane the flow pass is built for (the planner keeps the band count
 // at or below the device's SIMDs where it can).
 constexpr int kFlowRowChoices[6] = {4, 6, 8, 10, 12, 16};
-hipError_t launch_pair_flow(const FlowArgs& a, int rows, int elem, hipStream_t st);
-int flow_occupancy(int rows, int elem);   // workgroups of 4 waves per CU
+// The flow pass on `grid` workgroups of `wpg` waves (a.waves = grid * wpg),
+// each asking for `lds` bytes of LDS (at least wpg band profiles).
+hipError_t launch_pair_flow(const FlowArgs& a, int rows, int elem, int wpg, int grid, int lds, hipStream_t st);
+int flow_occupancy(int rows, int elem, int wpg, int lds);   // resident workgroups per CU (0 on error)
+__host__ __device__ constexpr int flow_lds_bytes(int rows, int elem)   // LDS of one wave's band profile
+{
+    return kCodes * kWave * flow_lds_stride(rows, elem);
+}
 
 // Alignment found by the traceback pass (device memory, written by the
 // traceback kernel): 1-based inclusive positions, operation count.

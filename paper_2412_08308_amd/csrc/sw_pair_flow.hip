@@ -18,7 +18,10 @@
 //
 // A band waits only for the band above it, which a lower-numbered wavefront
 // (dispatched earlier) or this wavefront's previous round runs, so the
-// pipeline needs no other ordering.  Every wait is bounded in time: a wave
+// pipeline needs no other ordering.  The bands advance at the pace of the
+// slowest one, so the launch places them evenly: workgroups of W waves (W / 4
+// per SIMD), one workgroup per CU (its LDS request keeps a second one off the
+// CU), each wave with a band profile of its own in LDS.  Every wait is bounded in time: a wave
 // that gives up sets the status word, the waves waiting behind it see it and
 // stop, and the score is then reported as -1 (k_pair_flow_finish).
 //
@@ -59,6 +62,29 @@ __device__ __forceinline__ void flow_ldprof(uint32_t (&v)[NW], const uint8_t* __
         v[NW - 1] = *reinterpret_cast<const uint32_t*>(p + 4 * (NW - 1));
 }
 
+// The NW words of a lane's entries for one code from the band's LDS profile.
+template <int NW, int PS>
+__device__ __forceinline__ void flow_ldlds(uint32_t (&v)[NW], uint32_t off)
+{
+    static_assert(NW * 4 <= PS, "entries fit the stride");
+    if constexpr (PS == 4) {
+        v[0] = *reinterpret_cast<const uint32_t*>(sw_lds + off);
+    } else if constexpr (PS == 8) {
+        const uint2 x = *reinterpret_cast<const uint2*>(sw_lds + off);
+        v[0] = x.x;
+        if constexpr (NW > 1) v[1] = x.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < NW; i += 4) {
+            const uint4 x = *reinterpret_cast<const uint4*>(sw_lds + off + 4 * i);
+            v[i] = x.x;
+            if (i + 1 < NW) v[i + 1] = x.y;
+            if (i + 2 < NW) v[i + 2] = x.z;
+            if (i + 3 < NW) v[i + 3] = x.w;
+        }
+    }
+}
+
 template <int ES, int NW>
 __device__ __forceinline__ int flow_entry(const uint32_t (&v)[NW], int r)
 {
@@ -93,11 +119,12 @@ __device__ __forceinline__ unsigned long long flow_wait(const FlowArgs& a, int j
 }
 
 template <int R, int ES>
-__device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int lane)
+__device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int lane, uint32_t lds0)
 {
     constexpr uint32_t CS = code_stride(R, ES);
     constexpr uint32_t BS = kCodes * CS;
     constexpr int NW = (R * ES + 3) / 4;
+    constexpr uint32_t PS = flow_lds_stride(R, ES);
 
     const int n = a.n;
     const int go = a.go, ge = a.ge;
@@ -114,7 +141,24 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
     int failed = 0;
     for (int b = wave_id; b < a.nb && !failed; b += a.waves) {
         const int rb = b * kWave + lane;
-        const uint8_t* __restrict__ prof = a.prof + (size_t)min(rb, a.nbr) * BS;
+        // the band's profile in this wave's LDS region: entry group (code c,
+        // lane g) at lds0 + (c * 64 + g) * PS, so lanes reading the same code
+        // read consecutive addresses; the profile reads of the sweep then wait
+        // on the LDS counter, never behind the coherent loads and stores of
+        // the handoff words.  A lane reads only the entries it wrote itself,
+        // and a wave's LDS accesses complete in order, so no barrier is needed
+        // (the waves of a workgroup run different numbers of bands).
+        {
+            const uint8_t* __restrict__ src = a.prof + (size_t)min(rb, a.nbr) * BS;
+            for (int c = 0; c < kCodes; ++c) {
+                uint32_t v[NW];
+                flow_ldprof<NW>(v, src + (uint32_t)c * CS);
+                uint32_t* d = reinterpret_cast<uint32_t*>(sw_lds + lds0 + ((uint32_t)c * kWave + lane) * PS);
+#pragma unroll
+                for (int i = 0; i < NW; ++i)
+                    d[i] = v[i];
+            }
+        }
         const bool has_top = b > 0;
         const bool put = b < a.nb - 1;
         const uint32_t want = (uint32_t)b;                 // the band above wrote tag (b - 1) + 1
@@ -129,12 +173,16 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
 #pragma unroll
         for (int u = 0; u < 16; ++u)
             ring[u] = flow_word(a.rows, min(u, n - 1));
+        // subject codes of the current and the next 16-column block; the block
+        // after is loaded a block ahead, so its wait never falls behind the
+        // handoff words' loads and stores just issued
         uint4 rv = resp[0];
+        uint4 rvn = resp[min(1, nblk - 1)];
         int code = head ? (int)(rv.x & 0xffu) : kPad;
         uint32_t pv[NW];
-        flow_ldprof<NW>(pv, prof + (uint32_t)code * CS);
+        flow_ldlds<NW, PS>(pv, lds0 + ((uint32_t)code * kWave + lane) * PS);
 
-        auto sweep = [&](auto edge, int t0, const uint4& rvn) {
+        auto sweep = [&](auto edge, int t0) {
             constexpr bool EDGE = decltype(edge)::value;
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
@@ -154,7 +202,7 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
                 const uint32_t nxt = u < 15 ? comp(rv, (u + 1) >> 2) >> (8 * ((u + 1) & 3)) : rvn.x;
                 const int cnext = head ? (int)(nxt & 0xffu) : cd;
                 uint32_t pvn[NW];
-                flow_ldprof<NW>(pvn, prof + (uint32_t)cnext * CS);
+                flow_ldlds<NW, PS>(pvn, lds0 + ((uint32_t)cnext * kWave + lane) * PS);
                 const int j = t - lane;                    // this lane's column
                 if (!EDGE || (j >= 0 && j < n)) {
                     const int yt = head ? (has_top ? yh : -go) : yd;
@@ -200,9 +248,10 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
         // between run without, in a loop of their own
         const int fast_lo = kWave, fast_hi = max(kWave, n & ~15);     // [fast_lo, fast_hi): every lane inside
         auto block = [&](auto edge, int t0) {
-            rv = resp[min(t0 >> 4, nblk - 1)];
-            const uint4 rvn = resp[min((t0 >> 4) + 1, nblk - 1)];
-            sweep(edge, t0, rvn);
+            const uint4 ahead = resp[min((t0 >> 4) + 2, nblk - 1)];
+            sweep(edge, t0);
+            rv = rvn;
+            rvn = ahead;
         };
         for (int t0 = 0; t0 < min(fast_lo, nsteps16) && !failed; t0 += 16)
             block(std::integral_constant<bool, true>{}, t0);
@@ -217,16 +266,16 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
         atomicMax(a.score, S);
 }
 
-// Up to 6 rows per lane the state fits 128 registers (four waves per SIMD);
-// more rows take up to 256 (two per SIMD; the pass usually runs one wave per
-// SIMD anyway).
+// Up to 6 rows per lane the state fits 128 registers (workgroups of up to 16
+// waves, four per SIMD); more rows take up to 256 (up to 8 waves, two per
+// SIMD).  Wave w of workgroup g is wave g * W + w of the launch.
 template <int R, int ES>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R <= 6 ? 4 : 2))) k_pair_flow(FlowArgs a)
+__global__ void __launch_bounds__(R <= 6 ? 1024 : 512) __attribute__((amdgpu_waves_per_eu(R <= 6 ? 4 : 2)))
+k_pair_flow(FlowArgs a)
 {
-    const int w = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-    if (w >= a.waves)
-        return;
-    pair_flow<R, ES>(a, w, threadIdx.x & 63);
+    const int wpg = (int)(blockDim.x >> 6);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    pair_flow<R, ES>(a, (int)blockIdx.x * wpg + w, (int)(threadIdx.x & 63), (uint32_t)(w * flow_lds_bytes(R, ES)));
 }
 
 // Clear the handoff words and the status word before a flow pass.
@@ -246,55 +295,51 @@ __global__ void k_pair_flow_finish(const int32_t* status, int32_t* score)
         *score = -1;
 }
 
-template <int R>
-static void launch_flow_rows(const FlowArgs& a, int elem, int blocks, hipStream_t st)
+// The kernel of (rows, elem); null for a shape it is not built for.
+static const void* flow_kernel(int rows, int elem)
 {
-    if (elem == 1)
-        hipLaunchKernelGGL((k_pair_flow<R, 1>), dim3(blocks), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_pair_flow<R, 2>), dim3(blocks), dim3(256), 0, st, a);
+    switch (rows * 4 + elem) {
+    case 4 * 4 + 1: return reinterpret_cast<const void*>(&k_pair_flow<4, 1>);
+    case 4 * 4 + 2: return reinterpret_cast<const void*>(&k_pair_flow<4, 2>);
+    case 6 * 4 + 1: return reinterpret_cast<const void*>(&k_pair_flow<6, 1>);
+    case 6 * 4 + 2: return reinterpret_cast<const void*>(&k_pair_flow<6, 2>);
+    case 8 * 4 + 1: return reinterpret_cast<const void*>(&k_pair_flow<8, 1>);
+    case 8 * 4 + 2: return reinterpret_cast<const void*>(&k_pair_flow<8, 2>);
+    case 10 * 4 + 1: return reinterpret_cast<const void*>(&k_pair_flow<10, 1>);
+    case 10 * 4 + 2: return reinterpret_cast<const void*>(&k_pair_flow<10, 2>);
+    case 12 * 4 + 1: return reinterpret_cast<const void*>(&k_pair_flow<12, 1>);
+    case 12 * 4 + 2: return reinterpret_cast<const void*>(&k_pair_flow<12, 2>);
+    case 16 * 4 + 1: return reinterpret_cast<const void*>(&k_pair_flow<16, 1>);
+    case 16 * 4 + 2: return reinterpret_cast<const void*>(&k_pair_flow<16, 2>);
+    default: return nullptr;
+    }
 }
 
-hipError_t launch_pair_flow(const FlowArgs& a, int rows, int elem, hipStream_t st)
+hipError_t launch_pair_flow(const FlowArgs& a, int rows, int elem, int wpg, int grid, int lds, hipStream_t st)
 {
+    const void* k = flow_kernel(rows, elem);
+    if (!k || wpg < 1 || wpg > (rows <= 6 ? 16 : 8) || grid < 1 || (int64_t)grid * wpg != a.waves ||
+        lds < wpg * flow_lds_bytes(rows, elem))
+        return hipErrorInvalidValue;
     const int64_t clear = (int64_t)a.n + 16;
     hipLaunchKernelGGL(k_flow_clear, dim3((unsigned)std::min<int64_t>((clear + 255) / 256, 1024)), dim3(256), 0,
                        st, a.rows, clear, a.status);
-    const int blocks = (a.waves + 3) / 4;
-    switch (rows) {
-    case 4: launch_flow_rows<4>(a, elem, blocks, st); break;
-    case 6: launch_flow_rows<6>(a, elem, blocks, st); break;
-    case 8: launch_flow_rows<8>(a, elem, blocks, st); break;
-    case 10: launch_flow_rows<10>(a, elem, blocks, st); break;
-    case 12: launch_flow_rows<12>(a, elem, blocks, st); break;
-    case 16: launch_flow_rows<16>(a, elem, blocks, st); break;
-    default: return hipErrorInvalidValue;
-    }
+    FlowArgs arg = a;
+    void* args[] = {&arg};
+    const hipError_t e = hipLaunchKernel(k, dim3((unsigned)grid), dim3((unsigned)(64 * wpg)), args, (size_t)lds, st);
+    if (e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_pair_flow_finish, dim3(1), dim3(1), 0, st, a.status, a.score);
     return hipGetLastError();
 }
 
-int flow_occupancy(int rows, int elem)
+int flow_occupancy(int rows, int elem, int wpg, int lds)
 {
+    const void* k = flow_kernel(rows, elem);
     int n = 0;
-    hipError_t e = hipSuccess;
-    auto occ = [&](auto kern) { e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, 256, 0); };
-    switch (rows * 4 + elem) {
-    case 4 * 4 + 1: occ(k_pair_flow<4, 1>); break;
-    case 4 * 4 + 2: occ(k_pair_flow<4, 2>); break;
-    case 6 * 4 + 1: occ(k_pair_flow<6, 1>); break;
-    case 6 * 4 + 2: occ(k_pair_flow<6, 2>); break;
-    case 8 * 4 + 1: occ(k_pair_flow<8, 1>); break;
-    case 8 * 4 + 2: occ(k_pair_flow<8, 2>); break;
-    case 10 * 4 + 1: occ(k_pair_flow<10, 1>); break;
-    case 10 * 4 + 2: occ(k_pair_flow<10, 2>); break;
-    case 12 * 4 + 1: occ(k_pair_flow<12, 1>); break;
-    case 12 * 4 + 2: occ(k_pair_flow<12, 2>); break;
-    case 16 * 4 + 1: occ(k_pair_flow<16, 1>); break;
-    case 16 * 4 + 2: occ(k_pair_flow<16, 2>); break;
-    default: return 1;
-    }
-    return (e != hipSuccess || n < 1) ? 1 : n;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * wpg, (size_t)lds) != hipSuccess)
+        return 0;
+    return n;
 }
 
 }  // namespace swdb

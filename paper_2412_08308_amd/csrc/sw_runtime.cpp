@@ -140,6 +140,11 @@ bool validate_options(const sw_options* opt, std::string& why)
     if (opt->pair_rows < 0) { why = "options.pair_rows"; return false; }
     if (opt->align_block < 0 || opt->align_block > (1 << 24)) { why = "options.align_block must be 0..2^24"; return false; }
     if (opt->slice_mcells < 0) { why = "options.slice_mcells"; return false; }
+    if (opt->slice_begin < 0 || opt->slice_count < 0) { why = "options.slice_begin / slice_count"; return false; }
+    if ((opt->slice_begin || opt->slice_count) && opt->slice_mcells <= 0) {
+        why = "options.slice_begin / slice_count need slice_mcells > 0";
+        return false;
+    }
     return true;
 }
 
@@ -706,9 +711,11 @@ size_t parts_bytes(const std::vector<Part>& parts)
 // Validation and planning shared by every search entry point.
 int plan_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, const int32_t* q_lens,
                 int32_t nq, const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt,
-                void* ws, size_t ws_bytes, int32_t* scores, std::vector<Part>& parts, bool& nothing)
+                void* ws, size_t ws_bytes, int32_t* scores, std::vector<Part>& parts, bool& nothing,
+                bool* from_first = nullptr)
 {
     nothing = false;
+    if (from_first) *from_first = true;
     int rc = validate_query_set(db, nq, q_lens);
     if (rc) return rc;
     if (nq > 0 && !q_offsets) return fail(SW_EINVAL, "null q_offsets");
@@ -744,6 +751,16 @@ int plan_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, co
         return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
     if (parts_bytes(parts) > need)     // the layouts are built so that this never holds
         return fail(SW_EINVAL, "internal error: search layout exceeds the workspace size");
+    if (opt && (opt->slice_begin > 0 || opt->slice_count > 0)) {
+        const size_t b = (size_t)opt->slice_begin;
+        if (b >= parts.size())
+            return fail(SW_EINVAL, "options.slice_begin " + std::to_string(b) + " is not below the " +
+                                       std::to_string(parts.size()) + " launches of this search");
+        const size_t e = opt->slice_count > 0 ? std::min(parts.size(), b + (size_t)opt->slice_count) : parts.size();
+        parts.erase(parts.begin() + e, parts.end());
+        parts.erase(parts.begin(), parts.begin() + b);
+        if (from_first) *from_first = b == 0;
+    }
     return SW_OK;
 }
 
@@ -832,17 +849,19 @@ int enqueue_search(sw_db_t db, const Layout& L, const uint8_t* blob, const uint8
 
 // Events of a multi-part search: begin before the first search kernel, end
 // after the last one, rescore-end after the last rescore.
+// from_first: the parts begin with the search's first launch, which zeroes
+// the status words (a later slice of a sliced search adds to them).
 int enqueue_parts(sw_db_t db, const std::vector<Part>& parts, const std::vector<uint8_t*>& blobs,
                   const uint8_t* queries, const int32_t* sm, int32_t go, int32_t ge, const sw_options* opt,
-                  void* ws, int32_t* scores, hipStream_t stream)
+                  void* ws, int32_t* scores, hipStream_t stream, bool from_first = true)
 {
     for (size_t g = 0; g < parts.size(); ++g) {
         const bool first = g == 0, last = g + 1 == parts.size();
         const int rc = enqueue_search(db, parts[g].L, blobs[g], queries, sm, go, ge,
                                       first && opt ? opt->ev_search_begin : nullptr,
                                       last && opt ? opt->ev_search_end : nullptr,
-                                      last && opt ? opt->ev_rescore_end : nullptr, ws, scores, first,
-                                      stream);
+                                      last && opt ? opt->ev_rescore_end : nullptr, ws, scores,
+                                      first && from_first, stream);
         if (rc) return rc;
     }
     return SW_OK;
@@ -853,8 +872,9 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
               void* ws, size_t ws_bytes, int32_t* scores, hipStream_t stream)
 {
     std::vector<Part> parts;
-    bool nothing = false;
-    int rc = plan_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, parts, nothing);
+    bool nothing = false, from_first = true;
+    int rc = plan_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, parts, nothing,
+                         &from_first);
     if (rc || nothing) return rc;
     std::vector<Staging*> st(parts.size(), nullptr);
     std::vector<uint8_t*> blobs(parts.size(), nullptr);
@@ -867,7 +887,7 @@ int do_search(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, cons
         }
         fill_blob(parts[g].L, parts[g].offs.data(), blobs[g]);
     }
-    rc = enqueue_parts(db, parts, blobs, queries, sm, go, ge, opt, ws, scores, stream);
+    rc = enqueue_parts(db, parts, blobs, queries, sm, go, ge, opt, ws, scores, stream, from_first);
     // the staging buffers are reusable once the stream has passed this point
     hipError_t e = hipSuccess;
     for (size_t g = 0; g < parts.size() && e == hipSuccess; ++g)
@@ -1437,8 +1457,9 @@ int sw_graph_create(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets
     if (!out) return fail(SW_EINVAL, "null output graph");
     *out = nullptr;
     std::vector<Part> parts;
-    bool nothing = false;
-    int rc = plan_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, parts, nothing);
+    bool nothing = false, from_first = true;
+    int rc = plan_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, parts, nothing,
+                         &from_first);
     if (rc) return rc;
     auto* g = new sw_graph_s();
     g->db = db;
@@ -1460,7 +1481,7 @@ int sw_graph_create(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets
     e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bail(SW_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     if (!nothing)
-        rc = enqueue_parts(db, parts, blobs, queries, sm, go, ge, nullptr, ws, scores, g->cap);
+        rc = enqueue_parts(db, parts, blobs, queries, sm, go, ge, nullptr, ws, scores, g->cap, from_first);
     const std::string err = g_err;
     e = hipStreamEndCapture(g->cap, &g->graph);
     if (rc) return bail(rc, "capture: " + err);
@@ -1614,7 +1635,8 @@ struct PairPlanC {
     int64_t nb = 0, nc = 0, nbr = 0;
     double est_s = 0;
     bool flow = false;          // one pipelined launch (wc, nc unused)
-    int waves = 0;              // flow: wavefronts of the launch
+    int waves = 0;              // flow: wavefronts of the launch (grid x wpg)
+    int wpg = 0, grid = 0, lds = 0;   // flow: waves per workgroup, workgroups, LDS per workgroup
 };
 
 constexpr int64_t kPairMaxCols = 1 << 20;
@@ -1719,37 +1741,70 @@ double pair_time_rect(int64_t m, int64_t n, int R, int K, int wc, int cu)
     return t + (double)(nb + nc - 1) * 4e-6;
 }
 
-// Pipelined pass: bands of 64 lanes x R rows, at most flow_waves_per_cu(R)
-// wavefronts per CU.  Every band sweeps n + 63 steps and
-// starts about kFlowLagSteps after the band above; a wave alone on its SIMD
-// runs a step latency-bound, k waves sharing a SIMD issue-bound.  Instructions
-// per step: R rows of the cell update plus the per-column work (profile and
-// word loads, shifts, the handoff store).
-constexpr double kFlowLagSteps = 86.0;
-constexpr uint64_t kFlowTimeoutTicks = 200000000;   // a wait's limit: 2 s of the 100 MHz real-time counter
+// Pipelined pass: bands of 64 lanes x R rows on workgroups of W waves, one
+// workgroup per CU (W / 4 waves per SIMD, so no SIMD carries more than the
+// others: the bands advance at the pace of the slowest).  Fitted to MI355X
+// (DNA pairs, one band at n = 50K..200K for the step, 16..512 bands at
+// n = 100K for the lag): a wave alone on its SIMD takes 369 + 32.4 (R - 4)
+// cycles per step (latency-bound, about 1.3 to 1.6 times its VALU issue
+// time); k waves sharing a SIMD issue-bound, k x 4.6 cycles per VALU
+// instruction; each band starts about 149 - 2.3 R steps after the band above
+// (the last lane's 63-column lag, the 16-step read-ahead and the latency of
+// the handoff words through memory).  With more than 64 bands at work every
+// step takes 1.16 times as long (measured with 633 to 2,930 bands of 4, 10
+// and 16 rows: clock and memory under a busy device).  Bands run in rounds
+// when they outnumber the waves; a round's band starts when its wave is free
+// and the band above is far enough ahead.
 constexpr double kFlowLaunchS = 15e-6;       // clear, launch and finish kernels
 constexpr int64_t kFlowMaxBands = (1 << 16) - 1;
 constexpr int64_t kFlowMaxValue = (1 << 24) - 1;
+constexpr uint64_t kFlowTimeoutTicks = 200000000;   // a wait's limit: 2 s of the 100 MHz real-time counter
+constexpr int kFlowGroupLds = 96 * 1024;     // LDS a workgroup asks for at least: over half a CU's
 
-double flow_instr_per_step(int R) { return 9.0 * R + 24.0; }
+// VALU instructions of one step (the counted hot loop of the kernel: 8 per
+// row and 26.25 per column)
+double flow_instr_per_step(int R) { return 8.0 * R + 26.25; }
 
 int64_t flow_bands(int64_t m, int R) { return ceil_div(ceil_div(std::max<int64_t>(m, 1), R), kWave); }
 
-// Resident waves per CU of the pipelined pass (its register budget: 128
-// registers up to 6 rows per lane, 256 beyond).
-int64_t flow_waves_per_cu(int R) { return R <= 6 ? 16 : 8; }
+// Waves per workgroup the kernel is built for: 16 (128 registers) up to 6
+// rows per lane, 8 (256 registers) beyond.
+int flow_max_wpg(int R) { return R <= 6 ? 16 : 8; }
 
-double flow_time(int64_t m, int64_t n, int R, int cu)
+struct FlowShape {
+    int wpg = 0, grid = 0, lds = 0;
+    double est_s = 1e300;
+};
+
+// The cheapest workgroup shape for R rows: W in 1, 2, 4, ..., as far as the
+// registers and the LDS (W band profiles within `lds_max`) allow; the grid
+// is at most one workgroup per CU (or grid_limit).
+FlowShape flow_shape(int64_t m, int64_t n, int R, int elem, int cu, int lds_max, int grid_limit)
 {
+    FlowShape best;
     const int64_t nb = flow_bands(m, R);
-    const int64_t cap = flow_waves_per_cu(R) * std::max(cu, 1);
-    const int64_t G = std::min(nb, cap);
-    const double k = std::ceil((double)G / (4.0 * std::max(cu, 1)));
-    const double rounds = std::ceil((double)nb / (double)G);
-    const double I = flow_instr_per_step(R);
-    const double step = std::max(4.92 * I, k * kPairIssueCycles * I);
-    const double steps = rounds * (double)(n + kWave - 1) + (double)G * kFlowLagSteps;
-    return steps * step / 2.4e9 + kFlowLaunchS;
+    const int per = flow_lds_bytes(R, elem);
+    const int cap = std::min(lds_max, kLdsPerCU);
+    for (int wpg = 1; wpg <= flow_max_wpg(R) && (int64_t)wpg * per <= cap; wpg *= 2) {
+        int64_t grid = std::min<int64_t>(ceil_div(nb, wpg), std::max(cu, 1));
+        if (grid_limit > 0) grid = std::min<int64_t>(grid, grid_limit);
+        const int64_t G = grid * wpg;
+        const double k = std::ceil(wpg / 4.0);
+        const double rounds = std::ceil((double)nb / (double)G);
+        const double busy = G > 64 ? 1.16 : 1.0;
+        const double step = busy * std::max(369.0 + 32.4 * (R - 4), k * kPairIssueCycles * flow_instr_per_step(R));
+        const double lag = 149.0 - 2.3 * R;
+        const double steps = std::max(rounds * (double)(n + kWave - 1) + (double)G * lag,
+                                      (double)nb * lag + (double)(n + kWave - 1));
+        const double t = steps * step / 2.4e9 + kFlowLaunchS;
+        if (t < best.est_s) {
+            best.wpg = wpg;
+            best.grid = (int)grid;
+            best.lds = std::max(wpg * per, std::min(cap, kFlowGroupLds));
+            best.est_s = t;
+        }
+    }
+    return best;
 }
 
 // Whether the pipelined pass can score the pair: its handoff words hold
@@ -1805,11 +1860,12 @@ PairPlanC pair_plan_search(int64_t m, int64_t n, int cu, int fixR, int fixK, int
 // milliseconds for the largest pairs); the last plans are kept, since callers
 // often repeat one pair size.  rect: plan for the rectangular tiles of an
 // alignment's code and checkpoint passes.
-PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool rect = false, int sm_max = 127)
+PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool rect = false, int sm_max = 127,
+                    int elem = 2, int lds_max = kLdsPerCU)
 {
     struct Entry {
         int64_t m = -1, n = -1;
-        int cu = 0, R = 0, K = 0, W = 0, mode = 0, sm = 0, grid = 0;
+        int cu = 0, R = 0, K = 0, W = 0, mode = 0, sm = 0, grid = 0, elem = 0, lds = 0;
         bool rect = false;
         PairPlanC p;
     };
@@ -1824,7 +1880,8 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool re
         std::lock_guard<std::mutex> lk(mu);
         for (const Entry& e : cache)
             if (e.m == m && e.n == n && e.cu == cu && e.R == fixR && e.K == fixK && e.W == fixW && e.rect == rect &&
-                e.mode == mode && e.sm == sm_max && e.grid == (opt ? opt->grid_limit : 0))
+                e.mode == mode && e.sm == sm_max && e.grid == (opt ? opt->grid_limit : 0) && e.elem == elem &&
+                e.lds == lds_max)
                 return e.p;
     }
     PairPlanC p;
@@ -1836,24 +1893,25 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool re
     if (mode != 1 && !(mode == 0 && (fixK || fixW))) {
         for (int R : kFlowRowChoices) {
             if ((fixR && R != fixR) || !flow_fits(m, n, R, sm_max)) continue;
-            const double t = flow_time(m, n, R, cu);
-            if (t < p.est_s) {
+            const FlowShape sh = flow_shape(m, n, R, elem, cu, lds_max, opt ? opt->grid_limit : 0);
+            if (sh.wpg > 0 && sh.est_s < p.est_s) {
                 PairPlanC f;
                 f.flow = true;
                 f.R = R;
                 f.K = kWave;
                 f.nbr = ceil_div(m, R);
                 f.nb = flow_bands(m, R);
-                f.waves = (int)std::min<int64_t>(f.nb, flow_waves_per_cu(R) * std::max(cu, 1));
-                if (opt && opt->grid_limit)      // a cap on workgroups (4 waves): bands run in rounds
-                    f.waves = (int)std::min<int64_t>(f.waves, (int64_t)opt->grid_limit * 4);
-                f.est_s = t;
+                f.wpg = sh.wpg;
+                f.grid = sh.grid;
+                f.lds = sh.lds;
+                f.waves = sh.grid * sh.wpg;
+                f.est_s = sh.est_s;
                 p = f;
             }
         }
     }
     std::lock_guard<std::mutex> lk(mu);
-    cache[next] = Entry{m, n, cu, fixR, fixK, fixW, mode, sm_max, opt ? opt->grid_limit : 0, rect, p};
+    cache[next] = Entry{m, n, cu, fixR, fixK, fixW, mode, sm_max, opt ? opt->grid_limit : 0, elem, lds_max, rect, p};
     next = (next + 1) % 8;
     return p;
 }
@@ -1924,6 +1982,10 @@ int validate_pair(int64_t m, int64_t n, const sw_options* opt, std::string& why)
     const int mode = opt ? opt->pair_mode : 0;
     if (mode < 0 || mode > 2) { why = "options.pair_mode must be 0, 1 or 2"; return 0; }
     if (opt && (opt->pair_sm_max < 0 || opt->pair_sm_max > 127)) { why = "options.pair_sm_max must be 0..127"; return 0; }
+    if (opt && (opt->pair_entry_bytes < 0 || opt->pair_entry_bytes > 2)) {
+        why = "options.pair_entry_bytes must be 0, 1 or 2";
+        return 0;
+    }
     if (opt && opt->pair_rows) {
         bool ok = false;
         if (mode == 2) {
@@ -1959,7 +2021,8 @@ int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, 
     if (!validate_pair(m, n, opt, why)) return fail(SW_EINVAL, why);
     if (!out) return fail(SW_EINVAL, "null output");
     const int sm_max = (opt && opt->pair_sm_max) ? opt->pair_sm_max : 127;
-    const PairPlanC p = pair_plan(m, n, cu_count > 0 ? cu_count : 256, opt, false, sm_max);
+    const int elem = (opt && opt->pair_entry_bytes) ? opt->pair_entry_bytes : 2;
+    const PairPlanC p = pair_plan(m, n, cu_count > 0 ? cu_count : 256, opt, false, sm_max, elem);
     if (!p.R) return fail(SW_EINVAL, "the pipelined pass cannot hold this pair's scores (max(SM) x min(m, n) >= 2^24)");
     *out = sw_pair_stats{};
     out->rows = p.R;
@@ -1974,6 +2037,8 @@ int sw_pair_plan(int64_t m, int64_t n, const sw_options* opt, int32_t cu_count, 
     else if (m > 0 && n > 0)
         skew_walk(skew_grid(m, n, p.R, p.K, p.wc), [&](int64_t, int64_t, int64_t) { ++launches; });
     out->launches = launches;
+    out->groups = p.grid;
+    out->group_waves = p.wpg;
     out->est_ms = p.est_s * 1e3;
     out->workspace = (int64_t)sw_pair_workspace_bytes(m, n, opt);
     return SW_OK;
@@ -2005,6 +2070,15 @@ int device_cu(int* cu)
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(cu, hipDeviceAttributeMultiprocessorCount, dev));
+    return SW_OK;
+}
+
+// LDS bytes a workgroup may ask for on the current device.
+int device_lds(int* lds)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     return SW_OK;
 }
 
@@ -2131,8 +2205,17 @@ int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint
         f.go = go;
         f.ge = ge;
         f.timeout = kFlowTimeoutTicks;
+        // every band's wave must be resident at once (a band waits for the
+        // band above, which may run on any other wave)
+        int cu = 0;
+        rc = device_cu(&cu);
+        if (rc) return rc;
+        const int occ = flow_occupancy(p.R, elem, p.wpg, p.lds);
+        if (occ < 1 || p.grid > occ * cu)
+            return fail(SW_EHIP, "pipelined pass: " + std::to_string(p.grid) + " workgroups of " +
+                                     std::to_string(p.wpg) + " waves do not fit the device at once");
         if (ev0) HIPCHK(hipEventRecord(ev0, stream));
-        HIPCHK(launch_pair_flow(f, p.R, elem, stream));
+        HIPCHK(launch_pair_flow(f, p.R, elem, p.wpg, p.grid, p.lds, stream));
         if (ev1) HIPCHK(hipEventRecord(ev1, stream));
         return SW_OK;
     }
@@ -2315,16 +2398,18 @@ int sw_pair_score(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     const size_t need = sw_pair_workspace_bytes(m, n, opt);
     if (ws_bytes < need)
         return fail(SW_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
-    int cu = 256;
+    int cu = 256, lds = kLdsPerCU;
     rc = device_cu(&cu);
+    if (rc) return rc;
+    rc = device_lds(&lds);
     if (rc) return rc;
     int sm_max = 0;
     for (int i = 0; i < kAlpha * kAlpha; ++i) sm_max = std::max(sm_max, (int)sm[i]);
-    const PairPlanC p = pair_plan(m, n, cu, opt, false, sm_max);
+    const int elem = (fit == kFitS8 || fit == kFitU8) ? 1 : 2;
+    const PairPlanC p = pair_plan(m, n, cu, opt, false, sm_max, elem, lds);
     if (!p.R) return fail(SW_EINVAL, "the pipelined pass cannot hold this pair's scores (max(SM) x min(m, n) >= 2^24)");
     const PairLayout L = pair_layout(m, n, &p, p.wc);
     if (L.total > need) return fail(SW_EINVAL, "internal error: pair layout exceeds the workspace size");
-    const int elem = (fit == kFitS8 || fit == kFitU8) ? 1 : 2;
     return pair_enqueue(p, L, static_cast<uint8_t*>(ws), query, m, subject, n, sm, go, ge, elem, score_out,
                         nullptr, nullptr, opt ? opt->ev_search_begin : nullptr,
                         opt ? opt->ev_search_end : nullptr, stream);

@@ -139,6 +139,23 @@ def test_flow_pass_rounds(R):
         assert _gpu_pair(a, b, sm, go, ge, pair_mode=2, pair_rows=R, grid_limit=grid) == exp
 
 
+@pytest.mark.parametrize("m,n,R,grid", [(70_001, 2_000, 4, 0), (70_001, 2_000, 16, 0), (30_000, 1_500, 6, 3),
+                                         (30_000, 1_500, 12, 5), (9_000, 700, 8, 1)])
+def test_flow_pass_workgroup_shapes(m, n, R, grid):
+    """Workgroups of several waves, each wave a band of its own with its own
+    LDS profile: the shapes the planner picks for a few hundred bands and
+    under a workgroup cap (rounds, waves left without a band)."""
+    import paper_2412_08308_amd as swdb
+    a, b = synth.dna_pair(m, n, seed=m + R, identity=0.8, indel_rate=0.01)
+    sm, go, ge = DNA
+    exp = oracle_pair(a, b, sm, go, ge)
+    p = swdb.pair_plan(m, n, swdb.options(pair_mode=2, pair_rows=R, grid_limit=grid, pair_sm_max=1,
+                                          pair_entry_bytes=1))
+    announce(f"flow shapes m={m} n={n} R={R} grid={grid}: {p['groups']} x {p['group_waves']} waves")
+    assert p["flow"] == 1 and p["group_waves"] >= 1
+    assert _gpu_pair(a, b, sm, go, ge, pair_mode=2, pair_rows=R, grid_limit=grid) == exp
+
+
 @pytest.mark.parametrize("go,ge", [(10, 2), (120, 1)])
 def test_flow_pass_protein(go, ge):
     """Protein pairs through the pipelined pass with both profile widths

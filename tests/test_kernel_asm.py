@@ -24,43 +24,75 @@ def _asm(unit, tmp_path):
     return out.read_text()
 
 
-def _full_mask_at(body, i, seen):
-    """Whether every path reaching line i of a kernel body arrives with the
-    whole wave active, judged from the nearest change of the execution mask
-    before it on each path: a restore (s_or_b64 / s_mov_b64 exec) or the
-    kernel's entry counts as full, a saveexec as narrowed.  At a label the
-    paths are its fall-through (unless the line before ends the flow) and
-    every branch to it; a label already under examination counts as full, the
-    other paths into the loop deciding."""
-    for k in range(i - 1, -1, -1):
-        u = body[k].strip()
-        if u.startswith(("s_or_b64 exec", "s_mov_b64 exec")):
-            return True
-        if "saveexec" in u:
-            return False
+_BRANCH = re.compile(r"\s*s_(c)?branch\w*\s+(\.LBB\w+)\s*$")
+
+
+def _full_mask_lines(body):
+    """For every line of a kernel body, whether every path reaching it
+    arrives with the whole wave active, judged from the nearest change of the
+    execution mask before it on each path: a restore (s_or_b64 / s_mov_b64
+    exec) or the kernel's entry counts as full, a saveexec as narrowed.  At a
+    label the paths are its fall-through (unless the line before ends the
+    flow) and every branch to it.  Solved as a greatest fixed point over the
+    labels (all start full; a label becomes narrowed once some path into it
+    arrives narrowed), so loops are decided by the paths into them."""
+    block = []                      # label (or None: the entry) of each line
+    local = []                      # the mask set in the line's block up to and including it, or None
+    label, cur = None, None
+    labels = {}
+    for k, ln in enumerate(body):
+        u = ln.strip()
         if u.startswith(".LBB") and u.split()[0].endswith(":"):
-            label = u.split(":")[0]
-            if label in seen:
-                return True
-            seen = seen | {label}
-            srcs = [n for n, ln in enumerate(body)
-                    if re.match(r"\s*s_(c)?branch\w*\s+" + re.escape(label) + r"\s*$", ln)]
-            prev = next((body[q].strip() for q in range(k - 1, -1, -1)
-                         if body[q].strip() and not body[q].strip().startswith(";")), "")
-            falls = not prev.startswith(("s_branch", "s_endpgm", "s_setpc"))
-            return all(_full_mask_at(body, n, seen) for n in srcs) and (not falls or _full_mask_at(body, k, seen))
-    return True
+            label, cur = u.split(":")[0], None
+            labels[label] = k
+        block.append(label)
+        if u.startswith(("s_or_b64 exec", "s_mov_b64 exec")):
+            cur = True
+        elif "saveexec" in u:
+            cur = False
+        local.append(cur)
+    entry = {L: True for L in labels}
+
+    def after(j):                       # the state just after line j
+        if local[j] is not None:
+            return local[j]
+        return True if block[j] is None else entry[block[j]]
+
+    def before(i):                      # the state just before line i
+        if block[i] is not None and labels[block[i]] == i:
+            return entry[block[i]]
+        return True if i == 0 else after(i - 1)
+
+    preds = {L: [] for L in labels}     # states flowing into each label
+    for n, ln in enumerate(body):
+        m = _BRANCH.match(ln)
+        if m and m.group(2) in preds:
+            preds[m.group(2)].append(lambda n=n: before(n))
+    for L, k in labels.items():
+        prev = next((q for q in range(k - 1, -1, -1)
+                     if body[q].strip() and not body[q].strip().startswith(";")), None)
+        if prev is not None and not body[prev].strip().startswith(("s_branch", "s_endpgm", "s_setpc")):
+            preds[L].append(lambda k=k: after(k - 1))        # fall-through
+    changed = True
+    while changed:
+        changed = False
+        for L in labels:
+            if entry[L] and not all(f() for f in preds[L]):
+                entry[L] = False
+                changed = True
+    return [before(i) for i in range(len(body))]
 
 
 def dpp_under_partial_exec(asm: str):
     """(kernel, line) of each DPP move that some path reaches with part of the
-    wave masked off (see _full_mask_at)."""
+    wave masked off (see _full_mask_lines)."""
     found = []
     for name in re.findall(r"^(_ZN4swdb\w*):", asm, re.M):
         m = re.search(r"^" + re.escape(name) + r":.*?s_endpgm", asm, re.S | re.M)
         body = m.group(0).split("\n")
+        full = _full_mask_lines(body)
         for i, line in enumerate(body):
-            if "_dpp" in line and not _full_mask_at(body, i, frozenset()):
+            if "_dpp" in line and not full[i]:
                 found.append((name, line.strip()))
     return found
 

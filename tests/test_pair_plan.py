@@ -50,6 +50,16 @@ def test_pipelined_plan(m, n):
         assert p["flow"] == 1 and p["rows"] == R and p["lanes"] == 64 and p["launches"] == 1
         assert p["bands"] == -(-(-(-m // R)) // 64)
         assert p["workspace"] == swdb.pair_workspace_bytes(m, n) > 0
+        # workgroups of W waves, one per CU: W band profiles fit the CU's LDS,
+        # the registers allow W / 4 waves per SIMD, and the waves reach every
+        # band (in rounds when there are more bands than waves)
+        for eb in (1, 2):
+            q = swdb.pair_plan(m, n, swdb.options(pair_mode="flow", pair_rows=R, pair_sm_max=1,
+                                                  pair_entry_bytes=eb))
+            W, G = q["group_waves"], q["groups"]
+            stride = next(x for x in (4, 8, 16, 32) if R * eb <= x)
+            assert 1 <= W <= (16 if R <= 6 else 8) and W * 33 * 64 * stride <= 160 * 1024
+            assert 1 <= G <= 256 and G == min(-(-q["bands"] // W), 256)
     # scores that do not fit 24 bits: the pipelined pass is refused or not chosen
     big = swdb.options(pair_mode="flow", pair_sm_max=127)
     if 127 * min(m, n) >= 1 << 24:
@@ -67,7 +77,19 @@ def test_pipelined_plan(m, n):
 def test_pipelined_rounds_follow_the_grid_cap():
     o = swdb.options(pair_mode="flow", pair_rows=4, pair_sm_max=1, grid_limit=2)
     p = swdb.pair_plan(20_000, 3_000, o)
-    assert p["flow"] == 1 and p["bands"] == 79
+    assert p["flow"] == 1 and p["bands"] == 79 and p["groups"] <= 2
+
+
+def test_pipelined_shape_keeps_simds_even():
+    """Up to one band per SIMD (1,024 on 256 CUs) the planner gives each band
+    a SIMD of its own; the paper's DNA pairs all take the pipelined pass."""
+    o = swdb.options(pair_sm_max=1, pair_entry_bytes=1)
+    for m, n in [(162_000, 172_000), (543_000, 536_000), (1_000_000, 1_000_000)]:
+        p = swdb.pair_plan(m, n, o)
+        assert p["flow"] == 1 and p["bands"] <= 1024 and p["group_waves"] <= 4
+        assert p["est_ms"] < swdb.pair_plan(m, n, swdb.options(pair_mode="tiles"))["est_ms"]
+    with pytest.raises(swdb.SwdbError):
+        swdb.pair_plan(10, 10, swdb.options(pair_entry_bytes=3))
 
 
 @pytest.mark.parametrize("n,K,wc", [(1, 1, 16), (5, 64, 16), (100, 2, 16), (1000, 64, 64), (777, 16, 48),
