@@ -18,8 +18,12 @@ scheduler thread
   and requests longer than ``long_s`` of estimated device time may hold all
   but one of the in-flight slots, so a short request always finds a slot;
 * the GPU backend cuts each batch's work into persistent launches of a few
-  milliseconds (``slice_mcells``), so a short batch on another stream gets
-  the device between the launches of a long one instead of after it;
+  milliseconds (``slice_mcells``).  A batch holding a long request is
+  *stepped*: the scheduler enqueues its launches itself, at most
+  ``long_depth`` of them outstanding over all long batches (earliest deadline
+  first), and none while a batch of short requests is in flight, so a short
+  request waits at most for the long launches already queued instead of
+  sharing the device with them for its whole run;
 * records a completion event per batch (after an asynchronous copy of the
   scores to pinned host memory) and resolves each request's future when it
   fires, with the latency (completion - arrival) attached.
@@ -27,7 +31,8 @@ scheduler thread
 Scores are exact integers, so a request's result is identical whether it runs
 alone or inside any batch.  ``GpuBackend`` does the device work through the
 library; the scheduler itself only needs the small backend interface
-(``need_bytes``, ``launch``, ``poll``, ``results``, ``cells``).
+(``need_bytes``, ``launch``, ``poll``, ``results``, ``cells``; stepped
+batches also ``advance``, ``remaining`` and ``queued``).
 """
 from __future__ import annotations
 
@@ -76,7 +81,8 @@ class GpuBackend:
         self.db = db
         self.matrix = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
         self.go, self.ge = int(gap_open), int(gap_extend)
-        self.opt = options(mode=mode, slice_mcells=slice_mcells, **opt_kw)
+        self._opt_kw = dict(mode=mode, slice_mcells=slice_mcells, **opt_kw)
+        self.opt = options(**self._opt_kw)
         self.device = db.device
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.nseq = db.nseq
@@ -92,7 +98,10 @@ class GpuBackend:
     def cells(self, qlens: Sequence[int]) -> int:
         return int(sum(qlens)) * self.db.total
 
-    def launch(self, slot: int, queries: List[np.ndarray]):
+    def launch(self, slot: int, queries: List[np.ndarray], stepped: bool = False):
+        """Enqueue a batch on stream ``slot``: all of its launches, or with
+        ``stepped`` (and slicing on) none yet -- ``advance`` enqueues them one
+        at a time."""
         torch = self.torch
         s = self.streams[slot]
         lens = [len(q) for q in queries]
@@ -104,18 +113,55 @@ class GpuBackend:
             cat = host.to(self.device, non_blocking=True)
             ws = self.db.alloc_workspace(lens, self.opt)
             out = torch.empty((len(lens), self.nseq), dtype=torch.int32, device=self.device)
-            self.db.search_batch((cat, offs, lens), self.matrix, self.go, self.ge, opt=self.opt, out=out,
-                                 workspace=ws, stream=s, check=False)
-            status = torch.zeros(4, dtype=torch.int32, pin_memory=True)
-            self.db.status_async(ws, status, stream=s)
-            res = torch.empty((len(lens), self.nseq), dtype=torch.int32, pin_memory=True)
-            res.copy_(out, non_blocking=True)
+        h = {"stream": s, "args": (cat, offs, lens), "ws": ws, "out": out, "keep": (host,),
+             "next": 0, "total": 1, "slice_events": collections.deque(), "event": None}
+        if stepped and self.opt.slice_mcells > 0 and sum(lens) > 0:
+            h["total"] = int(self.db.plan_info(lens, self.opt)["launches"])
+        if h["total"] <= 1 or not stepped:
+            self._enqueue(h, None)
+        return h
+
+    def _enqueue(self, h, k):
+        """Enqueue launch k of the batch (None: all of them); after the last
+        one, the status and score copies and the completion event."""
+        torch = self.torch
+        s = h["stream"]
+        opt = self.opt if k is None else options_for(self._opt_kw, slice_begin=k, slice_count=1)
+        with torch.cuda.stream(s):
+            self.db.search_batch(h["args"], self.matrix, self.go, self.ge, opt=opt, out=h["out"],
+                                 workspace=h["ws"], stream=s, check=False)
+            h["next"] = h["total"] if k is None else k + 1
             ev = torch.cuda.Event()
-            ev.record(s)
-        return {"event": ev, "res": res, "status": status, "keep": (host, cat, ws, out)}
+            if h["next"] >= h["total"]:
+                status = torch.zeros(4, dtype=torch.int32, pin_memory=True)
+                self.db.status_async(h["ws"], status, stream=s)
+                res = torch.empty(tuple(h["out"].shape), dtype=torch.int32, pin_memory=True)
+                res.copy_(h["out"], non_blocking=True)
+                h["status"], h["res"] = status, res
+                ev.record(s)
+                h["event"] = ev
+            else:
+                ev.record(s)
+            h["slice_events"].append(ev)
+
+    def advance(self, handle):
+        """Enqueue the stepped batch's next launch."""
+        if handle["next"] < handle["total"]:
+            self._enqueue(handle, handle["next"])
+
+    def remaining(self, handle) -> int:
+        """Launches of the batch not enqueued yet."""
+        return handle["total"] - handle["next"]
+
+    def queued(self, handle) -> int:
+        """Enqueued launches of the batch that have not finished."""
+        q = handle["slice_events"]
+        while q and q[0].query():
+            q.popleft()
+        return len(q)
 
     def poll(self, handle) -> bool:
-        return handle["event"].query()
+        return handle["event"] is not None and handle["event"].query()
 
     def results(self, handle) -> List[np.ndarray]:
         """Score rows of a finished batch; raises the batch's status error (a
@@ -129,16 +175,25 @@ class GpuBackend:
         return [r[k].copy() for k in range(r.shape[0])]
 
 
+def options_for(kw: dict, **more):
+    from . import options
+    return options(**{**kw, **more})
+
+
 class Server:
     """Continuous-batching request loop (see module docstring)."""
 
     def __init__(self, backend, max_batch: int = 16, max_inflight: Optional[int] = None,
                  mem_budget: Optional[int] = None, poll_interval: float = 1e-4, clock=time.perf_counter,
                  policy: str = "edf", rate_guess: float = 1e12, size_ratio: float = 4.0,
-                 long_s: float = 0.02):
+                 long_s: float = 0.02, long_depth: int = 2):
         if policy not in ("edf", "fifo"):
             raise ValueError("policy must be 'edf' or 'fifo'")
+        if long_depth < 1:
+            raise ValueError("long_depth must be >= 1")
         self.policy = policy
+        self.long_depth = int(long_depth)   # outstanding launches of stepped (long) batches
+        self.stepping = all(hasattr(backend, f) for f in ("advance", "remaining", "queued"))
         self.size_ratio = float(size_ratio)   # 0: batch regardless of size
         self.long_s = float(long_s)           # estimated device time that makes a request long
         self.rate = float(rate_guess)       # cells per second, updated from completed batches
@@ -170,6 +225,7 @@ class Server:
         self.batch_sizes = []
         self.errors = []
         self._failed = None            # the error that stopped the scheduler, if any
+        self._stepped = set()          # ids of in-flight handles whose launches the scheduler enqueues
 
     # ------------------------------------------------------------------ client side
 
@@ -254,6 +310,7 @@ class Server:
         for entry in done:
             slot, h, reqs, nbytes, t_launch = entry
             self._inflight.remove(entry)
+            self._stepped.discard(id(h))
             try:
                 rows = self.backend.results(h)
                 err = None
@@ -342,8 +399,12 @@ class Server:
                     nbytes = self.backend.need_bytes([r.qlen for r in live])
                     self._in_use += nbytes
                 batch = live
+            stepped = self.stepping and any(self._is_long(r.qlen) for r in batch)
             try:
-                h = self.backend.launch(slot, [r.query for r in batch])
+                if stepped:
+                    h = self.backend.launch(slot, [r.query for r in batch], stepped=True)
+                else:
+                    h = self.backend.launch(slot, [r.query for r in batch])
             except Exception as e:
                 for r in batch:
                     r.future.set_exception(e)
@@ -354,7 +415,28 @@ class Server:
                 continue
             self.batch_sizes.append(len(batch))
             self._inflight.append((slot, h, batch, nbytes, self.clock()))
+            if stepped:
+                self._stepped.add(id(h))
             launched = True
+
+    def _advance(self) -> bool:
+        """Enqueue launches of stepped batches: none while a batch that is
+        not stepped is in flight, else up to long_depth outstanding, earliest
+        deadline first."""
+        if not self._stepped:
+            return False
+        stepped = [e for e in self._inflight if id(e[1]) in self._stepped]
+        if len(stepped) < len(self._inflight):
+            return False
+        outstanding = sum(self.backend.queued(e[1]) for e in stepped)
+        moved = False
+        for e in sorted(stepped, key=lambda e: min(r.deadline for r in e[2])):
+            h = e[1]
+            while outstanding < self.long_depth and self.backend.remaining(h) > 0:
+                self.backend.advance(h)
+                outstanding += 1
+                moved = True
+        return moved
 
     def _is_long(self, qlen: int) -> bool:
         return self.backend.cells([qlen]) / self.rate > self.long_s
@@ -367,6 +449,7 @@ class Server:
             while True:
                 progressed = self._complete()
                 progressed |= self._admit()
+                progressed |= self._advance()
                 with self._cv:
                     if not self._running and not self._pending and not self._inflight:
                         return
@@ -387,6 +470,7 @@ class Server:
             self._running = False
             reqs = [r for _, _, batch, _, _ in self._inflight for r in batch] + list(self._pending)
             self._inflight = []
+            self._stepped.clear()
             self._pending.clear()
         for r in reqs:
             if not r.future.done():

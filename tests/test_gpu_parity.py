@@ -261,3 +261,72 @@ def test_sliced_launches(mode):
             assert np.array_equal(got, exp), mismatch_report(got, exp)
         finally:
             gdb2.release()
+
+
+@pytest.mark.parametrize("mode", ["auto", "i32", "tuned"])
+def test_sliced_search_launch_by_launch(mode):
+    """A sliced search enqueued one launch per call (slice_begin, slice_count
+    = 1) on one workspace equals the oracle, and its status words add up over
+    the calls as in one call (the flagged count of planted 16-bit overflows)."""
+    import torch
+    import paper_2412_08308_amd as swdb
+    rng = np.random.default_rng(23)
+    sm = synth.blosum_style_matrix()
+    lens = rng.integers(0, 900, size=900).tolist() + [0, 3, 5000]
+    _, db = synth.random_case(rng, 1, lens)
+    qs = [synth.residues(rng, int(m)) for m in [700, 0, 33, 2500]]
+    gdb = gpu_db(db)
+    try:
+        if mode == "tuned":
+            gdb.set_tuning([{"qlen": 100, "mode": 2, "waves": 8, "lane_cells": 24576},
+                            {"qlen": 9000, "mode": 1, "waves": 4, "lane_cells": 49152}])
+        lens_q = [len(q) for q in qs]
+        kw = dict(mode=mode, slice_mcells=2)
+        n = gdb.plan_info(lens_q, swdb.options(**kw))["launches"]
+        assert n > 3
+        qts = [torch.from_numpy(q).cuda() for q in qs]
+        cat = torch.cat(qts)
+        offs = np.concatenate([[0], np.cumsum(lens_q[:-1])]).astype(np.int64)
+        ws = gdb.alloc_workspace(lens_q, swdb.options(**kw))
+        out = torch.full((len(qs), db.nseq), -7, dtype=torch.int32, device="cuda")
+        announce(f"launch-by-launch search mode={mode}: {n} launches")
+        for k in range(n):
+            gdb.search_batch((cat, offs, lens_q), sm, 10, 2, opt=swdb.options(**kw, slice_begin=k, slice_count=1),
+                             out=out, workspace=ws, check=False)
+        gdb.status(ws, raise_on_error=True)
+        got = out.cpu().numpy().astype(np.int64)
+        for k, q in enumerate(qs):
+            exp = oracle_scores(db, q, sm, 10, 2)
+            assert np.array_equal(got[k], exp), f"{mode} query {k}: " + mismatch_report(got[k], exp)
+        with pytest.raises(swdb.SwdbError):
+            gdb.search_batch((cat, offs, lens_q), sm, 10, 2, opt=swdb.options(**kw, slice_begin=n), out=out,
+                             workspace=ws, check=False)
+    finally:
+        gdb.release()
+    if mode == "tuned":
+        return
+    sm2 = overflow_matrix(127, -10)
+    subj = [overflow_sequence(t, 127) for t in (32766, 32767, 40000)] * 4
+    subj += [rng.integers(2, 20, size=int(x)).astype(np.uint8) for x in rng.integers(10, 300, size=300)]
+    db2 = synth.Database.from_list(subj)
+    q2 = np.concatenate([np.zeros(400, np.uint8), np.ones(300, np.uint8)])
+    gdb2 = gpu_db(db2)
+    try:
+        kw = dict(mode=mode, slice_mcells=1)
+        n = gdb2.plan_info([len(q2)], swdb.options(**kw))["launches"]
+        assert n > 2
+        ws = gdb2.alloc_workspace([len(q2)], swdb.options(**kw))
+        out = torch.full((1, db2.nseq), -7, dtype=torch.int32, device="cuda")
+        qt = torch.from_numpy(q2).cuda()
+        announce(f"launch-by-launch overflow mode={mode}: {n} launches")
+        for k in range(n):
+            gdb2.search_batch([qt], sm2, 10, 2, opt=swdb.options(**kw, slice_begin=k, slice_count=1), out=out,
+                              workspace=ws, check=False)
+        st = gdb2.status(ws, raise_on_error=True)
+        got = out.cpu().numpy()[0].astype(np.int64)
+        exp = oracle_scores(db2, q2, sm2, 10, 2)
+        assert np.array_equal(got, exp), mismatch_report(got, exp)
+        if mode == "auto":
+            assert st["flagged"] == int(np.sum(exp >= 32767)) > 0
+    finally:
+        gdb2.release()

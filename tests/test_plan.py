@@ -182,4 +182,8 @@ def test_slice_option_validated():
     db = swdb.Database.describe(_lengths("tiny"))
     with pytest.raises(swdb.SwdbError):
         db.plan_info([10], swdb.options(slice_mcells=-1))
+    for bad in (dict(slice_begin=-1, slice_mcells=1), dict(slice_count=-2, slice_mcells=1),
+                dict(slice_begin=1), dict(slice_count=1)):       # a launch range needs slicing on
+        with pytest.raises(swdb.SwdbError):
+            db.plan_info([10], swdb.options(**bad))
     db.release()

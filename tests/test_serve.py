@@ -280,3 +280,78 @@ def test_latency_by_length_class():
     assert [c["requests"] for c in cls] == [2, 1, 3]
     assert cls[0]["qlen_lo"] == 0 and cls[2]["qlen_hi"] is None
     assert all(c["p50_s"] > 0 and c["p99_s"] >= c["p50_s"] for c in cls)
+
+
+class StepBackend(FakeBackend):
+    """A device that runs enqueued work in order, one piece at a time.  A
+    batch launched ``stepped`` has ``qlen // 10`` launches of ``slice_s``
+    each, which the scheduler enqueues with ``advance``; other batches run
+    whole (``delay``)."""
+
+    def __init__(self, *a, slice_s=0.01, **kw):
+        super().__init__(*a, **kw)
+        self.slice_s = slice_s
+        self.free_at = 0.0
+        self.log = []                  # (kind, query lengths, enqueued, start, end)
+
+    def _run(self, dur, kind, h):
+        now = time.perf_counter()
+        start = max(now, self.free_at)
+        self.free_at = start + dur
+        self.log.append((kind, [len(q) for q in h["q"]], now, start, self.free_at))
+        return self.free_at
+
+    def launch(self, slot, queries, stepped=False):
+        h = {"q": queries, "next": 0, "total": 1, "t": None, "ends": []}
+        self.launches.append((slot, [len(q) for q in queries]))
+        if stepped:
+            h["total"] = max(1, sum(len(q) for q in queries) // 10)
+        else:
+            h["t"] = self._run(self.delay, "whole", h)
+        return h
+
+    def advance(self, h):
+        h["ends"].append(self._run(self.slice_s, "slice", h))
+        h["next"] += 1
+        if h["next"] == h["total"]:
+            h["t"] = h["ends"][-1]
+
+    def remaining(self, h):
+        return h["total"] - h["next"]
+
+    def queued(self, h):
+        now = time.perf_counter()
+        return sum(1 for t in h["ends"] if now < t)
+
+    def poll(self, h):
+        return h["t"] is not None and time.perf_counter() >= h["t"]
+
+
+@pytest.mark.parametrize("depth", [1, 2])
+def test_long_batches_step_around_short_ones(depth):
+    """A long request runs launch by launch; a short one arriving meanwhile is
+    enqueued at once, waits only for the long launches already queued (at most
+    long_depth), and no long launch is enqueued while it is in flight."""
+    db, sm = _db(), synth.blosum_style_matrix()
+    be = StepBackend(db, sm, delay=0.02, slice_s=0.01)
+    rate = be.cells([1]) / 1e-3        # 1 ms per residue: 80 residues = 80 ms > long_s
+    srv = Server(be, max_batch=1, mem_budget=10**9, rate_guess=rate, long_s=0.03, long_depth=depth).start()
+    rng = np.random.default_rng(12)
+    long_q = rng.integers(0, 20, size=80).astype(np.uint8)
+    short_q = rng.integers(0, 20, size=6).astype(np.uint8)
+    fl = srv.submit(long_q)
+    time.sleep(0.035)
+    fs = srv.submit(short_q)
+    got_l, got_s = fl.result(timeout=10), fs.result(timeout=10)
+    srv.stop()
+    assert np.array_equal(got_l, oracle.search_db(long_q, db, sm, 10, 2))
+    assert np.array_equal(got_s, oracle.search_db(short_q, db, sm, 10, 2))
+    whole = [x for x in be.log if x[0] == "whole"]
+    slices = [x for x in be.log if x[0] == "slice"]
+    assert len(whole) == 1 and len(slices) == 8
+    _, _, enq, start, end = whole[0]
+    # at most `depth` long launches were queued ahead of the short request ...
+    assert sum(1 for x in slices if x[2] < enq and x[4] > enq) <= depth
+    # ... and none was enqueued while it was in flight
+    assert not [x for x in slices if enq <= x[2] < end]
+    assert fs.latency < 0.02 + depth * 0.01 + 0.03
