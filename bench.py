@@ -216,11 +216,17 @@ def serving(args, capacity_gcups, mode):
     n = args.serve_requests
     qs = synth.serve_requests(n)
     qlens = np.array([len(q) for q in qs])
-    slice_mcells = int(capacity_gcups * args.serve_slice_ms) if args.serve_slice_ms > 0 else 0
+    # launches of about serve_slice_ms: capacity in cells per ms, over the cells
+    # one lane sweeps per lane cell (two subjects per lane in the packed modes)
+    per_lane = 1 if mode == "i32" else 2
+    slice_mcells = int(capacity_gcups * args.serve_slice_ms / per_lane) if args.serve_slice_ms > 0 else 0
+    knobs = dict(KNOBS)
+    if args.serve_lane_cells:
+        knobs["lane_cells"] = args.serve_lane_cells
     be = GpuBackend(gdb, w5.matrix, w5.gap_open, w5.gap_extend, mode=mode, n_streams=4,
-                    slice_mcells=slice_mcells, **KNOBS)
+                    slice_mcells=slice_mcells, **knobs)
     rate = capacity_gcups * 1e9
-    srv_kw = dict(max_batch=16, rate_guess=rate, long_s=args.serve_long_ms / 1e3)
+    srv_kw = dict(max_batch=16, rate_guess=rate, long_s=args.serve_long_ms / 1e3, long_depth=args.serve_long_depth)
     with Server(be, **srv_kw) as srv:                    # warm-up: plans, allocator, code
         for f in [srv.submit(q) for q in qs[:8]]:
             f.result()
@@ -281,6 +287,7 @@ def serving(args, capacity_gcups, mode):
                         "clamped 50-5000; Poisson arrivals at rho x single-query capacity",
             "capacity_gcups": round(capacity_gcups, 1),
             "server": {"slice_mcells": slice_mcells, "slice_ms": args.serve_slice_ms, "long_ms": args.serve_long_ms,
+                       "long_depth": args.serve_long_depth, "lane_cells": args.serve_lane_cells,
                        "size_ratio": 4.0, "streams": 4, "max_batch": 16},
             "alone_by_length": [{"qlen": [c["qlen_lo"], c["qlen_hi"]], "requests": c["requests"],
                                  "p50_ms": round(c["p50_s"] * 1e3, 2), "p99_ms": round(c["p99_s"] * 1e3, 2)}
@@ -600,8 +607,12 @@ def main(argv=None):
     ap.add_argument("--serve-rho", type=float, nargs="+", default=[0.5, 0.8])
     ap.add_argument("--serve-scale", type=float, default=1.0)
     ap.add_argument("--serve-policies", nargs="+", default=["edf", "fifo"], choices=["edf", "fifo"])
-    ap.add_argument("--serve-slice-ms", type=float, default=3.0,
+    ap.add_argument("--serve-slice-ms", type=float, default=6.0,
                     help="device time per persistent launch of a serving batch (0: one launch)")
+    ap.add_argument("--serve-long-depth", type=int, default=2,
+                    help="launches of long (stepped) batches outstanding at once")
+    ap.add_argument("--serve-lane-cells", type=int, default=16384,
+                    help="work-item lane-cell target of serving searches (0 = planner)")
     ap.add_argument("--serve-long-ms", type=float, default=20.0,
                     help="estimated device time above which a request is long (keeps a slot for short ones)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

@@ -197,6 +197,7 @@ class Server:
         self.size_ratio = float(size_ratio)   # 0: batch regardless of size
         self.long_s = float(long_s)           # estimated device time that makes a request long
         self.rate = float(rate_guess)       # cells per second, updated from completed batches
+        self.nominal_rate = float(rate_guess)   # the rate that classes requests as long (fixed)
         self.backend = backend
         self.max_batch = int(max_batch)
         self.max_inflight = int(max_inflight or getattr(backend, "slots", 4))
@@ -307,6 +308,7 @@ class Server:
             slot, h, reqs, nbytes, t_launch = entry
             if self.backend.poll(h):
                 done.append(entry)
+        stepped = set(self._stepped)
         for entry in done:
             slot, h, reqs, nbytes, t_launch = entry
             self._inflight.remove(entry)
@@ -331,8 +333,10 @@ class Server:
                 cells = self.backend.cells([r.qlen for r in reqs])
                 self.cells_done += cells
                 self.last_completion = t
-                if t > t_launch and cells > 0 and len(self._inflight) == 0:
-                    # rate of a batch that ran alone at the end: an estimate of the device rate
+                if t > t_launch and cells > 0 and len(self._inflight) == 0 and id(h) not in stepped:
+                    # rate of a batch that ran alone at the end, all its launches
+                    # enqueued at once (a stepped batch's time includes the
+                    # launches held back for others): an estimate of the device rate
                     self.rate = 0.7 * self.rate + 0.3 * cells / (t - t_launch)
             with self._cv:
                 self._in_use -= nbytes
@@ -439,7 +443,8 @@ class Server:
         return moved
 
     def _is_long(self, qlen: int) -> bool:
-        return self.backend.cells([qlen]) / self.rate > self.long_s
+        # by the nominal rate: a class that does not drift with the estimate
+        return self.backend.cells([qlen]) / self.nominal_rate > self.long_s
 
     def _long_inflight(self) -> int:
         return sum(1 for _, _, reqs, _, _ in self._inflight if any(self._is_long(r.qlen) for r in reqs))

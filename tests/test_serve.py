@@ -355,3 +355,6 @@ def test_long_batches_step_around_short_ones(depth):
     # ... and none was enqueued while it was in flight
     assert not [x for x in slices if enq <= x[2] < end]
     assert fs.latency < 0.02 + depth * 0.01 + 0.03
+    # the long batch's time includes launches held back for the short one: it
+    # does not count as a measure of the device rate
+    assert srv.rate == rate
