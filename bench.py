@@ -93,7 +93,8 @@ def kernel_fingerprint() -> str:
     h = hashlib.sha1()
     csrc = os.path.join(ROOT, "paper_2412_08308_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".h", ".hip", ".cpp")) and f not in ("sw_isa_probe.hip", "sw_pair.hip", "sw_k_rescore.hip"):
+        if f.endswith((".h", ".hip", ".cpp")) and f not in ("sw_isa_probe.hip", "sw_pair.hip", "sw_k_rescore.hip",
+                                                             "sw_pair_flow.hip", "sw_swar8.h"):
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
