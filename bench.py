@@ -152,13 +152,15 @@ def digest_parity(name, rows, first_row=0):
     return {"rows": len(rows), "scores": n, "rows_mismatched": bad_rows, "blocks_mismatched": bad_blocks}
 
 
-def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False):
+def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False, extra=None):
     """Run warmup + steps searches; wall time per step and the search kernel's
-    own time (HIP events recorded by the library around its launch)."""
+    own time (HIP events recorded by the library around its launch).  ``extra``:
+    option fields set on top of the mode (a tuned schedule)."""
     import torch
     import paper_2412_08308_amd as swdb
     lens = [int(q.numel()) for q in queries]
-    base = swdb.options(mode=mode, **KNOBS)
+    kw = {**KNOBS, **(extra or {})}
+    base = swdb.options(mode=mode, **kw)
     ws = gdb.alloc_workspace(lens, base)
     out = torch.empty((len(queries), gdb.nseq) if batch else (gdb.nseq,), dtype=torch.int32, device="cuda")
     if batch:
@@ -179,7 +181,7 @@ def timed_search(gdb, queries, sm, go, ge, mode, steps, warmup, ev, batch=False)
     torch.cuda.synchronize()
     evs = []
     for _ in range(steps):
-        o = swdb.options(mode=mode, **KNOBS)
+        o = swdb.options(mode=mode, **kw)
         e = (ev.create(), ev.create(), ev.create())
         o.ev_search_begin, o.ev_search_end, o.ev_rescore_end = e[0].value, e[1].value, e[2].value
         evs.append((o, e))
@@ -687,9 +689,20 @@ def main(argv=None):
         batched = {"workload": "20 queries 144-5478 vs the same 200,000 subjects, one persistent launch "
                                "per schedule", "cells": bcells}
         bpar = {}
-        for bm in (["auto", "i32"] + (["tuned"] if tuning is not None else [])):
-            b = timed_search(gdb, qs, w3.matrix, w3.gap_open, w3.gap_extend, bm, args.batch_steps, 1, ev,
-                             batch=True)
+        legs = [("auto", "auto", None), ("i32", "i32", None)]
+        if tuning is not None:
+            # the batch tuned as a unit (sw_autotune_batch: one schedule timed on
+            # this batch), and the per-length tables of the single-query tuner
+            t0 = time.perf_counter()
+            bopt, brec = gdb.autotune_batch(qs, w3.matrix, w3.gap_open, w3.gap_extend)
+            batched["tune_s"] = round(time.perf_counter() - t0, 1)
+            batched["tuned_schedule"] = {k: brec[k] for k in ("mode", "waves", "lane_cells", "strict_groups")}
+            legs += [("tuned", {0: "auto", 1: "i32", 2: "i16"}[bopt.mode],
+                      {"waves": bopt.waves, "lane_cells": bopt.lane_cells, "strict_groups": bopt.strict_groups}),
+                     ("tuned_bins", "tuned", None)]
+        for bm, bmode, extra in legs:
+            b = timed_search(gdb, qs, w3.matrix, w3.gap_open, w3.gap_extend, bmode, args.batch_steps, 1, ev,
+                             batch=True, extra=extra)
             batched[bm] = {"gcups": round(bcells / (b["wall_ms"] / 1e3) / 1e9, 1),
                            "ms_per_batch": round(b["wall_ms"], 2), "search_kernel_ms": round(b["kernel_ms"], 2),
                            "flagged": b["flagged"]}
@@ -700,7 +713,7 @@ def main(argv=None):
                             "ms_per_batch": round(g["wall_ms"], 2), "replay_ms": round(g["replay_ms"], 2)}
         if args.scale == 1.0:
             bpar["graph"] = digest_parity("20q_vs_200k", g["out"])
-        batched["gcups"] = max(v["gcups"] for k, v in batched.items() if isinstance(v, dict))
+        batched["gcups"] = max(v["gcups"] for k, v in batched.items() if isinstance(v, dict) and "gcups" in v)
         if parity is not None and bpar:
             parity["20q_vs_200k"] = bpar
 

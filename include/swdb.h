@@ -124,6 +124,11 @@ typedef struct sw_options {
     int32_t pair_entry_bytes; /* sw_pair_plan: profile entry bytes the pair will
                               be scored with, 1 (every s + Go in [-128, 127]) or
                               2 (0 = 2); scoring calls take it from the matrix  */
+    int32_t strict_groups; /* searches: 1 = each subject's lane group is the
+                              cheapest whose per-lane work fits the item target;
+                              0 = also take a group of up to twice the target
+                              when it sweeps 10% fewer cells (the default)     */
+    int32_t pad;
     /* Optional timing events (created by the caller, may be NULL): recorded on
        the search stream immediately before the search kernel, immediately
        after it, and after the int32 rescore (16-bit modes).                   */
@@ -318,12 +323,36 @@ int sw_graph_destroy(sw_graph_t graph);
  * each length qlens[b] (HOST, ascending), times candidate schedules -- arithmetic
  * mode (packed 16-bit + rescore, or int32) x per-item work target x waves per
  * workgroup -- on this database with a query of that length drawn from the
- * database's own residue composition, and keeps the fastest.  Results go to
- * out[nbins] (HOST) and are installed on the handle for SW_MODE_TUNED.
+ * database's own residue composition, and keeps the fastest (the default
+ * schedule is the first candidate, and another replaces it only when more than
+ * 0.5% faster).  Results go to out[nbins] (HOST) and are installed on the
+ * handle for SW_MODE_TUNED.
  * Blocking (synchronises `stream`); allocates and frees its own device memory.
  */
 int sw_autotune(sw_db_t db, const int32_t* qlens, int32_t nbins, const int32_t* subst_matrix,
                 int32_t gap_open, int32_t gap_extend, hipStream_t stream, sw_tune_entry* out);
+
+/*
+ * Autotuner for one batch as a unit (the work distribution that paper
+ * Sections 4.3 and 6 find decisive, here over the CUs of one device): starting
+ * from the default schedule, varies one choice at a time -- arithmetic mode,
+ * waves per workgroup, the per-item work target, the lane-group rule
+ * (strict_groups) -- timing each on this batch itself (fastest of two runs
+ * after a warm-up), and keeps a change only when it is more than 1% faster.
+ *   queries     device, uint8, query k at q_offsets[k]
+ *   q_offsets   HOST, int64[nq];  q_lens HOST, int32[nq]
+ *   subst_matrix HOST, int32[32*32]
+ *   out         HOST: out->opt the schedule to pass to sw_db_search_batch or
+ *               sw_graph_create for this batch (events unset), out->gcups its
+ *               rate, out->qlen the longest query
+ * Installs nothing on the handle.  Allocates its workspace and a score buffer
+ * in stream-ordered memory on `stream` (freed before returning) and
+ * synchronises `stream`; a search status error is returned as such.
+ */
+int sw_autotune_batch(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets,
+                      const int32_t* q_lens, int32_t nq, const int32_t* subst_matrix,
+                      int32_t gap_open, int32_t gap_extend, hipStream_t stream,
+                      sw_tune_entry* out);
 
 /* Install (n > 0) or clear (n == 0) the handle's tuned schedules, e.g. from a
    cache of an earlier sw_autotune on the same database and device. */

@@ -53,6 +53,7 @@ class Options(ctypes.Structure):
                 ("slice_mcells", ctypes.c_int32), ("pair_mode", ctypes.c_int32),
                 ("pair_sm_max", ctypes.c_int32), ("slice_begin", ctypes.c_int32),
                 ("slice_count", ctypes.c_int32), ("pair_entry_bytes", ctypes.c_int32),
+                ("strict_groups", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("ev_search_begin", ctypes.c_void_p), ("ev_search_end", ctypes.c_void_p),
                 ("ev_rescore_end", ctypes.c_void_p)]
 
@@ -64,7 +65,8 @@ class TuneEntry(ctypes.Structure):
     def as_dict(self):
         return {"qlen": self.qlen, "gcups": self.gcups, "mode": self.opt.mode, "waves": self.opt.waves,
                 "lane_cells": self.opt.lane_cells, "max_lanes": self.opt.max_lanes,
-                "lds_limit": self.opt.lds_limit, "grid_limit": self.opt.grid_limit}
+                "lds_limit": self.opt.lds_limit, "grid_limit": self.opt.grid_limit,
+                "strict_groups": self.opt.strict_groups}
 
     @classmethod
     def from_dict(cls, d):
@@ -72,7 +74,7 @@ class TuneEntry(ctypes.Structure):
         e.qlen, e.gcups = int(d["qlen"]), float(d.get("gcups", 0.0))
         e.opt = options(mode=int(d["mode"]), waves=d.get("waves", 0), lane_cells=d.get("lane_cells", 0),
                         max_lanes=d.get("max_lanes", 0), lds_limit=d.get("lds_limit", 0),
-                        grid_limit=d.get("grid_limit", 0))
+                        grid_limit=d.get("grid_limit", 0), strict_groups=d.get("strict_groups", 0))
         return e
 
 
@@ -170,6 +172,8 @@ def lib():
     L.sw_db_sorted_lengths.argtypes = [vp, vp]
     L.sw_autotune.restype = ctypes.c_int
     L.sw_autotune.argtypes = [vp, vp, i32, vp, i32, i32, vp, ctypes.POINTER(TuneEntry)]
+    L.sw_autotune_batch.restype = ctypes.c_int
+    L.sw_autotune_batch.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, vp, ctypes.POINTER(TuneEntry)]
     L.sw_tune_set.restype = ctypes.c_int
     L.sw_tune_set.argtypes = [vp, ctypes.POINTER(TuneEntry), i32]
     L.sw_tune_get.restype = ctypes.c_int32
@@ -208,8 +212,9 @@ PAIR_MODES = {"auto": 0, "tiles": 1, "flow": 2}
 
 def options(mode="auto", waves=0, lane_cells=0, max_lanes=0, lds_limit=0, grid_limit=0,
             wide_profile=0, pair_cols=0, pair_rows=0, align_block=0, slice_mcells=0, pair_mode=0,
-            pair_sm_max=0, slice_begin=0, slice_count=0, pair_entry_bytes=0) -> Options:
+            pair_sm_max=0, slice_begin=0, slice_count=0, pair_entry_bytes=0, strict_groups=0) -> Options:
     o = Options()
+    o.strict_groups = int(strict_groups)
     o.pair_entry_bytes = int(pair_entry_bytes)
     o.slice_mcells = int(slice_mcells)
     o.slice_begin, o.slice_count = int(slice_begin), int(slice_count)
@@ -642,6 +647,25 @@ class Database:
         _check(lib().sw_autotune(self._handle(), ql.ctypes.data, len(ql), sm.ctypes.data, int(gap_open),
                                  int(gap_extend), _stream(stream), out), "sw_autotune")
         return [e.as_dict() for e in out]
+
+    def autotune_batch(self, queries, matrix, gap_open: int, gap_extend: int, stream=None):
+        """``sw_autotune_batch``: tune one batch as a unit.  ``queries`` as for
+        ``search_batch``.  Returns (Options for ``search_batch`` / ``capture``
+        of this batch, dict of the schedule and its measured GCUPS); installs
+        nothing."""
+        import torch
+        cat, offs, lens = self._batch_args(queries)
+        nq = len(lens)
+        if nq == 0:
+            raise ValueError("empty batch")
+        _on_stream(stream, cat)
+        sm = _matrix(matrix)
+        out = TuneEntry()
+        _check(lib().sw_autotune_batch(self._handle(), _dev(cat, torch.uint8, "queries"), offs.ctypes.data,
+                                       lens.ctypes.data, nq, sm.ctypes.data, int(gap_open), int(gap_extend),
+                                       _stream(stream), ctypes.byref(out)), "sw_autotune_batch")
+        d = out.as_dict()
+        return TuneEntry.from_dict(d).opt, d
 
     def set_tuning(self, entries):
         arr = (TuneEntry * len(entries))(*[TuneEntry.from_dict(d) for d in entries])

@@ -72,12 +72,12 @@ struct Staging {
 };
 
 struct PlanKey {
-    int rows, spl, waves, kmax, nbr;
+    int rows, spl, strict, kmax, nbr;
     int64_t target;
     bool operator<(const PlanKey& o) const
     {
-        return std::tie(rows, spl, waves, kmax, nbr, target) <
-               std::tie(o.rows, o.spl, o.waves, o.kmax, o.nbr, o.target);
+        return std::tie(rows, spl, strict, kmax, nbr, target) <
+               std::tie(o.rows, o.spl, o.strict, o.kmax, o.nbr, o.target);
     }
 };
 
@@ -96,6 +96,7 @@ struct Resolved {
     int rows, elem, spl, waves, kmax, lds_limit, grid_limit;
     int64_t target;
     bool i16;
+    bool strict;          // lane groups within the item target only (no relaxed choice)
 };
 
 }  // namespace
@@ -141,6 +142,7 @@ bool validate_options(const sw_options* opt, std::string& why)
     if (opt->align_block < 0 || opt->align_block > (1 << 24)) { why = "options.align_block must be 0..2^24"; return false; }
     if (opt->slice_mcells < 0) { why = "options.slice_mcells"; return false; }
     if (opt->slice_begin < 0 || opt->slice_count < 0) { why = "options.slice_begin / slice_count"; return false; }
+    if (opt->strict_groups < 0 || opt->strict_groups > 1) { why = "options.strict_groups must be 0 or 1"; return false; }
     if ((opt->slice_begin || opt->slice_count) && opt->slice_mcells <= 0) {
         why = "options.slice_begin / slice_count need slice_mcells > 0";
         return false;
@@ -185,6 +187,7 @@ Resolved resolve(const sw_db_s* db, const sw_options* opt, int fit, int32_t nq, 
     r.lds_limit = (opt && opt->lds_limit) ? opt->lds_limit : kDefaultLdsLimit;
     r.lds_limit = std::min(r.lds_limit, db->lds_max - 1024);
     r.grid_limit = opt ? opt->grid_limit : 0;
+    r.strict = opt && opt->strict_groups;
     double cells = 0;
     bool in_lds = false, in_global = false;
     for (int32_t k = 0; k < nq; ++k) {
@@ -260,7 +263,7 @@ int choose_k(int64_t n, int nbr, const Resolved& r)
             shortest = K;
         }
     }
-    if (best > 0 && relaxed > 0 && relaxed_cost <= (1.0 - kRelaxGain) * best_cost)
+    if (!r.strict && best > 0 && relaxed > 0 && relaxed_cost <= (1.0 - kRelaxGain) * best_cost)
         return relaxed;
     return best > 0 ? best : shortest;
 }
@@ -356,7 +359,7 @@ std::shared_ptr<QPlan> build_plan(const std::vector<int32_t>& slen, int nbr, con
 
 std::shared_ptr<QPlan> get_plan(sw_db_s* db, int nbr, const Resolved& r)
 {
-    PlanKey key{r.rows, r.spl, 0, r.kmax, nbr, r.target};   // items do not depend on waves
+    PlanKey key{r.rows, r.spl, r.strict ? 1 : 0, r.kmax, nbr, r.target};   // items do not depend on waves
     std::lock_guard<std::mutex> lk(db->mu);
     auto f = db->plans.find(key);
     if (f != db->plans.end())
@@ -1283,6 +1286,132 @@ int sw_db_search_batch(sw_db_t db, const uint8_t* queries, const int64_t* q_offs
     return do_search(db, queries, q_offsets, q_lens, nq, sm, go, ge, opt, ws, ws_bytes, scores, stream);
 }
 
+// One batch tuned as a unit: starting from the defaults, one choice at a
+// time (arithmetic mode, waves per workgroup, the item target, the lane-group
+// rule) is varied and timed on the batch itself, and a change is kept only
+// when it gains more than timing noise (1%; a batch's runs spread about 0.3%);
+// later choices are varied around the schedule kept so far.
+int sw_autotune_batch(sw_db_t db, const uint8_t* queries, const int64_t* q_offsets, const int32_t* q_lens,
+                      int32_t nq, const int32_t* sm, int32_t go, int32_t ge, hipStream_t stream, sw_tune_entry* out)
+{
+    if (!db) return fail(SW_EINVAL, "null database handle");
+    if (db->host_only) return fail(SW_EINVAL, "planning-only handle cannot search");
+    if (!out || !sm || nq <= 0 || !q_lens || !q_offsets || !queries)
+        return fail(SW_EINVAL, "bad batch autotune arguments");
+    int rc = validate_query_set(db, nq, q_lens);
+    if (rc) return rc;
+    std::string why;
+    if (!matrix_elem(sm, go, why)) return fail(SW_EINVAL, why);
+    if (db->nseq == 0) return fail(SW_EINVAL, "empty database");
+    int64_t sumq = 0;
+    int32_t maxm = 0;
+    for (int32_t k = 0; k < nq; ++k) {
+        sumq += q_lens[k];
+        maxm = std::max(maxm, q_lens[k]);
+    }
+    if (sumq == 0) return fail(SW_EINVAL, "batch of empty queries");
+
+    // the variations: each entry changes one field of the schedule kept so far
+    struct Var { int field, value; };    // field 0 mode, 1 waves, 2 lane_cells, 3 strict_groups
+    const std::vector<std::vector<Var>> rounds = {
+        {{0, SW_MODE_I32}},
+        {{1, 4}, {1, 8}},
+        {{2, 49152}, {2, 98304}, {2, 196608}, {2, 393216}},
+        {{3, 1}},
+    };
+    auto apply = [](sw_options o, const Var& v) {
+        if (v.field == 0) o.mode = v.value;
+        if (v.field == 1) o.waves = v.value;
+        if (v.field == 2) o.lane_cells = v.value;
+        if (v.field == 3) o.strict_groups = v.value;
+        return o;
+    };
+    // workspace for every schedule the search can reach
+    size_t ws_need = 0;
+    {
+        std::vector<sw_options> all{sw_options{}};
+        for (const auto& r : rounds) {
+            std::vector<sw_options> more;
+            for (const sw_options& o : all)
+                for (const Var& v : r) more.push_back(apply(o, v));
+            all.insert(all.end(), more.begin(), more.end());
+        }
+        for (const sw_options& o : all) {
+            const size_t b = sw_workspace_bytes(db, nq, q_lens, &o);
+            if (b == 0) return fail(SW_EINVAL, "workspace size of a candidate schedule");
+            ws_need = std::max(ws_need, b);
+        }
+    }
+    void* d_ws = nullptr;
+    int32_t* d_sc = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    auto cleanup = [&]() {
+        if (d_ws) (void)hipFreeAsync(d_ws, stream);
+        if (d_sc) (void)hipFreeAsync(d_sc, stream);
+        (void)hipStreamSynchronize(stream);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+#define TCHK(x)                                                                               \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess) {                                                               \
+            cleanup();                                                                        \
+            return fail(SW_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));             \
+        }                                                                                     \
+    } while (0)
+    TCHK(hipMallocAsync(&d_ws, std::max<size_t>(ws_need, 256), stream));
+    TCHK(hipMallocAsync((void**)&d_sc, sizeof(int32_t) * (size_t)nq * (size_t)db->nseq, stream));
+    TCHK(hipEventCreate(&ev[0]));
+    TCHK(hipEventCreate(&ev[1]));
+    // fastest of two timed runs after one that warms the plan cache
+    auto timed = [&](const sw_options& o, float& tmin) -> int {
+        tmin = -1;
+        for (int rep = 0; rep < 3; ++rep) {
+            hipError_t e = hipEventRecord(ev[0], stream);
+            if (e != hipSuccess) return fail(SW_EHIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
+            const int r = sw_db_search_batch(db, queries, q_offsets, q_lens, nq, sm, go, ge, &o, d_ws, ws_need,
+                                             d_sc, stream);
+            if (r) return r;
+            e = hipEventRecord(ev[1], stream);
+            sw_status st{};
+            const int sr = sw_search_status(d_ws, stream, &st);      // synchronises the stream
+            if (sr) return sr;
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (e != hipSuccess) return fail(SW_EHIP, std::string("batch autotune timing: ") + hipGetErrorString(e));
+            if (rep > 0 && (tmin < 0 || ms < tmin)) tmin = ms;
+        }
+        return SW_OK;
+    };
+    sw_options best{};
+    float tbest = 0;
+    rc = timed(best, tbest);
+    for (size_t r = 0; r < rounds.size() && rc == SW_OK; ++r) {
+        const sw_options base = best;
+        for (const Var& v : rounds[r]) {
+            const sw_options o = apply(base, v);
+            if (std::memcmp(&o, &base, sizeof o) == 0) continue;
+            float t = 0;
+            rc = timed(o, t);
+            if (rc) break;
+            if (t < 0.99f * tbest) {
+                tbest = t;
+                best = o;
+            }
+        }
+    }
+#undef TCHK
+    const std::string err = g_err;
+    cleanup();
+    if (rc) return fail(rc, "batch autotune search: " + err);
+    *out = sw_tune_entry{};
+    out->qlen = maxm;
+    out->opt = best;
+    out->gcups = (double)sumq * (double)db->total / (tbest * 1e-3) / 1e9;
+    return SW_OK;
+}
+
 int sw_tune_set(sw_db_t db, const sw_tune_entry* entries, int32_t n)
 {
     if (!db) return fail(SW_EINVAL, "null database handle");
@@ -1338,7 +1467,7 @@ int sw_autotune(sw_db_t db, const int32_t* qlens, int32_t nbins, const int32_t* 
     if (codes.empty()) codes.push_back(0);
 
     struct Cand { int32_t mode, waves, lane_cells; };
-    std::vector<Cand> cands;
+    std::vector<Cand> cands{{SW_MODE_AUTO, 0, 0}};    // the defaults first: the tuner never loses to them
     for (int32_t mode : {SW_MODE_I16, SW_MODE_I32})
         for (int32_t waves : {4, 8})
             for (int32_t lc : {24576, 49152, 98304, 196608})
@@ -1408,7 +1537,7 @@ int sw_autotune(sw_db_t db, const int32_t* qlens, int32_t nbins, const int32_t* 
                 if (rep > 0 && (tmin < 0 || ms < tmin)) tmin = ms;
             }
             if (rc) break;
-            if (best < 0 || tmin < best) {
+            if (best < 0 || tmin < 0.995f * best) {    // a change must gain more than timing noise
                 best = tmin;
                 be.qlen = m;
                 be.opt = o;

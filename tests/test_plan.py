@@ -97,6 +97,31 @@ def test_q567_vs_200k_plan_padding():
         db.release()
 
 
+def test_strict_lane_groups():
+    """strict_groups = 1 keeps every lane group within the item target: on the
+    benchmark workload the relaxed rule's larger groups disappear and more
+    cells are swept (the 1.091 of the docstring above); plans stay valid and
+    the option is checked."""
+    db = swdb.Database.describe(_lengths("q567_vs_200k"))
+    try:
+        for mode, spl in (("i32", 1), ("i16", 2)):
+            relaxed = check_plan(db, [567], swdb.options(mode=mode), spl)
+            strict = check_plan(db, [567], swdb.options(mode=mode, strict_groups=1), spl)
+            assert strict["lane_cells"] > relaxed["lane_cells"]
+        with pytest.raises(swdb.SwdbError):
+            db.plan_info([567], swdb.options(strict_groups=2))
+        # a planning-only handle cannot time searches: refused before any pointer is used
+        import ctypes
+        sm = np.ascontiguousarray(synth.blosum_style_matrix(), dtype=np.int32)
+        offs, lens = np.zeros(1, np.int64), np.array([5], np.int32)
+        out = swdb.TuneEntry()
+        rc = swdb.lib().sw_autotune_batch(db._handle(), ctypes.c_void_p(16), offs.ctypes.data, lens.ctypes.data, 1,
+                                          sm.ctypes.data, 10, 2, None, ctypes.byref(out))
+        assert rc == -1
+    finally:
+        db.release()
+
+
 def test_batch_plan_queue_order():
     db = swdb.Database.describe(_lengths("ragged"))
     try:
