@@ -386,9 +386,10 @@ __device__ __forceinline__ void item_i16(const SearchArgs& a, const Item it, con
 #pragma unroll 1
             for (int k4 = 0; k4 < n4; ++k4) {
                 const int col0 = blk + 4 * k4;
-                const uint32_t wA = rvA.x, wB = rvB.x;        // columns col0..col0+3
-                rvA = make_uint4(rvA.y, rvA.z, rvA.w, 0u);
-                rvB = make_uint4(rvB.y, rvB.z, rvB.w, 0u);
+                // columns col0..col0+3: the block's word picked rather than shifted
+                // out (the shift made every 4-column trip wait for all memory
+                // operations in flight, the next block's residues among them)
+                const uint32_t wA = comp(rvA, k4), wB = comp(rvB, k4);
                 uint32_t ringY[4], ringF[4];
                 if (rd && col0 < ncols && inb) {
                     const uint4* p4 = reinterpret_cast<const uint4*>(lslot + slot_col(col0, nsubw));
