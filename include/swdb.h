@@ -338,7 +338,9 @@ int sw_autotune(sw_db_t db, const int32_t* qlens, int32_t nbins, const int32_t* 
  * from the default schedule, varies one choice at a time -- arithmetic mode,
  * waves per workgroup, the per-item work target, the lane-group rule
  * (strict_groups) -- timing each on this batch itself (fastest of two runs
- * after a warm-up), and keeps a change only when it is more than 1% faster.
+ * after a warm-up), and keeps a change only when it is more than 1% faster
+ * in two timings of both; variations that resolve to the schedule already
+ * kept are skipped.
  *   queries     device, uint8, query k at q_offsets[k]
  *   q_offsets   HOST, int64[nq];  q_lens HOST, int32[nq]
  *   subst_matrix HOST, int32[32*32]
