@@ -80,3 +80,41 @@ def test_serve_memory_budget_forces_waiting():
             assert np.array_equal(g, oracle.search_db(q, db, sm, 10, 2))
     finally:
         gdb.release()
+
+
+@pytest.mark.parametrize("mode", ["auto", "i32"])
+def test_stepped_long_batches_equal_alone(mode):
+    """Searches cut into many launches, the long requests' launches enqueued
+    one at a time by the scheduler (slice_begin / slice_count) around short
+    requests: every result equals the query searched alone, and the long
+    batches really were stepped."""
+    import torch
+    import paper_2412_08308_amd as swdb
+    from paper_2412_08308_amd.serve import GpuBackend, Server
+    db, qs, rng = _workload(n=2500, nq=24, seed=23)
+    sm = synth.blosum_style_matrix()
+    gdb = gpu_db(db)
+    try:
+        alone = [gdb.search(torch.from_numpy(q).cuda(), sm, 10, 2, opt=swdb.options(mode=mode)).cpu().numpy()
+                 for q in qs]
+        be = GpuBackend(gdb, sm, 10, 2, mode=mode, n_streams=4, slice_mcells=20)
+        calls = []
+        adv = be.advance
+        be.advance = lambda h: (calls.append(h["next"]), adv(h))
+        cells = be.cells([int(np.median([len(q) for q in qs]))])
+        # a nominal rate that makes the longer half of the requests long
+        announce(f"stepped serving mode={mode}")
+        with Server(be, max_batch=4, rate_guess=cells / 0.02, long_s=0.02, long_depth=2) as srv:
+            futs = []
+            for q in qs:
+                futs.append(srv.submit(q))
+                time.sleep(float(rng.exponential(0.001)))
+            got = [f.result(timeout=120) for f in futs]
+        assert srv.stats()["completed"] == len(qs) and srv.stats()["errors"] == 0
+        assert len(calls) > 0 and max(calls) > 0, "no batch was enqueued launch by launch"
+        for k, (a, g) in enumerate(zip(alone, got)):
+            assert np.array_equal(a, g), f"request {k} (m={len(qs[k])}) differs when stepped"
+        for k in (0, 5):
+            assert np.array_equal(got[k], oracle.search_db(qs[k], db, sm, 10, 2))
+    finally:
+        gdb.release()
