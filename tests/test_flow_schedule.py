@@ -227,3 +227,148 @@ def test_flow_addresses_stay_in_bounds(R):
                 off = j if 0 <= j < n else n
                 assert 0 <= off <= n < n + 16
         assert nb <= (1 << 16) or m > (1 << 24)
+
+
+def lap_tag(column, ring, tag):
+    return (((column // ring) & 1) << 15) | (tag & 0x7FFF)
+
+
+def run_flow_groups(q, d, sm, go, ge, R, W, grid, rng, stall=0.0, K=64, ring=64, block=16, check=True, lap=True,
+                    wait=True):
+    """The pass with workgroups of W waves: wave w of workgroup g is wave
+    g * W + w and takes bands w', w' + G, ... (G = grid * W).  A band whose
+    band above runs on the previous wave of its workgroup (w >= 1) reads that
+    band's bottom row from a ring of `ring` tagged words in the workgroup's
+    memory instead of the global buffer; its writer waits, at the start of
+    each block of `block` steps, until the reader has published (at its own
+    block starts) that it consumed every column the block's words would
+    replace.  Progress counts columns across rounds as r * (n + ring) + column,
+    and a reader publishes (r + 1) * (n + ring) when its band ends.  A ring
+    word's tag holds the lap parity of its column (column // ring, bit 15)
+    beside the low 15 bits of band + 1: a slot also holds the same band's word
+    of a column one lap back, which the band tag alone would not tell apart."""
+    m, n = len(q), len(d)
+    nb = -(-m // (K * R))
+    G = grid * W
+    big = n + ring
+    gbuf = [0] * (n + 16)
+    rings = {(g, w): [0] * ring for g in range(grid) for w in range(W - 1)}     # link w -> w + 1
+    slot_of = {key: [None] * ring for key in rings}                         # (band, column) held
+    progress = {(g, w): 0 for g in range(grid) for w in range(1, W)}           # published by readers
+    written, consumed = {}, set()
+    waves = []
+    for g in range(grid):
+        for w in range(W):
+            wid = g * W + w
+            bands = list(range(wid, nb, G))
+            waves.append({"g": g, "w": w, "bands": bands, "cur": None, "r": -1})
+    S = 0
+    while True:
+        live = [x for x in waves if x["bands"] or x["cur"] is not None]
+        if not live:
+            break
+        x = live[rng.integers(len(live))]
+        if rng.random() < stall:
+            continue
+        if x["cur"] is None:
+            x["cur"] = Band(x["bands"].pop(0), q, d, sm, go, ge, R, K)
+            x["r"] += 1
+        band, g, w, r = x["cur"], x["g"], x["w"], x["r"]
+        t = band.t
+        lds_top = w >= 1 and band.b > 0
+        lds_bot = w <= W - 2 and band.b < nb - 1
+        if lds_top and t % block == 0:
+            progress[(g, w)] = max(progress[(g, w)], r * big + t)
+        if wait and lds_bot and t % block == 0:
+            # the block writes columns up to t + block - 1 - (K - 1)
+            if r * big + t + block - 1 - (K - 1) - ring >= progress[(g, w + 1)]:
+                continue                                  # reader too far behind: wait
+        top = None
+        if band.b > 0 and t < n:
+            if lds_top:
+                y, f, tag = unpack(rings[(g, w - 1)][t % ring], go)
+                want = lap_tag(t, ring, band.b) if lap else band.b & 0x7FFF
+            else:
+                y, f, tag = unpack(gbuf[t], go)
+                want = band.b
+            if tag != want:
+                continue                                  # not written yet: poll again later
+            if check:
+                assert written[(band.b - 1, t)] == (y, f), "accepted a word of another band"
+            consumed.add((band.b - 1, t))
+            top = (y, f)
+        out = band.step(top)
+        if out is not None and band.b < nb - 1:
+            jj, y, f = out
+            if lds_bot:
+                key = (g, w)
+                held = slot_of[key][jj % ring]
+                if check and held is not None:
+                    assert held in consumed, f"ring word {held} replaced before it was read"
+                rings[key][jj % ring] = pack(y, f, go, lap_tag(jj, ring, band.b + 1) if lap else (band.b + 1) & 0x7FFF)
+                slot_of[key][jj % ring] = (band.b, jj)
+            else:
+                gbuf[jj] = pack(y, f, go, band.b + 1)
+            written[(band.b, jj)] = (y, f)
+        if band.done():
+            S = max(S, band.S)
+            if lds_top:
+                progress[(g, w)] = (r + 1) * big
+            x["cur"] = None
+    return S
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_flow_groups_model_matches_oracle(seed):
+    """Workgroup rings under random and stalling schedules: scores equal the
+    oracle's, no ring word is replaced before its reader took it, and the
+    schedule never deadlocks (some wave can always move: the loop ends)."""
+    rng = np.random.default_rng(700 + seed)
+    K = int(rng.choice([4, 8]))
+    R = int(rng.choice([1, 2]))
+    W = int(rng.choice([2, 3, 4]))
+    grid = int(rng.integers(1, 3))
+    m = int(rng.integers(1, 4 * W * grid * K * R + 5))
+    n = int(rng.integers(1, 120))
+    ring = int(rng.choice([32, 40, 64]))
+    q = rng.integers(0, 4, size=m).astype(np.uint8)
+    d = np.concatenate([q[: n // 2], rng.integers(0, 4, size=n - n // 2)]).astype(np.uint8)
+    sm = synth.dna_matrix(2, -3)
+    go, ge = int(rng.integers(0, 6)), int(rng.integers(0, 3))
+    got = run_flow_groups(q, d, sm, go, ge, R, W, grid, rng, stall=float(rng.choice([0.0, 0.3])), K=K,
+                          ring=ring)
+    assert got == oracle.score(q, d, sm, go, ge)
+
+
+def test_flow_groups_model_needs_the_lap_bit():
+    """Without the lap parity in the ring tags a reader ahead of its writer
+    takes the same band's word of the column one lap back."""
+    caught = 0
+    for seed in range(12):
+        rng = np.random.default_rng(800 + seed)
+        q = rng.integers(0, 4, size=160).astype(np.uint8)
+        d = np.concatenate([q[10:90], rng.integers(0, 4, size=60)]).astype(np.uint8)
+        sm = synth.dna_matrix(2, -3)
+        try:
+            got = run_flow_groups(q, d, sm, 3, 1, 1, 4, 1, rng, stall=0.3, K=4, ring=32, lap=False)
+            caught += got != oracle.score(q, d, sm, 3, 1)
+        except (AssertionError, KeyError):
+            caught += 1
+    assert caught > 0
+
+
+def test_flow_groups_model_catches_a_missing_wait():
+    """The writer's wait is what keeps ring words alive: without it some word
+    is replaced before its reader took it (or a wrong score follows)."""
+    caught = 0
+    for seed in range(12):
+        rng = np.random.default_rng(950 + seed)
+        q = rng.integers(0, 4, size=200).astype(np.uint8)
+        d = np.concatenate([q[20:90], rng.integers(0, 4, size=60)]).astype(np.uint8)
+        sm = synth.dna_matrix(2, -3)
+        try:
+            got = run_flow_groups(q, d, sm, 3, 1, 1, 3, 1, rng, stall=0.3, K=4, ring=32, wait=False)
+            caught += got != oracle.score(q, d, sm, 3, 1)
+        except (AssertionError, KeyError):
+            caught += 1
+    assert caught > 0
