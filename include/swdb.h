@@ -128,7 +128,8 @@ typedef struct sw_options {
                               cheapest whose per-lane work fits the item target;
                               0 = also take a group of up to twice the target
                               when it sweeps 10% fewer cells (the default)     */
-    int32_t pad;
+    int32_t pair_group_waves; /* sw_pair_score, pipelined pass: waves per
+                              workgroup, 1, 2, 4, 8 or 16 (0 = planner)       */
     /* Optional timing events (created by the caller, may be NULL): recorded on
        the search stream immediately before the search kernel, immediately
        after it, and after the int32 rescore (16-bit modes).                   */

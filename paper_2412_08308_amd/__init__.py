@@ -53,7 +53,7 @@ class Options(ctypes.Structure):
                 ("slice_mcells", ctypes.c_int32), ("pair_mode", ctypes.c_int32),
                 ("pair_sm_max", ctypes.c_int32), ("slice_begin", ctypes.c_int32),
                 ("slice_count", ctypes.c_int32), ("pair_entry_bytes", ctypes.c_int32),
-                ("strict_groups", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("strict_groups", ctypes.c_int32), ("pair_group_waves", ctypes.c_int32),
                 ("ev_search_begin", ctypes.c_void_p), ("ev_search_end", ctypes.c_void_p),
                 ("ev_rescore_end", ctypes.c_void_p)]
 
@@ -212,8 +212,10 @@ PAIR_MODES = {"auto": 0, "tiles": 1, "flow": 2}
 
 def options(mode="auto", waves=0, lane_cells=0, max_lanes=0, lds_limit=0, grid_limit=0,
             wide_profile=0, pair_cols=0, pair_rows=0, align_block=0, slice_mcells=0, pair_mode=0,
-            pair_sm_max=0, slice_begin=0, slice_count=0, pair_entry_bytes=0, strict_groups=0) -> Options:
+            pair_sm_max=0, slice_begin=0, slice_count=0, pair_entry_bytes=0, strict_groups=0,
+            pair_group_waves=0) -> Options:
     o = Options()
+    o.pair_group_waves = int(pair_group_waves)
     o.strict_groups = int(strict_groups)
     o.pair_entry_bytes = int(pair_entry_bytes)
     o.slice_mcells = int(slice_mcells)

@@ -211,6 +211,11 @@ __host__ __device__ constexpr int flow_lds_bytes(int rows, int elem)   // LDS of
 {
     return kCodes * kWave * flow_lds_stride(rows, elem);
 }
+// LDS a workgroup of wpg waves needs: one band profile per wave.
+__host__ __device__ constexpr int flow_group_lds(int rows, int elem, int wpg)
+{
+    return wpg * flow_lds_bytes(rows, elem);
+}
 
 // Alignment found by the traceback pass (device memory, written by the
 // traceback kernel): 1-based inclusive positions, operation count.

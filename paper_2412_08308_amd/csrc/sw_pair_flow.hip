@@ -319,7 +319,7 @@ hipError_t launch_pair_flow(const FlowArgs& a, int rows, int elem, int wpg, int 
 {
     const void* k = flow_kernel(rows, elem);
     if (!k || wpg < 1 || wpg > (rows <= 6 ? 16 : 8) || grid < 1 || (int64_t)grid * wpg != a.waves ||
-        lds < wpg * flow_lds_bytes(rows, elem))
+        lds < flow_group_lds(rows, elem, wpg))
         return hipErrorInvalidValue;
     const int64_t clear = (int64_t)a.n + 16;
     hipLaunchKernelGGL(k_flow_clear, dim3((unsigned)std::min<int64_t>((clear + 255) / 256, 1024)), dim3(256), 0,

@@ -1896,11 +1896,12 @@ double pair_time_rect(int64_t m, int64_t n, int R, int K, int wc, int cu)
 // time); k waves sharing a SIMD issue-bound, k x 4.6 cycles per VALU
 // instruction; each band starts about 149 - 2.3 R steps after the band above
 // (the last lane's 63-column lag, the 16-step read-ahead and the latency of
-// the handoff words through memory).  With more than 64 bands at work every
-// step takes 1.16 times as long (measured with 633 to 2,930 bands of 4, 10
-// and 16 rows: clock and memory under a busy device).  Bands run in rounds
-// when they outnumber the waves; a round's band starts when its wave is free
-// and the band above is far enough ahead.
+// the handoff words through memory).  Waves sharing a CU step about 1.16
+// times slower than a wave alone on its CU (1.02 with one wave per CU;
+// measured with 16 to 1,000 bands of 4 and 16 rows at n = 100K and on the
+// paper's pairs), so up to one band per CU the workgroups hold one wave each.
+// Bands run in rounds when they outnumber the waves; a round's band starts
+// when its wave is free and the band above is far enough ahead.
 constexpr double kFlowLaunchS = 15e-6;       // clear, launch and finish kernels
 constexpr int64_t kFlowMaxBands = (1 << 16) - 1;
 constexpr int64_t kFlowMaxValue = (1 << 24) - 1;
@@ -1925,19 +1926,23 @@ struct FlowShape {
 // The cheapest workgroup shape for R rows: W in 1, 2, 4, ..., as far as the
 // registers and the LDS (W band profiles within `lds_max`) allow; the grid
 // is at most one workgroup per CU (or grid_limit).
-FlowShape flow_shape(int64_t m, int64_t n, int R, int elem, int cu, int lds_max, int grid_limit)
+FlowShape flow_shape(int64_t m, int64_t n, int R, int elem, int cu, int lds_max, int grid_limit, int fix_wpg = 0)
 {
     FlowShape best;
     const int64_t nb = flow_bands(m, R);
-    const int per = flow_lds_bytes(R, elem);
     const int cap = std::min(lds_max, kLdsPerCU);
-    for (int wpg = 1; wpg <= flow_max_wpg(R) && (int64_t)wpg * per <= cap; wpg *= 2) {
+    for (int wpg = 1; wpg <= flow_max_wpg(R) && flow_group_lds(R, elem, wpg) <= cap; wpg *= 2) {
+        if (fix_wpg && wpg != fix_wpg) continue;
+        // two-wave workgroups of 4 rows per lane measured 1.3 to 1.5 times
+        // slower per step than four-wave ones (both waves on one SIMD): not
+        // a planner choice
+        if (!fix_wpg && wpg == 2) continue;
         int64_t grid = std::min<int64_t>(ceil_div(nb, wpg), std::max(cu, 1));
         if (grid_limit > 0) grid = std::min<int64_t>(grid, grid_limit);
         const int64_t G = grid * wpg;
         const double k = std::ceil(wpg / 4.0);
         const double rounds = std::ceil((double)nb / (double)G);
-        const double busy = G > 64 ? 1.16 : 1.0;
+        const double busy = wpg > 1 ? 1.16 : 1.02;
         const double step = busy * std::max(369.0 + 32.4 * (R - 4), k * kPairIssueCycles * flow_instr_per_step(R));
         const double lag = 149.0 - 2.3 * R;
         const double steps = std::max(rounds * (double)(n + kWave - 1) + (double)G * lag,
@@ -1946,7 +1951,7 @@ FlowShape flow_shape(int64_t m, int64_t n, int R, int elem, int cu, int lds_max,
         if (t < best.est_s) {
             best.wpg = wpg;
             best.grid = (int)grid;
-            best.lds = std::max(wpg * per, std::min(cap, kFlowGroupLds));
+            best.lds = std::max(flow_group_lds(R, elem, wpg), std::min(cap, kFlowGroupLds));
             best.est_s = t;
         }
     }
@@ -2011,7 +2016,7 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool re
 {
     struct Entry {
         int64_t m = -1, n = -1;
-        int cu = 0, R = 0, K = 0, W = 0, mode = 0, sm = 0, grid = 0, elem = 0, lds = 0;
+        int cu = 0, R = 0, K = 0, W = 0, mode = 0, sm = 0, grid = 0, elem = 0, lds = 0, gw = 0;
         bool rect = false;
         PairPlanC p;
     };
@@ -2027,7 +2032,7 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool re
         for (const Entry& e : cache)
             if (e.m == m && e.n == n && e.cu == cu && e.R == fixR && e.K == fixK && e.W == fixW && e.rect == rect &&
                 e.mode == mode && e.sm == sm_max && e.grid == (opt ? opt->grid_limit : 0) && e.elem == elem &&
-                e.lds == lds_max)
+                e.lds == lds_max && e.gw == (opt ? opt->pair_group_waves : 0))
                 return e.p;
     }
     PairPlanC p;
@@ -2039,7 +2044,8 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool re
     if (mode != 1 && !(mode == 0 && (fixK || fixW))) {
         for (int R : kFlowRowChoices) {
             if ((fixR && R != fixR) || !flow_fits(m, n, R, sm_max)) continue;
-            const FlowShape sh = flow_shape(m, n, R, elem, cu, lds_max, opt ? opt->grid_limit : 0);
+            const FlowShape sh = flow_shape(m, n, R, elem, cu, lds_max, opt ? opt->grid_limit : 0,
+                                            opt ? opt->pair_group_waves : 0);
             if (sh.wpg > 0 && sh.est_s < p.est_s) {
                 PairPlanC f;
                 f.flow = true;
@@ -2057,7 +2063,8 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool re
         }
     }
     std::lock_guard<std::mutex> lk(mu);
-    cache[next] = Entry{m, n, cu, fixR, fixK, fixW, mode, sm_max, opt ? opt->grid_limit : 0, elem, lds_max, rect, p};
+    cache[next] = Entry{m, n, cu, fixR, fixK, fixW, mode, sm_max, opt ? opt->grid_limit : 0, elem, lds_max,
+                        opt ? opt->pair_group_waves : 0, rect, p};
     next = (next + 1) % 8;
     return p;
 }
@@ -2128,6 +2135,11 @@ int validate_pair(int64_t m, int64_t n, const sw_options* opt, std::string& why)
     const int mode = opt ? opt->pair_mode : 0;
     if (mode < 0 || mode > 2) { why = "options.pair_mode must be 0, 1 or 2"; return 0; }
     if (opt && (opt->pair_sm_max < 0 || opt->pair_sm_max > 127)) { why = "options.pair_sm_max must be 0..127"; return 0; }
+    if (opt && opt->pair_group_waves &&
+        (opt->pair_group_waves < 0 || opt->pair_group_waves > 16 || (opt->pair_group_waves & (opt->pair_group_waves - 1)))) {
+        why = "options.pair_group_waves must be 0, 1, 2, 4, 8 or 16";
+        return 0;
+    }
     if (opt && (opt->pair_entry_bytes < 0 || opt->pair_entry_bytes > 2)) {
         why = "options.pair_entry_bytes must be 0, 1 or 2";
         return 0;

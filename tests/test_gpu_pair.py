@@ -139,9 +139,11 @@ def test_flow_pass_rounds(R):
         assert _gpu_pair(a, b, sm, go, ge, pair_mode=2, pair_rows=R, grid_limit=grid) == exp
 
 
-@pytest.mark.parametrize("m,n,R,grid", [(70_001, 2_000, 4, 0), (70_001, 2_000, 16, 0), (30_000, 1_500, 6, 3),
-                                         (30_000, 1_500, 12, 5), (9_000, 700, 8, 1)])
-def test_flow_pass_workgroup_shapes(m, n, R, grid):
+@pytest.mark.parametrize("m,n,R,grid,W", [(70_001, 2_000, 4, 0, 0), (70_001, 2_000, 16, 0, 0), (30_000, 1_500, 6, 3, 0),
+                                           (30_000, 1_500, 12, 5, 0), (9_000, 700, 8, 1, 0), (70_001, 2_000, 4, 0, 1),
+                                           (70_001, 2_000, 4, 0, 2), (70_001, 2_000, 6, 0, 8), (9_000, 700, 4, 1, 16),
+                                           (30_000, 1_500, 16, 2, 4)])
+def test_flow_pass_workgroup_shapes(m, n, R, grid, W):
     """Workgroups of several waves, each wave a band of its own with its own
     LDS profile: the shapes the planner picks for a few hundred bands and
     under a workgroup cap (rounds, waves left without a band)."""
@@ -150,10 +152,10 @@ def test_flow_pass_workgroup_shapes(m, n, R, grid):
     sm, go, ge = DNA
     exp = oracle_pair(a, b, sm, go, ge)
     p = swdb.pair_plan(m, n, swdb.options(pair_mode=2, pair_rows=R, grid_limit=grid, pair_sm_max=1,
-                                          pair_entry_bytes=1))
-    announce(f"flow shapes m={m} n={n} R={R} grid={grid}: {p['groups']} x {p['group_waves']} waves")
-    assert p["flow"] == 1 and p["group_waves"] >= 1
-    assert _gpu_pair(a, b, sm, go, ge, pair_mode=2, pair_rows=R, grid_limit=grid) == exp
+                                          pair_entry_bytes=1, pair_group_waves=W))
+    announce(f"flow shapes m={m} n={n} R={R} grid={grid} W={W}: {p['groups']} x {p['group_waves']} waves")
+    assert p["flow"] == 1 and p["group_waves"] >= 1 and (W == 0 or p["group_waves"] == W)
+    assert _gpu_pair(a, b, sm, go, ge, pair_mode=2, pair_rows=R, grid_limit=grid, pair_group_waves=W) == exp
 
 
 @pytest.mark.parametrize("go,ge", [(10, 2), (120, 1)])

@@ -90,6 +90,16 @@ def test_pipelined_shape_keeps_simds_even():
         assert p["est_ms"] < swdb.pair_plan(m, n, swdb.options(pair_mode="tiles"))["est_ms"]
     with pytest.raises(swdb.SwdbError):
         swdb.pair_plan(10, 10, swdb.options(pair_entry_bytes=3))
+    # the workgroup shape: one wave per CU up to a band per CU, forced shapes kept
+    o = swdb.options(pair_mode="flow", pair_rows=4, pair_sm_max=1, pair_entry_bytes=1)
+    assert swdb.pair_plan(50_000, 50_000, o)["group_waves"] == 1
+    for W in (1, 2, 4, 8, 16):
+        q = swdb.pair_plan(70_001, 2_000, swdb.options(pair_mode="flow", pair_rows=4, pair_sm_max=1,
+                                                       pair_entry_bytes=1, pair_group_waves=W))
+        assert q["group_waves"] == W and q["groups"] == min(-(-q["bands"] // W), 256)
+    for bad in (3, 32, -1):
+        with pytest.raises(swdb.SwdbError):
+            swdb.pair_plan(1000, 1000, swdb.options(pair_mode="flow", pair_group_waves=bad))
 
 
 @pytest.mark.parametrize("n,K,wc", [(1, 1, 16), (5, 64, 16), (100, 2, 16), (1000, 64, 64), (777, 16, 48),
