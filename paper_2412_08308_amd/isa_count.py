@@ -133,12 +133,16 @@ def count(asm_text: str) -> dict:
 def run(out: str = OUT) -> dict:
     res = {}
     with tempfile.TemporaryDirectory(prefix="swdb_isa_") as td:
-        for src in SOURCES:
+        jobs = []
+        for src in SOURCES:                 # the units compile in parallel
             asm = os.path.join(td, src + ".s")
             cmd = [HIPCC] + FLAGS + ["-x", "hip", "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", asm]
-            r = subprocess.run(cmd, capture_output=True, text=True)
-            if r.returncode != 0:
-                raise RuntimeError(f"{src} assembly failed:\n" + r.stdout + r.stderr)
+            jobs.append((src, asm, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                                    text=True)))
+        for src, asm, proc in jobs:
+            log, _ = proc.communicate()
+            if proc.returncode != 0:
+                raise RuntimeError(f"{src} assembly failed:\n" + log)
             res.update(count(open(asm).read()))
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1, sort_keys=True)

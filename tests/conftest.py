@@ -19,3 +19,11 @@ def pytest_configure(config):
 def oracle_lib():
     import oracle
     return oracle.load()
+
+
+@pytest.fixture(scope="session")
+def isa_counts(tmp_path_factory):
+    """VALU-per-cell counts of this build's gfx950 assembly (isa_count.run),
+    compiled once for every test that reads them."""
+    from paper_2412_08308_amd import isa_count
+    return isa_count.run(out=str(tmp_path_factory.mktemp("isa") / "counts.json"))

@@ -131,13 +131,12 @@ def test_dpp_check_follows_paths():
 
 
 @pytest.mark.skipif(not shutil.which(HIPCC) and not os.path.exists(HIPCC), reason="hipcc not available")
-def test_hot_loop_counts_are_sane(tmp_path):
+def test_hot_loop_counts_are_sane(isa_counts):
     """The roofline's VALU-per-cell figures come from isa_count.py's choice of
     hot loop; a change in the kernels' loop structure must not make it count a
     fragment or the wrong copy (the ranges bracket the counted loops), and the
     counted loops of the default variants keep their state in registers."""
-    from paper_2412_08308_amd import isa_count
-    r = isa_count.run(out=str(tmp_path / "counts.json"))
+    r = isa_counts
     # the pair kernel's edge copy of its loop counts about 1 VALU per cell more
     # than the copy inside the matrix: the pair bounds exclude it
     bounds = {"i16_p8_lds_k1": (5.2, 6.2), "i16_p8_lds_kn": (5.2, 6.5), "i32_p8_lds_k1": (7.6, 8.8),

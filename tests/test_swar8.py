@@ -68,11 +68,10 @@ def test_swar8_helpers_match_bytewise_arithmetic(tmp_path):
 
 
 @pytest.mark.skipif(not shutil.which(HIPCC) and not os.path.exists(HIPCC), reason="hipcc not available")
-def test_eight_bit_lanes_issue_more_per_cell(tmp_path):
+def test_eight_bit_lanes_issue_more_per_cell(isa_counts):
     """Four 8-bit cells per lane cost more VALU instructions per cell than
     two 16-bit cells per lane, by a wide margin."""
-    from paper_2412_08308_amd import isa_count
-    r = isa_count.run(out=str(tmp_path / "counts.json"))
+    r = isa_counts
     i8, i16 = r["i8x4_probe"]["valu_per_cell"], r["i16_p8_lds_k1"]["valu_per_cell"]
     assert r["i8x4_probe"]["scratch"] == 0
     assert i8 > 3 * i16, (i8, i16)
