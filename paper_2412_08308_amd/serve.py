@@ -437,10 +437,29 @@ class Server:
         for e in sorted(stepped, key=lambda e: min(r.deadline for r in e[2])):
             h = e[1]
             while outstanding < self.long_depth and self.backend.remaining(h) > 0:
-                self.backend.advance(h)
+                try:
+                    self.backend.advance(h)
+                except Exception as err:          # a failed launch fails its own batch only
+                    self._drop(e, err)
+                    break
                 outstanding += 1
                 moved = True
         return moved
+
+    def _drop(self, entry, err):
+        """Fail an in-flight batch whose launch could not be enqueued and
+        give back its slot and memory."""
+        slot, h, reqs, nbytes, _ = entry
+        if entry in self._inflight:
+            self._inflight.remove(entry)
+        self._stepped.discard(id(h))
+        self.errors.append(err)
+        for r in reqs:
+            if not r.future.done():
+                r.future.set_exception(err)
+        with self._cv:
+            self._in_use -= nbytes
+            self._free_slots.append(slot)
 
     def _is_long(self, qlen: int) -> bool:
         # by the nominal rate: a class that does not drift with the estimate

@@ -358,3 +358,31 @@ def test_long_batches_step_around_short_ones(depth):
     # the long batch's time includes launches held back for the short one: it
     # does not count as a measure of the device rate
     assert srv.rate == rate
+
+
+class StepFails(StepBackend):
+    """advance() raises for batches holding a query of a given length."""
+
+    def __init__(self, *a, bad_len=None, **kw):
+        super().__init__(*a, **kw)
+        self.bad_len = bad_len
+
+    def advance(self, h):
+        if any(len(q) == self.bad_len for q in h["q"]) and h["next"] >= 2:
+            raise RuntimeError("injected launch failure in a stepped batch")
+        super().advance(h)
+
+
+def test_failed_stepped_launch_fails_its_batch_only():
+    db, sm = _db(), synth.blosum_style_matrix()
+    be = StepFails(db, sm, delay=0.01, slice_s=0.005, bad_len=70)
+    rate = be.cells([1]) / 1e-3
+    rng = np.random.default_rng(13)
+    with Server(be, max_batch=1, mem_budget=10**9, rate_guess=rate, long_s=0.03) as srv:
+        bad = srv.submit(rng.integers(0, 20, size=70).astype(np.uint8))
+        good = [srv.submit(rng.integers(0, 20, size=m).astype(np.uint8)) for m in (80, 6, 9)]
+        with pytest.raises(RuntimeError):
+            bad.result(timeout=10)
+        for f in good:
+            assert f.result(timeout=10).shape == (db.nseq,)
+    assert srv.stats()["errors"] == 1 and srv.stats()["completed"] == 3
