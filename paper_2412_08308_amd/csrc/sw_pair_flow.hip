@@ -137,6 +137,10 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
     // the tail lane's handoff store; the other lanes aim at entry n, past the
     // descriptor's range (dropped), still inside the buffer's n + 16 entries
     const __amdgpu_buffer_rsrc_t rows_out = __builtin_amdgcn_make_buffer_rsrc(a.rows, (short)0, n * 8, 0x00020000);
+    // the same words read ahead through a range-checked descriptor: a word
+    // past column n - 1 reads as 0 (its tag never matches), so the offset
+    // needs no clamp
+    const __amdgpu_buffer_rsrc_t rows_in = rows_out;
     int S = 0;
     int failed = 0;
     for (int b = wave_id; b < a.nb && !failed; b += a.waves) {
@@ -161,6 +165,10 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
         }
         const bool has_top = b > 0;
         const bool put = b < a.nb - 1;
+        // inside the matrix every lane's column is in [0, n): the band's last
+        // lane stores column t - 63 at byte t * 8 + sbase, the other lanes past
+        // the descriptor's range (dropped)
+        const int sbase = (tail && put) ? -(kWave - 1) * 8 : (1 << 30);
         const uint32_t want = (uint32_t)b;                 // the band above wrote tag (b - 1) + 1
         const uint32_t wtag = (uint32_t)(b + 1) << 16;     // this band's tag, in the word's high half
         int Y[R], E[R];
@@ -188,11 +196,14 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
             for (int u = 0; u < 16; ++u) {
                 const int t = t0 + u;
                 unsigned long long word = ring[u];
-                if (has_top && t < n && __builtin_amdgcn_readfirstlane((uint32_t)(word >> 48)) != want)
+                if (has_top && (!EDGE || t < n) && __builtin_amdgcn_readfirstlane((uint32_t)(word >> 48)) != want)
                     word = flow_wait(a, t, want, &failed);
-                ring[u] = flow_word(a.rows, min(t + 16, n - 1));
                 const int yh = (int)(word & 0xffffffu) - go;
                 const int fh = (int)((word >> 24) & 0xffffffu) - go;
+                // the word of column t + 16, into the slot just consumed (an
+                // agent-scope coherent read, as flow_word)
+                const u32x2 nw = __builtin_amdgcn_raw_buffer_load_b64(rows_in, (t + 16) * 8, 0, kStoreSc1);
+                ring[u] = ((unsigned long long)nw[1] << 32) | nw[0];
                 // shifts with the whole wave active, pinned so that none is
                 // folded into a select under a partial execution mask
                 int cd = shr1(code), yd = shr1(ybot), fd = shr1(fbot);
@@ -233,10 +244,14 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
                     ybot = hup;
                     fbot = F;
                 }
-                const bool st = tail && put && !failed && j >= 0 && j < n;
                 const uint32_t yv = (uint32_t)(ybot + go), fv = (uint32_t)(fbot + go);
                 const u32x2 v = {(yv & 0xffffffu) | (fv << 24), ((fv >> 8) & 0xffffu) | wtag};
-                __builtin_amdgcn_raw_buffer_store_b64(v, rows_out, st ? j * 8 : n * 8, 0, kStoreSc1);
+                if constexpr (EDGE) {
+                    const bool st = tail && put && !failed && j >= 0 && j < n;
+                    __builtin_amdgcn_raw_buffer_store_b64(v, rows_out, st ? j * 8 : n * 8, 0, kStoreSc1);
+                } else {
+                    __builtin_amdgcn_raw_buffer_store_b64(v, rows_out, t * 8 + sbase, 0, kStoreSc1);
+                }
                 code = cnext;
 #pragma unroll
                 for (int i = 0; i < NW; ++i)

@@ -1890,18 +1890,17 @@ double pair_time_rect(int64_t m, int64_t n, int R, int K, int wc, int cu)
 // Pipelined pass: bands of 64 lanes x R rows on workgroups of W waves, one
 // workgroup per CU (W / 4 waves per SIMD, so no SIMD carries more than the
 // others: the bands advance at the pace of the slowest).  Fitted to MI355X
-// (DNA pairs, one band at n = 50K..200K for the step, 16..512 bands at
-// n = 100K for the lag): a wave alone on its SIMD takes 369 + 32.4 (R - 4)
-// cycles per step (latency-bound, about 1.3 to 1.6 times its VALU issue
-// time); k waves sharing a SIMD issue-bound, k x 4.6 cycles per VALU
-// instruction; each band starts about 149 - 2.3 R steps after the band above
-// (the last lane's 63-column lag, the 16-step read-ahead and the latency of
-// the handoff words through memory).  Waves sharing a CU step about 1.16
-// times slower than a wave alone on its CU (1.02 with one wave per CU;
-// measured with 16 to 1,000 bands of 4 and 16 rows at n = 100K and on the
-// paper's pairs), so up to one band per CU the workgroups hold one wave each.
-// Bands run in rounds when they outnumber the waves; a round's band starts
-// when its wave is free and the band above is far enough ahead.
+// (DNA pairs of every R, one band at n = 100K and 200K for the step, 256 and
+// 1,000 bands for the lag and the sharing): a wave alone on its SIMD takes
+// 309 + 32.2 (R - 4) cycles per step, about 4 cycles per instruction of any
+// kind (it issues one at a time); k waves sharing a SIMD issue-bound, k x 4.6
+// cycles per VALU instruction; each band starts about 127 - 1.55 R steps
+// after the band above (the last lane's 63-column lag, the 16-step read-ahead
+// and the latency of the handoff words through memory).  Waves sharing a CU
+// step 1.33 - 0.012 R times slower than a wave alone (1.10 with one wave per
+// CU), so up to one band per CU the workgroups hold one wave each.  Bands run
+// in rounds when they outnumber the waves; a round's band starts when its
+// wave is free and the band above is far enough ahead.
 constexpr double kFlowLaunchS = 15e-6;       // clear, launch and finish kernels
 constexpr int64_t kFlowMaxBands = (1 << 16) - 1;
 constexpr int64_t kFlowMaxValue = (1 << 24) - 1;
@@ -1909,8 +1908,8 @@ constexpr uint64_t kFlowTimeoutTicks = 200000000;   // a wait's limit: 2 s of th
 constexpr int kFlowGroupLds = 96 * 1024;     // LDS a workgroup asks for at least: over half a CU's
 
 // VALU instructions of one step (the counted hot loop of the kernel: 8 per
-// row and 26.25 per column)
-double flow_instr_per_step(int R) { return 8.0 * R + 26.25; }
+// row and 25.4 per column)
+double flow_instr_per_step(int R) { return 8.0 * R + 25.4; }
 
 int64_t flow_bands(int64_t m, int R) { return ceil_div(ceil_div(std::max<int64_t>(m, 1), R), kWave); }
 
@@ -1942,9 +1941,9 @@ FlowShape flow_shape(int64_t m, int64_t n, int R, int elem, int cu, int lds_max,
         const int64_t G = grid * wpg;
         const double k = std::ceil(wpg / 4.0);
         const double rounds = std::ceil((double)nb / (double)G);
-        const double busy = wpg > 1 ? 1.16 : 1.02;
-        const double step = busy * std::max(369.0 + 32.4 * (R - 4), k * kPairIssueCycles * flow_instr_per_step(R));
-        const double lag = 149.0 - 2.3 * R;
+        const double busy = wpg > 1 ? 1.33 - 0.012 * R : 1.10;
+        const double step = busy * std::max(309.0 + 32.2 * (R - 4), k * kPairIssueCycles * flow_instr_per_step(R));
+        const double lag = 127.0 - 1.55 * R;
         const double steps = std::max(rounds * (double)(n + kWave - 1) + (double)G * lag,
                                       (double)nb * lag + (double)(n + kWave - 1));
         const double t = steps * step / 2.4e9 + kFlowLaunchS;
