@@ -118,6 +118,16 @@ __device__ __forceinline__ unsigned long long flow_wait(const FlowArgs& a, int j
     }
 }
 
+// max(a, b, c) as one v_max3_i32: written out because the compiler, knowing
+// the cell values are non-negative, splits it into a signed and an unsigned
+// two-input maximum
+__device__ __forceinline__ int max3_i32(int a, int b, int c)
+{
+    int r;
+    asm volatile("v_max3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 template <int R, int ES>
 __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int lane, uint32_t lds0)
 {
@@ -163,100 +173,103 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
                     d[i] = v[i];
             }
         }
-        const bool has_top = b > 0;
-        const bool put = b < a.nb - 1;
-        // inside the matrix every lane's column is in [0, n): the band's last
-        // lane stores column t - 63 at byte t * 8 + sbase, the other lanes past
-        // the descriptor's range (dropped)
-        const int sbase = (tail && put) ? -(kWave - 1) * 8 : (1 << 30);
-        const uint32_t want = (uint32_t)b;                 // the band above wrote tag (b - 1) + 1
-        const uint32_t wtag = (uint32_t)(b + 1) << 16;     // this band's tag, in the word's high half
-        int Y[R], E[R];
+        // the rest of the band, compiled twice: the first band (no band
+        // above) and every other one, whose steps then carry no per-step test
+        // of that and no selects between the border and the band above
+        auto run_band = [&](auto top) {
+            constexpr bool has_top = decltype(top)::value;
+            const bool put = b < a.nb - 1;
+            // inside the matrix every lane's column is in [0, n): the band's last
+            // lane stores column t - 63 at byte t * 8 + sbase, the other lanes past
+            // the descriptor's range (dropped)
+            const int sbase = (tail && put) ? -(kWave - 1) * 8 : (1 << 30);
+            const uint32_t want = (uint32_t)b;                 // the band above wrote tag (b - 1) + 1
+            const uint32_t wtag = (uint32_t)(b + 1) << 16;     // this band's tag, in the word's high half
+            int Y[R], E[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) { Y[r] = -go; E[r] = 0; }
-        int ydiag = -go, ybot = -go, fbot = 0;
-        // the head's words of the first 16 columns; then each word is loaded 16
-        // steps before its use, into the ring slot the step just consumed
-        unsigned long long ring[16];
+            for (int r = 0; r < R; ++r) { Y[r] = -go; E[r] = 0; }
+            int ydiag = -go, ybot = -go, fbot = 0;
+            // the head's words of the first 16 columns; then each word is loaded 16
+            // steps before its use, into the ring slot the step just consumed
+            unsigned long long ring[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-            ring[u] = flow_word(a.rows, min(u, n - 1));
-        // subject codes of the current and the next 16-column block; the block
-        // after is loaded a block ahead, so its wait never falls behind the
-        // handoff words' loads and stores just issued
-        uint4 rv = resp[0];
-        uint4 rvn = resp[min(1, nblk - 1)];
-        int code = head ? (int)(rv.x & 0xffu) : kPad;
-        uint32_t pv[NW];
-        flow_ldlds<NW, PS>(pv, lds0 + ((uint32_t)code * kWave + lane) * PS);
+            for (int u = 0; u < 16; ++u)
+                ring[u] = flow_word(a.rows, min(u, n - 1));
+            // subject codes of the current and the next 16-column block; the block
+            // after is loaded a block ahead, so its wait never falls behind the
+            // handoff words' loads and stores just issued
+            uint4 rv = resp[0];
+            uint4 rvn = resp[min(1, nblk - 1)];
+            int code = head ? (int)(rv.x & 0xffu) : kPad;
+            uint32_t pv[NW];
+            flow_ldlds<NW, PS>(pv, lds0 + ((uint32_t)code * kWave + lane) * PS);
 
-        auto sweep = [&](auto edge, int t0) {
-            constexpr bool EDGE = decltype(edge)::value;
+            auto sweep = [&](auto edge, int t0) {
+                constexpr bool EDGE = decltype(edge)::value;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int t = t0 + u;
-                unsigned long long word = ring[u];
-                if (has_top && (!EDGE || t < n) && __builtin_amdgcn_readfirstlane((uint32_t)(word >> 48)) != want)
-                    word = flow_wait(a, t, want, &failed);
-                const int yh = (int)(word & 0xffffffu) - go;
-                const int fh = (int)((word >> 24) & 0xffffffu) - go;
-                // the word of column t + 16, into the slot just consumed (an
-                // agent-scope coherent read, as flow_word)
-                const u32x2 nw = __builtin_amdgcn_raw_buffer_load_b64(rows_in, (t + 16) * 8, 0, kStoreSc1);
-                ring[u] = ((unsigned long long)nw[1] << 32) | nw[0];
-                // shifts with the whole wave active, pinned so that none is
-                // folded into a select under a partial execution mask
-                int cd = shr1(code), yd = shr1(ybot), fd = shr1(fbot);
-                pin(cd);
-                pin(yd);
-                pin(fd);
-                const uint32_t nxt = u < 15 ? comp(rv, (u + 1) >> 2) >> (8 * ((u + 1) & 3)) : rvn.x;
-                const int cnext = head ? (int)(nxt & 0xffu) : cd;
-                uint32_t pvn[NW];
-                flow_ldlds<NW, PS>(pvn, lds0 + ((uint32_t)cnext * kWave + lane) * PS);
-                const int j = t - lane;                    // this lane's column
-                if (!EDGE || (j >= 0 && j < n)) {
-                    const int yt = head ? (has_top ? yh : -go) : yd;
-                    const int ft = head ? (has_top ? fh : 0) : fd;
-                    int dg = ydiag;
-                    ydiag = yt;
-                    int hup = yt, F = ft;
-                    int hprev = 0;
+                for (int u = 0; u < 16; ++u) {
+                    const int t = t0 + u;
+                    unsigned long long word = ring[u];
+                    if (has_top && (!EDGE || t < n) && __builtin_amdgcn_readfirstlane((uint32_t)(word >> 48)) != want)
+                        word = flow_wait(a, t, want, &failed);
+                    const int yh = (int)(word & 0xffffffu) - go;
+                    const int fh = (int)((word >> 24) & 0xffffffu) - go;
+                    // the word of column t + 16, into the slot just consumed (an
+                    // agent-scope coherent read, as flow_word)
+                    const u32x2 nw = __builtin_amdgcn_raw_buffer_load_b64(rows_in, (t + 16) * 8, 0, kStoreSc1);
+                    ring[u] = ((unsigned long long)nw[1] << 32) | nw[0];
+                    // shifts with the whole wave active, pinned so that none is
+                    // folded into a select under a partial execution mask
+                    int cd = shr1(code), yd = shr1(ybot), fd = shr1(fbot);
+                    pin(cd);
+                    pin(yd);
+                    pin(fd);
+                    const uint32_t nxt = u < 15 ? comp(rv, (u + 1) >> 2) >> (8 * ((u + 1) & 3)) : rvn.x;
+                    const int cnext = head ? (int)(nxt & 0xffu) : cd;
+                    uint32_t pvn[NW];
+                    flow_ldlds<NW, PS>(pvn, lds0 + ((uint32_t)cnext * kWave + lane) * PS);
+                    const int j = t - lane;                    // this lane's column
+                    if (!EDGE || (j >= 0 && j < n)) {
+                        const int yt = head ? (has_top ? yh : -go) : yd;
+                        const int ft = head ? (has_top ? fh : 0) : fd;
+                        int dg = ydiag;
+                        ydiag = yt;
+                        int hup = yt, F = ft;
+                        int hprev = 0;
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int tt = dg + flow_entry<ES>(pv, r);      // H[i-1][j-1] + s
-                        const int e = imax3(E[r] - ge, Y[r], 0);        // E (clamped at 0)
-                        F = max(F - ge, hup);                           // F
-                        const int h = imax3(tt, e, F);                  // H
-                        if (r & 1) {
-                            S = imax3(S, hprev, h);
-                            pin(S);
-                        } else {
-                            hprev = h;
+                        for (int r = 0; r < R; ++r) {
+                            const int tt = dg + flow_entry<ES>(pv, r);      // H[i-1][j-1] + s
+                            const int e = imax3(E[r] - ge, Y[r], 0);        // E (clamped at 0)
+                            F = max(F - ge, hup);                           // F
+                            const int h = imax3(tt, e, F);                  // H
+                            if (r & 1) {
+                                S = max3_i32(S, hprev, h);
+                            } else {
+                                hprev = h;
+                            }
+                            if ((R & 1) && r == R - 1)
+                                S = max(S, h);
+                            dg = Y[r];
+                            hup = h - go;
+                            Y[r] = hup;
+                            E[r] = e;
                         }
-                        if ((R & 1) && r == R - 1)
-                            S = max(S, h);
-                        dg = Y[r];
-                        hup = h - go;
-                        Y[r] = hup;
-                        E[r] = e;
+                        ybot = hup;
+                        fbot = F;
                     }
-                    ybot = hup;
-                    fbot = F;
-                }
-                const uint32_t yv = (uint32_t)(ybot + go), fv = (uint32_t)(fbot + go);
-                const u32x2 v = {(yv & 0xffffffu) | (fv << 24), ((fv >> 8) & 0xffffu) | wtag};
-                if constexpr (EDGE) {
-                    const bool st = tail && put && !failed && j >= 0 && j < n;
-                    __builtin_amdgcn_raw_buffer_store_b64(v, rows_out, st ? j * 8 : n * 8, 0, kStoreSc1);
-                } else {
-                    __builtin_amdgcn_raw_buffer_store_b64(v, rows_out, t * 8 + sbase, 0, kStoreSc1);
-                }
-                code = cnext;
+                    const uint32_t yv = (uint32_t)(ybot + go), fv = (uint32_t)(fbot + go);
+                    const u32x2 v = {(yv & 0xffffffu) | (fv << 24), ((fv >> 8) & 0xffffu) | wtag};
+                    if constexpr (EDGE) {
+                        const bool st = tail && put && !failed && j >= 0 && j < n;
+                        __builtin_amdgcn_raw_buffer_store_b64(v, rows_out, st ? j * 8 : n * 8, 0, kStoreSc1);
+                    } else {
+                        __builtin_amdgcn_raw_buffer_store_b64(v, rows_out, t * 8 + sbase, 0, kStoreSc1);
+                    }
+                    code = cnext;
 #pragma unroll
-                for (int i = 0; i < NW; ++i)
-                    pv[i] = pvn[i];
-            }
+                    for (int i = 0; i < NW; ++i)
+                        pv[i] = pvn[i];
+                }
         };
         // blocks where some lane is outside [0, n) (the pipeline's fill and
         // drain) run a copy of the sweep with a per-lane predicate; the blocks
@@ -274,6 +287,11 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
             block(std::integral_constant<bool, false>{}, t0);
         for (int t0 = max(fast_lo, fast_hi); t0 < nsteps16 && !failed; t0 += 16)
             block(std::integral_constant<bool, true>{}, t0);
+        };
+        if (b > 0)
+            run_band(std::integral_constant<bool, true>{});
+        else
+            run_band(std::integral_constant<bool, false>{});
     }
     for (int k = 32; k >= 1; k >>= 1)
         S = max(S, __shfl_xor(S, k));

@@ -1891,10 +1891,12 @@ double pair_time_rect(int64_t m, int64_t n, int R, int K, int wc, int cu)
 // workgroup per CU (W / 4 waves per SIMD, so no SIMD carries more than the
 // others: the bands advance at the pace of the slowest).  Fitted to MI355X
 // (DNA pairs of every R, one band at n = 100K and 200K for the step, 256 and
-// 1,000 bands for the lag and the sharing): a wave alone on its SIMD takes
-// 309 + 32.2 (R - 4) cycles per step, about 4 cycles per instruction of any
-// kind (it issues one at a time); k waves sharing a SIMD issue-bound, k x 4.6
-// cycles per VALU instruction; each band starts about 127 - 1.55 R steps
+// 1,000 bands for the lag and the sharing, refitted on the three paper sizes
+// at 4, 10 and 16 rows): a wave alone on its SIMD takes 46.8 + 4.04 cycles
+// per VALU instruction of a step (it issues one instruction at a time, the
+// few scalar and memory ones of a step included in the constant); k >= 2
+// waves sharing a SIMD issue-bound, k x 4.6 cycles per VALU instruction;
+// each band starts about 127 - 1.55 R steps
 // after the band above (the last lane's 63-column lag, the 16-step read-ahead
 // and the latency of the handoff words through memory).  Waves sharing a CU
 // step 1.33 - 0.012 R times slower than a wave alone (1.10 with one wave per
@@ -1907,9 +1909,9 @@ constexpr int64_t kFlowMaxValue = (1 << 24) - 1;
 constexpr uint64_t kFlowTimeoutTicks = 200000000;   // a wait's limit: 2 s of the 100 MHz real-time counter
 constexpr int kFlowGroupLds = 96 * 1024;     // LDS a workgroup asks for at least: over half a CU's
 
-// VALU instructions of one step (the counted hot loop of the kernel: 8 per
-// row and 25.4 per column)
-double flow_instr_per_step(int R) { return 8.0 * R + 25.4; }
+// VALU instructions of one step (the counted hot loop of the kernel, a band
+// with a band above it: 7.5 per row and 21.25 per column)
+double flow_instr_per_step(int R) { return 7.5 * R + 21.25; }
 
 int64_t flow_bands(int64_t m, int R) { return ceil_div(ceil_div(std::max<int64_t>(m, 1), R), kWave); }
 
@@ -1942,7 +1944,8 @@ FlowShape flow_shape(int64_t m, int64_t n, int R, int elem, int cu, int lds_max,
         const double k = std::ceil(wpg / 4.0);
         const double rounds = std::ceil((double)nb / (double)G);
         const double busy = wpg > 1 ? 1.33 - 0.012 * R : 1.10;
-        const double step = busy * std::max(309.0 + 32.2 * (R - 4), k * kPairIssueCycles * flow_instr_per_step(R));
+        const double alone = 46.8 + 4.04 * flow_instr_per_step(R);
+        const double step = busy * (k > 1 ? std::max(alone, k * kPairIssueCycles * flow_instr_per_step(R)) : alone);
         const double lag = 127.0 - 1.55 * R;
         const double steps = std::max(rounds * (double)(n + kWave - 1) + (double)G * lag,
                                       (double)nb * lag + (double)(n + kWave - 1));

@@ -64,6 +64,9 @@ _FLOW = [k for k in VARIANTS if k.startswith("flow_")]
 # kernels with two copies of the hot loop (tiles at the matrix edge with a
 # per-column predicate, tiles inside without): count the copy inside
 INTERIOR = {"pair_r8_p8", "pair_r8_p16", "pair_r16_p8", "pair_r16_p16", *_FLOW}
+# kernels whose first band has a copy of its own with no band above to read
+# from: the loop counted is one that loads the row above (every other band's)
+READS_ABOVE = set(_FLOW)
 # subject columns one trip of the hot loop sweeps, where not four (the pair
 # kernels unroll the 16 columns of a residue block)
 TRIP_COLS = {"pair_r8_p8": 16, "pair_r8_p16": 16, "pair_r16_p8": 16, "pair_r16_p16": 16,
@@ -71,12 +74,13 @@ TRIP_COLS = {"pair_r8_p8": 16, "pair_r8_p16": 16, "pair_r16_p8": 16, "pair_r16_p
 SOURCES = ["sw_isa_probe.hip", "sw_pair.hip", "sw_pair_flow.hip", "sw_k_rescore.hip"]
 
 
-def _hot_loop(lines, interior=False):
+def _hot_loop(lines, interior=False, reads_above=False):
     """Lines of the blocks of the hot loop: of the loops in the function, the
     one whose own blocks (its header block and every block the compiler
     annotates as directly inside it, wherever they are placed; not the blocks
     of loops nested in it) hold the most VALU instructions.  interior: of the
-    loops holding at least 70% of that count, the one with the fewest."""
+    loops holding at least 70% of that count, the one with the fewest.
+    reads_above: of those, only loops with a buffer load count."""
     blocks = []            # (label, annotation, start, end)
     starts = [i for i, ln in enumerate(lines) if re.match(r"^\.LBB\w+:", ln)]
     for n, i in enumerate(starts):
@@ -102,7 +106,9 @@ def _hot_loop(lines, interior=False):
         return []
     top = max(v for v, _ in loops)
     if interior:
-        return min((lp for lp in loops if lp[0] >= 0.7 * top), key=lambda lp: lp[0])[1]
+        cand = [lp for lp in loops if lp[0] >= 0.7 * top
+                and (not reads_above or any(l.strip().startswith("buffer_load") for l in lp[1]))]
+        return min(cand, key=lambda lp: lp[0])[1]
     return max(loops, key=lambda lp: lp[0])[1]
 
 
@@ -113,7 +119,7 @@ def count(asm_text: str) -> dict:
         body = next((f for f in funcs if f.startswith("_Z") and frag in f.split(":")[0]), None)
         if body is None:
             continue
-        loop = _hot_loop(body.split("\n"), key in INTERIOR)
+        loop = _hot_loop(body.split("\n"), key in INTERIOR, key in READS_ABOVE)
         ins = [l.strip().split()[0] for l in loop
                if l.strip() and not l.strip().startswith((".", ";")) and not l.strip().endswith(":")]
         c = collections.Counter(ins)
