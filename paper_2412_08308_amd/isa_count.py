@@ -80,7 +80,8 @@ def _hot_loop(lines, interior=False, reads_above=False):
     annotates as directly inside it, wherever they are placed; not the blocks
     of loops nested in it) hold the most VALU instructions.  interior: of the
     loops holding at least 70% of that count, the one with the fewest.
-    reads_above: of those, only loops with a buffer load count."""
+    reads_above: of those, only the loops with the most vector-memory loads
+    (the copy that reads the row above) count."""
     blocks = []            # (label, annotation, start, end)
     starts = [i for i, ln in enumerate(lines) if re.match(r"^\.LBB\w+:", ln)]
     for n, i in enumerate(starts):
@@ -106,8 +107,11 @@ def _hot_loop(lines, interior=False, reads_above=False):
         return []
     top = max(v for v, _ in loops)
     if interior:
-        cand = [lp for lp in loops if lp[0] >= 0.7 * top
-                and (not reads_above or any(l.strip().startswith("buffer_load") for l in lp[1]))]
+        cand = [lp for lp in loops if lp[0] >= 0.7 * top]
+        if reads_above:
+            loads = lambda lp: sum(1 for l in lp[1] if l.strip().startswith(("buffer_load", "global_load")))
+            most = max(loads(lp) for lp in cand)
+            cand = [lp for lp in cand if loads(lp) == most]
         return min(cand, key=lambda lp: lp[0])[1]
     return max(loops, key=lambda lp: lp[0])[1]
 
