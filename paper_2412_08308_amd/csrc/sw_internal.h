@@ -19,6 +19,7 @@ constexpr int kAlpha = 32;           // residue codes 0..31 accepted at the ABI
 constexpr int kCodes = 33;           // + internal pad code
 constexpr uint8_t kPad = 32;         // pad code: subject tails and chunk fill
 constexpr int kWave = 64;
+constexpr int kXcds = 8;             // accelerator dies of the device, an L2 each; workgroups go to them in turn
 constexpr int kRescoreMaxWaves = 8; // wavefronts of a rescore workgroup, at most
 constexpr int kFlagSortCap = 4096;   // overflow lists up to this length are sorted by cost
 constexpr int kI16Rows = 24;       // query rows per lane of the packed 16-bit variant

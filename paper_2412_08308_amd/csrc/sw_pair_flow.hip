@@ -17,8 +17,10 @@
 // word carries its own validity), so bands on different XCDs meet in memory.
 //
 // A band waits only for the band above it, which a lower-numbered wavefront
-// (dispatched earlier) or this wavefront's previous round runs, so the
-// pipeline needs no other ordering.  The bands advance at the pace of the
+// or this wavefront's previous round runs; every wavefront of the launch is
+// resident at once (the host checks the occupancy first), so the pipeline
+// needs no other ordering.  Wavefronts are numbered XCD by XCD, so that most
+// handoffs stay within one L2.  The bands advance at the pace of the
 // slowest one, so the launch places them evenly: workgroups of W waves (W / 4
 // per SIMD), one workgroup per CU (its LDS request keeps a second one off the
 // CU), each wave with a band profile of its own in LDS.  Every wait is bounded in time: a wave
@@ -308,7 +310,14 @@ k_pair_flow(FlowArgs a)
 {
     const int wpg = (int)(blockDim.x >> 6);
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    pair_flow<R, ES>(a, (int)blockIdx.x * wpg + w, (int)(threadIdx.x & 63), (uint32_t)(w * flow_lds_bytes(R, ES)));
+    // Workgroups go to the device's 8 XCDs in turn (workgroup g to XCD g mod
+    // 8), each XCD with an L2 of its own.  Number them XCD by XCD, so that a
+    // band and the one below it share an L2 except where one XCD's share of
+    // the workgroups ends; the numbering is a permutation of the grid.
+    const int G = (int)gridDim.x, g = (int)blockIdx.x;
+    const int x = g & (kXcds - 1), per = G / kXcds, extra = G % kXcds;
+    const int group = x * per + min(x, extra) + g / kXcds;
+    pair_flow<R, ES>(a, group * wpg + w, (int)(threadIdx.x & 63), (uint32_t)(w * flow_lds_bytes(R, ES)));
 }
 
 // Clear the handoff words and the status word before a flow pass.
