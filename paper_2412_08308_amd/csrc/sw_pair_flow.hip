@@ -272,23 +272,23 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
                     for (int i = 0; i < NW; ++i)
                         pv[i] = pvn[i];
                 }
-        };
-        // blocks where some lane is outside [0, n) (the pipeline's fill and
-        // drain) run a copy of the sweep with a per-lane predicate; the blocks
-        // between run without, in a loop of their own
-        const int fast_lo = kWave, fast_hi = max(kWave, n & ~15);     // [fast_lo, fast_hi): every lane inside
-        auto block = [&](auto edge, int t0) {
-            const uint4 ahead = resp[min((t0 >> 4) + 2, nblk - 1)];
-            sweep(edge, t0);
-            rv = rvn;
-            rvn = ahead;
-        };
-        for (int t0 = 0; t0 < min(fast_lo, nsteps16) && !failed; t0 += 16)
-            block(std::integral_constant<bool, true>{}, t0);
-        for (int t0 = fast_lo; t0 < fast_hi && !failed; t0 += 16)
-            block(std::integral_constant<bool, false>{}, t0);
-        for (int t0 = max(fast_lo, fast_hi); t0 < nsteps16 && !failed; t0 += 16)
-            block(std::integral_constant<bool, true>{}, t0);
+            };
+            // blocks where some lane is outside [0, n) (the pipeline's fill and
+            // drain) run a copy of the sweep with a per-lane predicate; the blocks
+            // between run without, in a loop of their own
+            const int fast_lo = kWave, fast_hi = max(kWave, n & ~15);     // [fast_lo, fast_hi): every lane inside
+            auto block = [&](auto edge, int t0) {
+                const uint4 ahead = resp[min((t0 >> 4) + 2, nblk - 1)];
+                sweep(edge, t0);
+                rv = rvn;
+                rvn = ahead;
+            };
+            for (int t0 = 0; t0 < min(fast_lo, nsteps16) && !failed; t0 += 16)
+                block(std::integral_constant<bool, true>{}, t0);
+            for (int t0 = fast_lo; t0 < fast_hi && !failed; t0 += 16)
+                block(std::integral_constant<bool, false>{}, t0);
+            for (int t0 = max(fast_lo, fast_hi); t0 < nsteps16 && !failed; t0 += 16)
+                block(std::integral_constant<bool, true>{}, t0);
         };
         if (b > 0)
             run_band(std::integral_constant<bool, true>{});
