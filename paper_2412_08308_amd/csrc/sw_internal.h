@@ -204,6 +204,9 @@ __host__ __device__ constexpr int flow_lds_stride(int R, int ES)
 // Rows per lane the flow pass is built for (the planner keeps the band count
 // at or below the device's SIMDs where it can).
 constexpr int kFlowRowChoices[6] = {4, 6, 8, 10, 12, 16};
+// From this many rows per lane the flow pass checks the handoff words' tags
+// once per 16-step block; below, once per step.
+constexpr int kFlowBlockwiseRows = 8;
 // The flow pass on `grid` workgroups of `wpg` waves (a.waves = grid * wpg),
 // each asking for `lds` bytes of LDS (at least wpg band profiles).
 hipError_t launch_pair_flow(const FlowArgs& a, int rows, int elem, int wpg, int grid, int lds, hipStream_t st);

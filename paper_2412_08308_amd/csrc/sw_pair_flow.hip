@@ -100,6 +100,11 @@ __device__ __forceinline__ int flow_entry(const uint32_t (&v)[NW], int r)
 // another wave has failed, or the time limit (or a poll count of the same
 // order) passes; then *failed is set.
 constexpr uint32_t kFlowMaxPolls = 1u << 25;
+// Columns a band that had to wait lets the band above get ahead of its
+// read-ahead: a handoff word can take a few microseconds to reach the band
+// below, and a band that falls back by less keeps waiting again (measured on
+// MI355X at 10 and 16 rows per lane: 32 columns beat 16).
+constexpr int kFlowSlack = 32;
 
 __device__ __forceinline__ unsigned long long flow_wait(const FlowArgs& a, int j, uint32_t want,
                                                            int* failed)
@@ -130,6 +135,11 @@ __device__ __forceinline__ int max3_i32(int a, int b, int c)
     return r;
 }
 
+__device__ __forceinline__ uint32_t min3_u32(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_elementwise_min(__builtin_elementwise_min(a, b), c);
+}
+
 template <int R, int ES>
 __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int lane, uint32_t lds0)
 {
@@ -137,6 +147,7 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
     constexpr uint32_t BS = kCodes * CS;
     constexpr int NW = (R * ES + 3) / 4;
     constexpr uint32_t PS = flow_lds_stride(R, ES);
+    constexpr bool BLOCKWISE = R >= kFlowBlockwiseRows;     // the handoff words' tags checked per 16-step block
 
     const int n = a.n;
     const int go = a.go, ge = a.ge;
@@ -208,11 +219,43 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
 
             auto sweep = [&](auto edge, int t0) {
                 constexpr bool EDGE = decltype(edge)::value;
+                // From kFlowBlockwiseRows rows per lane on, while every column of the block is
+                // inside the matrix, the tags of its 16 words (slot u holds
+                // column t0 + u) are checked at once: the band above writes
+                // tag b, older words carry smaller tags, so the block is ready
+                // when the least tag is b.  A stale word was read ahead before
+                // the band above wrote it, and so were the words after it: the
+                // band then waits until the band above is kFlowSlack columns
+                // past the block's last word and reads all 16 again, falling
+                // behind the band above in one wait rather than one poll per
+                // step.  The check waits for the block's last read-ahead loads,
+                // which shorter steps (fewer rows) do not hide: there each
+                // step checks its own word.
+                const bool whole = BLOCKWISE && (!EDGE || t0 + 15 < n);
+                auto ready = [&]() {
+                    uint32_t least = (uint32_t)(ring[0] >> 32);
+#pragma unroll
+                    for (int u = 1; u < 16; u += 2)
+                        least = min3_u32(least, (uint32_t)(ring[u] >> 32),
+                                         (uint32_t)(ring[u + 1 < 16 ? u + 1 : u] >> 32));
+                    return __builtin_amdgcn_readfirstlane(least) >= (want << 16);
+                };
+                if (has_top && whole && __builtin_expect(!ready(), 0)) {
+                    do {
+                        flow_wait(a, min(t0 + 15 + kFlowSlack, n - 1), want, &failed);
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) {
+                            const u32x2 rw = __builtin_amdgcn_raw_buffer_load_b64(rows_in, (t0 + u) * 8, 0, kStoreSc1);
+                            ring[u] = ((unsigned long long)rw[1] << 32) | rw[0];
+                        }
+                    } while (!failed && !ready());
+                }
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
                     const int t = t0 + u;
                     unsigned long long word = ring[u];
-                    if (has_top && (!EDGE || t < n) && __builtin_amdgcn_readfirstlane((uint32_t)(word >> 48)) != want)
+                    if (has_top && !whole && (!EDGE || t < n) &&
+                        __builtin_amdgcn_readfirstlane((uint32_t)(word >> 48)) != want)
                         word = flow_wait(a, t, want, &failed);
                     const int yh = (int)(word & 0xffffffu) - go;
                     const int fh = (int)((word >> 24) & 0xffffffu) - go;

@@ -1891,14 +1891,16 @@ double pair_time_rect(int64_t m, int64_t n, int R, int K, int wc, int cu)
 // workgroup per CU (W / 4 waves per SIMD, so no SIMD carries more than the
 // others: the bands advance at the pace of the slowest).  Fitted to MI355X
 // (DNA pairs of every R, one band at n = 100K and 200K for the step, 256 and
-// 1,000 bands for the lag and the sharing, refitted on the three paper sizes
+// 1,000 bands for the lag and the sharing, refitted on the paper's five pairs
 // at 4, 10 and 16 rows): a wave alone on its SIMD takes 46.8 + 4.04 cycles
-// per VALU instruction of a step (it issues one instruction at a time, the
-// few scalar and memory ones of a step included in the constant); k >= 2
-// waves sharing a SIMD issue-bound, k x 4.6 cycles per VALU instruction;
-// each band starts about 127 - 1.55 R steps
-// after the band above (the last lane's 63-column lag, the 16-step read-ahead
-// and the latency of the handoff words through memory).  Waves sharing a CU
+// per VALU instruction of a step with a tag check per step (it issues one
+// instruction at a time, the few scalar and memory ones of a step included
+// in the constant), 4.0 with one check per 16-step block; k >= 2 waves
+// sharing a SIMD issue-bound, k x 4.6 cycles per VALU instruction; each band
+// starts about 127 - 1.55 R steps (per-step checks) or 156 - 1.2 R steps
+// (block checks, whose waits leave more slack) after the band above (the
+// last lane's 63-column lag, the 16-step read-ahead and the latency of the
+// handoff words through memory).  Waves sharing a CU
 // step 1.33 - 0.012 R times slower than a wave alone (1.10 with one wave per
 // CU), so up to one band per CU the workgroups hold one wave each.  Bands run
 // in rounds when they outnumber the waves; a round's band starts when its
@@ -1910,10 +1912,21 @@ constexpr uint64_t kFlowTimeoutTicks = 200000000;   // a wait's limit: 2 s of th
 constexpr int kFlowGroupLds = 96 * 1024;     // LDS a workgroup asks for at least: over half a CU's
 
 // VALU instructions of one step (the counted hot loop of the kernel, a band
-// with a band above it: 7.5 per row and 21.25 per column)
-double flow_instr_per_step(int R) { return 7.5 * R + 21.25; }
+// with a band above it: 7.5 per row, and 21.25 per column with a tag check
+// per step or 20 with one per block)
+double flow_instr_per_step(int R) { return 7.5 * R + (R >= kFlowBlockwiseRows ? 20.0 : 21.25); }
 
 int64_t flow_bands(int64_t m, int R) { return ceil_div(ceil_div(std::max<int64_t>(m, 1), R), kWave); }
+
+// Cycles of one step of a band with R rows on workgroups of wpg waves.
+double flow_step_cycles(int R, int wpg)
+{
+    const double k = std::ceil(wpg / 4.0);
+    const double busy = wpg > 1 ? 1.33 - 0.012 * R : 1.10;
+    const double alone = R >= kFlowBlockwiseRows ? 4.0 * flow_instr_per_step(R)
+                                                 : 46.8 + 4.04 * flow_instr_per_step(R);
+    return busy * (k > 1 ? std::max(alone, k * kPairIssueCycles * flow_instr_per_step(R)) : alone);
+}
 
 // Waves per workgroup the kernel is built for: 16 (128 registers) up to 6
 // rows per lane, 8 (256 registers) beyond.
@@ -1941,12 +1954,9 @@ FlowShape flow_shape(int64_t m, int64_t n, int R, int elem, int cu, int lds_max,
         int64_t grid = std::min<int64_t>(ceil_div(nb, wpg), std::max(cu, 1));
         if (grid_limit > 0) grid = std::min<int64_t>(grid, grid_limit);
         const int64_t G = grid * wpg;
-        const double k = std::ceil(wpg / 4.0);
         const double rounds = std::ceil((double)nb / (double)G);
-        const double busy = wpg > 1 ? 1.33 - 0.012 * R : 1.10;
-        const double alone = 46.8 + 4.04 * flow_instr_per_step(R);
-        const double step = busy * (k > 1 ? std::max(alone, k * kPairIssueCycles * flow_instr_per_step(R)) : alone);
-        const double lag = 127.0 - 1.55 * R;
+        const double step = flow_step_cycles(R, wpg);
+        const double lag = R >= kFlowBlockwiseRows ? 156.0 - 1.2 * R : 127.0 - 1.55 * R;
         const double steps = std::max(rounds * (double)(n + kWave - 1) + (double)G * lag,
                                       (double)nb * lag + (double)(n + kWave - 1));
         const double t = steps * step / 2.4e9 + kFlowLaunchS;

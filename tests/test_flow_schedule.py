@@ -163,6 +163,113 @@ def test_flow_model_matches_oracle(seed):
     assert got == oracle.score(q, d, sm, go, ge)
 
 
+def run_flow_blockwise(q, d, sm, go, ge, R, G, rng, stall=0.0, K=64, slack=32, check_all=True):
+    """The pass with the block-wise tag check (from 8 rows per lane on): the
+    head keeps a ring of 16 words, the word of column t + 16 read (a snapshot
+    of the buffer) at step t, past column n - 1 read as 0 (the range-checked
+    descriptor).  At the start of a block whose columns are all inside the
+    matrix the least tag of its 16 words must be the band's own b; otherwise
+    the band polls until the word of column min(t0 + 15 + slack, n - 1)
+    carries tag b, reads the 16 words again and checks once more.  The block
+    that reaches past column n - 1 checks its words one by one (polling the
+    buffer).  check_all=False checks only the block's first word."""
+    m, n = len(q), len(d)
+    nb = -(-m // (K * R))
+    buf = [0] * (n + 16)
+    written = {}
+    consumed = set()
+    load = lambda j: buf[j] if j < n else 0
+    waves = [{"bands": list(range(w, nb, G)), "cur": None} for w in range(min(G, nb))]
+    S = 0
+    while True:
+        live = [w for w in waves if w["bands"] or w["cur"] is not None]
+        if not live:
+            break
+        w = live[rng.integers(len(live))]
+        if rng.random() < stall:
+            continue
+        if w["cur"] is None:
+            band = Band(w["bands"].pop(0), q, d, sm, go, ge, R, K)
+            band.ring = [load(min(u, n - 1)) for u in range(16)]
+            band.checked = -1
+            w["cur"] = band
+        band = w["cur"]
+        t = band.t
+        top = None
+        if band.b > 0:
+            t0 = t - t % 16
+            whole = t0 + 15 < n
+            if whole and band.checked != t0:
+                tags = [unpack(x, go)[2] for x in band.ring]
+                assert max(tags) <= band.b, "a word of a band below was read"
+                if (min(tags) if check_all else tags[0]) < band.b:
+                    if unpack(buf[min(t0 + 15 + slack, n - 1)], go)[2] != band.b:
+                        continue                              # still waiting
+                    band.ring = [load(t0 + u) for u in range(16)]
+                    continue                                  # check the words read again
+                band.checked = t0
+            word = band.ring[t % 16]
+            if t < n:
+                y, f, tag = unpack(word, go)
+                if not whole and tag != band.b:
+                    y, f, tag = unpack(buf[t], go)            # poll the word itself
+                    if tag != band.b:
+                        continue
+                if check_all:
+                    assert tag == band.b and written[(band.b - 1, t)] == (y, f), "accepted a word of another band"
+                consumed.add((band.b - 1, t))
+                top = (y, f)
+            band.ring[t % 16] = load(t + 16)                  # read ahead
+        out = band.step(top)
+        if out is not None and band.b < nb - 1:
+            jj, y, f = out
+            if band.b >= 1 and check_all:
+                assert (band.b - 1, jj) in consumed, "word overwritten before it was read"
+            buf[jj] = pack(y, f, go, band.b + 1)
+            written[(band.b, jj)] = (y, f)
+        if band.done():
+            S = max(S, band.S)
+            w["cur"] = None
+    return S
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_blockwise_check_matches_oracle(seed):
+    """Block-wise checks with a read-ahead ring and the resynchronising wait,
+    under random and stalling schedules: every accepted word is the band
+    above's for that column, no word is replaced before it was read, and the
+    score equals the oracle's."""
+    rng = np.random.default_rng(700 + seed)
+    K = int(rng.choice([4, 8, 16]))
+    R = int(rng.choice([1, 2]))
+    m = int(rng.integers(1, 3 * K * R + 5))
+    n = int(rng.integers(1, 70))
+    alpha = int(rng.choice([2, 4, 20]))
+    q = rng.integers(0, alpha, size=m).astype(np.uint8)
+    h = min(n // 2, m) if seed % 3 == 0 else 0          # a homologous stretch
+    d = np.concatenate([q[:h], rng.integers(0, alpha, size=n - h)]).astype(np.uint8)
+    sm = synth.random_matrix(rng, -4, 5)
+    go, ge = int(rng.integers(0, 8)), int(rng.integers(0, 4))
+    G = int(rng.integers(1, 5))
+    slack = int(rng.choice([0, 4, 32]))
+    got = run_flow_blockwise(q, d, sm, go, ge, R, G, rng, stall=float(rng.choice([0.0, 0.3])), K=K, slack=slack)
+    assert got == oracle.score(q, d, sm, go, ge)
+
+
+def test_blockwise_model_needs_every_tag():
+    """Checking only the block's first word lets later stale words through:
+    the adversarial schedules then give wrong scores."""
+    wrong = 0
+    for seed in range(12):
+        rng = np.random.default_rng(950 + seed)
+        q = rng.integers(0, 4, size=40).astype(np.uint8)
+        d = np.concatenate([q[5:35], rng.integers(0, 4, size=20)]).astype(np.uint8)
+        sm = synth.dna_matrix(2, -3)
+        got = run_flow_blockwise(q, d, sm, 3, 1, 2, 3, rng, stall=0.3, K=4, slack=0, check_all=False)
+        wrong += got != oracle.score(q, d, sm, 3, 1)
+    assert wrong > 0
+
+
 def test_model_catches_a_missing_tag_check():
     """The schedules are adversarial enough: a reader that takes whatever
     word it finds (no tag check) reads too early and gets wrong scores."""
@@ -213,11 +320,15 @@ def test_flow_addresses_stay_in_bounds(R):
             for g in (0, 63):
                 rb = min(b * 64 + g, nbr)
                 assert 0 <= rb <= nbr
-            # head reads words j = t for t < n; prefetch of the next block clamps to n - 1
+            # the head polls words j = t < n; the read-ahead and a block's
+            # reloads (columns up to t0 + 31) go through a descriptor whose
+            # range is the n words (a read past it returns 0 and touches no
+            # memory), inside the n + 16 allocated entries; a block's wait
+            # for the band above polls column min(t0 + 15 + 32, n - 1)
+            assert n * 8 <= (n + 16) * 8
             for t0 in range(0, steps + 16, 16):
-                for u in range(16):
-                    jw = min(t0 + 16 + u, n - 1)
-                    assert 0 <= jw < n
+                jr = min(t0 + 15 + 32, n - 1)
+                assert 0 <= jr < n
                 blk = min(t0 + 16, n_pad - 16) // 16
                 assert 0 <= blk * 16 and blk * 16 + 16 <= n_pad
             # the tail's store: column j = t - 63 in [0, n), else the dropped
