@@ -536,97 +536,136 @@ __global__ void k_walk_init(const unsigned long long* __restrict__ end_key, cons
     *w = s;
 }
 
+__device__ __forceinline__ int walk_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __global__ void __launch_bounds__(64) k_walk(const uint32_t* __restrict__ dir, int64_t stride, int64_t r_lo,
                                              int64_t c_lo, int64_t r_hi, int64_t c_hi, WalkState* wst,
                                              char* __restrict__ ops, int64_t cap)
 {
     __shared__ uint32_t win[kWinCols][kWinWords];
     const int lane = threadIdx.x;
-    WalkState s = *wst;
-    if (s.done)
+    const WalkState s0 = *wst;
+    if (s0.done)
         return;
-    const int64_t w_lo = r_lo >> 3;            // r_lo is a multiple of 8
-    int64_t c0 = -1, w0 = 0;                   // window: block columns c0.., block words w0..
-    // code of 1-based cell (ii, jj) inside the block, reloading the window if needed
-    auto code = [&](int64_t ii, int64_t jj) -> uint32_t {
-        const int64_t col = jj - 1 - c_lo, row = ii - 1, wd = (row >> 3) - w_lo;
-        if (c0 < 0 || col < c0 || col >= c0 + kWinCols || wd < w0 || wd >= w0 + kWinWords) {
+    // The state is the same in every lane: held in 32-bit scalars (positions,
+    // block bounds and operation counts are below 2^31), so that a step of the
+    // walk is a few scalar instructions and one LDS read.
+    int i = walk_uniform((int)s0.i), j = walk_uniform((int)s0.j), n_ops = walk_uniform((int)s0.n_ops);
+    int st = walk_uniform(s0.st), prev_m = walk_uniform(s0.prev_m), ok = walk_uniform(s0.ok), done = 0;
+    int bi = 0, bj = 0;
+    const int rlo = (int)r_lo, clo = (int)c_lo;
+    const int rhi = (int)(r_hi < INT32_MAX ? r_hi : INT32_MAX), chi = (int)(c_hi < INT32_MAX ? c_hi : INT32_MAX);
+    const int lim = (int)(cap < INT32_MAX ? cap : INT32_MAX);
+    const int w_lo = rlo >> 3;                 // r_lo is a multiple of 8
+    // window: block columns c0 .. c0 + 63, block words w0 .. w0 + 15.  Every
+    // step moves up, left or both, so a window placed with the walk's cell at
+    // its lower right corner is left only through its top or left edge.
+    int c0 = INT32_MAX, w0 = 0;
+    for (;;) {
+        if (i < 1 || j < 1 || n_ops >= lim) {                // off the matrix: inconsistent codes
+            done = 1;
+            ok = 0;
+            break;
+        }
+        if (i - 1 < rlo || j - 1 < clo || i - 1 >= rhi || j - 1 >= chi)
+            break;                                            // the next cell is in another block
+        const int col = j - 1 - clo, row = i - 1, wd = (row >> 3) - w_lo;
+        if (col < c0 || wd < w0) {
             __syncthreads();
             c0 = col - (kWinCols - 1) > 0 ? col - (kWinCols - 1) : 0;
-            w0 = wd - (kWinWords - 4) > 0 ? wd - (kWinWords - 4) : 0;
-            const int64_t cc = c0 + lane;
+            w0 = wd - (kWinWords - 1) > 0 ? wd - (kWinWords - 1) : 0;
+            const int cc = c0 + lane;
             if (cc <= col) {
                 // all loads in flight at once: clamped addresses, words past
                 // the column's end read as zero afterwards
                 uint32_t v[kWinWords];
 #pragma unroll
                 for (int k = 0; k < kWinWords; ++k)
-                    v[k] = dir[cc * stride + min(w0 + k, stride - 1)];
+                    v[k] = dir[(int64_t)cc * stride + min((int64_t)w0 + k, stride - 1)];
 #pragma unroll
                 for (int k = 0; k < kWinWords; ++k)
-                    win[lane][k] = (w0 + k < stride) ? v[k] : 0u;
+                    win[lane][k] = ((int64_t)w0 + k < stride) ? v[k] : 0u;
             }
             __syncthreads();
         }
-        const uint32_t word = win[col - c0][wd - w0];
-        return (word >> (4 * (row & 7))) & 15u;
-    };
-    while (!s.done) {
-        if (s.i < 1 || s.j < 1 || s.n_ops >= cap) {          // off the matrix: inconsistent codes
-            s.done = 1;
-            s.ok = 0;
-            break;
-        }
-        if (s.i - 1 < r_lo || s.j - 1 < c_lo || s.i - 1 >= r_hi || s.j - 1 >= c_hi)
-            break;                                            // the next cell is in another block
-        const uint32_t c = code(s.i, s.j);
-        if (s.st == 0) {
-            const uint32_t src = c & 3u;
+        // Cells the walk may reach from here in one direction without leaving
+        // the window (hence the block) or passing the operation cap: lane l
+        // looks at the l-th of them, and a ballot takes the run of steps that
+        // continue the same way, so a run costs one pass instead of one per
+        // step.
+        const int room_r = row - ((w0 + w_lo) << 3) + 1, room_c = col - c0 + 1;
+        const int left = lim - n_ops;
+        const int dr = st == 1 ? 0 : 1, dc = st == 2 ? 0 : 1;        // diagonal, left (E) or up (F)
+        const int room = min(min(dr ? room_r : kWave, dc ? room_c : kWave), min(left, kWave));
+        const int l = lane < room ? lane : 0;
+        const int rr = row - dr * l, cl = col - dc * l;
+        const uint32_t c = (win[cl - c0][(rr >> 3) - w_lo - w0] >> (4 * (rr & 7))) & 15u;
+        if (st == 0) {
+            const unsigned long long run = __ballot(lane < room && (c & 3u) == 1u);
+            const int k = ~run ? __builtin_ctzll(~run) : kWave;       // diagonal steps in a row
+            if (k > 0) {
+                // the walk ends at the border after the first cell of the
+                // run on row 1 or column 1
+                const int nb = min(i, j) <= k ? min(i, j) : k;
+                if (lane < nb)
+                    ops[n_ops + lane] = 'M';
+                n_ops += nb;
+                prev_m = 1;
+                if (nb < k || min(i, j) == k) {
+                    done = 1;
+                    bi = i - (nb - 1);
+                    bj = j - (nb - 1);
+                    break;
+                }
+                i -= k;
+                j -= k;
+                continue;
+            }
+            const uint32_t src = (uint32_t)walk_uniform((int)c) & 3u;
             if (src == 0u) {
                 // H = 0: after a diagonal step the alignment began at the
                 // previous cell; anywhere else the codes are inconsistent
-                s.done = 1;
-                s.ok = s.prev_m;
-                s.bi = s.i + 1;
-                s.bj = s.j + 1;
+                done = 1;
+                ok = prev_m;
+                bi = i + 1;
+                bj = j + 1;
                 break;
             }
-            if (src == 1u) {
-                if (lane == 0)
-                    ops[s.n_ops] = 'M';
-                ++s.n_ops;
-                s.prev_m = 1;
-                if (s.i == 1 || s.j == 1) {               // border
-                    s.done = 1;
-                    s.bi = s.i;
-                    s.bj = s.j;
-                    break;
-                }
-                --s.i;
-                --s.j;
-                continue;
-            }
-            s.prev_m = 0;
-            s.st = src == 2u ? 1 : 2;
+            prev_m = 0;
+            st = src == 2u ? 1 : 2;
             continue;
         }
-        if (lane == 0)
-            ops[s.n_ops] = s.st == 1 ? 'D' : 'I';
-        ++s.n_ops;
-        s.prev_m = 0;
-        if (s.st == 1) {
-            if (c & 4u)
-                s.st = 0;
-            --s.j;
-        } else {
-            if (c & 8u)
-                s.st = 0;
-            --s.i;
-        }
+        // in a gap: each cell emits its operation; the gap was opened at the
+        // first cell whose flag says so, and the walk is back in H after it
+        const unsigned long long opened = __ballot(lane < room && (c & (st == 1 ? 4u : 8u)) != 0u);
+        const int k = opened ? __builtin_ctzll(opened) + 1 : room;
+        if (lane < k)
+            ops[n_ops + lane] = st == 1 ? 'D' : 'I';
+        n_ops += k;
+        prev_m = 0;
+        if (st == 1)
+            j -= k;
+        else
+            i -= k;
+        if (opened)
+            st = 0;
     }
     __syncthreads();
-    if (lane == 0)
+    if (lane == 0) {
+        WalkState s = s0;
+        s.i = i;
+        s.j = j;
+        s.n_ops = n_ops;
+        s.st = st;
+        s.prev_m = prev_m;
+        s.ok = ok;
+        s.done = done;
+        if (done && bi) {
+            s.bi = bi;
+            s.bj = bj;
+        }
         *wst = s;
+    }
 }
 
 __global__ void __launch_bounds__(64) k_walk_finish(const WalkState* __restrict__ wst,
