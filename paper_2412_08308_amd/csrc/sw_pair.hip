@@ -100,6 +100,8 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
     int S = 0;
     const int s_target = TRACE ? *a.score : 0;
     unsigned long long key = ~0ull;          // first cell holding s_target (TRACE)
+    // direction word of this lane's row block at column c0 + j: dir[doff + j * stride]
+    const int64_t doff = (c0 - a.dir_col0) * a.dir_stride + (rb - a.dir_rb0);
 
     // Lane g works on column step - g.  Its code for the next step is the code
     // lane g - 1 holds now (the head reads it from the residue stream), so the
@@ -153,7 +155,9 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
                     ydiag = yt;
                     int hup = yt, F = ft;
                     int hprev = 0;
-                    uint32_t word = 0, hits = 0;
+                    uint32_t word = 0;
+                    int hs[TRACE ? R : 1];                // the column's H (trace)
+                    int cmax = 0;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const int t = dg + pent<ES>(pv, r);
@@ -166,9 +170,12 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
                             uint32_t code = h == 0 ? 0u : (h == t ? 1u : (h == e ? 2u : 3u));
                             code |= (Y[r] >= eo ? 4u : 0u) | (hup >= fo ? 8u : 0u);
                             word |= code << (4 * r);
-                            hits |= (h == s_target ? 1u : 0u) << r;
-                        }
-                        if (r & 1) {
+                            hs[r] = h;
+                            if (r & 1)
+                                cmax = imax3(cmax, hprev, h);
+                            else
+                                hprev = h;
+                        } else if (r & 1) {
                             S = imax3(S, hprev, h);
                             pin(S);
                         } else {
@@ -191,10 +198,18 @@ __device__ __forceinline__ void pair_tile(const PairArgs& a, int lane)
                         const int64_t col = c0 + j;
                         if (valid) {
                             if (a.dir)
-                                a.dir[(col - a.dir_col0) * a.dir_stride + (rb - a.dir_rb0)] = word;
-                            const int64_t row = row0 + (hits ? __builtin_ctz(hits) : 0);
-                            if (hits && key == ~0ull && col < a.n && row < a.m)
-                                key = ((unsigned long long)col << 32) | (unsigned long long)row;
+                                a.dir[doff + (int64_t)j * a.dir_stride] = word;
+                            // no H exceeds the pair's score: only a column whose
+                            // maximum is the score holds the end cell
+                            if (cmax == s_target) {
+                                uint32_t hits = 0;
+#pragma unroll
+                                for (int r = 0; r < R; ++r)
+                                    hits |= (hs[r] == s_target ? 1u : 0u) << r;
+                                const int64_t row = row0 + __builtin_ctz(hits);
+                                if (key == ~0ull && col < a.n && row < a.m)
+                                    key = ((unsigned long long)col << 32) | (unsigned long long)row;
+                            }
                         }
                     }
                 }
@@ -320,6 +335,8 @@ __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
     unsigned long long key = ~0ull;          // first cell holding s_target (TRACE)
     uint32_t* const dsink =
         reinterpret_cast<uint32_t*>(a.sink + (int64_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64);
+    // direction word of this lane's row block at column j: dir[doff + j * stride]
+    const int64_t doff = (int64_t)(rb - a.dir_rb0) - a.dir_col0 * a.dir_stride;
 
     // every lane of the wave inside [0, n) on every step: no per-column predicate
     const bool inner = !valid || (j0 >= 0 && j0 + wc <= n);
@@ -394,7 +411,9 @@ __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
                         ydiag = yt;
                         int hup = yt, F = ft;
                         int hprev = 0;
-                        uint32_t word = 0, hits = 0;
+                        uint32_t word = 0;
+                        int hs[TRACE ? R : 1];            // the column's H (trace)
+                        int cmax = 0;
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const int t = dg + pent<ES>(pv, r);
@@ -407,9 +426,12 @@ __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
                                 uint32_t cc = h == 0 ? 0u : (h == t ? 1u : (h == e ? 2u : 3u));
                                 cc |= (Y[r] >= eo ? 4u : 0u) | (hup >= fo ? 8u : 0u);
                                 word |= cc << (4 * r);
-                                hits |= (h == s_target ? 1u : 0u) << r;
-                            }
-                            if (r & 1) {
+                                hs[r] = h;
+                                if (r & 1)
+                                    cmax = imax3(cmax, hprev, h);
+                                else
+                                    hprev = h;
+                            } else if (r & 1) {
                                 S = imax3(S, hprev, h);
                                 pin(S);
                             } else {
@@ -425,11 +447,18 @@ __device__ __forceinline__ void pair_skew_tile(const PairArgs& a, int lane)
                         const u32x2 v = {(unsigned)ybot, (unsigned)fbot};
                         __builtin_amdgcn_raw_buffer_store_b64(v, rows_out, put_bottom ? j * 8 : sink, 0, 0);
                         if constexpr (TRACE) {
-                            *((valid && a.dir) ? a.dir + ((int64_t)j - a.dir_col0) * a.dir_stride + (rb - a.dir_rb0)
-                                               : dsink) = word;
-                            const int64_t row = row0 + (hits ? __builtin_ctz(hits) : 0);
-                            const bool first = valid && hits && key == ~0ull && row < a.m;
-                            key = first ? ((unsigned long long)j << 32) | (unsigned long long)row : key;
+                            *((valid && a.dir) ? a.dir + (doff + (int64_t)j * a.dir_stride) : dsink) = word;
+                            // no H exceeds the pair's score: only a column whose
+                            // maximum is the score holds the end cell
+                            if (cmax == s_target) {
+                                uint32_t hits = 0;
+#pragma unroll
+                                for (int r = 0; r < R; ++r)
+                                    hits |= (hs[r] == s_target ? 1u : 0u) << r;
+                                const int64_t row = row0 + __builtin_ctz(hits);
+                                if (valid && key == ~0ull && row < a.m)
+                                    key = ((unsigned long long)j << 32) | (unsigned long long)row;
+                            }
                         }
                     }
                     code = cnext;
