@@ -242,11 +242,15 @@ def serving(args, capacity_gcups, mode):
     alone.stop()
     alone_cls = alone.stats_by_length(edges)
     mean_m = float(np.mean(qlens))
+    # load rho is the utilisation: arrival rate x the mean service time of a
+    # request served alone by the same server (options, slices, streams)
+    alone_mean_s = float(np.mean(alone.latencies))
+    serve_capacity = mean_m * w5.db.total / alone_mean_s / 1e9
     runs, checks = [], []
     for policy in args.serve_policies:
         arng = np.random.default_rng(78)          # the same arrival times for every policy
         for rho in args.serve_rho:
-            lam = rho * capacity_gcups * 1e9 / (mean_m * w5.db.total)
+            lam = rho / alone_mean_s
             arrivals = synth.poisson_arrivals(arng, lam, n)
             srv = Server(be, policy=policy, **srv_kw).start()
             futs = []
@@ -269,7 +273,10 @@ def serving(args, capacity_gcups, mode):
             print(f"[bench] serving {policy} rho={rho}: p50 {st['p50_s'] * 1e3:.1f} ms p99 {st['p99_s'] * 1e3:.1f} ms",
                   file=sys.stderr, flush=True)
             cls = srv.stats_by_length(edges)
+            offered = lam * mean_m * w5.db.total / 1e9
             runs.append({"policy": policy, "rho": rho, "rate_per_s": round(lam, 2), "requests": n,
+                         "offered_gcups": round(offered, 1),
+                         "offered_over_search_capacity": round(offered / capacity_gcups, 3),
                          "p50_ms": round(st["p50_s"] * 1e3, 2), "p99_ms": round(st["p99_s"] * 1e3, 2),
                          "sustained_gcups": round(st["sustained_gcups"], 1),
                          "mean_batch": round(st["mean_batch"], 2), "max_batch": st["max_batch"],
@@ -287,8 +294,11 @@ def serving(args, capacity_gcups, mode):
                   "sampled_requests": sum(c["requests"] for c in sp),
                   "sampled_scores": sum(c["scores"] for c in sp), "sample_mismatches": sum(c["mismatches"] for c in sp)}
     return {"workload": f"{w5.db.nseq} subjects ({w5.db.total} residues); {n} queries log-normal median 350 "
-                        "clamped 50-5000; Poisson arrivals at rho x single-query capacity",
+                        "clamped 50-5000; Poisson arrivals at utilisation rho (arrival rate x mean alone "
+                        "service time)",
             "capacity_gcups": round(capacity_gcups, 1),
+            "alone_mean_ms": round(alone_mean_s * 1e3, 2),
+            "alone_capacity_gcups": round(serve_capacity, 1),
             "server": {"slice_mcells": slice_mcells, "slice_ms": args.serve_slice_ms, "long_ms": args.serve_long_ms,
                        "long_depth": args.serve_long_depth, "lane_cells": args.serve_lane_cells,
                        "size_ratio": 4.0, "streams": 4, "max_batch": 16},
