@@ -541,9 +541,11 @@ __global__ void k_trace_reset(unsigned long long* end_key)
 // a WalkState, and the host supplies the block holding the next cell.
 //
 // One wavefront per walk call: the codes of a window of 64 columns x 128 rows
-// around the walk sit in LDS (each lane loads one column), every lane runs the
-// same walk on them (uniform control flow; lane 0 writes the operations), and
-// the wave reloads the window when the walk leaves it.
+// around the walk sit in LDS (each lane loads one column), and the wave
+// reloads the window when the walk leaves it.  The walk's state is uniform;
+// each pass takes the run of steps that continue in one direction (lane l
+// reads the l-th cell along it, a ballot finds where the run ends) and its
+// lanes write the run's operations.
 constexpr int kWinCols = 64, kWinWords = 16;   // 16 words of 8 rows = 128 rows
 
 __global__ void k_walk_init(const unsigned long long* __restrict__ end_key, const int32_t* __restrict__ score,

@@ -10,9 +10,10 @@
 // a buffer updated in place: bits 0-23 hold H - Go + Go, bits 24-47 F + Go,
 // bits 48-63 a tag, band + 1.  The head lane of the band below reads the word
 // of its column 16 steps ahead and, before using it, checks that the tag names
-// the band just above; tags are unique per band within a call (the buffer is
-// cleared first), so a word not yet written is never mistaken for one that
-// is.  The words are read and written with agent-scope coherent accesses
+// the band just above (each step its own word, or from 8 rows per lane on,
+// the 16 words of a block at once); tags are unique per band within a call
+// (the buffer is cleared first), so a word not yet written is never mistaken
+// for one that is.  The words are read and written with agent-scope coherent accesses
 // (relaxed atomics: no cache writeback or invalidate is needed, since every
 // word carries its own validity), so bands on different XCDs meet in memory.
 //
@@ -23,9 +24,10 @@
 // handoffs stay within one L2.  The bands advance at the pace of the
 // slowest one, so the launch places them evenly: workgroups of W waves (W / 4
 // per SIMD), one workgroup per CU (its LDS request keeps a second one off the
-// CU), each wave with a band profile of its own in LDS.  Every wait is bounded in time: a wave
-// that gives up sets the status word, the waves waiting behind it see it and
-// stop, and the score is then reported as -1 (k_pair_flow_finish).
+// CU), each wave with a band profile of its own in LDS.  Every wait is
+// bounded in time: a wave that gives up sets the status word, the waves
+// waiting behind it see it and stop, and the score is then reported as -1
+// (k_pair_flow_finish).
 //
 // The packing holds values in [0, 2^24): the host takes this pass only when
 // the largest possible score, max(SM) x min(m, n), is below 2^24 and the
