@@ -489,17 +489,18 @@ int sw_pair_score_static(const uint8_t* query, int64_t m, const uint8_t* subject
 
 /* ------------------------------------------------------------------ alignment of one pair
  *
- * The optional traceback after the score (paper Section 2.2: the alignment is
- * recovered from the matrix "if required"): the optimal local alignment of
+ * The optional traceback after the score (paper Section 2.2: the alignment
+ * itself can be recovered from the matrix when it is wanted): the optimal local alignment of
  * one pair, not only its score.  Two passes of the pair tiles (8 query rows
  * per lane, 64 lanes per band): the score, then the same cells again writing a
- * 4-bit direction code per cell and finding the end cell; one lane then walks
- * the codes back.  With whole-matrix codes both passes run the skewed tiles;
+ * 4-bit direction code per cell and finding the end cell; one wavefront then
+ * walks the codes back.  With whole-matrix codes both passes run the skewed tiles;
  * the passes of a blocked alignment run rectangular tiles (lane g on column
  * step - g of its chunk), whose checkpoint columns and blocks follow columns.  Beyond 2^35 cells (or with options.align_block) the score
  * pass also keeps checkpoint rows and columns at block edges, and the codes
- * are recomputed one block at a time along the walk; the alignment is the
- * same.  Tie-breaks (the paper gives none): the end is the first
+ * are recomputed block by block along the walk (the blocks above and to the
+ * left of the walk's block on two more streams beside it, where the walk
+ * usually goes next); the alignment is the same.  Tie-breaks (the paper gives none): the end is the first
  * cell holding the score in column-major order (smallest subject position,
  * then smallest query position); walking back, the diagonal is taken before E
  * before F, a gap is opened (from H) rather than extended when both give its
@@ -516,7 +517,7 @@ typedef struct sw_alignment {
 /* Workspace bytes sw_align_pair needs (0 on invalid input).  Whole-matrix
    direction codes (m * n <= 2^35 and options.align_block = 0) take half a
    byte per cell: about m * n / 2 bytes (14.6 GB for 162K x 172K).  Blocks of
-   side B take about 16 * m * n / B + B^2 / 2 bytes (2.8 GB for 1M x 1M with
+   side B take about 16 * m * n / B + 3 B^2 / 2 bytes (8.1 GB for 1M x 1M with
    B = 65536). */
 size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt);
 

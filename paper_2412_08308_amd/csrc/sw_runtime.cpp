@@ -2432,6 +2432,7 @@ bool align_blocked(int64_t m, int64_t n, const sw_options* opt)
 // the bound over every chunk width.
 struct AlignLayout {
     size_t ckpt_row = 0, ckpt_col = 0, chunk_max = 0, dir = 0, tail = 0, total = 0;
+    size_t dir_alt[2] = {0, 0}, set_alt[2] = {0, 0};     // blocks: the neighbours' codes and pair buffers
     int64_t row_stride = 0, col_stride = 0, n_ckrow = 0, n_ckcol = 0, gb = 1, gc = 1;
 };
 
@@ -2459,7 +2460,15 @@ AlignLayout align_layout(int64_t m, int64_t n, const sw_options* opt, const Pair
         A.ckpt_row = off; off += align_up(A.n_ckrow * A.row_stride * 8, 256);
         A.ckpt_col = off; off += align_up(A.n_ckcol * A.col_stride * 8, 256);
         A.chunk_max = off; off += align_up(nchunks * 4, 256);
-        A.dir = off; off += align_up(A.gb * 64 * blk_cols * 4, 256);
+        const size_t dsz = align_up(A.gb * 64 * blk_cols * 4, 256);
+        A.dir = off; off += dsz;
+        // the two neighbour blocks computed beside the walk's block: their
+        // codes and a set of pair buffers each
+        const size_t setsz = align_up(pair_layout(m, n, p, p ? p->wc : wide).total, 256);
+        for (int k = 0; k < 2; ++k) {
+            A.dir_alt[k] = off; off += dsz;
+            A.set_alt[k] = off; off += setsz;
+        }
     }
     A.tail = off;                 // end key, spare key, walk state
     off += 512;
@@ -2531,21 +2540,97 @@ int align_blocks(const PairPlanC& p, const PairLayout& L, const AlignLayout& A, 
     HIPCHK(hipMemcpyAsync(&st, walk, sizeof st, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     a.end_key = spare_key;        // block passes look for no end cell
-    a.dir = dir;
+    // The walk leaves a block through its top or left edge, so the next block
+    // is usually the one above or the one to the left.  A round computes the
+    // codes of the walk's block (up to its cell) and, on two more streams, of
+    // those two neighbours (the one above up to the walk's column, the one to
+    // the left up to its row): the device runs the three block passes at once,
+    // and a walk that enters a neighbour goes on there without a new round.
+    struct Region {
+        PairArgs a;
+        uint32_t* dir = nullptr;
+        bool ok = false;
+        int64_t kb = 0, kc = 0, b_org = 0, b_hi = 0, c_org = 0, c_hi = 0;
+    };
+    Region reg[3];
+    reg[0].a = a;
+    reg[0].dir = dir;
+    for (int k = 0; k < 2; ++k) {
+        uint8_t* base = x + A.set_alt[k];
+        reg[k + 1].a = a;
+        reg[k + 1].a.rowbuf = reinterpret_cast<int2*>(base + L.rowbuf);
+        reg[k + 1].a.colbuf = reinterpret_cast<int2*>(base + L.colbuf);
+        reg[k + 1].a.corner = reinterpret_cast<int32_t*>(base + L.corner);
+        reg[k + 1].a.carry = reinterpret_cast<int4*>(base + L.carry);
+        reg[k + 1].a.sink = base + L.sink;
+        reg[k + 1].dir = reinterpret_cast<uint32_t*>(x + A.dir_alt[k]);
+    }
+    struct Side {                 // the neighbours' streams (default priority) and events
+        hipStream_t s[2] = {nullptr, nullptr};
+        hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+        ~Side()
+        {
+            for (hipStream_t hs : s) if (hs) (void)hipStreamDestroy(hs);
+            for (hipEvent_t he : e) if (he) (void)hipEventDestroy(he);
+        }
+    } side;
+    for (auto& hs : side.s) HIPCHK(hipStreamCreateWithFlags(&hs, hipStreamNonBlocking));
+    for (auto& he : side.e) HIPCHK(hipEventCreateWithFlags(&he, hipEventDisableTiming));
+    auto enqueue = [&](Region& r, hipStream_t s) -> int {
+        PairArgs& ra = r.a;
+        ra.b_org = (int32_t)r.b_org;
+        ra.top_ckpt = r.kb > 0 ? ckrow + (r.kb - 1) * A.row_stride : nullptr;
+        ra.dir = r.dir;
+        ra.dir_col0 = r.c_org * p.wc;
+        ra.dir_rb0 = (int32_t)(r.b_org * p.K);
+        ra.dir_stride = (r.b_hi - r.b_org + 1) * p.K;
+        HIPCHK(launch_block_init(ra, r.kb, r.kc, r.b_hi, r.c_org, r.c_hi, s));
+        return pair_diagonals(ra, PairPass::kTrace, 8, elem, r.b_org, r.b_hi, r.c_org, r.c_hi, s);
+    };
     while (!st.done) {
         const int64_t row = st.i - 1, col = st.j - 1;
         const int64_t kb = row / (A.gb * kBandRows), kc = col / (A.gc * p.wc);
-        const int64_t b_org = kb * A.gb, b_hi = row / kBandRows, c_org = kc * A.gc, c_hi = col / p.wc;
-        a.b_org = (int32_t)b_org;
-        a.top_ckpt = kb > 0 ? ckrow + (kb - 1) * A.row_stride : nullptr;
-        a.dir_col0 = c_org * p.wc;
-        a.dir_rb0 = (int32_t)(b_org * p.K);
-        a.dir_stride = (b_hi - b_org + 1) * p.K;
-        HIPCHK(launch_block_init(a, kb, kc, b_hi, c_org, c_hi, stream));
-        rc = pair_diagonals(a, PairPass::kTrace, 8, elem, b_org, b_hi, c_org, c_hi, stream);
-        if (rc) return rc;
-        HIPCHK(launch_walk(dir, a.dir_stride, b_org * kBandRows, c_org * p.wc, (b_hi + 1) * kBandRows,
-                           (c_hi + 1) * p.wc, walk, ops, m + n, stream));
+        const int64_t bb = row / kBandRows, cc = col / p.wc;
+        int use = -1;
+        for (int k = 0; k < 3; ++k) {
+            const Region& r = reg[k];
+            if (r.ok && r.kb == kb && r.kc == kc && bb >= r.b_org && bb <= r.b_hi && cc >= r.c_org && cc <= r.c_hi)
+                use = k;
+        }
+        if (use < 0) {
+            Region& cur = reg[0];
+            cur.ok = true;
+            cur.kb = kb; cur.kc = kc;
+            cur.b_org = kb * A.gb; cur.b_hi = bb;
+            cur.c_org = kc * A.gc; cur.c_hi = cc;
+            Region& up = reg[1];
+            up.ok = kb > 0;
+            up.kb = kb - 1; up.kc = kc;
+            up.b_org = (kb - 1) * A.gb; up.b_hi = kb * A.gb - 1;
+            up.c_org = cur.c_org; up.c_hi = cc;
+            Region& left = reg[2];
+            left.ok = kc > 0;
+            left.kb = kb; left.kc = kc - 1;
+            left.b_org = cur.b_org; left.b_hi = bb;
+            left.c_org = (kc - 1) * A.gc; left.c_hi = kc * A.gc - 1;
+            HIPCHK(hipEventRecord(side.e[0], stream));
+            for (int k = 0; k < 2; ++k) {
+                if (!reg[k + 1].ok) continue;
+                HIPCHK(hipStreamWaitEvent(side.s[k], side.e[0], 0));
+                rc = enqueue(reg[k + 1], side.s[k]);
+                if (rc) return rc;
+                HIPCHK(hipEventRecord(side.e[k + 1], side.s[k]));
+            }
+            rc = enqueue(cur, stream);
+            if (rc) return rc;
+            for (int k = 0; k < 2; ++k)
+                if (reg[k + 1].ok)
+                    HIPCHK(hipStreamWaitEvent(stream, side.e[k + 1], 0));
+            use = 0;
+        }
+        const Region& r = reg[use];
+        HIPCHK(launch_walk(r.dir, r.a.dir_stride, r.b_org * kBandRows, r.c_org * p.wc, (r.b_hi + 1) * kBandRows,
+                           (r.c_hi + 1) * p.wc, walk, ops, m + n, stream));
         HIPCHK(hipMemcpyAsync(&st, walk, sizeof st, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         if (!st.done && st.i - 1 == row && st.j - 1 == col)
