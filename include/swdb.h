@@ -498,9 +498,9 @@ int sw_pair_score_static(const uint8_t* query, int64_t m, const uint8_t* subject
  * the passes of a blocked alignment run rectangular tiles (lane g on column
  * step - g of its chunk), whose checkpoint columns and blocks follow columns.  Beyond 2^35 cells (or with options.align_block) the score
  * pass also keeps checkpoint rows and columns at block edges, and the codes
- * are recomputed block by block along the walk (the blocks above and to the
- * left of the walk's block on two more streams beside it, where the walk
- * usually goes next); the alignment is the same.  Tie-breaks (the paper gives none): the end is the first
+ * are recomputed block by block along the walk (the blocks above, to the
+ * left and above-left of the walk's block on three more streams beside it,
+ * where the walk usually goes next); the alignment is the same.  Tie-breaks (the paper gives none): the end is the first
  * cell holding the score in column-major order (smallest subject position,
  * then smallest query position); walking back, the diagonal is taken before E
  * before F, a gap is opened (from H) rather than extended when both give its
@@ -517,7 +517,7 @@ typedef struct sw_alignment {
 /* Workspace bytes sw_align_pair needs (0 on invalid input).  Whole-matrix
    direction codes (m * n <= 2^35 and options.align_block = 0) take half a
    byte per cell: about m * n / 2 bytes (14.6 GB for 162K x 172K).  Blocks of
-   side B take about 16 * m * n / B + 3 B^2 / 2 bytes (8.1 GB for 1M x 1M with
+   side B take about 16 * m * n / B + 2 B^2 bytes (10.8 GB for 1M x 1M with
    B = 65536). */
 size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt);
 

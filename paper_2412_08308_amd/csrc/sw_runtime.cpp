@@ -2432,7 +2432,7 @@ bool align_blocked(int64_t m, int64_t n, const sw_options* opt)
 // the bound over every chunk width.
 struct AlignLayout {
     size_t ckpt_row = 0, ckpt_col = 0, chunk_max = 0, dir = 0, tail = 0, total = 0;
-    size_t dir_alt[2] = {0, 0}, set_alt[2] = {0, 0};     // blocks: the neighbours' codes and pair buffers
+    size_t dir_alt[3] = {0, 0, 0}, set_alt[3] = {0, 0, 0};   // blocks: the neighbours' codes and pair buffers
     int64_t row_stride = 0, col_stride = 0, n_ckrow = 0, n_ckcol = 0, gb = 1, gc = 1;
 };
 
@@ -2462,10 +2462,10 @@ AlignLayout align_layout(int64_t m, int64_t n, const sw_options* opt, const Pair
         A.chunk_max = off; off += align_up(nchunks * 4, 256);
         const size_t dsz = align_up(A.gb * 64 * blk_cols * 4, 256);
         A.dir = off; off += dsz;
-        // the two neighbour blocks computed beside the walk's block: their
+        // the three neighbour blocks computed beside the walk's block: their
         // codes and a set of pair buffers each
         const size_t setsz = align_up(pair_layout(m, n, p, p ? p->wc : wide).total, 256);
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < 3; ++k) {
             A.dir_alt[k] = off; off += dsz;
             A.set_alt[k] = off; off += setsz;
         }
@@ -2541,21 +2541,23 @@ int align_blocks(const PairPlanC& p, const PairLayout& L, const AlignLayout& A, 
     HIPCHK(hipStreamSynchronize(stream));
     a.end_key = spare_key;        // block passes look for no end cell
     // The walk leaves a block through its top or left edge, so the next block
-    // is usually the one above or the one to the left.  A round computes the
-    // codes of the walk's block (up to its cell) and, on two more streams, of
-    // those two neighbours (the one above up to the walk's column, the one to
-    // the left up to its row): the device runs the three block passes at once,
-    // and a walk that enters a neighbour goes on there without a new round.
+    // is usually the one above or the one to the left, and the one after that
+    // often the one above and to the left.  A round computes the codes of the
+    // walk's block (up to its cell) and, on three more streams, of those
+    // three neighbours (the one above up to the walk's column, the one to the
+    // left up to its row, the diagonal one whole): the device runs the four
+    // block passes at once, and a walk that enters a neighbour goes on there
+    // without a new round.
     struct Region {
         PairArgs a;
         uint32_t* dir = nullptr;
         bool ok = false;
         int64_t kb = 0, kc = 0, b_org = 0, b_hi = 0, c_org = 0, c_hi = 0;
     };
-    Region reg[3];
+    Region reg[4];
     reg[0].a = a;
     reg[0].dir = dir;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
         uint8_t* base = x + A.set_alt[k];
         reg[k + 1].a = a;
         reg[k + 1].a.rowbuf = reinterpret_cast<int2*>(base + L.rowbuf);
@@ -2566,8 +2568,8 @@ int align_blocks(const PairPlanC& p, const PairLayout& L, const AlignLayout& A, 
         reg[k + 1].dir = reinterpret_cast<uint32_t*>(x + A.dir_alt[k]);
     }
     struct Side {                 // the neighbours' streams (default priority) and events
-        hipStream_t s[2] = {nullptr, nullptr};
-        hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+        hipStream_t s[3] = {nullptr, nullptr, nullptr};
+        hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
         ~Side()
         {
             for (hipStream_t hs : s) if (hs) (void)hipStreamDestroy(hs);
@@ -2592,7 +2594,7 @@ int align_blocks(const PairPlanC& p, const PairLayout& L, const AlignLayout& A, 
         const int64_t kb = row / (A.gb * kBandRows), kc = col / (A.gc * p.wc);
         const int64_t bb = row / kBandRows, cc = col / p.wc;
         int use = -1;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             const Region& r = reg[k];
             if (r.ok && r.kb == kb && r.kc == kc && bb >= r.b_org && bb <= r.b_hi && cc >= r.c_org && cc <= r.c_hi)
                 use = k;
@@ -2613,8 +2615,13 @@ int align_blocks(const PairPlanC& p, const PairLayout& L, const AlignLayout& A, 
             left.kb = kb; left.kc = kc - 1;
             left.b_org = cur.b_org; left.b_hi = bb;
             left.c_org = (kc - 1) * A.gc; left.c_hi = kc * A.gc - 1;
+            Region& diag = reg[3];
+            diag.ok = kb > 0 && kc > 0;
+            diag.kb = kb - 1; diag.kc = kc - 1;
+            diag.b_org = up.b_org; diag.b_hi = up.b_hi;
+            diag.c_org = left.c_org; diag.c_hi = left.c_hi;
             HIPCHK(hipEventRecord(side.e[0], stream));
-            for (int k = 0; k < 2; ++k) {
+            for (int k = 0; k < 3; ++k) {
                 if (!reg[k + 1].ok) continue;
                 HIPCHK(hipStreamWaitEvent(side.s[k], side.e[0], 0));
                 rc = enqueue(reg[k + 1], side.s[k]);
@@ -2623,7 +2630,7 @@ int align_blocks(const PairPlanC& p, const PairLayout& L, const AlignLayout& A, 
             }
             rc = enqueue(cur, stream);
             if (rc) return rc;
-            for (int k = 0; k < 2; ++k)
+            for (int k = 0; k < 3; ++k)
                 if (reg[k + 1].ok)
                     HIPCHK(hipStreamWaitEvent(stream, side.e[k + 1], 0));
             use = 0;

@@ -186,9 +186,9 @@ def _a256(x):
 def _align_extra(m, n, p, block, o):
     """Workspace past the pair buffers for the alignment schedule p: whole-
     matrix direction words, or checkpoint rows / columns, chunk maxima and the
-    direction words of three blocks (8 rows x 64 lanes per band; the walk's
-    block and the two neighbours computed beside it, each neighbour with a set
-    of pair buffers, here at their bound); then the end key and walk state."""
+    direction words of four blocks (8 rows x 64 lanes per band; the walk's
+    block and the three neighbours computed beside it, each neighbour with a
+    set of pair buffers, here at their bound); then the end key and walk state."""
     nb, nc, wc = p["bands"], p["chunks"], p["cols"]
     cols = nc * wc
     if block == 0 and m * n <= 1 << 35:
@@ -197,7 +197,7 @@ def _align_extra(m, n, p, block, o):
     gb, gc = -(-B // 512), -(-B // wc)
     dirs = _a256(gb * 64 * gc * wc * 4)
     return (_a256((nb - 1) // gb * cols * 8) + _a256((nc - 1) // gc * nb * 512 * 8) + _a256(nc * 4)
-            + 3 * dirs + 2 * _a256(swdb.pair_workspace_bytes(m, n, o)) + 512)
+            + 4 * dirs + 3 * _a256(swdb.pair_workspace_bytes(m, n, o)) + 512)
 
 
 @pytest.mark.parametrize("m,n", [(3000, 4000), (162_000, 172_000), (1_000_000, 1_000_000), (7_000_000, 5_000_000)])
@@ -217,10 +217,10 @@ def test_align_workspace_covers_every_tiling(m, n):
 
 def test_align_workspace_blocks_beyond_whole_matrix_codes():
     # whole-matrix codes: half a byte per cell; blocks: checkpoints and the
-    # codes of three 65,536 x 65,536 blocks (2 GiB each), far below the
+    # codes of four 65,536 x 65,536 blocks (2 GiB each), far below the
     # half-byte-per-cell codes of the whole matrix (500 GB at 1M x 1M)
     assert swdb.align_workspace_bytes(162_000, 172_000) > 162_000 * 172_000 // 2
-    assert swdb.align_workspace_bytes(1_000_000, 1_000_000) < 9 << 30
+    assert swdb.align_workspace_bytes(1_000_000, 1_000_000) < 11 << 30
     assert swdb.align_workspace_bytes(7_000_000, 5_000_000) < 24 << 30
     small = swdb.align_workspace_bytes(3000, 4000, swdb.options(align_block=512))
     assert small < swdb.align_workspace_bytes(3000, 4000)
