@@ -535,7 +535,10 @@ size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt);
  *                   of them are written
  * Asynchronous on `stream` with whole-matrix codes; with blocks the call
  * reads the walk's position after each block and returns with the stream
- * drained.  Returns SW_EINVAL, SW_ENOMEM or SW_EHIP.
+ * drained.  With whole-matrix codes the score may come from the pipelined
+ * pass (as in sw_pair_score); out->score = -1 (and no operations) then means
+ * that a wait of that pass gave up, an error.  Returns SW_EINVAL, SW_ENOMEM
+ * or SW_EHIP.
  */
 int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64_t n,
                   const int32_t* subst_matrix, int32_t gap_open, int32_t gap_extend,

@@ -436,6 +436,8 @@ def align_pair(query, subject, matrix, gap_open: int, gap_extend: int, opt: Opti
     a = Alignment.from_buffer_copy(out.cpu().numpy().tobytes())
     if a.n_ops < 0:
         raise SwdbError(-3, "sw_align_pair", "inconsistent direction codes")
+    if a.score < 0:
+        raise SwdbError(-3, "sw_align_pair", "a wait of the pipelined score pass gave up")
     return {"score": a.score, "q_begin": a.q_begin, "s_begin": a.s_begin, "q_end": a.q_end, "s_end": a.s_end,
             "ops": ops[:a.n_ops].cpu().numpy().tobytes().decode() if a.n_ops > 0 else ""}
 

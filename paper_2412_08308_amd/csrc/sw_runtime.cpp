@@ -2756,7 +2756,19 @@ int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     rc = device_cu(&cu);
     if (rc) return rc;
     const PairPlanC p = align_plan(m, n, cu, opt);
-    const PairLayout L = pair_layout(m, n, &p, p.wc);
+    const int elem = (fit == kFitS8 || fit == kFitU8) ? 1 : 2;
+    // With whole-matrix codes the score may come from the pipelined pass
+    // when the planner takes it for the pair; its buffers and the tiles' then
+    // sit in the layout bound for every schedule, which holds both.
+    PairPlanC sp{};
+    if (!align_blocked(m, n, opt) && m > 0 && n > 0) {
+        int lds = kLdsPerCU, sm_max = 0;
+        rc = device_lds(&lds);
+        if (rc) return rc;
+        for (int i = 0; i < kAlpha * kAlpha; ++i) sm_max = std::max(sm_max, (int)sm[i]);
+        sp = pair_plan(m, n, cu, opt, false, sm_max, elem, lds);
+    }
+    const PairLayout L = sp.flow ? pair_layout(m, n, nullptr, pair_wc_max(opt)) : pair_layout(m, n, &p, p.wc);
     const size_t x_off = align_up(L.total, 256);
     const AlignLayout A = align_layout(m, n, opt, &p);
     if (x_off + A.total > need)
@@ -2764,15 +2776,35 @@ int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     uint8_t* w = static_cast<uint8_t*>(ws);
     uint8_t* x = w + x_off;
     auto* o = reinterpret_cast<AlignOut*>(out);
-    const int elem = (fit == kFitS8 || fit == kFitU8) ? 1 : 2;
     if (align_blocked(m, n, opt))
         return align_blocks(p, L, A, w, x, query, m, subject, n, sm, go, ge, elem, o, ops, opt, stream);
     auto* dir = reinterpret_cast<uint32_t*>(x + A.dir);
     auto* end_key = reinterpret_cast<unsigned long long*>(x + A.tail);
     auto* walk = reinterpret_cast<WalkState*>(x + A.tail + 256);
-    rc = pair_enqueue(p, L, w, query, m, subject, n, sm, go, ge, elem, &o->score, dir, end_key,
-                      opt ? opt->ev_search_begin : nullptr, opt ? opt->ev_search_end : nullptr, stream);
-    if (rc) return rc;
+    if (sp.flow) {
+        // the score (-1 if a wait of the pass gave up), then the code pass
+        // over the alignment's tiles; their setup clears a spare word, not
+        // the score
+        rc = pair_enqueue(sp, L, w, query, m, subject, n, sm, go, ge, elem, &o->score, nullptr, nullptr,
+                          opt ? opt->ev_search_begin : nullptr, nullptr, stream);
+        if (rc) return rc;
+        PairArgs a{};
+        bool empty = false;
+        rc = pair_setup(p, L, w, query, m, subject, n, sm, go, ge, elem, reinterpret_cast<int32_t*>(x + A.tail + 64),
+                        stream, a, empty);
+        if (rc) return rc;
+        a.score = &o->score;
+        a.dir = dir;
+        a.end_key = end_key;
+        HIPCHK(launch_trace_reset(end_key, stream));
+        rc = pair_skew_diagonals(a, p, elem, stream, true);
+        if (rc) return rc;
+        if (opt && opt->ev_search_end) HIPCHK(hipEventRecord(opt->ev_search_end, stream));
+    } else {
+        rc = pair_enqueue(p, L, w, query, m, subject, n, sm, go, ge, elem, &o->score, dir, end_key,
+                          opt ? opt->ev_search_begin : nullptr, opt ? opt->ev_search_end : nullptr, stream);
+        if (rc) return rc;
+    }
     if (m == 0 || n == 0) {
         HIPCHK(launch_trace_reset(end_key, stream));
     }

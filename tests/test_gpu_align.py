@@ -30,6 +30,24 @@ def test_dna_alignments(m, n):
     assert _gpu_align(a, b, sm, go, ge) == oracle.align(a, b, sm, go, ge)
 
 
+@pytest.mark.parametrize("mode", ["tiles", "flow"])
+def test_score_pass_either_way(mode):
+    """With whole-matrix codes the score comes from the tile pass or the
+    pipelined pass (the planner's choice, forced here), the codes from the
+    tiles: the alignment is the oracle's either way."""
+    sm, go, ge = DNA
+    for m, n, seed in [(2000, 2300, 5), (700, 5000, 6), (4100, 900, 7)]:
+        a, b = synth.dna_pair(m, n, seed=seed, identity=0.8, indel_rate=0.02)
+        announce(f"align m={m} n={n} score pass {mode}")
+        assert _gpu_align(a, b, sm, go, ge, pair_mode=mode) == oracle.align(a, b, sm, go, ge)
+    rng = np.random.default_rng(61)
+    psm = synth.blosum_style_matrix()
+    a = synth.residues(rng, 900)
+    b = np.concatenate([synth.residues(rng, 200), synth.mutate(rng, a[100:700], 0.6), synth.residues(rng, 150)])
+    announce(f"align protein score pass {mode}")
+    assert _gpu_align(a, b, psm, 10, 2, pair_mode=mode) == oracle.align(a, b, psm, 10, 2)
+
+
 @pytest.mark.parametrize("go,ge", [(10, 2), (0, 3), (4, 4), (120, 1)])
 def test_protein_alignments(go, ge):
     # (120, 1): 16-bit profile entries; the others 8-bit
