@@ -491,10 +491,11 @@ int sw_pair_score_static(const uint8_t* query, int64_t m, const uint8_t* subject
  *
  * The optional traceback after the score (paper Section 2.2: the alignment
  * itself can be recovered from the matrix when it is wanted): the optimal local alignment of
- * one pair, not only its score.  Two passes of the pair tiles (8 query rows
- * per lane, 64 lanes per band): the score, then the same cells again writing a
- * 4-bit direction code per cell and finding the end cell; one wavefront then
- * walks the codes back.  With whole-matrix codes both passes run the skewed tiles;
+ * one pair, not only its score.  Two passes: the score (with whole-matrix
+ * codes from the pipelined pass when the planner picks it, else the pair
+ * tiles), then the pair tiles (8 query rows per lane, 64 lanes per band)
+ * writing a 4-bit direction code per cell and finding the end cell; one
+ * wavefront then walks the codes back.  With whole-matrix codes both passes run the skewed tiles;
  * the passes of a blocked alignment run rectangular tiles (lane g on column
  * step - g of its chunk), whose checkpoint columns and blocks follow columns.  Beyond 2^35 cells (or with options.align_block) the score
  * pass also keeps checkpoint rows and columns at block edges, and the codes
