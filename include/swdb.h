@@ -490,18 +490,20 @@ int sw_pair_score_static(const uint8_t* query, int64_t m, const uint8_t* subject
 /* ------------------------------------------------------------------ alignment of one pair
  *
  * The optional traceback after the score (paper Section 2.2: the alignment
- * itself can be recovered from the matrix when it is wanted): the optimal local alignment of
- * one pair, not only its score.  Two passes: the score (with whole-matrix
+ * itself can be recovered from the matrix when it is wanted): the optimal
+ * local alignment of one pair, not only its score.  Two passes: the score (with whole-matrix
  * codes from the pipelined pass when the planner picks it, else the pair
  * tiles), then the pair tiles (8 query rows per lane, 64 lanes per band)
  * writing a 4-bit direction code per cell and finding the end cell; one
- * wavefront then walks the codes back.  With whole-matrix codes both passes run the skewed tiles;
- * the passes of a blocked alignment run rectangular tiles (lane g on column
- * step - g of its chunk), whose checkpoint columns and blocks follow columns.  Beyond 2^35 cells (or with options.align_block) the score
- * pass also keeps checkpoint rows and columns at block edges, and the codes
- * are recomputed block by block along the walk (the blocks above, to the
- * left and above-left of the walk's block on three more streams beside it,
- * where the walk usually goes next); the alignment is the same.  Tie-breaks (the paper gives none): the end is the first
+ * wavefront then walks the codes back.  With whole-matrix codes the tile
+ * passes run skewed tiles; the passes of a blocked alignment run rectangular
+ * tiles (lane g on column step - g of its chunk), whose checkpoint columns
+ * and blocks follow columns.  Beyond 2^35 cells (or with options.align_block)
+ * the score pass also keeps checkpoint rows and columns at block edges, and
+ * the codes are recomputed block by block along the walk (the blocks above,
+ * to the left and above-left of the walk's block on three more streams beside
+ * it, where the walk usually goes next); the alignment is the same.
+ * Tie-breaks (the paper gives none): the end is the first
  * cell holding the score in column-major order (smallest subject position,
  * then smallest query position); walking back, the diagonal is taken before E
  * before F, a gap is opened (from H) rather than extended when both give its
