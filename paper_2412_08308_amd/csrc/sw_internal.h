@@ -194,6 +194,11 @@ struct FlowArgs {
     int32_t waves;               // wavefronts of the launch
     int32_t go, ge;
     uint64_t timeout;            // s_memrealtime ticks a wait may last
+    // direction-code pass (null dir: the score pass)
+    uint32_t* dir;               // [column * dir_stride + row block] 4-bit codes of 8 rows
+    unsigned long long* end_key; // first cell holding the score, (column << 32) | row (atomic minimum)
+    int64_t dir_stride;          // row blocks per column
+    int64_t m;                   // query length (rows past it hold no end cell)
 };
 // Bytes per (code, lane) entry group of a band's profile staged in LDS by the
 // flow pass: the lane's R entries rounded up to a power of two (aligned reads).
@@ -210,7 +215,8 @@ constexpr int kFlowBlockwiseRows = 8;
 // The flow pass on `grid` workgroups of `wpg` waves (a.waves = grid * wpg),
 // each asking for `lds` bytes of LDS (at least wpg band profiles).
 hipError_t launch_pair_flow(const FlowArgs& a, int rows, int elem, int wpg, int grid, int lds, hipStream_t st);
-int flow_occupancy(int rows, int elem, int wpg, int lds);   // resident workgroups per CU (0 on error)
+// resident workgroups per CU (0 on error); trace: the direction-code pass
+int flow_occupancy(int rows, int elem, int wpg, int lds, bool trace = false);
 __host__ __device__ constexpr int flow_lds_bytes(int rows, int elem)   // LDS of one wave's band profile
 {
     return kCodes * kWave * flow_lds_stride(rows, elem);

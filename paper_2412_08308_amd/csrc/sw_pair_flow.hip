@@ -142,9 +142,14 @@ __device__ __forceinline__ uint32_t min3_u32(uint32_t a, uint32_t b, uint32_t c)
     return __builtin_elementwise_min(__builtin_elementwise_min(a, b), c);
 }
 
-template <int R, int ES>
+// TRACE: the direction-code pass of an alignment with whole-matrix codes (8
+// rows per lane, the tile passes' row blocks): every cell's 4-bit code into
+// dir[column * dir_stride + row block] and the first cell holding the score,
+// column-major, into end_key, exactly as the code tiles do; no score.
+template <int R, int ES, bool TRACE = false>
 __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int lane, uint32_t lds0)
 {
+    static_assert(!TRACE || R == 8, "direction words hold 8 rows");
     constexpr uint32_t CS = code_stride(R, ES);
     constexpr uint32_t BS = kCodes * CS;
     constexpr int NW = (R * ES + 3) / 4;
@@ -168,6 +173,8 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
     const __amdgpu_buffer_rsrc_t rows_in = rows_out;
     int S = 0;
     int failed = 0;
+    const int s_target = TRACE ? *a.score : 0;
+    unsigned long long key = ~0ull;          // first cell holding s_target (TRACE)
     for (int b = wave_id; b < a.nb && !failed; b += a.waves) {
         const int rb = b * kWave + lane;
         // the band's profile in this wave's LDS region: entry group (code c,
@@ -283,18 +290,32 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
                         ydiag = yt;
                         int hup = yt, F = ft;
                         int hprev = 0;
+                        uint32_t word = 0;
+                        int hs[TRACE ? R : 1];            // the column's H (trace)
+                        int cmax = 0;
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const int tt = dg + flow_entry<ES>(pv, r);      // H[i-1][j-1] + s
-                            const int e = imax3(E[r] - ge, Y[r], 0);        // E (clamped at 0)
-                            F = max(F - ge, hup);                           // F
+                            const int eo = E[r] - ge;
+                            const int e = imax3(eo, Y[r], 0);               // E (clamped at 0)
+                            const int fo = F - ge;
+                            F = max(fo, hup);                               // F
                             const int h = imax3(tt, e, F);                  // H
-                            if (r & 1) {
+                            if constexpr (TRACE) {
+                                uint32_t cc = h == 0 ? 0u : (h == tt ? 1u : (h == e ? 2u : 3u));
+                                cc |= (Y[r] >= eo ? 4u : 0u) | (hup >= fo ? 8u : 0u);
+                                word |= cc << (4 * r);
+                                hs[r] = h;
+                                if (r & 1)
+                                    cmax = max3_i32(cmax, hprev, h);
+                                else
+                                    hprev = h;
+                            } else if (r & 1) {
                                 S = max3_i32(S, hprev, h);
                             } else {
                                 hprev = h;
                             }
-                            if ((R & 1) && r == R - 1)
+                            if (!TRACE && (R & 1) && r == R - 1)
                                 S = max(S, h);
                             dg = Y[r];
                             hup = h - go;
@@ -303,6 +324,21 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
                         }
                         ybot = hup;
                         fbot = F;
+                        if constexpr (TRACE) {
+                            a.dir[(int64_t)j * a.dir_stride + rb] = word;
+                            // no H exceeds the pair's score: only a column whose
+                            // maximum is the score holds the end cell
+                            if (cmax == s_target) {
+                                uint32_t hits = 0;
+#pragma unroll
+                                for (int r = 0; r < R; ++r)
+                                    hits |= (hs[r] == s_target ? 1u : 0u) << r;
+                                const int64_t row = (int64_t)rb * R + __builtin_ctz(hits);
+                                const unsigned long long k2 = ((unsigned long long)j << 32) | (unsigned long long)row;
+                                if (row < a.m && k2 < key)
+                                    key = k2;
+                            }
+                        }
                     }
                     const uint32_t yv = (uint32_t)(ybot + go), fv = (uint32_t)(fbot + go);
                     const u32x2 v = {(yv & 0xffffffu) | (fv << 24), ((fv >> 8) & 0xffffu) | wtag};
@@ -340,6 +376,16 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
         else
             run_band(std::integral_constant<bool, false>{});
     }
+    if constexpr (TRACE) {
+        // first hit of the wave (column, then row), into the pair's end key
+        for (int k = 32; k >= 1; k >>= 1) {
+            const unsigned long long o = __shfl_xor(key, k);
+            key = o < key ? o : key;
+        }
+        if (lane == 0 && key != ~0ull)
+            atomicMin(a.end_key, key);
+        return;
+    }
     for (int k = 32; k >= 1; k >>= 1)
         S = max(S, __shfl_xor(S, k));
     if (lane == 0 && S > 0)
@@ -349,7 +395,7 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
 // Up to 6 rows per lane the state fits 128 registers (workgroups of up to 16
 // waves, four per SIMD); more rows take up to 256 (up to 8 waves, two per
 // SIMD).  Wave w of workgroup g is wave g * W + w of the launch.
-template <int R, int ES>
+template <int R, int ES, bool TRACE = false>
 __global__ void __launch_bounds__(R <= 6 ? 1024 : 512) __attribute__((amdgpu_waves_per_eu(R <= 6 ? 4 : 2)))
 k_pair_flow(FlowArgs a)
 {
@@ -362,7 +408,7 @@ k_pair_flow(FlowArgs a)
     const int G = (int)gridDim.x, g = (int)blockIdx.x;
     const int x = g & (kXcds - 1), per = G / kXcds, extra = G % kXcds;
     const int group = x * per + min(x, extra) + g / kXcds;
-    pair_flow<R, ES>(a, group * wpg + w, (int)(threadIdx.x & 63), (uint32_t)(w * flow_lds_bytes(R, ES)));
+    pair_flow<R, ES, TRACE>(a, group * wpg + w, (int)(threadIdx.x & 63), (uint32_t)(w * flow_lds_bytes(R, ES)));
 }
 
 // Clear the handoff words and the status word before a flow pass.
@@ -382,9 +428,15 @@ __global__ void k_pair_flow_finish(const int32_t* status, int32_t* score)
         *score = -1;
 }
 
-// The kernel of (rows, elem); null for a shape it is not built for.
-static const void* flow_kernel(int rows, int elem)
+// The kernel of (rows, elem), or of the direction-code pass (8 rows per
+// lane); null for a shape it is not built for.
+static const void* flow_kernel(int rows, int elem, bool trace = false)
 {
+    if (trace) {
+        if (rows != 8) return nullptr;
+        return elem == 1 ? reinterpret_cast<const void*>(&k_pair_flow<8, 1, true>)
+                         : reinterpret_cast<const void*>(&k_pair_flow<8, 2, true>);
+    }
     switch (rows * 4 + elem) {
     case 4 * 4 + 1: return reinterpret_cast<const void*>(&k_pair_flow<4, 1>);
     case 4 * 4 + 2: return reinterpret_cast<const void*>(&k_pair_flow<4, 2>);
@@ -404,7 +456,7 @@ static const void* flow_kernel(int rows, int elem)
 
 hipError_t launch_pair_flow(const FlowArgs& a, int rows, int elem, int wpg, int grid, int lds, hipStream_t st)
 {
-    const void* k = flow_kernel(rows, elem);
+    const void* k = flow_kernel(rows, elem, a.dir != nullptr);
     if (!k || wpg < 1 || wpg > (rows <= 6 ? 16 : 8) || grid < 1 || (int64_t)grid * wpg != a.waves ||
         lds < flow_group_lds(rows, elem, wpg))
         return hipErrorInvalidValue;
@@ -420,9 +472,9 @@ hipError_t launch_pair_flow(const FlowArgs& a, int rows, int elem, int wpg, int 
     return hipGetLastError();
 }
 
-int flow_occupancy(int rows, int elem, int wpg, int lds)
+int flow_occupancy(int rows, int elem, int wpg, int lds, bool trace)
 {
-    const void* k = flow_kernel(rows, elem);
+    const void* k = flow_kernel(rows, elem, trace);
     int n = 0;
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * wpg, (size_t)lds) != hipSuccess)
         return 0;

@@ -2350,6 +2350,45 @@ int pair_diagonals(PairArgs a, PairPass kind, int R, int elem, int64_t b0, int64
     return SW_OK;
 }
 
+// The pipelined pass of plan p over the pair set up in `a` (layout L): the
+// score into `score`, or with `dir` the direction-code pass (8 rows per
+// lane, dir_stride row blocks per column) and the end key; -1 into `score`
+// if a wait gave up.
+int flow_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const PairArgs& a, int64_t n, int32_t go,
+                 int32_t ge, int elem, int32_t* score, uint32_t* dir, unsigned long long* end_key, int64_t dir_stride,
+                 int64_t m, hipStream_t stream)
+{
+    FlowArgs f{};
+    f.subj = a.subj;
+    f.prof = a.prof;
+    f.rows = reinterpret_cast<unsigned long long*>(w + L.flow);
+    f.score = score;
+    f.status = reinterpret_cast<int32_t*>(w + L.flow_status);
+    f.n = (int32_t)n;
+    f.n_pad = (int32_t)L.n_pad;
+    f.nbr = (int32_t)p.nbr;
+    f.nb = (int32_t)p.nb;
+    f.waves = p.waves;
+    f.go = go;
+    f.ge = ge;
+    f.timeout = kFlowTimeoutTicks;
+    f.dir = dir;
+    f.end_key = end_key;
+    f.dir_stride = dir_stride;
+    f.m = m;
+    // every band's wave must be resident at once (a band waits for the
+    // band above, which may run on any other wave)
+    int cu = 0;
+    int rc = device_cu(&cu);
+    if (rc) return rc;
+    const int occ = flow_occupancy(p.R, elem, p.wpg, p.lds, dir != nullptr);
+    if (occ < 1 || p.grid > occ * cu)
+        return fail(SW_EHIP, "pipelined pass: " + std::to_string(p.grid) + " workgroups of " +
+                                 std::to_string(p.wpg) + " waves do not fit the device at once");
+    HIPCHK(launch_pair_flow(f, p.R, elem, p.wpg, p.grid, p.lds, stream));
+    return SW_OK;
+}
+
 // Everything one pass over a pair enqueues: setup, then the anti-diagonal
 // launches (score pass), and for an alignment with direction codes for the
 // whole matrix a second pass of the same tiles writing the codes and the end key.
@@ -2364,31 +2403,9 @@ int pair_enqueue(const PairPlanC& p, const PairLayout& L, uint8_t* w, const uint
     if (rc || empty)
         return rc;
     if (p.flow) {
-        FlowArgs f{};
-        f.subj = a.subj;
-        f.prof = a.prof;
-        f.rows = reinterpret_cast<unsigned long long*>(w + L.flow);
-        f.score = score_out;
-        f.status = reinterpret_cast<int32_t*>(w + L.flow_status);
-        f.n = (int32_t)n;
-        f.n_pad = (int32_t)L.n_pad;
-        f.nbr = (int32_t)p.nbr;
-        f.nb = (int32_t)p.nb;
-        f.waves = p.waves;
-        f.go = go;
-        f.ge = ge;
-        f.timeout = kFlowTimeoutTicks;
-        // every band's wave must be resident at once (a band waits for the
-        // band above, which may run on any other wave)
-        int cu = 0;
-        rc = device_cu(&cu);
-        if (rc) return rc;
-        const int occ = flow_occupancy(p.R, elem, p.wpg, p.lds);
-        if (occ < 1 || p.grid > occ * cu)
-            return fail(SW_EHIP, "pipelined pass: " + std::to_string(p.grid) + " workgroups of " +
-                                     std::to_string(p.wpg) + " waves do not fit the device at once");
         if (ev0) HIPCHK(hipEventRecord(ev0, stream));
-        HIPCHK(launch_pair_flow(f, p.R, elem, p.wpg, p.grid, p.lds, stream));
+        rc = flow_enqueue(p, L, w, a, n, go, ge, elem, score_out, nullptr, nullptr, 0, 0, stream);
+        if (rc) return rc;
         if (ev1) HIPCHK(hipEventRecord(ev1, stream));
         return SW_OK;
     }
@@ -2760,15 +2777,23 @@ int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     // With whole-matrix codes the score may come from the pipelined pass
     // when the planner takes it for the pair; its buffers and the tiles' then
     // sit in the layout bound for every schedule, which holds both.
-    PairPlanC sp{};
+    // So may the code pass: the pipelined pass with 8 rows per lane (the
+    // tiles' row blocks) when the planner takes it over the tiles.
+    PairPlanC sp{}, cp{};
     if (!align_blocked(m, n, opt) && m > 0 && n > 0) {
         int lds = kLdsPerCU, sm_max = 0;
         rc = device_lds(&lds);
         if (rc) return rc;
         for (int i = 0; i < kAlpha * kAlpha; ++i) sm_max = std::max(sm_max, (int)sm[i]);
         sp = pair_plan(m, n, cu, opt, false, sm_max, elem, lds);
+        sw_options co = opt ? *opt : sw_options{};
+        co.pair_rows = 8;
+        const PairPlanC c = pair_plan(m, n, cu, &co, false, sm_max, elem, lds);
+        if (c.flow && c.R == 8 && c.nb == p.nb)
+            cp = c;
     }
-    const PairLayout L = sp.flow ? pair_layout(m, n, nullptr, pair_wc_max(opt)) : pair_layout(m, n, &p, p.wc);
+    const bool either = sp.flow || cp.flow;
+    const PairLayout L = either ? pair_layout(m, n, nullptr, pair_wc_max(opt)) : pair_layout(m, n, &p, p.wc);
     const size_t x_off = align_up(L.total, 256);
     const AlignLayout A = align_layout(m, n, opt, &p);
     if (x_off + A.total > need)
@@ -2781,23 +2806,27 @@ int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     auto* dir = reinterpret_cast<uint32_t*>(x + A.dir);
     auto* end_key = reinterpret_cast<unsigned long long*>(x + A.tail);
     auto* walk = reinterpret_cast<WalkState*>(x + A.tail + 256);
-    if (sp.flow) {
-        // the score (-1 if a wait of the pass gave up), then the code pass
-        // over the alignment's tiles; their setup clears a spare word, not
-        // the score
-        rc = pair_enqueue(sp, L, w, query, m, subject, n, sm, go, ge, elem, &o->score, nullptr, nullptr,
+    if (either) {
+        // the score (-1 if a wait of the pipelined pass gave up), then the
+        // code pass; its setup clears a spare word, not the score
+        rc = pair_enqueue(sp.flow ? sp : p, L, w, query, m, subject, n, sm, go, ge, elem, &o->score, nullptr, nullptr,
                           opt ? opt->ev_search_begin : nullptr, nullptr, stream);
         if (rc) return rc;
+        const PairPlanC& q = cp.flow ? cp : p;
         PairArgs a{};
         bool empty = false;
-        rc = pair_setup(p, L, w, query, m, subject, n, sm, go, ge, elem, reinterpret_cast<int32_t*>(x + A.tail + 64),
+        rc = pair_setup(q, L, w, query, m, subject, n, sm, go, ge, elem, reinterpret_cast<int32_t*>(x + A.tail + 64),
                         stream, a, empty);
         if (rc) return rc;
-        a.score = &o->score;
-        a.dir = dir;
-        a.end_key = end_key;
         HIPCHK(launch_trace_reset(end_key, stream));
-        rc = pair_skew_diagonals(a, p, elem, stream, true);
+        if (cp.flow) {
+            rc = flow_enqueue(cp, L, w, a, n, go, ge, elem, &o->score, dir, end_key, p.nb * p.K, m, stream);
+        } else {
+            a.score = &o->score;
+            a.dir = dir;
+            a.end_key = end_key;
+            rc = pair_skew_diagonals(a, p, elem, stream, true);
+        }
         if (rc) return rc;
         if (opt && opt->ev_search_end) HIPCHK(hipEventRecord(opt->ev_search_end, stream));
     } else {

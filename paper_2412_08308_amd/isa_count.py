@@ -59,7 +59,7 @@ VARIANTS = {
 # pipelined pair pass (csrc/sw_pair_flow.hip): R rows per lane, 8- / 16-bit profile
 for _R in (4, 6, 8, 10, 12, 16):
     for _ES in (1, 2):
-        VARIANTS[f"flow_r{_R}_p{8 * _ES}"] = (f"k_pair_flowILi{_R}ELi{_ES}E", _R, 1)
+        VARIANTS[f"flow_r{_R}_p{8 * _ES}"] = (f"k_pair_flowILi{_R}ELi{_ES}ELb0E", _R, 1)
 _FLOW = [k for k in VARIANTS if k.startswith("flow_")]
 # kernels with two copies of the hot loop (tiles at the matrix edge with a
 # per-column predicate, tiles inside without): count the copy inside
