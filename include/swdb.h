@@ -538,7 +538,7 @@ size_t sw_align_workspace_bytes(int64_t m, int64_t n, const sw_options* opt);
  *                   of them are written
  * Asynchronous on `stream` with whole-matrix codes; with blocks the call
  * reads the walk's position after each block and returns with the stream
- * drained.  With whole-matrix codes the score may come from the pipelined
+ * drained.  With whole-matrix codes either pass may run on the pipelined
  * pass (as in sw_pair_score); out->score = -1 (and no operations) then means
  * that a wait of that pass gave up, an error.  Returns SW_EINVAL, SW_ENOMEM
  * or SW_EHIP.
