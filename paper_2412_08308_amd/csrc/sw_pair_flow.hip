@@ -394,7 +394,8 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
 
 // Up to 6 rows per lane the state fits 128 registers (workgroups of up to 16
 // waves, four per SIMD); more rows take up to 256 (up to 8 waves, two per
-// SIMD).  Wave w of workgroup g is wave g * W + w of the launch.
+// SIMD).  Wave w of workgroup g is wave group * W + w of the launch, group the
+// number of g counted XCD by XCD (below).  TRACE: the direction-code pass.
 template <int R, int ES, bool TRACE = false>
 __global__ void __launch_bounds__(R <= 6 ? 1024 : 512) __attribute__((amdgpu_waves_per_eu(R <= 6 ? 4 : 2)))
 k_pair_flow(FlowArgs a)
