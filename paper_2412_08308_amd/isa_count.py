@@ -1,11 +1,12 @@
 """VALU instructions per DP cell in the hot loops of the search kernels.
 
 Compiles ``csrc/sw_isa_probe.hip`` (each hot-loop variant alone in a kernel,
-same flags as the library), ``csrc/sw_pair.hip`` and ``csrc/sw_k_rescore.hip``
-to AMD assembly of this build, finds each kernel's hot loop -- one trip sweeps
-four subject columns of R query rows, i.e. 4*R cells per lane (8*R for the
-packed 16-bit variant, two subjects per lane; 16 columns for the pair kernel)
--- and counts its instructions by class.  The VALU count per cell is the ISA operation count of the integer-VALU
+same flags as the library), ``csrc/sw_pair.hip``, ``csrc/sw_pair_flow.hip``
+and ``csrc/sw_k_rescore.hip`` to AMD assembly of this build, finds each
+kernel's hot loop -- one trip sweeps four subject columns of R query rows,
+i.e. 4*R cells per lane (8*R for the packed 16-bit variant, two subjects per
+lane; 16 columns for the pair kernels) -- and counts its instructions by
+class.  The VALU count per cell is the ISA operation count of the integer-VALU
 roofline.
 """
 from __future__ import annotations
