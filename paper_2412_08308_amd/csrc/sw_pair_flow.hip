@@ -142,14 +142,15 @@ __device__ __forceinline__ uint32_t min3_u32(uint32_t a, uint32_t b, uint32_t c)
     return __builtin_elementwise_min(__builtin_elementwise_min(a, b), c);
 }
 
-// TRACE: the direction-code pass of an alignment with whole-matrix codes (8
-// rows per lane, the tile passes' row blocks): every cell's 4-bit code into
-// dir[column * dir_stride + row block] and the first cell holding the score,
+// TRACE: the direction-code pass of an alignment with whole-matrix codes:
+// every cell's 4-bit code into the 32-bit word dir[column * dir_stride + row
+// block] of its 8-row block (with 4 rows per lane, a lane writes the low or
+// the high half of its block's word) and the first cell holding the score,
 // column-major, into end_key, exactly as the code tiles do; no score.
 template <int R, int ES, bool TRACE = false>
 __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int lane, uint32_t lds0)
 {
-    static_assert(!TRACE || R == 8, "direction words hold 8 rows");
+    static_assert(!TRACE || R == 8 || R == 4, "direction words hold 8 rows");
     constexpr uint32_t CS = code_stride(R, ES);
     constexpr uint32_t BS = kCodes * CS;
     constexpr int NW = (R * ES + 3) / 4;
@@ -325,7 +326,11 @@ __device__ __forceinline__ void pair_flow(const FlowArgs& a, int wave_id, int la
                         ybot = hup;
                         fbot = F;
                         if constexpr (TRACE) {
-                            a.dir[(int64_t)j * a.dir_stride + rb] = word;
+                            if constexpr (R == 8)
+                                a.dir[(int64_t)j * a.dir_stride + rb] = word;
+                            else                     // rows 4 (rb & 1) .. 4 (rb & 1) + 3 of block rb / 2
+                                reinterpret_cast<uint16_t*>(a.dir)[(int64_t)j * 2 * a.dir_stride + rb] =
+                                    (uint16_t)word;
                             // no H exceeds the pair's score: only a column whose
                             // maximum is the score holds the end cell
                             if (cmax == s_target) {
@@ -429,14 +434,18 @@ __global__ void k_pair_flow_finish(const int32_t* status, int32_t* score)
         *score = -1;
 }
 
-// The kernel of (rows, elem), or of the direction-code pass (8 rows per
+// The kernel of (rows, elem), or of the direction-code pass (4 or 8 rows per
 // lane); null for a shape it is not built for.
 static const void* flow_kernel(int rows, int elem, bool trace = false)
 {
     if (trace) {
-        if (rows != 8) return nullptr;
-        return elem == 1 ? reinterpret_cast<const void*>(&k_pair_flow<8, 1, true>)
-                         : reinterpret_cast<const void*>(&k_pair_flow<8, 2, true>);
+        switch (rows * 4 + elem) {
+        case 4 * 4 + 1: return reinterpret_cast<const void*>(&k_pair_flow<4, 1, true>);
+        case 4 * 4 + 2: return reinterpret_cast<const void*>(&k_pair_flow<4, 2, true>);
+        case 8 * 4 + 1: return reinterpret_cast<const void*>(&k_pair_flow<8, 1, true>);
+        case 8 * 4 + 2: return reinterpret_cast<const void*>(&k_pair_flow<8, 2, true>);
+        default: return nullptr;
+        }
     }
     switch (rows * 4 + elem) {
     case 4 * 4 + 1: return reinterpret_cast<const void*>(&k_pair_flow<4, 1>);

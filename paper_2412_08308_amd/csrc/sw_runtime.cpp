@@ -2051,8 +2051,10 @@ PairPlanC pair_plan(int64_t m, int64_t n, int cu, const sw_options* opt, bool re
                 return e.p;
     }
     PairPlanC p;
+    // row counts only the pipelined pass has leave the tiles free (with none
+    // of theirs the search would find no candidate)
     if (mode != 2 || m <= 0 || n <= 0)          // an empty pair has nothing to pipeline
-        p = pair_plan_search(m, n, cu, mode == 0 && fixR && !(fixR == 8 || fixR == 16) ? 0 : fixR, fixK, fixW, rect);
+        p = pair_plan_search(m, n, cu, fixR == 8 || fixR == 16 ? fixR : 0, fixK, fixW, rect);
     else
         p.est_s = 1e300;
     // the pipelined pass, where the scores fit its words (and no tile knob is set)
@@ -2777,8 +2779,9 @@ int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64
     // With whole-matrix codes the score may come from the pipelined pass
     // when the planner takes it for the pair; its buffers and the tiles' then
     // sit in the layout bound for every schedule, which holds both.
-    // So may the code pass: the pipelined pass with 8 rows per lane (the
-    // tiles' row blocks) when the planner takes it over the tiles.
+    // So may the code pass: the pipelined pass with 4 or 8 rows per lane (the
+    // tiles' 8-row blocks, or halves of them) when the planner takes it over
+    // the tiles.
     PairPlanC sp{}, cp{};
     if (!align_blocked(m, n, opt) && m > 0 && n > 0) {
         int lds = kLdsPerCU, sm_max = 0;
@@ -2786,11 +2789,15 @@ int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64
         if (rc) return rc;
         for (int i = 0; i < kAlpha * kAlpha; ++i) sm_max = std::max(sm_max, (int)sm[i]);
         sp = pair_plan(m, n, cu, opt, false, sm_max, elem, lds);
+        // 4 rows per lane write half words: twice the bands of 8 rows, all
+        // inside the code region (ceil(m / 256) <= 2 ceil(m / 512) bands)
         sw_options co = opt ? *opt : sw_options{};
-        co.pair_rows = 8;
-        const PairPlanC c = pair_plan(m, n, cu, &co, false, sm_max, elem, lds);
-        if (c.flow && c.R == 8 && c.nb == p.nb)
-            cp = c;
+        for (int R : {4, 8}) {
+            co.pair_rows = R;
+            const PairPlanC c = pair_plan(m, n, cu, &co, false, sm_max, elem, lds);
+            if (c.flow && c.R == R && c.nb * R <= p.nb * 8 && (!cp.flow || c.est_s < cp.est_s))
+                cp = c;
+        }
     }
     const bool either = sp.flow || cp.flow;
     const PairLayout L = either ? pair_layout(m, n, nullptr, pair_wc_max(opt)) : pair_layout(m, n, &p, p.wc);
