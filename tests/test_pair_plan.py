@@ -244,3 +244,26 @@ def test_pair_plan_cache_keys_every_option():
     small = swdb.pair_plan(m, n, cu_count=32)
     assert small["est_ms"] > base["est_ms"]        # fewer compute units: a slower plan
     assert swdb.pair_plan(m, n, cu_count=256) == base
+
+
+def test_pair_plan_every_option_gives_a_plan_or_an_error():
+    """Every combination of the pair knobs either plans (a positive tiling or
+    a pipelined shape with a finite estimate) or is rejected with an error,
+    never a zero plan.  (The alignment also plans internally with row counts
+    only the pipelined pass has, which this call rejects outside the pipelined
+    mode; the GPU alignment test that forces the tiles covers that route.)"""
+    import math
+    for m, n in [(1, 1), (3000, 4000), (70_001, 2_000)]:
+        for mode in ("auto", "tiles", "flow"):
+            for R in (0, 4, 6, 8, 10, 12, 16, 24):
+                for K in (0, 1, 8, 64):
+                    for wc in (0, 16, 8192):
+                        o = swdb.options(pair_mode=mode, pair_rows=R, max_lanes=K, pair_cols=wc, pair_sm_max=1)
+                        try:
+                            p = swdb.pair_plan(m, n, o)
+                        except swdb.SwdbError:
+                            continue
+                        assert p["rows"] > 0 and p["lanes"] > 0 and math.isfinite(p["est_ms"])
+                        assert p["flow"] or (p["cols"] > 0 and p["chunks"] > 0 and p["bands"] > 0)
+                        if R and not p["flow"]:
+                            assert p["rows"] == R
