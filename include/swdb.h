@@ -106,7 +106,8 @@ typedef struct sw_options {
                               launches, 2 = one pipelined launch (bands hand rows
                               to the band below through memory; needs the largest
                               score below 2^24); pair_rows then picks R from
-                              4, 6, 8, 10, 12, 16                              */
+                              4, 6, 8, 10, 12, 16 (sw_align_pair: the code pass
+                              runs there with 4 or 8 only, the tiles else)     */
     int32_t pair_sm_max;   /* sw_pair_plan: the largest substitution-matrix entry
                               the pair will be scored with (0 = 127); scoring
                               calls take it from the matrix                    */

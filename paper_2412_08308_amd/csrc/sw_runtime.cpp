@@ -2791,8 +2791,11 @@ int sw_align_pair(const uint8_t* query, int64_t m, const uint8_t* subject, int64
         sp = pair_plan(m, n, cu, opt, false, sm_max, elem, lds);
         // 4 rows per lane write half words: twice the bands of 8 rows, all
         // inside the code region (ceil(m / 256) <= 2 ceil(m / 512) bands)
+        // (an explicit pair_rows holds for the code pass too: 4 or 8 there,
+        // any other leaves the codes to the tiles)
         sw_options co = opt ? *opt : sw_options{};
         for (int R : {4, 8}) {
+            if (opt && opt->pair_rows && opt->pair_rows != R) continue;
             co.pair_rows = R;
             const PairPlanC c = pair_plan(m, n, cu, &co, false, sm_max, elem, lds);
             if (c.flow && c.R == R && c.nb * R <= p.nb * 8 && (!cp.flow || c.est_s < cp.est_s))

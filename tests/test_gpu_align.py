@@ -48,6 +48,18 @@ def test_score_pass_either_way(mode):
     assert _gpu_align(a, b, psm, 10, 2, pair_mode=mode) == oracle.align(a, b, psm, 10, 2)
 
 
+@pytest.mark.parametrize("rows", [4, 8])
+def test_pipelined_code_pass_rows(rows):
+    """The pipelined code pass with its row count fixed: 8 rows per lane fill
+    a direction word, 4 rows one half of it; row counts just past a band
+    (256 rows at 4, 512 at 8) and narrow or wide pairs."""
+    sm, go, ge = DNA
+    for m, n, seed in [(257, 900, 11), (513, 700, 12), (2001, 2300, 13), (77, 3000, 14), (4103, 900, 15)]:
+        a, b = synth.dna_pair(m, n, seed=seed, identity=0.8, indel_rate=0.02)
+        announce(f"align m={m} n={n} code pass rows={rows}")
+        assert _gpu_align(a, b, sm, go, ge, pair_mode="flow", pair_rows=rows) == oracle.align(a, b, sm, go, ge)
+
+
 @pytest.mark.parametrize("go,ge", [(10, 2), (0, 3), (4, 4), (120, 1)])
 def test_protein_alignments(go, ge):
     # (120, 1): 16-bit profile entries; the others 8-bit
